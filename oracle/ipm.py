@@ -1,0 +1,137 @@
+"""A tiny primal-dual interior-point method around the Hessian equation (test infrastructure).
+
+Used to check, on a real interior-point path, that the Hessian equation the GPU
+library solves is the one an interior-point method needs (Section 2), that the
+iterates become ill-conditioned as the paper describes (Proposition "Weig"), and
+that PCG with the paper's preconditioner needs a flat, small number of
+iterations as mu -> 0 (Section 3, Lemma "Htilde").
+
+Problem: the bipartite matrix-completion SDP (eq matcomp_sdp), n = p + q,
+A_i = 1/2 [[0, E^T], [E, 0]] for each observed (i, j), C = I.
+
+Method: infeasible path-following with the Nesterov-Todd scaling (Section 2.2,
+third bullet): W is the positive definite matrix with X = W S W.  With
+R_d = C - S - sum y_i A_i, the NT Newton system reduces to the Hessian equation
+(eq hesseqn1)  H dy = b - sigma mu A(S^{-1}) + A(W R_d W),
+then dS = R_d - sum dy_i A_i and dX = sigma mu S^{-1} - X - W dS W
+(Todd, Toh and Tutuncu, SIAM J. Optim. 1998).  Steps go 0.9 of the way to the
+boundary of the cone, sigma = 0.1.  The paper's own outer solver is SeDuMi's,
+which is not reproduced: parity with it is unpinned.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import alg1
+from .hessian import hessian_dense
+
+
+def matcomp_instance(p, q, k, m, seed):
+    rng = np.random.default_rng(seed)
+    G1 = rng.standard_normal((p, k))
+    G2 = rng.standard_normal((q, k))
+    Mtrue = G1 @ G2.T
+    t = np.sort(rng.choice(p * q, size=m, replace=False))
+    ii, jj = t // q, t % q
+    a = ii.astype(np.int64)
+    b = (p + jj).astype(np.int64)
+    val = np.full(m, 0.5)
+    bvec = Mtrue[ii, jj]
+    return dict(n=p + q, p=p, q=q, k=k, a=a, b=b, val=val, bvec=bvec, Mtrue=Mtrue)
+
+
+def _sqrtm_psd(X):
+    lam, V = np.linalg.eigh(X)
+    return (V * np.sqrt(np.maximum(lam, 0.0))) @ V.T
+
+
+def nt_scaling(X, S):
+    """W = S^{-1/2} (S^{1/2} X S^{1/2})^{1/2} S^{-1/2}; satisfies W S W = X."""
+    lam, V = np.linalg.eigh(S)
+    Sh = (V * np.sqrt(lam)) @ V.T
+    Sih = (V / np.sqrt(lam)) @ V.T
+    W = Sih @ _sqrtm_psd(Sh @ X @ Sh) @ Sih
+    return 0.5 * (W + W.T)
+
+
+def _max_step(X, dX):
+    L = np.linalg.cholesky(X)
+    Li = np.linalg.inv(L)
+    lam = np.linalg.eigvalsh(Li @ dX @ Li.T)
+    lo = lam[0]
+    return np.inf if lo >= 0 else -1.0 / lo
+
+
+@dataclass
+class IPMRecord:
+    mu: float
+    pinf: float
+    dinf: float
+    gap: float
+    pcg_iters: int
+    dy_rel_diff: float     # ||dy_pcg - dy_dense|| / ||dy_dense||
+    w_gap: float           # lambda_k(W) / lambda_{k+1}(W)
+
+
+@dataclass
+class IPMResult:
+    X: np.ndarray
+    y: np.ndarray
+    S: np.ndarray
+    iters: int
+    converged: bool
+    records: list = field(default_factory=list)
+
+
+def run(inst, tol=1e-9, max_iter=60, sigma=0.1, frac=0.9, pcg_k=None, pcg_eps=1e-10):
+    n, a, b, val, bvec = inst["n"], inst["a"], inst["b"], inst["val"], inst["bvec"]
+    m = len(a)
+    Cst = alg1.Constraints(n, a, b, val)
+    Cmat = np.eye(n)
+    xi = max(10.0, np.sqrt(n), n * float(np.max((1 + np.abs(bvec)) / (1 + np.sqrt(Cst.g)))))
+    eta = max(10.0, np.sqrt(n), 1.0 + np.linalg.norm(Cmat))
+    X = xi * np.eye(n)
+    S = eta * np.eye(n)
+    y = np.zeros(m)
+    k = pcg_k if pcg_k is not None else inst["k"]
+    recs = []
+    conv = False
+    it = 0
+    for it in range(max_iter):
+        mu = float(np.sum(X * S)) / n
+        Ay = Cst.mat(y).toarray()
+        Rd = Cmat - S - Ay
+        Rp = bvec - Cst.At(X)
+        pinf = np.linalg.norm(Rp) / (1 + np.linalg.norm(bvec))
+        dinf = np.linalg.norm(Rd) / (1 + np.linalg.norm(Cmat))
+        gap = float(np.sum(X * S)) / (1 + abs(np.trace(X)) + abs(bvec @ y))
+        if max(pinf, dinf, gap) <= tol:
+            conv = True
+            break
+        W = nt_scaling(X, S)
+        Si = np.linalg.inv(S)
+        rhs = bvec - sigma * mu * Cst.At(Si) + Cst.At(W @ Rd @ W)
+        H = hessian_dense(W, a, b, val)
+        dy = np.linalg.solve(H, rhs)
+        # the same Newton system solved by Algorithm 1 (PCG, true rank k)
+        lamW = np.linalg.eigvalsh(W)
+        F = alg1.factor(Cst, W, k)
+        res = alg1.solve(F, rhs, eps=pcg_eps, max_iter=500,
+                         Hmul=lambda v: H @ v)
+        diff = float(np.linalg.norm(res.y - dy) / max(np.linalg.norm(dy), 1e-300))
+        recs.append(IPMRecord(mu=mu, pinf=pinf, dinf=dinf, gap=gap, pcg_iters=res.iters,
+                              dy_rel_diff=diff, w_gap=float(lamW[n - k] / lamW[n - k - 1])))
+        dS = Rd - Cst.mat(dy).toarray()
+        dX = sigma * mu * Si - X - W @ dS @ W
+        dX = 0.5 * (dX + dX.T)
+        ap = min(1.0, frac * _max_step(X, dX))
+        ad = min(1.0, frac * _max_step(S, dS))
+        X = X + ap * dX
+        X = 0.5 * (X + X.T)
+        y = y + ad * dy
+        S = S + ad * dS
+        S = 0.5 * (S + S.T)
+    return IPMResult(X=X, y=y, S=S, iters=it, converged=conv, records=recs)

@@ -1,0 +1,199 @@
+/*
+ * lrsdp.h -- C ABI of the MI355X (gfx950) solver for the interior-point Hessian
+ * equation of a large-and-sparse low-rank SDP.
+ *
+ * Paper: R. Y. Zhang and J. Lavaei, "Modified Interior-Point Method for
+ * Large-and-Sparse Low-Rank Semidefinite Programs" (arXiv 1703.10973).
+ *
+ * The operation is Algorithm 1 of Section 3.3: given the SDP data A_1..A_m
+ * (eqs SDP/SDD), a scaling matrix W (positive definite, Section 2.2), a rank k
+ * and a right-hand side r, return y with ||H y - r|| <= eps ||r||, where
+ * H = A^T (W kron W) A (eqs hesseqn2 and hesseqn1).  H is applied matrix-free;
+ * PCG is preconditioned by H~ = tau^2 A^T A + bold U bold U^T (eq AtIUUtAt)
+ * through the Sherman-Morrison-Woodbury form (eq SMW2).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers on the context's device unless the
+ *     comment says "host".  The library copies what it keeps; no caller pointer
+ *     is retained after a call returns.  The caller owns every array it passes.
+ *   - Matrices are dense, row-major, with leading dimension equal to the number
+ *     of columns (W, Z, W0 are symmetric or lower triangular n x n).
+ *   - Work is enqueued on the context's stream; every call that returns a status
+ *     synchronizes that stream before returning, so outputs are ready on return.
+ *   - Return value: LRSDP_OK (0), a positive warning, or a negative error.  After
+ *     an error every handle stays valid and may be reused or destroyed.
+ *   - A handle must not be used by two host threads at once.
+ */
+#ifndef LRSDP_H
+#define LRSDP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Only the functions below are exported from the shared library. */
+#if defined(__GNUC__) || defined(__clang__)
+#define LRSDP_API __attribute__((visibility("default")))
+#else
+#define LRSDP_API
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define LRSDP_OK                      0
+#define LRSDP_NOT_CONVERGED           1   /* warning: y holds the last iterate, info filled   */
+#define LRSDP_ERR_INVALID_ARG        -1   /* n <= 0, k not in [1, n-1], index out of range,   */
+                                          /* row > col, null pointer, bad option value        */
+#define LRSDP_ERR_DUPLICATE_PAIR     -2   /* two constraints with the same entry (a, b)      */
+#define LRSDP_ERR_UNSUPPORTED        -3   /* a constraint with more than one triplet, i.e.    */
+                                          /* A^T A not diagonal (Assumption 2 then needs a     */
+                                          /* sparse Cholesky of A^T A, which is not built)     */
+#define LRSDP_ERR_NOT_PD_W           -4   /* lambda_min(W) <= 0 or W not finite                */
+#define LRSDP_ERR_CHOL_Z             -5   /* Cholesky of 2 W0 + U U^T broke down               */
+#define LRSDP_ERR_CHOL_S             -6   /* Cholesky of bold S broke down                     */
+#define LRSDP_ERR_OUT_OF_BUDGET      -7   /* the context's HBM budget would be exceeded         */
+#define LRSDP_ERR_STAGNATED          -8   /* refinement stopped reducing the true residual     */
+#define LRSDP_ERR_INDEFINITE_PRECOND -9   /* PCG met r^T z <= 0 or p^T H p <= 0                */
+#define LRSDP_ERR_DEVICE            -10   /* a HIP runtime call failed                          */
+#define LRSDP_ERR_EIG               -11   /* the symmetric eigensolver did not converge         */
+
+/* ------------------------------------------------------------------ handles */
+typedef struct lrsdp_ctx lrsdp_ctx;          /* device, stream, HBM budget                     */
+typedef struct lrsdp_problem lrsdp_problem;  /* the data A_1..A_m on the device (step A0)      */
+typedef struct lrsdp_factor lrsdp_factor;    /* W and the preconditioner factors (Alg. 1 1-2) */
+
+/* ------------------------------------------------------------------ options */
+#define LRSDP_PREC_FP64   0   /* H v with W in FP64                                            */
+#define LRSDP_PREC_FP32   1   /* split H v: W0 part in FP32 (FP32 accumulation), rest FP64/dd  */
+#define LRSDP_PREC_BF16   2   /* split H v: W0 part with BF16 operands, FP32 accumulation      */
+
+#define LRSDP_DD_OFF      0   /* plain PCG in FP64, answer in y only                            */
+#define LRSDP_DD_ON       1   /* outer refinement with double-double residual, answer y + y_lo  */
+#define LRSDP_DD_AUTO     2   /* ON when lambda_{n-k}(W) / lambda_{n-k+1}(W) < dd_auto_ratio     */
+
+typedef struct lrsdp_opts {
+  double eps;            /* target relative residual ||r - H y|| / ||r|| (default 1e-8)     */
+  int max_iter;          /* PCG iterations per inner solve (default 200)                    */
+  int precision;         /* LRSDP_PREC_* (default FP64)                                     */
+  int dd_mode;           /* LRSDP_DD_* (default AUTO)                                       */
+  int deflate;           /* 1: deflate the k(k-1)/2 null directions of bold S (default 1)   */
+  int max_outer;         /* outer refinement steps (default 8)                              */
+  double inner_eps;      /* inner PCG tolerance in refinement mode (default 1e-3)           */
+  double dd_auto_ratio;  /* spectral-gap threshold for LRSDP_DD_AUTO (default 2e-5)         */
+  int dd_precond;        /* SMW pieces in double-double: 0 off, 1 on, 2 auto (default 2:    */
+                         /* on when tau < 1e-7 lambda_max(W))                                */
+} lrsdp_opts;
+
+typedef struct lrsdp_info {
+  int status;            /* same as the return value                                        */
+  int iters;             /* PCG iterations, summed over inner solves                        */
+  int outer_iters;       /* refinement steps (0 when dd_mode resolved to OFF)               */
+  int dd_used;           /* 1 if the answer is the pair y + y_lo                            */
+  double relres;         /* final relative residual: recursive (OFF) or double-double true  */
+  double tau;            /* lambda_min(W)                                                   */
+  double setup_ms;       /* time of the factor this solve used (Alg. 1 steps 1-2)           */
+  double solve_ms;       /* wall time of this call                                          */
+} lrsdp_info;
+
+/* Fills *o with the defaults listed above.  o: host. */
+LRSDP_API void lrsdp_opts_default(lrsdp_opts* o);
+
+/* Human-readable name of a status code (static storage). */
+LRSDP_API const char* lrsdp_status_string(int status);
+
+/* ------------------------------------------------------------------ context */
+/* Creates a context on HIP device `device`.  `stream` is a hipStream_t to run on (NULL:
+ * the library creates its own default-priority stream).  `hbm_budget_bytes` caps the
+ * device memory all handles of this context may hold (0: no cap).  out: host. */
+LRSDP_API int lrsdp_ctx_create(int device, void* stream, size_t hbm_budget_bytes, lrsdp_ctx** out);
+LRSDP_API void lrsdp_ctx_destroy(lrsdp_ctx* ctx);
+/* Device bytes currently held by handles of this context.  out: host. */
+LRSDP_API int lrsdp_ctx_memory(const lrsdp_ctx* ctx, size_t* in_use, size_t* budget);
+
+/* Kernel timing: with profiling on, selected kernels are bracketed by HIP events on the
+ * context's stream and their count, total time and algorithmic bytes / flops accumulate per
+ * class.  `enable` is a bit mask of classes (bit LRSDP_K_*; -1 all, 0 off); every call resets
+ * the counters.  Used by benchmarks to compute roofline fractions. */
+#define LRSDP_K_HV      0   /* fused scatter -> SpMM -> sampled-gather H v kernel (A5/A7)     */
+#define LRSDP_K_GEMM    1   /* FP64 MFMA GEMM (bold S formation, POTRF/TRTRI/LAUUM updates)   */
+#define LRSDP_K_TRI     2   /* Householder tridiagonalization step (A1)                       */
+#define LRSDP_K_GEMV    3   /* bold S^{-1} w GEMV (A6)                                         */
+#define LRSDP_K_BZ      4   /* sparse B_JL Z pass of bold S formation (A3)                    */
+#define LRSDP_K_RESDD   5   /* double-double residual r - H y (A8)                            */
+#define LRSDP_K_COUNT   6
+LRSDP_API int lrsdp_ctx_profile(lrsdp_ctx* ctx, int enable);
+/* Counters of one kernel class; every output is host and may be NULL. */
+LRSDP_API int lrsdp_ctx_profile_read(const lrsdp_ctx* ctx, int kernel_class, int64_t* launches,
+                                     double* total_ms, double* bytes, double* flops);
+
+/* ------------------------------------------------------------------ A0: data */
+/* The constraint matrices as triplets (eqs SDP/SDD; Assumption 2).  Entry t says
+ * (A_con[t])_{row[t], col[t]} = (A_con[t])_{col[t], row[t]} = val[t], row[t] <= col[t],
+ * 0-based.  Each constraint must own exactly one triplet and the pairs (row, col) must be
+ * distinct, so the supports are disjoint and A^T A is diagonal with entries val^2 (row ==
+ * col) or 2 val^2.  con, row, col: int32 device arrays of length nnz; val: double device
+ * array.  Errors: INVALID_ARG, DUPLICATE_PAIR, UNSUPPORTED (nnz != m or a constraint
+ * without / with several triplets), OUT_OF_BUDGET.  Builds the symmetric sparsity pattern of
+ * mat(A v) (CSR, sorted columns) used by every product with A and A^T. */
+LRSDP_API int lrsdp_problem_create(lrsdp_ctx* ctx, int64_t n, int64_t m, int64_t nnz,
+                         const int32_t* con, const int32_t* row, const int32_t* col,
+                         const double* val, lrsdp_problem** out);
+LRSDP_API void lrsdp_problem_destroy(lrsdp_problem* p);
+/* n, m and the number of stored entries of the symmetric pattern.  Outputs: host. */
+LRSDP_API int lrsdp_problem_info(const lrsdp_problem* p, int64_t* n, int64_t* m, int64_t* nnz_pattern);
+
+/* ------------------------------------------------------------------ A5: H v */
+/* Hv = H v = [A_i . (W mat(A v) W)]_i in FP64 (eq hesseqn2), W an n x n symmetric device
+ * array (not retained), v and Hv length-m device arrays.  Parity hook for step A5. */
+LRSDP_API int lrsdp_hessian_apply(lrsdp_problem* p, const double* W, const double* v, double* Hv);
+
+/* ------------------------------------------------------------------ A1-A4: setup */
+/* Algorithm 1 steps 1-2 for scaling matrix W (n x n symmetric positive definite, device,
+ * copied) and rank k (1 <= k < n): eigendecomposition of W (lambda_min and the k largest
+ * pairs), tau = lambda_min(W), U = V_l (Lambda_l - tau)^{1/2}, W0 = W - U U^T, Z = chol(2 W0
+ * + U U^T) (eqs Wsplit1, Wsplit2, hessExp2), bold S = tau^2 I + bold U^T (A^T A)^{-1} bold U
+ * (eq SMW2), its deflation (opts->deflate) and Cholesky factor L, kept as the explicit
+ * inverse bold S^{-1} = L^{-T} L^{-1}.  opts may be NULL (defaults).  Errors: INVALID_ARG,
+ * NOT_PD_W, EIG, CHOL_Z, CHOL_S, OUT_OF_BUDGET, DEVICE. */
+LRSDP_API int lrsdp_factor_create(lrsdp_problem* p, const double* W, int32_t k, const lrsdp_opts* opts,
+                        lrsdp_factor** out);
+LRSDP_API void lrsdp_factor_destroy(lrsdp_factor* f);
+
+/* Export of the setup results for parity checks.  Host outputs: tau, shift (the deflation
+ * shift, 0 if none), lam[k + 1] = {lambda_min(W), then the k largest eigenvalues ascending},
+ * setup_ms.  Device outputs (each may be NULL): U (n x k), W0 (n x n), Z (n x n, lower, zero
+ * above the diagonal), Sinv (nk x nk, full symmetric, nk index p + n j). */
+LRSDP_API int lrsdp_factor_export(const lrsdp_factor* f, double* tau, double* shift, double* lam,
+                        double* setup_ms, double* U, double* W0, double* Z, double* Sinv);
+
+/* Step A7 parity hook: H v in the split form of eq hessExp1 with the W0 part computed in
+ * `precision` (LRSDP_PREC_*) and the rank-k part in FP64 with M U in double-double. */
+LRSDP_API int lrsdp_hessian_apply_split(lrsdp_factor* f, const double* v, double* Hv, int precision);
+
+/* Step A6 parity hook: z = H~^{-1} v by eq SMW2.  dd = 0: FP64 with the explicit bold S^{-1};
+ * dd = 1: w = bold U^T G^{-1} v and t = bold S^{-1} w carried in double-double (t refined
+ * against the matrix-free bold S); dd = 2: FP64 with one refinement step of t.  v, z:
+ * length-m device arrays. */
+LRSDP_API int lrsdp_precond_apply(lrsdp_factor* f, const double* v, double* z, int dd);
+
+/* The true relative residual ||r - H (y + y_lo)|| / ||r|| with every product in
+ * double-double (step A8's outer residual).  y_lo may be NULL.  res (device, length m, may be
+ * NULL) receives r - H y rounded to FP64; relres: host. */
+LRSDP_API int lrsdp_residual_dd(lrsdp_factor* f, const double* r, const double* y, const double* y_lo,
+                      double* res, double* relres);
+
+/* ------------------------------------------------------------------ A8: solve */
+/* Algorithm 1 step 3: PCG on H y = r (r, y: length-m device arrays) with the factor's
+ * preconditioner, to ||H y - r|| <= eps ||r||.  With refinement (dd_mode) the answer is the
+ * double-double pair y + y_lo (y_lo: length-m device array; required when dd_mode != OFF,
+ * zero-filled when the pair is not needed).  info: host, may be NULL.  Returns OK,
+ * NOT_CONVERGED, STAGNATED, INDEFINITE_PRECOND, INVALID_ARG or DEVICE. */
+LRSDP_API int lrsdp_solve(lrsdp_factor* f, const double* r, double* y, double* y_lo,
+                const lrsdp_opts* opts, lrsdp_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LRSDP_H */

@@ -1,0 +1,150 @@
+"""MI355X (gfx950) solver for the interior-point Hessian equation of low-rank SDPs.
+
+Hot path of Zhang and Lavaei's modified interior-point method (arXiv 1703.10973,
+Algorithm 1): PCG on H y = r with H = A^T (W kron W) A applied matrix-free and the
+low-rank-correcting preconditioner built from a partial eigendecomposition of W.
+All computation runs in the HIP library liblrsdp.so (include/lrsdp.h); this package is
+its thin Python binding.  The C functions are re-exported under their own names, and
+Context / Problem / Factor wrap the handles.
+"""
+
+from __future__ import annotations
+
+import weakref
+
+import torch
+
+from ._lib import (  # noqa: F401
+    LRSDP_DD_AUTO, LRSDP_DD_OFF, LRSDP_DD_ON, LRSDP_PREC_BF16, LRSDP_PREC_FP32,
+    LRSDP_PREC_FP64, LrsdpError, header_symbols, lib, lrsdp_ctx_create, lrsdp_ctx_destroy,
+    lrsdp_ctx_memory, lrsdp_ctx_profile, lrsdp_ctx_profile_read, LRSDP_K_NAMES,
+    lrsdp_factor_create, lrsdp_factor_destroy, lrsdp_factor_export,
+    lrsdp_hessian_apply, lrsdp_hessian_apply_split, lrsdp_info, lrsdp_opts,
+    lrsdp_opts_default, lrsdp_precond_apply, lrsdp_problem_create, lrsdp_problem_destroy,
+    lrsdp_problem_info, lrsdp_residual_dd, lrsdp_solve, status_string)
+
+
+def opts(**kw):
+    """lrsdp_opts with the library defaults, overridden by keyword."""
+    o = lrsdp_opts_default()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """A device, stream and HBM budget.  Closing it first closes every problem and factor
+    created under it (the C ABI requires children to be destroyed before their parent)."""
+
+    def __init__(self, device=0, stream=None, hbm_budget_bytes=0):
+        self.device = device
+        self.handle = None
+        self._children = weakref.WeakSet()
+        self.handle = lrsdp_ctx_create(device, stream, hbm_budget_bytes)
+
+    def memory(self):
+        return lrsdp_ctx_memory(self.handle)
+
+    def profile(self, enable=True):
+        lrsdp_ctx_profile(self.handle, enable)
+
+    def profile_read(self):
+        return {name: lrsdp_ctx_profile_read(self.handle, i) for i, name in enumerate(LRSDP_K_NAMES)}
+
+    def close(self):
+        if self.handle:
+            for ch in list(self._children):
+                ch.close()
+            lrsdp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """Constraint data A_1..A_m as device triplets (step A0)."""
+
+    def __init__(self, ctx: Context, n, m, con, row, col, val):
+        self.ctx = ctx
+        self.n, self.m = int(n), int(m)
+        self.handle = None
+        self._children = weakref.WeakSet()
+        self.handle = lrsdp_problem_create(ctx.handle, n, m, con, row, col, val)
+        ctx._children.add(self)
+
+    def hessian_apply(self, W, v, out=None):
+        out = torch.empty_like(v) if out is None else out
+        lrsdp_hessian_apply(self.handle, W, v, out)
+        return out
+
+    def info(self):
+        return lrsdp_problem_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            for ch in list(self._children):
+                ch.close()
+            lrsdp_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Factor:
+    """W and the preconditioner of Algorithm 1 steps 1-2."""
+
+    def __init__(self, problem: Problem, W, k, options=None):
+        self.problem = problem
+        self.k = int(k)
+        self.handle = None
+        self.handle = lrsdp_factor_create(problem.handle, W, k, options)
+        problem._children.add(self)
+
+    def export(self, U=False, W0=False, Z=False, Sinv=False):
+        n, k = self.problem.n, self.k
+        dev = torch.device("cuda", self.problem.ctx.device)
+        mk = lambda flag, shape: torch.empty(shape, dtype=torch.float64, device=dev) if flag else None  # noqa: E731
+        tU, tW0, tZ, tS = mk(U, (k, n)), mk(W0, (n, n)), mk(Z, (n, n)), mk(Sinv, (n * k, n * k))
+        out = lrsdp_factor_export(self.handle, k, tU, tW0, tZ, tS)
+        out.update(U=tU, W0=tW0, Z=tZ, Sinv=tS)
+        return out
+
+    def hessian_apply_split(self, v, precision=LRSDP_PREC_FP64, out=None):
+        out = torch.empty_like(v) if out is None else out
+        lrsdp_hessian_apply_split(self.handle, v, out, precision)
+        return out
+
+    def precond_apply(self, v, dd=False, out=None):
+        out = torch.empty_like(v) if out is None else out
+        lrsdp_precond_apply(self.handle, v, out, 1 if dd else 0)
+        return out
+
+    def residual_dd(self, r, y, y_lo=None):
+        return lrsdp_residual_dd(self.handle, r, y, y_lo)
+
+    def solve(self, r, options=None, want_lo=True):
+        y = torch.empty_like(r)
+        ylo = torch.empty_like(r) if want_lo else None
+        st, info = lrsdp_solve(self.handle, r, y, ylo, options)
+        return y, ylo, st, info
+
+    def close(self):
+        if self.handle:
+            lrsdp_factor_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

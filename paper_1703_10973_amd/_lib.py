@@ -1,0 +1,272 @@
+"""ctypes binding of liblrsdp.so: the C ABI of include/lrsdp.h, same names, marshalling only.
+
+Every array argument is a torch tensor on the GPU (its device pointer is passed); scalars
+and the options / info structs are host values.  Nothing here computes: each call goes
+straight to the HIP library, and importing fails loudly when the library is not built.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import torch  # noqa: F401  (loads torch's HIP runtime first so the library binds to it)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblrsdp.so")
+
+LRSDP_OK = 0
+LRSDP_NOT_CONVERGED = 1
+LRSDP_ERR_INVALID_ARG = -1
+LRSDP_ERR_DUPLICATE_PAIR = -2
+LRSDP_ERR_UNSUPPORTED = -3
+LRSDP_ERR_NOT_PD_W = -4
+LRSDP_ERR_CHOL_Z = -5
+LRSDP_ERR_CHOL_S = -6
+LRSDP_ERR_OUT_OF_BUDGET = -7
+LRSDP_ERR_STAGNATED = -8
+LRSDP_ERR_INDEFINITE_PRECOND = -9
+LRSDP_ERR_DEVICE = -10
+LRSDP_ERR_EIG = -11
+
+LRSDP_PREC_FP64, LRSDP_PREC_FP32, LRSDP_PREC_BF16 = 0, 1, 2
+LRSDP_DD_OFF, LRSDP_DD_ON, LRSDP_DD_AUTO = 0, 1, 2
+
+
+class lrsdp_opts(C.Structure):
+    _fields_ = [("eps", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int),
+                ("dd_mode", C.c_int), ("deflate", C.c_int), ("max_outer", C.c_int),
+                ("inner_eps", C.c_double), ("dd_auto_ratio", C.c_double),
+                ("dd_precond", C.c_int)]
+
+
+class lrsdp_info(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int), ("outer_iters", C.c_int),
+                ("dd_used", C.c_int), ("relres", C.c_double), ("tau", C.c_double),
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LrsdpError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+_lib = None
+
+_P = C.c_void_p
+_SIGS = {
+    "lrsdp_opts_default": (None, [C.POINTER(lrsdp_opts)]),
+    "lrsdp_status_string": (C.c_char_p, [C.c_int]),
+    "lrsdp_ctx_create": (C.c_int, [C.c_int, _P, C.c_size_t, C.POINTER(_P)]),
+    "lrsdp_ctx_destroy": (None, [_P]),
+    "lrsdp_ctx_memory": (C.c_int, [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "lrsdp_ctx_profile": (C.c_int, [_P, C.c_int]),
+    "lrsdp_ctx_profile_read": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "lrsdp_problem_create": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P,
+                                       C.POINTER(_P)]),
+    "lrsdp_problem_destroy": (None, [_P]),
+    "lrsdp_problem_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_int64)]),
+    "lrsdp_hessian_apply": (C.c_int, [_P, _P, _P, _P]),
+    "lrsdp_factor_create": (C.c_int, [_P, _P, C.c_int32, C.POINTER(lrsdp_opts), C.POINTER(_P)]),
+    "lrsdp_factor_destroy": (None, [_P]),
+    "lrsdp_factor_export": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double), _P, _P, _P,
+                                      _P]),
+    "lrsdp_hessian_apply_split": (C.c_int, [_P, _P, _P, C.c_int]),
+    "lrsdp_precond_apply": (C.c_int, [_P, _P, _P, C.c_int]),
+    "lrsdp_residual_dd": (C.c_int, [_P, _P, _P, _P, _P, C.POINTER(C.c_double)]),
+    "lrsdp_solve": (C.c_int, [_P, _P, _P, _P, C.POINTER(lrsdp_opts), C.POINTER(lrsdp_info)]),
+}
+
+
+def header_symbols():
+    """Function names declared in include/lrsdp.h (parsed from the header text)."""
+    hdr = os.path.join(os.path.dirname(HERE), "include", "lrsdp.h")
+    with open(hdr) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"LRSDP_API\s+[\w\s\*]*?\b(lrsdp_\w+)\s*\(", text)))
+
+
+def _check_single_hip_runtime():
+    """Refuse to run with two HIP runtimes mapped (torch's and another one)."""
+    try:
+        with open("/proc/self/maps") as f:
+            paths = {ln.split()[-1] for ln in f if "libamdhip64" in ln}
+    except OSError:
+        return
+    real = {os.path.realpath(p) for p in paths}
+    if len(real) > 1:
+        raise RuntimeError(f"two HIP runtimes are loaded: {sorted(real)}")
+
+
+def lib():
+    """The loaded library (loaded on first use)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1703_10973_amd.build`")
+        h = C.CDLL(LIB_PATH, mode=C.RTLD_LOCAL)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(h, name)
+            fn.restype = res
+            fn.argtypes = args
+        _check_single_hip_runtime()
+        _lib = h
+    return _lib
+
+
+def status_string(s):
+    return lib().lrsdp_status_string(int(s)).decode()
+
+
+def _ptr(t, dtype=None, numel=None, name="array"):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _ok(st, where, allow_warn=False):
+    if st < 0 or (st > 0 and not allow_warn):
+        raise LrsdpError(st, where)
+    return st
+
+
+# ----------------------------------------------------------------- C ABI, same names
+
+def lrsdp_opts_default():
+    o = lrsdp_opts()
+    lib().lrsdp_opts_default(C.byref(o))
+    return o
+
+
+def lrsdp_ctx_create(device=0, stream=None, hbm_budget_bytes=0):
+    out = C.c_void_p()
+    sp = C.c_void_p(stream) if stream else None
+    _ok(lib().lrsdp_ctx_create(int(device), sp, C.c_size_t(hbm_budget_bytes), C.byref(out)),
+        "lrsdp_ctx_create")
+    return out
+
+
+def lrsdp_ctx_destroy(ctx):
+    lib().lrsdp_ctx_destroy(ctx)
+
+
+def lrsdp_ctx_memory(ctx):
+    a, b = C.c_size_t(), C.c_size_t()
+    _ok(lib().lrsdp_ctx_memory(ctx, C.byref(a), C.byref(b)), "lrsdp_ctx_memory")
+    return a.value, b.value
+
+
+LRSDP_K_NAMES = ["hv", "gemm", "tri", "gemv", "bz", "resdd"]
+
+
+def lrsdp_ctx_profile(ctx, enable):
+    _ok(lib().lrsdp_ctx_profile(ctx, int(enable)), "lrsdp_ctx_profile")
+
+
+def lrsdp_ctx_profile_read(ctx, kernel_class):
+    n, ms, by, fl = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
+    _ok(lib().lrsdp_ctx_profile_read(ctx, int(kernel_class), C.byref(n), C.byref(ms), C.byref(by),
+                                     C.byref(fl)), "lrsdp_ctx_profile_read")
+    return dict(launches=n.value, ms=ms.value, bytes=by.value, flops=fl.value)
+
+
+def lrsdp_problem_create(ctx, n, m, con, row, col, val):
+    nnz = con.numel()
+    out = C.c_void_p()
+    st = lib().lrsdp_problem_create(
+        ctx, int(n), int(m), int(nnz), _ptr(con, torch.int32, nnz, "con"),
+        _ptr(row, torch.int32, nnz, "row"), _ptr(col, torch.int32, nnz, "col"),
+        _ptr(val, torch.float64, nnz, "val"), C.byref(out))
+    _ok(st, "lrsdp_problem_create")
+    return out
+
+
+def lrsdp_problem_destroy(p):
+    lib().lrsdp_problem_destroy(p)
+
+
+def lrsdp_problem_info(p):
+    n, m, z = C.c_int64(), C.c_int64(), C.c_int64()
+    _ok(lib().lrsdp_problem_info(p, C.byref(n), C.byref(m), C.byref(z)), "lrsdp_problem_info")
+    return n.value, m.value, z.value
+
+
+def lrsdp_hessian_apply(p, W, v, Hv):
+    _ok(lib().lrsdp_hessian_apply(p, _ptr(W, torch.float64, name="W"),
+                                  _ptr(v, torch.float64, name="v"),
+                                  _ptr(Hv, torch.float64, v.numel(), "Hv")),
+        "lrsdp_hessian_apply")
+
+
+def lrsdp_factor_create(p, W, k, opts=None):
+    out = C.c_void_p()
+    st = lib().lrsdp_factor_create(p, _ptr(W, torch.float64, name="W"), int(k),
+                                   C.byref(opts) if opts is not None else None, C.byref(out))
+    _ok(st, "lrsdp_factor_create")
+    return out
+
+
+def lrsdp_factor_destroy(f):
+    lib().lrsdp_factor_destroy(f)
+
+
+def lrsdp_factor_export(f, k, U=None, W0=None, Z=None, Sinv=None):
+    tau, shift, ms = C.c_double(), C.c_double(), C.c_double()
+    lam = (C.c_double * (k + 1))()
+    st = lib().lrsdp_factor_export(f, C.byref(tau), C.byref(shift), lam, C.byref(ms),
+                                   _ptr(U, torch.float64, name="U"),
+                                   _ptr(W0, torch.float64, name="W0"),
+                                   _ptr(Z, torch.float64, name="Z"),
+                                   _ptr(Sinv, torch.float64, name="Sinv"))
+    _ok(st, "lrsdp_factor_export")
+    return dict(tau=tau.value, shift=shift.value, lam=list(lam), setup_ms=ms.value)
+
+
+def lrsdp_hessian_apply_split(f, v, Hv, precision):
+    _ok(lib().lrsdp_hessian_apply_split(f, _ptr(v, torch.float64, name="v"),
+                                        _ptr(Hv, torch.float64, v.numel(), "Hv"),
+                                        int(precision)), "lrsdp_hessian_apply_split")
+
+
+def lrsdp_precond_apply(f, v, z, dd=0):
+    _ok(lib().lrsdp_precond_apply(f, _ptr(v, torch.float64, name="v"),
+                                  _ptr(z, torch.float64, v.numel(), "z"), int(dd)),
+        "lrsdp_precond_apply")
+
+
+def lrsdp_residual_dd(f, r, y, y_lo=None, res=None):
+    rel = C.c_double()
+    _ok(lib().lrsdp_residual_dd(f, _ptr(r, torch.float64, name="r"),
+                                _ptr(y, torch.float64, r.numel(), "y"),
+                                _ptr(y_lo, torch.float64, r.numel(), "y_lo"),
+                                _ptr(res, torch.float64, r.numel(), "res"), C.byref(rel)),
+        "lrsdp_residual_dd")
+    return rel.value
+
+
+def lrsdp_solve(f, r, y, y_lo=None, opts=None):
+    info = lrsdp_info()
+    st = lib().lrsdp_solve(f, _ptr(r, torch.float64, name="r"),
+                           _ptr(y, torch.float64, r.numel(), "y"),
+                           _ptr(y_lo, torch.float64, r.numel(), "y_lo"),
+                           C.byref(opts) if opts is not None else None, C.byref(info))
+    if st < 0 and st != LRSDP_ERR_STAGNATED:
+        raise LrsdpError(st, "lrsdp_solve")
+    return st, info.as_dict()

@@ -1,0 +1,478 @@
+// Steps A6 and A7: products with bold U = A^T (U kron Z) and the preconditioner.
+//
+// eq Umv:  bold U vec X = [A_i . (Z X U^T)]_i,  bold U^T y = vec(Z^T mat(A y) U)
+// eq SMW2: H~^{-1} v = (tau^2 A^T A)^{-1} (v - bold U bold S^{-1} bold U^T (A^T A)^{-1} v)
+// eq hessExp1 (split product): H v = A^T vec(W0 M W0) + A^T vec(U P^T W0 + W0 P U^T + U K U^T),
+//   P = M U, K = U^T M U, M = mat(A v).
+//
+// n x k operands are stored column-major (k rows of n), which is also the nk layout of
+// bold S (index p + n j).  Double-double variants carry w = bold U^T G^{-1} v (its sparse
+// product M U) and t = bold S^{-1} w (FP64 inverse plus residual refinement against the
+// matrix-free bold S) in extended precision, which keeps H~^{-1} positive definite when
+// tau ~ 1e-8 makes the FP64 Sherman-Morrison-Woodbury form unstable.
+#include "dense.h"
+
+namespace lrsdp {
+namespace {
+
+constexpr int KMAX = 16;
+constexpr int kT = 256;
+
+// ---------------------------------------------------------------- mat(A v) values
+// mval[e] = val_i * scale_i * v_i, i = src[e]  (scale = 1/g when ginv != nullptr)
+__global__ void k_mval(int nnz, const int32_t* src, const double* val, const double* ginv,
+                       const double* v, double* mval) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const int i = src[e];
+  const double u = ginv ? v[i] * ginv[i] : v[i];
+  mval[e] = val[i] * u;
+}
+
+// double-double version, v may carry a low part
+__global__ void k_mval_dd(int nnz, const int32_t* src, const double* val, const double* ginv,
+                          const double* vh, const double* vl, double* mh, double* ml) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nnz) return;
+  const int i = src[e];
+  dd u = {vh[i], vl ? vl[i] : 0.0};
+  if (ginv) u = dd_mul_d(u, ginv[i]);
+  u = dd_mul_d(u, val[i]);
+  mh[e] = u.hi;
+  ml[e] = u.lo;
+}
+
+// ---------------------------------------------------------------- M U (sparse x n x k)
+__global__ void k_spmm_U(int n, int k, const int32_t* rowptr, const int32_t* colidx,
+                         const double* mval, const double* U, double* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  double acc[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+  for (int e = rowptr[p]; e < rowptr[p + 1]; ++e) {
+    const int q = colidx[e];
+    const double mv = mval[e];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < k) acc[j] = fma(mv, U[(size_t)j * n + q], acc[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    if (j < k) out[(size_t)j * n + p] = acc[j];
+}
+
+__global__ void k_spmm_U_dd(int n, int k, const int32_t* rowptr, const int32_t* colidx,
+                            const double* mh, const double* ml, const double* U, double* oh,
+                            double* ol) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  dd acc[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) acc[j] = {0.0, 0.0};
+  for (int e = rowptr[p]; e < rowptr[p + 1]; ++e) {
+    const int q = colidx[e];
+    const double h = mh[e], l = ml[e];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < k) acc[j] = dd_fma2(acc[j], U[(size_t)j * n + q], h, l);
+  }
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    if (j < k) {
+      oh[(size_t)j * n + p] = acc[j].hi;
+      ol[(size_t)j * n + p] = acc[j].lo;
+    }
+}
+
+// ---------------------------------------------------------------- dense n x n times n x k
+// out[j][p] = sum_{q in range(p)} A[p][q] X[j][q]; range: 0 full, 1 q <= p, 2 q >= p.
+__global__ __launch_bounds__(kT) void k_rows_k(int n, int k, const double* __restrict__ A,
+                                               int range, const double* __restrict__ X,
+                                               double* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+  if (p >= n) return;
+  const int qlo = (range == 2) ? p : 0;
+  const int qhi = (range == 1) ? p + 1 : n;
+  const double* a = A + (size_t)p * n;
+  double acc[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+  for (int q = qlo + lane; q < qhi; q += 64) {
+    const double av = a[q];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < k) acc[j] = fma(av, X[(size_t)j * n + q], acc[j]);
+  }
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    if (j < k) {
+      const double s = wave_sum(acc[j]);
+      if (lane == 0) out[(size_t)j * n + p] = s;
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_rows_k_dd(int n, int k, const double* __restrict__ A,
+                                                  int range, const double* __restrict__ Xh,
+                                                  const double* __restrict__ Xl,
+                                                  double* __restrict__ oh,
+                                                  double* __restrict__ ol) {
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
+  if (p >= n) return;
+  const int qlo = (range == 2) ? p : 0;
+  const int qhi = (range == 1) ? p + 1 : n;
+  const double* a = A + (size_t)p * n;
+  dd acc[KMAX];
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j) acc[j] = {0.0, 0.0};
+  for (int q = qlo + lane; q < qhi; q += 64) {
+    const double av = a[q];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+      if (j < k) acc[j] = dd_fma2(acc[j], av, Xh[(size_t)j * n + q], Xl ? Xl[(size_t)j * n + q] : 0.0);
+  }
+#pragma unroll
+  for (int j = 0; j < KMAX; ++j)
+    if (j < k) {
+      const dd s = wave_sum_dd(acc[j]);
+      if (lane == 0) {
+        oh[(size_t)j * n + p] = s.hi;
+        ol[(size_t)j * n + p] = s.lo;
+      }
+    }
+}
+
+// ---------------------------------------------------------------- sampled products
+// z_i = (v_i - x_i) ginv_i / tau^2,  x_i = (coef_i / 2)(Y_a . U_b + Y_b . U_a)  [= (bold U t)_i]
+__global__ void k_smw_out(int m, int n, int k, const int32_t* a, const int32_t* b,
+                          const double* coef, const double* ginv, double inv_tau2,
+                          const double* Y, const double* U, const double* v, double* z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int ai = a[i], bi = b[i];
+  double s = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double* y = Y + (size_t)j * n;
+    const double* u = U + (size_t)j * n;
+    s = fma(y[ai], u[bi], s);
+    s = fma(y[bi], u[ai], s);
+  }
+  const double x = 0.5 * coef[i] * s;
+  z[i] = (v[i] - x) * ginv[i] * inv_tau2;
+}
+
+// x_i = (coef_i / 2)(Y_a . U_b + Y_b . U_a) in double-double; optional z = (v - x) g^{-1}/tau^2
+__global__ void k_sampled_dd(int m, int n, int k, const int32_t* a, const int32_t* b,
+                             const double* coef, const double* Yh, const double* Yl,
+                             const double* U, double* xh, double* xl, const double* v,
+                             const double* ginv, double inv_tau2, double* z) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int ai = a[i], bi = b[i];
+  dd s = {0.0, 0.0};
+  for (int j = 0; j < k; ++j) {
+    const size_t o = (size_t)j * n;
+    s = dd_fma2(s, U[o + bi], Yh[o + ai], Yl[o + ai]);
+    s = dd_fma2(s, U[o + ai], Yh[o + bi], Yl[o + bi]);
+  }
+  s = dd_mul_d(s, 0.5 * coef[i]);
+  if (z) {
+    dd d = dd_add_d({-s.hi, -s.lo}, v[i]);
+    z[i] = (d.hi + d.lo) * ginv[i] * inv_tau2;
+  } else {
+    xh[i] = s.hi;
+    xl[i] = s.lo;
+  }
+}
+
+// y <- y * ginv in double-double (in place)
+__global__ void k_scale_dd(int m, const double* ginv, double* yh, double* yl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  dd u = dd_mul_d({yh[i], yl[i]}, ginv[i]);
+  yh[i] = u.hi;
+  yl[i] = u.lo;
+}
+
+// K = U^T P (k x k) in double-double, then symmetrized and rounded: one wave per (j, l).
+__global__ __launch_bounds__(64) void k_UtP(int n, int k, const double* U, const double* Ph,
+                                            const double* Pl, double* Kdd) {
+  const int j = blockIdx.x / k, l = blockIdx.x % k;
+  const int lane = threadIdx.x;
+  dd s = {0.0, 0.0};
+  for (int p = lane; p < n; p += 64)
+    s = dd_fma2(s, U[(size_t)j * n + p], Ph[(size_t)l * n + p], Pl[(size_t)l * n + p]);
+  s = wave_sum_dd(s);
+  if (lane == 0) {
+    Kdd[2 * (j * k + l)] = s.hi;
+    Kdd[2 * (j * k + l) + 1] = s.lo;
+  }
+}
+
+// Hv_i += coef_i [ sum_j (U_ja Q_jb + Q_ja U_jb) + U_a^T Ks U_b ],  Ks = (K + K^T) / 2
+__global__ void k_lowrank_add(int m, int n, int k, const int32_t* a, const int32_t* b,
+                              const double* coef, const double* U, const double* Q,
+                              const double* Kdd, double* Hv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int ai = a[i], bi = b[i];
+  double s = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const size_t o = (size_t)j * n;
+    s = fma(U[o + ai], Q[o + bi], s);
+    s = fma(Q[o + ai], U[o + bi], s);
+  }
+  double t = 0.0;
+  for (int j = 0; j < k; ++j) {
+    double kr = 0.0;
+    for (int l = 0; l < k; ++l) {
+      const double kjl = Kdd[2 * (j * k + l)] + Kdd[2 * (j * k + l) + 1];
+      const double klj = Kdd[2 * (l * k + j)] + Kdd[2 * (l * k + j) + 1];
+      kr = fma(0.5 * (kjl + klj), U[(size_t)l * n + bi], kr);
+    }
+    t = fma(U[(size_t)j * n + ai], kr, t);
+  }
+  Hv[i] += coef[i] * (s + t);
+}
+
+// ---------------------------------------------------------------- nk-vector helpers
+__global__ void k_dd_combine(int N, const double* h, const double* l, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) out[i] = h[i] + l[i];
+}
+// (ah, al) - (bh, bl) rounded to FP64
+__global__ void k_dd_sub_round(int N, const double* ah, const double* al, const double* bh,
+                               const double* bl, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  dd d = dd_add({ah[i], al[i]}, {-bh[i], -bl[i]});
+  out[i] = d.hi + d.lo;
+}
+// (th, tl) += d
+__global__ void k_dd_accum(int N, double* th, double* tl, const double* d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  dd u = dd_add_d({th[i], tl[i]}, d[i]);
+  th[i] = u.hi;
+  tl[i] = u.lo;
+}
+// s += tau2 * t  (all double-double, tau2 an FP64 constant)
+__global__ void k_dd_axpy_const(int N, double c, const double* th, const double* tl, double* sh,
+                                double* sl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  dd u = dd_add({sh[i], sl[i]}, dd_mul_d({th[i], tl[i]}, c));
+  sh[i] = u.hi;
+  sl[i] = u.lo;
+}
+// c = Q^T t  (r values, double-double), one wave per column of Q (nk x r row-major)
+__global__ __launch_bounds__(64) void k_Qt_dd(int N, int r, const double* Q, const double* th,
+                                              const double* tl, double* c) {
+  const int col = blockIdx.x, lane = threadIdx.x;
+  dd s = {0.0, 0.0};
+  for (int i = lane; i < N; i += 64) s = dd_fma2(s, Q[(size_t)i * r + col], th[i], tl[i]);
+  s = wave_sum_dd(s);
+  if (lane == 0) {
+    c[2 * col] = s.hi;
+    c[2 * col + 1] = s.lo;
+  }
+}
+// s += shift * Q c  (double-double)
+__global__ void k_Qc_dd(int N, int r, double shift, const double* Q, const double* c, double* sh,
+                        double* sl) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  dd acc = {0.0, 0.0};
+  for (int q = 0; q < r; ++q) acc = dd_fma2(acc, Q[(size_t)i * r + q], c[2 * q], c[2 * q + 1]);
+  acc = dd_mul_d(acc, shift);
+  dd u = dd_add({sh[i], sl[i]}, acc);
+  sh[i] = u.hi;
+  sl[i] = u.lo;
+}
+
+int rows_k(int n, int k, const double* A, int range, const double* X, double* out,
+           hipStream_t s) {
+  k_rows_k<<<(n + 3) / 4, kT, 0, s>>>(n, k, A, range, X, out);
+  return LRSDP_OK;
+}
+int rows_k_dd(int n, int k, const double* A, int range, const double* Xh, const double* Xl,
+              double* oh, double* ol, hipStream_t s) {
+  k_rows_k_dd<<<(n + 3) / 4, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol);
+  return LRSDP_OK;
+}
+
+// bold S t in double-double (deflated as factored), t = (th, tl) -> (sh, sl).
+int schur_apply_dd(const lrsdp_factor* f, const double* th, const double* tl, double* sh,
+                   double* sl, hipStream_t s) {
+  const lrsdp_problem* P = f->P;
+  const Work w = work_view(f);
+  const int n = f->n, k = f->k, m = P->m, nk = f->nk;
+  // a. Y = Z T (dd)        b. y = bold U t (dd)
+  rows_k_dd(n, k, f->Z, 1, th, tl, w.y, w.yl, s);
+  k_sampled_dd<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, w.y, w.yl, f->U,
+                                                 w.t0, w.t1, nullptr, nullptr, 0.0, nullptr);
+  // c. mat(A G^{-1} y) (dd)   d. P = M U (dd)   e. s = Z^T P (dd)
+  k_mval_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, P->ginv, w.t0, w.t1,
+                                                   P->mval, P->vec_scratch);
+  k_spmm_U_dd<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, P->mval,
+                                               P->vec_scratch, f->U, w.y, w.yl);
+  rows_k_dd(n, k, f->Zt, 2, w.y, w.yl, sh, sl, s);
+  // f. + tau^2 t + shift Q (Q^T t)
+  k_dd_axpy_const<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->tau2, th, tl, sh, sl);
+  if (f->r) {
+    k_Qt_dd<<<f->r, 64, 0, s>>>(nk, f->r, f->QN, th, tl, w.kk);
+    k_Qc_dd<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->r, f->shift, f->QN, w.kk, sh, sl);
+  }
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
+
+// ---------------------------------------------------------------- FP64 matrix-free bold S
+// x_i = scale_i (coef_i / 2)(Y_a . U_b + Y_b . U_a)   [= scale_i (bold U t)_i]
+__global__ void k_sampled_f64(int m, int n, int k, const int32_t* a, const int32_t* b,
+                              const double* coef, const double* scale, const double* Y,
+                              const double* U, double* x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const int ai = a[i], bi = b[i];
+  double s = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const size_t o = (size_t)j * n;
+    s = fma(Y[o + ai], U[o + bi], s);
+    s = fma(Y[o + bi], U[o + ai], s);
+  }
+  x[i] = 0.5 * coef[i] * s * (scale ? scale[i] : 1.0);
+}
+__global__ void k_axpy(int N, double c, const double* t, double* s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) s[i] = fma(c, t[i], s[i]);
+}
+__global__ void k_sub(int N, const double* a, const double* b, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) out[i] = a[i] - b[i];
+}
+__global__ void k_add(int N, double* t, const double* d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) t[i] += d[i];
+}
+__global__ __launch_bounds__(64) void k_Qt(int N, int r, const double* Q, const double* t,
+                                           double* c) {
+  const int col = blockIdx.x, lane = threadIdx.x;
+  double s = 0.0;
+  for (int i = lane; i < N; i += 64) s = fma(Q[(size_t)i * r + col], t[i], s);
+  s = wave_sum(s);
+  if (lane == 0) c[col] = s;
+}
+__global__ void k_Qc(int N, int r, double shift, const double* Q, const double* c, double* s) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  double acc = 0.0;
+  for (int q = 0; q < r; ++q) acc = fma(Q[(size_t)i * r + q], c[q], acc);
+  s[i] = fma(shift, acc, s[i]);
+}
+
+// s = bold S t in FP64 (deflated as factored), matrix-free through eq Umv.
+int schur_apply_f64(const lrsdp_factor* f, const double* t, double* sout, hipStream_t s) {
+  const lrsdp_problem* P = f->P;
+  const Work w = work_view(f);
+  const int n = f->n, k = f->k, m = P->m, nk = f->nk;
+  rows_k(n, k, f->Z, 1, t, w.y, s);                                        // Z T
+  k_sampled_f64<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, P->ginv, w.y,
+                                                  f->U, w.t0);             // G^{-1} bold U t
+  k_mval<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, nullptr, w.t0, P->mval);
+  k_spmm_U<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, P->mval, f->U, w.y);
+  rows_k(n, k, f->Zt, 2, w.y, sout, s);                                    // Z^T M U
+  k_axpy<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->tau2, t, sout);
+  if (f->r) {
+    k_Qt<<<f->r, 64, 0, s>>>(nk, f->r, f->QN, t, w.kk);
+    k_Qc<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->r, f->shift, f->QN, w.kk, sout);
+  }
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
+
+}  // namespace
+
+// refine != 0: one step of FP64 residual refinement of t = bold S^{-1} w against the
+// matrix-free bold S.  The explicit inverse alone acts like the inverse of a matrix off by
+// ~u kappa(bold S) ||bold S||; after one step the error is that of a backward-stable solve,
+// ~u ||bold S||, which keeps H~^{-1} positive definite while tau^2 >> u ||bold S||.
+int precond_apply_f64(const lrsdp_factor* f, const double* v, double* z, hipStream_t s,
+                      int refine) {
+  const lrsdp_problem* P = f->P;
+  const Work w = work_view(f);
+  const int n = f->n, k = f->k, m = P->m, nk = f->nk;
+  if (k > KMAX) return LRSDP_ERR_INVALID_ARG;
+  k_mval<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, P->ginv, v, P->mval);
+  k_spmm_U<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, P->mval, f->U, w.y);
+  rows_k(n, k, f->Zt, 2, w.y, w.w, s);                    // w = vec(Z^T M U)
+  LRSDP_TRY(gemv(f->Sinv, nk, nk, w.w, w.t, s));           // t = bold S^{-1} w
+  if (refine) {
+    LRSDP_TRY(schur_apply_f64(f, w.t, w.s, s));
+    k_sub<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.s, w.g0);
+    LRSDP_TRY(gemv(f->Sinv, nk, nk, w.g0, w.g1, s));
+    k_add<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.t, w.g1);
+  }
+  rows_k(n, k, f->Z, 1, w.t, w.y, s);                      // Y = Z T
+  k_smw_out<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, P->ginv,
+                                             1.0 / f->tau2, w.y, f->U, v, z);
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
+
+int precond_apply_dd(const lrsdp_factor* f, const double* v, double* z, hipStream_t s,
+                     int nref) {
+  const lrsdp_problem* P = f->P;
+  const Work w = work_view(f);
+  const int n = f->n, k = f->k, m = P->m, nk = f->nk;
+  if (k > KMAX) return LRSDP_ERR_INVALID_ARG;
+  // w = bold U^T G^{-1} v in double-double
+  k_mval_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, P->ginv, v, nullptr,
+                                                   P->mval, P->vec_scratch);
+  k_spmm_U_dd<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, P->mval,
+                                               P->vec_scratch, f->U, w.y, w.yl);
+  rows_k_dd(n, k, f->Zt, 2, w.y, w.yl, w.w, w.wl, s);
+  // t = bold S^{-1} w: FP64 inverse, refined against the matrix-free bold S in double-double
+  k_dd_combine<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.wl, w.g0);
+  LRSDP_TRY(gemv(f->Sinv, nk, nk, w.g0, w.t, s));
+  LRSDP_HIP(hipMemsetAsync(w.tl, 0, (size_t)nk * sizeof(double), s));
+  for (int it = 0; it < nref; ++it) {
+    LRSDP_TRY(schur_apply_dd(f, w.t, w.tl, w.s, w.sl, s));
+    k_dd_sub_round<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.wl, w.s, w.sl, w.g0);
+    LRSDP_TRY(gemv(f->Sinv, nk, nk, w.g0, w.g1, s));
+    k_dd_accum<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.t, w.tl, w.g1);
+  }
+  // x = bold U t (dd);  z = (v - x) G^{-1} / tau^2
+  rows_k_dd(n, k, f->Z, 1, w.t, w.tl, w.y, w.yl, s);
+  k_sampled_dd<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, w.y, w.yl, f->U,
+                                                 nullptr, nullptr, v, P->ginv, 1.0 / f->tau2, z);
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
+
+int split_apply(lrsdp_factor* f, const double* v, double* Hv, int precision, hipStream_t s) {
+  lrsdp_problem* P = f->P;
+  const Work w = work_view(f);
+  const int n = f->n, k = f->k, m = P->m;
+  if (k > KMAX) return LRSDP_ERR_INVALID_ARG;
+  LRSDP_TRY(ensure_lowprec(f, precision, s));
+  // A^T vec(W0 M W0) in the requested precision
+  if (precision == LRSDP_PREC_FP32) LRSDP_TRY(hv_apply_f32(P, f->W0f, v, Hv, s));
+  else if (precision == LRSDP_PREC_BF16) LRSDP_TRY(hv_apply_bf16(P, f->W0b, v, Hv, s));
+  else LRSDP_TRY(hv_apply_f64(P, f->W0, v, Hv, s));
+  // P = M U (dd), Q = W0 P, K = U^T P (dd), then the sampled rank-k terms
+  k_mval_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, nullptr, v, nullptr,
+                                                   P->mval, P->vec_scratch);
+  k_spmm_U_dd<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, P->mval,
+                                               P->vec_scratch, f->U, w.g0, w.g1);
+  rows_k(n, k, f->W0, 0, w.g0, w.s, s);
+  k_UtP<<<k * k, 64, 0, s>>>(n, k, f->U, w.g0, w.g1, w.kk);
+  k_lowrank_add<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, f->U, w.s, w.kk,
+                                                  Hv);
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
+
+}  // namespace lrsdp

@@ -1,0 +1,63 @@
+// Dense FP64 kernels on the CDNA4 matrix cores (v_mfma_f64_16x16x4_f64), used by the
+// setup steps: Cholesky of 2 W0 + U U^T (size n) and of bold S (size nk), the explicit
+// bold S^{-1} = L^{-T} L^{-1}, and the GEMMs that form bold S.
+#pragma once
+
+#include "internal.h"
+
+namespace lrsdp {
+
+// Triangular-structure hints: K-range trimming per output tile (tile granularity 64), so a
+// product with a triangular operand skips its zero tiles.  Within a 64-aligned diagonal tile
+// the stored zeros are read, so triangular operands must hold explicit zeros there.
+enum GemmFlags : unsigned {
+  kKFromRow = 1u,   // op(A)[i][k] == 0 for k < i   -> k starts at the tile's first row
+  kKToRow = 2u,     // op(A)[i][k] == 0 for k > i   -> k ends after the tile's last row
+  kKFromCol = 4u,   // op(B)[k][j] == 0 for k < j
+  kKToCol = 8u,     // op(B)[k][j] == 0 for k > j
+  kLowerOut = 16u,  // compute / write only C[i][j] with j <= i
+};
+
+struct GemmArgs {
+  int M = 0, N = 0, K = 0;
+  const double* A = nullptr;
+  int lda = 0;
+  bool transA = false;  // false: A is M x K row-major; true: A is K x M
+  const double* B = nullptr;
+  int ldb = 0;
+  bool transB = false;  // false: B is K x N; true: B is N x K
+  double* C = nullptr;
+  int ldc = 0;
+  double alpha = 1.0, beta = 0.0;
+  unsigned flags = 0;
+  int batch = 1;                  // with offs: number of products (grid.y)
+  const int64_t* offs = nullptr;  // device, 3 x batch element offsets of A, B, C
+};
+
+// C = alpha op(A) op(B) + beta C (row-major), FP64 MFMA.
+int gemm(const GemmArgs& g, hipStream_t s);
+
+// Inverted 64 x 64 diagonal blocks of a Cholesky factor (doubles needed for order N).
+size_t dinv_doubles(int N);
+// Cholesky A = L L^T in place (lower; the strict upper triangle of each 64-aligned diagonal
+// block is zeroed, the rest of the upper triangle is left as is).  dinv receives the inverses
+// of the 64-aligned diagonal blocks of L.  On a non-positive pivot *flag (device int) gets 1.
+int potrf(double* A, int N, int lda, int* flag, double* dinv, hipStream_t s);
+// B := B L^{-T}, B M x N, L N x N lower with its diagonal-block inverses dinv (from potrf).
+int trsm_rlt(double* B, int M, int N, int ldb, const double* L, int ldl, const double* dinv,
+             hipStream_t s);
+// L := L^{-1} in place (lower, upper triangle zero).  tmp: at least ceil(N/2)^2 doubles.
+int trtri(double* L, int N, int ldl, double* tmp, const double* dinv, hipStream_t s);
+// X := M^T M (lower part), M lower triangular N x N; X and M distinct.
+int lauum(const double* M, int N, int ldm, double* X, int ldx, hipStream_t s);
+// Copy the lower triangle into the upper one.
+int mirror_lower(double* A, int N, int lda, hipStream_t s);
+// Zero the strict upper triangle.
+int zero_upper(double* A, int N, int lda, hipStream_t s);
+// Out-of-place transpose (N x N).
+int transpose(const double* A, int N, int lda, double* B, int ldb, hipStream_t s);
+
+// y = A x, A N x N row-major (dense GEMV, one wavefront per row).
+int gemv(const double* A, int N, int lda, const double* x, double* y, hipStream_t s);
+
+}  // namespace lrsdp

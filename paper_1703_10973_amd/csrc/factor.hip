@@ -1,0 +1,430 @@
+// Algorithm 1 steps 1-2 on the device (steps A1-A4):
+//   1a  tau = lambda_min(W), (V_l, Lambda_l) = the k largest eigenpairs      (eig.hip)
+//   1b  U = V_l (Lambda_l - tau I)^{1/2};  W0 = W - U U^T;  Z = chol(2 W0 + U U^T)
+//   2   bold S = tau^2 I + bold U^T (A^T A)^{-1} bold U, block (J, L) of which is
+//       tau^2 delta_JL I + Z^T B_JL Z,  B_JL = 1/2 [diag(Obar (u_J o u_L)) + D_{u_L} Obar D_{u_J}],
+//       because A (A^T A)^{-1} A^T is the projector that samples the symmetric part of a
+//       matrix on the pattern Obar (disjoint supports).  Each block is one sparse-times-
+//       dense pass (R = B_JL Z) and one FP64 MFMA GEMM (Z^T R, Z triangular).
+//       Deflation: the k(k-1)/2 vectors vec(Z^{-1} U K), K skew, span directions that
+//       bold U annihilates, where bold S has eigenvalue tau^2; adding shift Q_N Q_N^T
+//       (Q_N orthonormal, shift = max diag bold S) leaves bold U bold S^{-1} bold U^T unchanged.
+//       L L^T = bold S, then bold S^{-1} = L^{-T} L^{-1} is formed once (TRTRI + LAUUM) so
+//       that each PCG iteration applies it as one bandwidth-bound GEMV.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "dense.h"
+#include "eig.h"
+
+namespace lrsdp {
+namespace {
+
+constexpr int kT = 256;
+
+__global__ void k_make_U(int n, int k, const double* lam, const double* Vl, double* U) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * k) return;
+  const int j = idx / n;
+  const double tau = lam[0];
+  const double sc = sqrt(fmax(lam[1 + j] - tau, 0.0));
+  U[idx] = Vl[idx] * sc;
+}
+
+// W0 = W - U U^T with U U^T accumulated error-free, rounded once; Zin = 2 W0 + U U^T.
+__global__ void k_make_W0(int n, int k, const double* W, const double* U, double* W0,
+                          double* Zin) {
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  const int p = (int)(idx / n), q = (int)(idx - (size_t)p * n);
+  dd acc = {W[idx], 0.0};
+  double uu = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double a = U[(size_t)j * n + p], b = U[(size_t)j * n + q];
+    dd pr = two_prod(a, b);
+    acc = dd_add(acc, {-pr.hi, -pr.lo});
+    uu = fma(a, b, uu);
+  }
+  const double w0 = acc.hi + acc.lo;
+  W0[idx] = w0;
+  Zin[idx] = fma(2.0, w0, uu);
+}
+
+// P_J[a][c] = sum_{b in Obar(a)} u_J[b] Z[b][c] for every J at once (Z rows read once).
+// Grid: (row a, column chunk); each thread owns one column c and k accumulators.
+__global__ __launch_bounds__(kT) void k_PJ(int n, int k, const int32_t* rowptr,
+                                           const int32_t* colidx, const double* U,
+                                           const double* Z, double* PJ) {
+  constexpr int KM = 16;
+  const int a = blockIdx.x;
+  const int c = blockIdx.y * kT + threadIdx.x;
+  if (c >= n) return;
+  double acc[KM];
+#pragma unroll
+  for (int J = 0; J < KM; ++J) acc[J] = 0.0;
+  for (int e = rowptr[a]; e < rowptr[a + 1]; ++e) {
+    const int b = colidx[e];
+    const double z = Z[(size_t)b * n + c];
+#pragma unroll
+    for (int J = 0; J < KM; ++J)
+      if (J < k) acc[J] = fma(U[(size_t)J * n + b], z, acc[J]);
+  }
+  const size_t nn = (size_t)n * n;
+#pragma unroll
+  for (int J = 0; J < KM; ++J)
+    if (J < k) PJ[J * nn + (size_t)a * n + c] = acc[J];
+}
+
+// d_JL[a] = sum_{b in Obar(a)} u_J[b] u_L[b] for every pair J >= L (pair index J(J+1)/2 + L).
+__global__ void k_dJL(int n, int k, const int32_t* rowptr, const int32_t* colidx,
+                      const double* U, double* d) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  for (int J = 0; J < k; ++J)
+    for (int L = 0; L <= J; ++L) {
+      double s = 0.0;
+      for (int e = rowptr[a]; e < rowptr[a + 1]; ++e) {
+        const int b = colidx[e];
+        s = fma(U[(size_t)J * n + b], U[(size_t)L * n + b], s);
+      }
+      d[(size_t)(J * (J + 1) / 2 + L) * n + a] = s;
+    }
+}
+
+// R_JL = B_JL Z = 1/2 (diag(d_JL) Z + D_{u_L} P_J)
+__global__ void k_R_pair(int n, int J, int L, const double* Z, const double* U,
+                         const double* PJ, const double* dJL, double* R) {
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t nn = (size_t)n * n;
+  if (idx >= nn) return;
+  const int a = (int)(idx / n);
+  R[idx] = 0.5 * fma(dJL[a], Z[idx], U[(size_t)L * n + a] * PJ[J * nn + idx]);
+}
+
+__global__ void k_add_diag(double* S, int n, int ld, double v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) S[(size_t)i * ld + i] += v;
+}
+
+// N (nk x r): column c <-> pair (i < j): block j holds y_i, block i holds -y_j, y = rows of Yt.
+__global__ void k_null_basis(int n, int k, int r, const double* Yt, double* N) {
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  const size_t nk = (size_t)n * k;
+  if (idx >= nk * r) return;
+  const size_t row = idx / r;
+  const int c = (int)(idx - row * r);
+  const int blk = (int)(row / n), p = (int)(row - (size_t)blk * n);
+  int i = 0, cc = c;
+  while (cc >= k - 1 - i) {
+    cc -= k - 1 - i;
+    ++i;
+  }
+  const int j = i + 1 + cc;
+  double v = 0.0;
+  if (blk == j) v = Yt[(size_t)i * n + p];
+  else if (blk == i) v = -Yt[(size_t)j * n + p];
+  N[idx] = v;
+}
+
+__global__ __launch_bounds__(kT) void k_max_diag(const double* S, int N, int ld, double* out) {
+  __shared__ double red[kT];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < N; i += kT) m = fmax(m, S[(size_t)i * ld + i]);
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = kT / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
+__global__ void k_f64_to_f32(size_t cnt, const double* a, float* b) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < cnt) b[i] = static_cast<float>(a[i]);
+}
+__global__ void k_f64_to_bf16(size_t cnt, const double* a, uint16_t* b) {
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < cnt) b[i] = f32_to_bf16_rne(static_cast<float>(a[i]));
+}
+
+int read_flag(lrsdp_ctx* ctx, int* out) {
+  LRSDP_HIP(hipMemcpyAsync(out, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  LRSDP_HIP(hipStreamSynchronize(ctx->stream));
+  return LRSDP_OK;
+}
+
+}  // namespace
+
+size_t work_doubles(int n, int m, int k) {
+  const size_t nk = (size_t)n * k;
+  return 12 * (size_t)m + 10 * nk + 2 * (size_t)k * k + 8192;
+}
+
+Work work_view(const lrsdp_factor* f) {
+  Work w;
+  const size_t m = f->P->m, nk = f->nk;
+  double* b = f->work;
+  double** mv[] = {&w.x, &w.r, &w.z, &w.p, &w.q, &w.t0, &w.t1, &w.t2, &w.t3, &w.ylo, &w.dd0, &w.dd1};
+  for (auto pp : mv) {
+    *pp = b;
+    b += m;
+  }
+  double** kv[] = {&w.w, &w.wl, &w.t, &w.tl, &w.s, &w.sl, &w.y, &w.yl, &w.g0, &w.g1};
+  for (auto pp : kv) {
+    *pp = b;
+    b += nk;
+  }
+  w.kk = b;
+  b += 2 * (size_t)f->k * f->k;
+  w.part = b;
+  return w;
+}
+
+int ensure_lowprec(lrsdp_factor* f, int precision, hipStream_t s) {
+  lrsdp_ctx* ctx = f->P->ctx;
+  const size_t nn = (size_t)f->n * f->n;
+  if (precision == LRSDP_PREC_FP32 && !f->W0f) {
+    LRSDP_TRY(dev_alloc_n(ctx, &f->W0f, nn));
+    f->bytes += nn * sizeof(float);
+    k_f64_to_f32<<<grid_for((int64_t)nn, 256), 256, 0, s>>>(nn, f->W0, f->W0f);
+    LRSDP_HIP(hipGetLastError());
+  }
+  if (precision == LRSDP_PREC_BF16 && !f->W0b) {
+    LRSDP_TRY(dev_alloc_n(ctx, &f->W0b, nn));
+    f->bytes += nn * sizeof(uint16_t);
+    k_f64_to_bf16<<<grid_for((int64_t)nn, 256), 256, 0, s>>>(nn, f->W0, f->W0b);
+    LRSDP_HIP(hipGetLastError());
+  }
+  return LRSDP_OK;
+}
+
+void factor_release(lrsdp_factor* f) {
+  lrsdp_ctx* ctx = f->P->ctx;
+  const size_t nn = (size_t)f->n * f->n, nk = f->nk;
+  dev_free(ctx, f->lam_dev, (f->k + 1) * sizeof(double));
+  dev_free(ctx, f->W, nn * sizeof(double));
+  dev_free(ctx, f->W0, nn * sizeof(double));
+  dev_free(ctx, f->W0f, nn * sizeof(float));
+  dev_free(ctx, f->W0b, nn * sizeof(uint16_t));
+  dev_free(ctx, f->U, nk * sizeof(double));
+  dev_free(ctx, f->Z, nn * sizeof(double));
+  dev_free(ctx, f->Zt, nn * sizeof(double));
+  dev_free(ctx, f->Sinv, nk * nk * sizeof(double));
+  dev_free(ctx, f->QN, nk * (size_t)f->r * sizeof(double));
+  dev_free(ctx, f->work, f->work_doubles * sizeof(double));
+  dev_free(ctx, f->sc, 64 * sizeof(double));
+  f->lam_dev = f->W = f->W0 = f->U = f->Z = f->Zt = f->Sinv = f->QN = f->work = f->sc = nullptr;
+  f->W0f = nullptr;
+  f->W0b = nullptr;
+}
+
+int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
+  auto t_start = std::chrono::steady_clock::now();
+  lrsdp_problem* P = f->P;
+  lrsdp_ctx* ctx = P->ctx;
+  hipStream_t s = ctx->stream;
+  const int n = f->n, k = f->k, nk = f->nk;
+  const size_t nn = (size_t)n * n;
+  f->r = (o.deflate && k >= 2) ? k * (k - 1) / 2 : 0;
+  const int r = f->r;
+
+  // persistent buffers
+  LRSDP_TRY(dev_alloc_n(ctx, &f->lam_dev, (size_t)k + 1));
+  LRSDP_TRY(dev_alloc_n(ctx, &f->W, nn));
+  LRSDP_TRY(dev_alloc_n(ctx, &f->W0, nn));
+  LRSDP_TRY(dev_alloc_n(ctx, &f->U, (size_t)nk));
+  LRSDP_TRY(dev_alloc_n(ctx, &f->Z, nn));
+  LRSDP_TRY(dev_alloc_n(ctx, &f->Zt, nn));
+  LRSDP_TRY(dev_alloc_n(ctx, &f->Sinv, (size_t)nk * nk));
+  if (r) LRSDP_TRY(dev_alloc_n(ctx, &f->QN, (size_t)nk * r));
+  f->work_doubles = work_doubles(n, P->m, k);
+  LRSDP_TRY(dev_alloc_n(ctx, &f->work, f->work_doubles));
+  LRSDP_TRY(dev_alloc_n(ctx, &f->sc, (size_t)64));
+  f->bytes = (k + 1 + 5 * nn + (size_t)nk + (size_t)nk * nk + (size_t)nk * r + f->work_doubles +
+              64) * sizeof(double);
+
+  LRSDP_HIP(hipMemcpyAsync(f->W, W, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+
+  // ---- 1a: partial eigendecomposition (temporary workspace)
+  void* ews = nullptr;
+  const size_t ewb = eig_workspace_bytes(n, k);
+  LRSDP_TRY(dev_alloc(ctx, &ews, ewb));
+  double* Vl = f->U;  // eigenvectors land in U's buffer, scaled in place below
+  int rc = eig_top_and_min(f->W, n, k, ews, f->lam_dev, Vl, s);
+  if (rc == LRSDP_OK) {
+    f->lam.assign(k + 1, 0.0);
+    if (hipMemcpyAsync(f->lam.data(), f->lam_dev, (k + 1) * sizeof(double),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      rc = LRSDP_ERR_DEVICE;
+  }
+  dev_free(ctx, ews, ewb);
+  LRSDP_TRY(rc);
+  f->tau = f->lam[0];
+  for (double v : f->lam)
+    if (!std::isfinite(v)) return LRSDP_ERR_EIG;
+  if (!(f->tau > 0.0)) return LRSDP_ERR_NOT_PD_W;
+  f->tau2 = f->tau * f->tau;
+
+  // ---- 1b: U, W0, Z
+  k_make_U<<<grid_for((int64_t)nk, 256), 256, 0, s>>>(n, k, f->lam_dev, Vl, f->U);
+  k_make_W0<<<grid_for((int64_t)nn, 256), 256, 0, s>>>(n, k, f->W, f->U, f->W0, f->Z);
+  LRSDP_HIP(hipGetLastError());
+  // temporaries: inverse diagonal blocks of Z, bold S and the Gram matrix; bold S itself;
+  // P_J and the R_JL blocks of its formation
+  const int npairs = k * (k + 1) / 2;
+  const size_t pair_cap = std::max<size_t>(1, std::min<size_t>(npairs, (size_t)(1u << 28) / nn));
+  struct Tmp {
+    double* p = nullptr;
+    size_t cnt = 0;
+  } dZ{nullptr, dinv_doubles(n)}, dS{nullptr, dinv_doubles(nk)}, Sb{nullptr, (size_t)nk * nk},
+      PJ{nullptr, (size_t)k * nn}, Rb{nullptr, pair_cap * nn}, dd_{nullptr, (size_t)npairs * n},
+      offs{nullptr, 3 * pair_cap};
+  Tmp* tmps[] = {&dZ, &dS, &Sb, &PJ, &Rb, &dd_, &offs};
+  for (Tmp* t : tmps) {
+    if ((rc = dev_alloc_n(ctx, &t->p, t->cnt)) < 0) break;
+  }
+  auto free_tmp = [&]() {
+    (void)hipStreamSynchronize(s);
+    for (Tmp* t : tmps) dev_free(ctx, t->p, t->cnt * sizeof(double));
+  };
+  if (rc < 0) {
+    free_tmp();
+    return rc;
+  }
+  do {
+    if (hipMemsetAsync(ctx->d_flag, 0, sizeof(int), s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    if ((rc = potrf(f->Z, n, n, ctx->d_flag, dZ.p, s))) break;
+    if ((rc = zero_upper(f->Z, n, n, s))) break;
+    int flag = 0;
+    if ((rc = read_flag(ctx, &flag))) break;
+    if (flag) {
+      rc = LRSDP_ERR_CHOL_Z;
+      break;
+    }
+    if ((rc = transpose(f->Z, n, n, f->Zt, n, s))) break;
+
+    // ---- 2: bold S (lower block triangle).  P_J = Obar D_{u_J} Z for every J in one sparse
+    //      pass, R_JL = 1/2 (diag(d_JL) Z + D_{u_L} P_J), then batched GEMMs Z^T R_JL.
+    double* S = Sb.p;
+    {
+      ProfMark pm = prof_begin(LRSDP_K_BZ, s);
+      k_PJ<<<dim3(n, (n + kT - 1) / kT), kT, 0, s>>>(n, k, P->rowptr, P->colidx, f->U, f->Z, PJ.p);
+      k_dJL<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, f->U, dd_.p);
+      prof_end(pm, s, 8.0 * ((double)k + 1) * nn + 12.0 * P->nnz,
+               2.0 * (double)P->nnz * n * k);
+    }
+    std::vector<int> pj, pl;
+    for (int J = 0; J < k; ++J)
+      for (int L = 0; L <= J; ++L) {
+        pj.push_back(J);
+        pl.push_back(L);
+      }
+    for (int q0 = 0; q0 < npairs && rc == LRSDP_OK; q0 += (int)pair_cap) {
+      const int cnt = std::min<int>((int)pair_cap, npairs - q0);
+      std::vector<int64_t> ho(3 * cnt);
+      for (int q = 0; q < cnt; ++q) {
+        const int J = pj[q0 + q], L = pl[q0 + q];
+        ho[3 * q] = 0;
+        ho[3 * q + 1] = (int64_t)q * nn;
+        ho[3 * q + 2] = (int64_t)n * J * nk + (int64_t)n * L;
+      }
+      if (hipMemcpyAsync(offs.p, ho.data(), ho.size() * sizeof(int64_t), hipMemcpyHostToDevice,
+                         s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        rc = LRSDP_ERR_DEVICE;
+        break;
+      }
+      for (int q = 0; q < cnt; ++q) {
+        const int J = pj[q0 + q], L = pl[q0 + q];
+        const int pidx = J * (J + 1) / 2 + L;
+        k_R_pair<<<grid_for((int64_t)nn, 256), 256, 0, s>>>(n, J, L, f->Z, f->U, PJ.p,
+                                                            dd_.p + (size_t)pidx * n,
+                                                            Rb.p + (size_t)q * nn);
+      }
+      GemmArgs g;
+      g.M = n; g.N = n; g.K = n;
+      g.A = f->Z; g.lda = n; g.transA = true;  // op(A) = Z^T, zero below its diagonal
+      g.B = Rb.p; g.ldb = n;
+      g.C = S; g.ldc = nk;
+      g.flags = kKFromRow;
+      g.batch = cnt;
+      g.offs = reinterpret_cast<const int64_t*>(offs.p);
+      rc = gemm(g, s);
+      if (rc == LRSDP_OK && hipStreamSynchronize(s) != hipSuccess) rc = LRSDP_ERR_DEVICE;
+    }
+    if (rc != LRSDP_OK) break;
+    for (int J = 0; J < k; ++J)
+      k_add_diag<<<grid_for(n, 256), 256, 0, s>>>(S + (size_t)n * J * nk + (size_t)n * J, n, nk,
+                                                   f->tau2);
+    // ---- deflation of null(bold U) directions
+    if (r) {
+      double* Yt = Rb.p;  // k x n: (Z^{-1} U)^T = U^T Z^{-T}
+      if (hipMemcpyAsync(Yt, f->U, (size_t)nk * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+          hipSuccess) {
+        rc = LRSDP_ERR_DEVICE;
+        break;
+      }
+      if ((rc = trsm_rlt(Yt, k, n, n, f->Z, n, dZ.p, s))) break;
+      double* G = Rb.p + nk;   // r x r Gram matrix
+      double* dG = PJ.p;       // its inverse diagonal blocks (P_J no longer needed)
+      k_null_basis<<<grid_for((int64_t)nk * r, 256), 256, 0, s>>>(n, k, r, Yt, f->QN);
+      for (int pass = 0; pass < 2 && rc == LRSDP_OK; ++pass) {  // Cholesky QR, twice
+        GemmArgs g;
+        g.M = r; g.N = r; g.K = nk;
+        g.A = f->QN; g.lda = r; g.transA = true;
+        g.B = f->QN; g.ldb = r;
+        g.C = G; g.ldc = r;
+        if ((rc = gemm(g, s))) break;
+        if ((rc = potrf(G, r, r, ctx->d_flag, dG, s))) break;
+        if ((rc = trsm_rlt(f->QN, nk, r, r, G, r, dG, s))) break;
+      }
+      if (rc) break;
+      k_max_diag<<<1, kT, 0, s>>>(S, nk, nk, f->sc);
+      double shift = 0.0;
+      if (hipMemcpyAsync(&shift, f->sc, sizeof(double), hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        rc = LRSDP_ERR_DEVICE;
+        break;
+      }
+      f->shift = shift;
+      GemmArgs g;
+      g.M = nk; g.N = nk; g.K = r;
+      g.A = f->QN; g.lda = r;
+      g.B = f->QN; g.ldb = r; g.transB = true;
+      g.C = S; g.ldc = nk;
+      g.alpha = shift; g.beta = 1.0; g.flags = kLowerOut;
+      if ((rc = gemm(g, s))) break;
+    }
+    // ---- L L^T = bold S, then bold S^{-1} = L^{-T} L^{-1}
+    if (hipMemsetAsync(ctx->d_flag, 0, sizeof(int), s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    if ((rc = potrf(S, nk, nk, ctx->d_flag, dS.p, s))) break;
+    if ((rc = zero_upper(S, nk, nk, s))) break;
+    int fl = 0;
+    if ((rc = read_flag(ctx, &fl))) break;
+    if (fl) {
+      rc = LRSDP_ERR_CHOL_S;
+      break;
+    }
+    if ((rc = trtri(S, nk, nk, f->Sinv, dS.p, s))) break;
+    if ((rc = lauum(S, nk, nk, f->Sinv, nk, s))) break;
+    if ((rc = mirror_lower(f->Sinv, nk, nk, s))) break;
+    if (hipStreamSynchronize(s) != hipSuccess) rc = LRSDP_ERR_DEVICE;
+  } while (0);
+  free_tmp();
+  LRSDP_TRY(rc);
+  auto t_end = std::chrono::steady_clock::now();
+  f->setup_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+  return LRSDP_OK;
+}
+
+}  // namespace lrsdp

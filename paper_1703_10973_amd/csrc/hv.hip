@@ -1,0 +1,313 @@
+// Steps A5 / A7 / A8-residual: the matrix-free Hessian product of eq hesseqn2,
+//   (H v)_i = A_i . (W M W),  M = mat(A v) = sum_i v_i A_i,
+// as three stages that never form a dense n x n intermediate in HBM:
+//   1. scatter   mval[e] = val_{src(e)} v_{src(e)} on the symmetric CSR pattern of M;
+//   2. SpMM      Tt = W M (= (M W)^T, M and W symmetric) for a block of CB rows of W that
+//                sits in LDS; M's pattern is streamed (it is small and L2-resident);
+//   3. gather    (W M W)_{ab} = W[a, :] . Tt[b, :] for the constraints owned by the block's
+//                rows, one wavefront per constraint with a wave reduction; the LDS copy of Tt
+//                is read, W's row a streams from L2 / HBM with coalesced 64-wide loads.
+// Work per product: 2 (nnz + m) n flops; HBM traffic: W once (the LDS blocks) plus the
+// gather's row reads, which hit L2 / MALL for n up to a few thousand.
+#include "internal.h"
+
+namespace lrsdp {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr size_t kLdsBudget = 64 * 1024;  // two blocks per CU
+
+__global__ void k_scatter(int nnz, const int32_t* __restrict__ src,
+                          const double* __restrict__ val, const double* __restrict__ v,
+                          double* __restrict__ mval) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) {
+    int i = src[e];
+    mval[e] = val[i] * v[i];
+  }
+}
+
+template <typename TW, typename TA>
+__device__ __forceinline__ TA load_w(const TW* W, size_t idx);
+template <>
+__device__ __forceinline__ double load_w<double, double>(const double* W, size_t idx) {
+  return W[idx];
+}
+template <>
+__device__ __forceinline__ float load_w<float, float>(const float* W, size_t idx) {
+  return W[idx];
+}
+template <>
+__device__ __forceinline__ float load_w<uint16_t, float>(const uint16_t* W, size_t idx) {
+  return bf16_to_f32(W[idx]);
+}
+
+template <typename TA>
+__device__ __forceinline__ TA to_ta(double x);
+template <>
+__device__ __forceinline__ double to_ta<double>(double x) { return x; }
+template <>
+__device__ __forceinline__ float to_ta<float>(double x) { return static_cast<float>(x); }
+
+// Which of the block's CB rows owns list position t (own_ptr is the prefix over rows).
+__device__ __forceinline__ int owner_row(const int32_t* own_ptr, int c0, int cb, int t) {
+  int c = 0;
+  while (c + 1 < cb && own_ptr[c0 + c + 1] <= t) ++c;
+  return c;
+}
+
+template <typename TW, typename TA, int CB, bool kBf16Values>
+__global__ __launch_bounds__(kThreads) void k_hv_fused(
+    int n, int ldn, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+    const double* __restrict__ mval, const TW* __restrict__ W,
+    const int32_t* __restrict__ own_ptr, const int32_t* __restrict__ own_con,
+    const int32_t* __restrict__ own_oth, const double* __restrict__ coef,
+    double* __restrict__ Hv) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  TA* Wb = reinterpret_cast<TA*>(smem_raw);  // [CB][ldn]
+  TA* Tt = Wb + CB * ldn;                    // [CB][ldn]
+  const int c0 = blockIdx.x * CB;
+  const int cb = min(CB, n - c0);
+
+  // 1. stage rows c0..c0+cb-1 of W
+  for (int idx = threadIdx.x; idx < CB * n; idx += kThreads) {
+    int c = idx / n, q = idx - c * n;
+    Wb[c * ldn + q] = (c < cb) ? load_w<TW, TA>(W, (size_t)(c0 + c) * n + q) : TA(0);
+  }
+  __syncthreads();
+
+  // 2. Tt[c][p] = sum_q M_pq W[c0 + c, q] over the sorted pattern of row p.  Eight lanes
+  //    share a row (coalesced loads of the pattern, several in flight per lane), then a
+  //    three-step shuffle reduction; a fixed lane-to-entry map keeps the sum order fixed.
+  {
+    const int sub = threadIdx.x & 7;
+    for (int p = threadIdx.x >> 3; p < n; p += kThreads / 8) {
+      TA acc[CB];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[c] = TA(0);
+      const int lo = rowptr[p], hi = rowptr[p + 1];
+#pragma unroll 2
+      for (int e = lo + sub; e < hi; e += 8) {
+        const int q = colidx[e];
+        TA mv = to_ta<TA>(mval[e]);
+        if constexpr (kBf16Values) mv = bf16_to_f32(f32_to_bf16_rne(mv));
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[c] = fma(mv, Wb[c * ldn + q], acc[c]);
+      }
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        TA v = acc[c];
+        v += __shfl_xor(v, 1, 8);
+        v += __shfl_xor(v, 2, 8);
+        v += __shfl_xor(v, 4, 8);
+        acc[c] = v;
+      }
+      if (sub == 0) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) Tt[c * ldn + p] = acc[c];
+      }
+    }
+  }
+  __syncthreads();
+
+  // 3. one wavefront per owned constraint: X_ab = W[a, :] . Tt[b - c0, :]
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nwv = kThreads / kWave;
+  const int t0 = own_ptr[c0], t1 = own_ptr[c0 + cb];
+  for (int t = t0 + wid; t < t1; t += nwv) {
+    const int c = owner_row(own_ptr, c0, cb, t);
+    const int a = own_oth[t];
+    const TW* wa = W + (size_t)a * n;
+    const TA* tt = Tt + c * ldn;
+    TA s = TA(0);
+#pragma unroll 4
+    for (int p = lane; p < n; p += kWave) s = fma(load_w<TW, TA>(wa, p), tt[p], s);
+    s = wave_sum(s);
+    if (lane == 0) {
+      const int i = own_con[t];
+      Hv[i] = coef[i] * static_cast<double>(s);
+    }
+  }
+}
+
+template <typename TW, typename TA, bool kBf16Values>
+int launch_hv(const lrsdp_problem* P, const TW* W, const double* v, double* Hv, hipStream_t s) {
+  const int n = P->n;
+  k_scatter<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, v, P->mval);
+  const int ldn = n;
+  const size_t row_bytes = 2 * (size_t)ldn * sizeof(TA);
+  int cb = static_cast<int>(kLdsBudget / row_bytes);
+  size_t budget = kLdsBudget;
+  if (cb < 1) {  // large n: one block per CU
+    budget = 160 * 1024;
+    cb = static_cast<int>(budget / row_bytes);
+    if (cb < 1) return LRSDP_ERR_INVALID_ARG;
+  }
+  cb = cb >= 8 ? 8 : cb >= 4 ? 4 : cb >= 2 ? 2 : 1;
+  const size_t smem = (size_t)cb * row_bytes;
+  const int grid = (n + cb - 1) / cb;
+  ProfMark pm = prof_begin(LRSDP_K_HV, s);
+#define LRSDP_HV_CASE(CBV)                                                                  \
+  case CBV:                                                                                 \
+    hipLaunchKernelGGL((k_hv_fused<TW, TA, CBV, kBf16Values>), dim3(grid), dim3(kThreads), \
+                       smem, s, n, ldn, P->rowptr, P->colidx, P->mval, W, P->own_ptr,       \
+                       P->own_con, P->own_oth, P->coef, Hv);                                \
+    break;
+  switch (cb) {
+    LRSDP_HV_CASE(1)
+    LRSDP_HV_CASE(2)
+    LRSDP_HV_CASE(4)
+    LRSDP_HV_CASE(8)
+  }
+#undef LRSDP_HV_CASE
+  LRSDP_HIP(hipGetLastError());
+  // compulsory traffic of the fused kernel: W once, the pattern (column + value), and per
+  // constraint its owner entry, coefficient and output; flops 2 (nnz + m) n
+  prof_end(pm, s, (double)sizeof(TW) * n * n + 12.0 * P->nnz + 24.0 * P->m,
+           2.0 * ((double)P->nnz + P->m) * n);
+  return LRSDP_OK;
+}
+
+// ---------------------------------------------------------------- double-double residual
+// res = r - H (y + ylo) with every product error-free and every sum in double-double.
+
+__global__ void k_scatter_dd(int nnz, const int32_t* __restrict__ src,
+                             const double* __restrict__ val, const double* __restrict__ y,
+                             const double* __restrict__ ylo, double* __restrict__ mhi,
+                             double* __restrict__ mlo) {
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) {
+    int i = src[e];
+    dd p = two_prod(val[i], y[i]);
+    if (ylo) p.lo = fma(val[i], ylo[i], p.lo);
+    p = quick_two_sum(p.hi, p.lo);
+    mhi[e] = p.hi;
+    mlo[e] = p.lo;
+  }
+}
+
+template <int CB>
+__global__ __launch_bounds__(kThreads) void k_residual_dd(
+    int n, int ldn, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+    const double* __restrict__ mhi, const double* __restrict__ mlo,
+    const double* __restrict__ W, const int32_t* __restrict__ own_ptr,
+    const int32_t* __restrict__ own_con, const int32_t* __restrict__ own_oth,
+    const double* __restrict__ coef, const double* __restrict__ r, double* __restrict__ res,
+    double* __restrict__ res_lo) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Wb = reinterpret_cast<double*>(smem_raw);  // [CB][ldn]
+  double* Th = Wb + CB * ldn;
+  double* Tl = Th + CB * ldn;
+  const int c0 = blockIdx.x * CB;
+  const int cb = min(CB, n - c0);
+  for (int idx = threadIdx.x; idx < CB * n; idx += kThreads) {
+    int c = idx / n, q = idx - c * n;
+    Wb[c * ldn + q] = (c < cb) ? W[(size_t)(c0 + c) * n + q] : 0.0;
+  }
+  __syncthreads();
+  {
+    const int sub = threadIdx.x & 7;
+    for (int p = threadIdx.x >> 3; p < n; p += kThreads / 8) {
+      dd acc[CB];
+#pragma unroll
+      for (int c = 0; c < CB; ++c) acc[c] = {0.0, 0.0};
+      const int lo = rowptr[p], hi = rowptr[p + 1];
+      for (int e = lo + sub; e < hi; e += 8) {
+        const int q = colidx[e];
+        const double h = mhi[e], l = mlo[e];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[c] = dd_fma2(acc[c], Wb[c * ldn + q], h, l);
+      }
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        dd v = acc[c];
+        v = dd_add(v, {__shfl_xor(v.hi, 1, 8), __shfl_xor(v.lo, 1, 8)});
+        v = dd_add(v, {__shfl_xor(v.hi, 2, 8), __shfl_xor(v.lo, 2, 8)});
+        v = dd_add(v, {__shfl_xor(v.hi, 4, 8), __shfl_xor(v.lo, 4, 8)});
+        acc[c] = v;
+      }
+      if (sub == 0) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+          Th[c * ldn + p] = acc[c].hi;
+          Tl[c * ldn + p] = acc[c].lo;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nwv = kThreads / kWave;
+  const int t0 = own_ptr[c0], t1 = own_ptr[c0 + cb];
+  for (int t = t0 + wid; t < t1; t += nwv) {
+    const int c = owner_row(own_ptr, c0, cb, t);
+    const int a = own_oth[t];
+    const double* wa = W + (size_t)a * n;
+    dd s = {0.0, 0.0};
+    for (int p = lane; p < n; p += kWave) s = dd_fma2(s, wa[p], Th[c * ldn + p], Tl[c * ldn + p]);
+    s = wave_sum_dd(s);
+    if (lane == 0) {
+      const int i = own_con[t];
+      dd hv = dd_mul_d(s, coef[i]);
+      dd d = dd_add_d({-hv.hi, -hv.lo}, r[i]);
+      res[i] = d.hi;
+      if (res_lo) res_lo[i] = d.lo;
+    }
+  }
+}
+
+}  // namespace
+
+int hv_apply_f64(const lrsdp_problem* P, const double* W, const double* v, double* Hv,
+                 hipStream_t s) {
+  return launch_hv<double, double, false>(P, W, v, Hv, s);
+}
+int hv_apply_f32(const lrsdp_problem* P, const float* W, const double* v, double* Hv,
+                 hipStream_t s) {
+  return launch_hv<float, float, false>(P, W, v, Hv, s);
+}
+int hv_apply_bf16(const lrsdp_problem* P, const uint16_t* W, const double* v, double* Hv,
+                  hipStream_t s) {
+  return launch_hv<uint16_t, float, true>(P, W, v, Hv, s);
+}
+
+int hv_residual_dd(const lrsdp_problem* P, const double* W, const double* r, const double* y,
+                   const double* ylo, double* res, double* res_lo, hipStream_t s) {
+  const int n = P->n;
+  // mat(A y) in double-double: two nnz arrays carved from the problem's scratch space
+  double* mhi = P->mval;
+  double* mlo = P->vec_scratch;  // sized max(4 m, nnz) at problem creation
+  k_scatter_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, y, ylo, mhi, mlo);
+  const int ldn = n;
+  const size_t row_bytes = 3 * (size_t)ldn * sizeof(double);
+  int cb = static_cast<int>(kLdsBudget / row_bytes);
+  size_t budget = kLdsBudget;
+  if (cb < 1) {
+    budget = 160 * 1024;
+    cb = static_cast<int>(budget / row_bytes);
+    if (cb < 1) return LRSDP_ERR_INVALID_ARG;
+  }
+  cb = cb >= 4 ? 4 : cb >= 2 ? 2 : 1;
+  const size_t smem = (size_t)cb * row_bytes;
+  const int grid = (n + cb - 1) / cb;
+  ProfMark pm = prof_begin(LRSDP_K_RESDD, s);
+#define LRSDP_RES_CASE(CBV)                                                                \
+  case CBV:                                                                                \
+    hipLaunchKernelGGL((k_residual_dd<CBV>), dim3(grid), dim3(kThreads), smem, s, n, ldn,  \
+                       P->rowptr, P->colidx, mhi, mlo, W, P->own_ptr, P->own_con,          \
+                       P->own_oth, P->coef, r, res, res_lo);                                \
+    break;
+  switch (cb) {
+    LRSDP_RES_CASE(1)
+    LRSDP_RES_CASE(2)
+    LRSDP_RES_CASE(4)
+  }
+#undef LRSDP_RES_CASE
+  LRSDP_HIP(hipGetLastError());
+  prof_end(pm, s, 8.0 * n * n + 20.0 * P->nnz + 40.0 * P->m, 2.0 * ((double)P->nnz + P->m) * n);
+  return LRSDP_OK;
+}
+
+}  // namespace lrsdp

@@ -1,0 +1,228 @@
+// Step A0: the constraint triplets -> per-constraint pairs and the symmetric CSR pattern.
+//
+// Constraint i is A_i with (A_i)_ab = (A_i)_ba = val_i (eqs SDP/SDD).  With disjoint supports
+// A^T A is diagonal (Assumption 2): g_i = val_i^2 (a == b) or 2 val_i^2.  mat(A v) lives on
+// the symmetric pattern Obar = {(a,b), (b,a)}, stored as CSR with sorted columns so that every
+// product with it accumulates in a fixed order.
+#include "internal.h"
+
+namespace lrsdp {
+namespace {
+
+enum : int {
+  kFlagRange = 1,       // index out of range / row > col / bad value
+  kFlagMulti = 2,       // a constraint with != 1 triplet
+  kFlagDup = 4,         // two constraints with the same pair
+};
+
+__global__ void k_validate(int64_t nnz, int n, int m, const int32_t* con, const int32_t* row,
+                           const int32_t* col, const double* val, int* cnt, int* flag) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nnz) return;
+  int c = con[t], r = row[t], q = col[t];
+  double v = val[t];
+  bool ok = c >= 0 && c < m && r >= 0 && q < n && r <= q && v == v && v != 0.0 &&
+            fabs(v) < 1e300;
+  if (!ok) {
+    atomicOr(flag, kFlagRange);
+    return;
+  }
+  atomicAdd(&cnt[c], 1);
+}
+
+__global__ void k_scatter_con(int64_t nnz, int n, int m, const int32_t* con, const int32_t* row,
+                              const int32_t* col, const double* val, const int* cnt, int* flag,
+                              int32_t* a, int32_t* b, double* vv, double* coef, double* ginv) {
+  int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (t >= nnz) return;
+  int c = con[t], r = row[t], q = col[t];
+  double v = val[t];
+  // invalid triplets were flagged by k_validate; never index with them
+  if (c < 0 || c >= m || r < 0 || q >= n || r > q || !(v == v) || v == 0.0) return;
+  if (cnt[c] != 1) return;  // reported by k_check_counts
+  a[c] = r;
+  b[c] = q;
+  vv[c] = v;
+  coef[c] = (r == q) ? v : 2.0 * v;
+  ginv[c] = (r == q) ? 1.0 / (v * v) : 1.0 / (2.0 * v * v);
+}
+
+__global__ void k_check_counts(int m, const int* cnt, int* flag) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m && cnt[i] != 1) atomicOr(flag, kFlagMulti);
+}
+
+__global__ void k_degree(int m, const int32_t* a, const int32_t* b, int* deg, int* odeg) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  int r = a[i], q = b[i];
+  atomicAdd(&deg[r], 1);
+  if (r != q) atomicAdd(&deg[q], 1);
+  // owner of the sampled product: alternate endpoints to balance the work per index
+  int own = ((i & 1) == 0) ? q : r;
+  atomicAdd(&odeg[own], 1);
+}
+
+// Exclusive scan of n ints into ptr[0..n]; one block.
+__global__ void k_scan(int n, const int* deg, int32_t* ptr) {
+  __shared__ int part[1024];
+  const int T = blockDim.x;
+  int chunk = (n + T - 1) / T;
+  int lo = threadIdx.x * chunk, hi = min(n, lo + chunk);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += deg[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int i = 0; i < T; ++i) {
+      int t = part[i];
+      part[i] = acc;
+      acc += t;
+    }
+    ptr[n] = acc;
+  }
+  __syncthreads();
+  int acc = part[threadIdx.x];
+  for (int i = lo; i < hi; ++i) {
+    ptr[i] = acc;
+    acc += deg[i];
+  }
+}
+
+__global__ void k_fill(int m, const int32_t* a, const int32_t* b, const int32_t* rowptr,
+                       int* fill, int32_t* colidx, int32_t* src, const int32_t* optr, int* ofill,
+                       int32_t* own_con, int32_t* own_oth) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  int r = a[i], q = b[i];
+  int pos = rowptr[r] + atomicAdd(&fill[r], 1);
+  colidx[pos] = q;
+  src[pos] = i;
+  if (r != q) {
+    pos = rowptr[q] + atomicAdd(&fill[q], 1);
+    colidx[pos] = r;
+    src[pos] = i;
+  }
+  int own = ((i & 1) == 0) ? q : r;
+  int oth = ((i & 1) == 0) ? r : q;
+  int op = optr[own] + atomicAdd(&ofill[own], 1);
+  own_con[op] = i;
+  own_oth[op] = oth;
+}
+
+// Sort each CSR row by column (insertion sort: rows are short) and flag duplicates.
+__global__ void k_sort_rows(int n, const int32_t* rowptr, int32_t* colidx, int32_t* src,
+                            int* flag) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  int lo = rowptr[r], hi = rowptr[r + 1];
+  for (int i = lo + 1; i < hi; ++i) {
+    int c = colidx[i], s = src[i];
+    int j = i - 1;
+    while (j >= lo && colidx[j] > c) {
+      colidx[j + 1] = colidx[j];
+      src[j + 1] = src[j];
+      --j;
+    }
+    colidx[j + 1] = c;
+    src[j + 1] = s;
+  }
+  for (int i = lo + 1; i < hi; ++i)
+    if (colidx[i] == colidx[i - 1]) atomicOr(flag, kFlagDup);
+}
+
+// Sort each owner list by constraint id so that the work assignment is reproducible.
+__global__ void k_sort_owned(int n, const int32_t* optr, int32_t* con, int32_t* oth) {
+  int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  int lo = optr[r], hi = optr[r + 1];
+  for (int i = lo + 1; i < hi; ++i) {
+    int c = con[i], o = oth[i];
+    int j = i - 1;
+    while (j >= lo && con[j] > c) {
+      con[j + 1] = con[j];
+      oth[j + 1] = oth[j];
+      --j;
+    }
+    con[j + 1] = c;
+    oth[j + 1] = o;
+  }
+}
+
+}  // namespace
+
+int ingest(lrsdp_ctx* ctx, lrsdp_problem* P, const int32_t* con, const int32_t* row,
+           const int32_t* col, const double* val, int64_t nnz_t) {
+  hipStream_t s = ctx->stream;
+  const int n = P->n, m = P->m;
+  int* cnt = nullptr;
+  int* deg = nullptr;  // n deg, n fill, n odeg, n ofill
+  LRSDP_TRY(dev_alloc_n(ctx, &cnt, (size_t)m));
+  int st = dev_alloc_n(ctx, &deg, (size_t)4 * n);
+  if (st < 0) {
+    dev_free(ctx, cnt, (size_t)m * sizeof(int));
+    return st;
+  }
+  auto cleanup = [&]() {
+    dev_free(ctx, cnt, (size_t)m * sizeof(int));
+    dev_free(ctx, deg, (size_t)4 * n * sizeof(int));
+  };
+  int* fill = deg + n;
+  int* odeg = deg + 2 * n;
+  int* ofill = deg + 3 * n;
+  int rc = LRSDP_OK;
+  do {
+    if (hipMemsetAsync(cnt, 0, (size_t)m * sizeof(int), s) != hipSuccess ||
+        hipMemsetAsync(deg, 0, (size_t)4 * n * sizeof(int), s) != hipSuccess ||
+        hipMemsetAsync(ctx->d_flag, 0, sizeof(int), s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    const int T = 256;
+    k_validate<<<grid_for(nnz_t, T), T, 0, s>>>(nnz_t, n, m, con, row, col, val, cnt,
+                                                 ctx->d_flag);
+    k_check_counts<<<grid_for(m, T), T, 0, s>>>(m, cnt, ctx->d_flag);
+    k_scatter_con<<<grid_for(nnz_t, T), T, 0, s>>>(nnz_t, n, m, con, row, col, val, cnt, ctx->d_flag,
+                                                    P->a, P->b, P->val, P->coef, P->ginv);
+    int flag = 0;
+    if (hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    if (flag & kFlagRange) { rc = LRSDP_ERR_INVALID_ARG; break; }
+    if (flag & kFlagMulti) { rc = LRSDP_ERR_UNSUPPORTED; break; }
+    k_degree<<<grid_for(m, T), T, 0, s>>>(m, P->a, P->b, deg, odeg);
+    k_scan<<<1, 1024, 0, s>>>(n, deg, P->rowptr);
+    k_scan<<<1, 1024, 0, s>>>(n, odeg, P->own_ptr);
+    int nnz = 0;
+    if (hipMemcpyAsync(&nnz, P->rowptr + n, sizeof(int), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    P->nnz = nnz;
+    int e1 = dev_alloc_n(ctx, &P->colidx, (size_t)nnz);
+    int e2 = e1 < 0 ? e1 : dev_alloc_n(ctx, &P->src, (size_t)nnz);
+    int e3 = e2 < 0 ? e2 : dev_alloc_n(ctx, &P->mval, (size_t)nnz);
+    if (e3 < 0) { rc = e3; break; }
+    k_fill<<<grid_for(m, T), T, 0, s>>>(m, P->a, P->b, P->rowptr, fill, P->colidx, P->src,
+                                         P->own_ptr, ofill, P->own_con, P->own_oth);
+    k_sort_rows<<<grid_for(n, 128), 128, 0, s>>>(n, P->rowptr, P->colidx, P->src, ctx->d_flag);
+    k_sort_owned<<<grid_for(n, 128), 128, 0, s>>>(n, P->own_ptr, P->own_con, P->own_oth);
+    if (hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    if (flag & kFlagDup) { rc = LRSDP_ERR_DUPLICATE_PAIR; break; }
+  } while (0);
+  cleanup();
+  return rc;
+}
+
+}  // namespace lrsdp

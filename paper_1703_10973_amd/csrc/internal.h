@@ -1,0 +1,165 @@
+// Handles and kernel launchers of the Hessian-equation solver (internal).
+#pragma once
+
+#include "common.h"
+
+namespace lrsdp {
+
+// Per-context kernel timing (HIP events on the context's stream around selected launches).
+struct ProfStat {
+  int64_t launches = 0;
+  double ms = 0.0, bytes = 0.0, flops = 0.0;
+};
+struct Profiler {
+  bool enabled = false;
+  unsigned mask = 0;  // bit i: time kernel class i
+  ProfStat stat[LRSDP_K_COUNT];
+  struct Pending {
+    int kid;
+    hipEvent_t a, b;
+    double bytes, flops;
+  };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+};
+
+}  // namespace lrsdp
+
+struct lrsdp_ctx {
+  lrsdp::Profiler prof;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0;   // 0: unlimited
+  size_t in_use = 0;
+  double* h_pinned = nullptr;   // small pinned host staging area (scalars)
+  int* d_flag = nullptr;        // device error/status word
+};
+
+struct lrsdp_problem {
+  lrsdp_ctx* ctx = nullptr;
+  int n = 0, m = 0, nnz = 0;        // nnz: entries of the symmetric pattern of mat(A v)
+  int32_t* a = nullptr;             // m, row of the entry of A_i (a <= b)
+  int32_t* b = nullptr;             // m, column
+  double* val = nullptr;            // m, (A_i)_ab
+  double* coef = nullptr;           // m, A_i . X = coef_i X_ab for symmetric X
+  double* ginv = nullptr;           // m, 1 / (A^T A)_ii
+  int32_t* rowptr = nullptr;        // n + 1, CSR of the symmetric pattern, sorted columns
+  int32_t* colidx = nullptr;        // nnz
+  int32_t* src = nullptr;           // nnz, constraint supplying each pattern entry
+  int32_t* own_ptr = nullptr;       // n + 1, constraints grouped by the index that computes them
+  int32_t* own_con = nullptr;       // m, constraint id
+  int32_t* own_oth = nullptr;       // m, the other index of the pair
+  double* mval = nullptr;           // nnz scratch: values of mat(A v) in pattern order
+  double* vec_scratch = nullptr;    // 4 m scratch for parity hooks
+  size_t bytes = 0;
+};
+
+namespace lrsdp {
+
+// ---------------------------------------------------------------- profiling
+// The API entry points bind the context's profiler to the calling thread (ProfScope);
+// launch sites bracket the kernels they want timed with prof_begin / prof_end.
+extern thread_local Profiler* tls_prof;
+struct ProfMark {
+  int kid = -1;
+  hipEvent_t a = nullptr;
+};
+ProfMark prof_begin(int kid, hipStream_t s);
+void prof_end(const ProfMark& mk, hipStream_t s, double bytes, double flops);
+inline bool prof_on() { return tls_prof && tls_prof->enabled; }
+void prof_flush(Profiler* p);  // after the stream is synchronized
+struct ProfScope {
+  Profiler* prev;
+  Profiler* mine;
+  explicit ProfScope(lrsdp_ctx* c) : prev(tls_prof), mine(&c->prof) { tls_prof = mine; }
+  ~ProfScope() {
+    prof_flush(mine);
+    tls_prof = prev;
+  }
+};
+
+// ---------------------------------------------------------------- memory
+int dev_alloc(lrsdp_ctx* ctx, void** p, size_t bytes);
+void dev_free(lrsdp_ctx* ctx, void* p, size_t bytes);
+
+template <typename T>
+int dev_alloc_n(lrsdp_ctx* ctx, T** p, size_t count) {
+  return dev_alloc(ctx, reinterpret_cast<void**>(p), count * sizeof(T));
+}
+
+// ---------------------------------------------------------------- A0 ingest (ingest.hip)
+int ingest(lrsdp_ctx* ctx, lrsdp_problem* P, const int32_t* con, const int32_t* row,
+           const int32_t* col, const double* val, int64_t nnz_triplets);
+
+// ---------------------------------------------------------------- A5 / A7 H v (hv.hip)
+// Hv = coef * (W mat(A v) W)_{ab}; W given in FP64, FP32 or BF16 (uint16 bits).
+int hv_apply_f64(const lrsdp_problem* P, const double* W, const double* v, double* Hv,
+                 hipStream_t s);
+int hv_apply_f32(const lrsdp_problem* P, const float* W, const double* v, double* Hv,
+                 hipStream_t s);
+int hv_apply_bf16(const lrsdp_problem* P, const uint16_t* W, const double* v, double* Hv,
+                  hipStream_t s);
+// Double-double H (y + ylo); writes res = r - H y (rounded) and per-block partial sums of
+// res^2 and r^2 into part (2 * gridDim doubles); returns nothing on host.
+int hv_residual_dd(const lrsdp_problem* P, const double* W, const double* r, const double* y,
+                   const double* ylo, double* res, double* res_lo, hipStream_t s);
+
+}  // namespace lrsdp
+
+// ------------------------------------------------------------------ the factor (Alg. 1 1-2)
+struct lrsdp_factor {
+  lrsdp_problem* P = nullptr;
+  int n = 0, k = 0, nk = 0, r = 0;   // r = k(k-1)/2 deflation directions kept
+  double tau = 0.0, tau2 = 0.0, shift = 0.0, setup_ms = 0.0;
+  std::vector<double> lam;           // host copy: lambda_min, then the k largest ascending
+  double* lam_dev = nullptr;         // k + 1
+  double* W = nullptr;               // n x n, copy of the caller's W
+  double* W0 = nullptr;              // n x n, W - U U^T rounded once from double-double
+  float* W0f = nullptr;              // n x n, FP32 copy of W0 (lazy)
+  uint16_t* W0b = nullptr;           // n x n, BF16 copy of W0 (lazy)
+  double* U = nullptr;               // k x n (n x k column-major)
+  double* Z = nullptr;               // n x n lower, Z Z^T = 2 W0 + U U^T
+  double* Zt = nullptr;              // n x n, Z^T
+  double* Sinv = nullptr;            // nk x nk, full symmetric bold S^{-1}
+  double* QN = nullptr;              // nk x r orthonormal deflation basis
+  // per-solve work vectors (allocated with the factor)
+  double* work = nullptr;            // see factor.hip for the carve-up
+  size_t work_doubles = 0;
+  double* sc = nullptr;              // device scalars
+  size_t bytes = 0;
+};
+
+namespace lrsdp {
+
+int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o);
+void factor_release(lrsdp_factor* f);
+int ensure_lowprec(lrsdp_factor* f, int precision, hipStream_t s);
+
+// Work-vector views (each m or nk long) inside f->work.
+struct Work {
+  // m-vectors
+  double *x, *r, *z, *p, *q, *t0, *t1, *t2, *t3, *ylo, *dd0, *dd1;
+  // nk-vectors / k x n blocks
+  double *w, *wl, *t, *tl, *s, *sl, *y, *yl, *g0, *g1;
+  // small
+  double *kk;     // k x k
+  double *part;   // reduction partials
+};
+Work work_view(const lrsdp_factor* f);
+size_t work_doubles(int n, int m, int k);
+
+// ---------------------------------------------------------------- apply.hip
+int precond_apply_f64(const lrsdp_factor* f, const double* v, double* z, hipStream_t s,
+                      int refine);
+int precond_apply_dd(const lrsdp_factor* f, const double* v, double* z, hipStream_t s,
+                     int nref);
+int split_apply(lrsdp_factor* f, const double* v, double* Hv, int precision, hipStream_t s);
+
+// ---------------------------------------------------------------- pcg.hip
+int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lrsdp_opts& o,
+              lrsdp_info* info);
+int residual_dd(lrsdp_factor* f, const double* r, const double* y, const double* ylo,
+                double* res, double* res_lo, double* relres);
+
+}  // namespace lrsdp

@@ -1,0 +1,45 @@
+"""The C-ABI library loads and exports every function include/lrsdp.h declares (no GPU)."""
+
+import ctypes
+import os
+
+import pytest
+
+LIB = os.path.join(os.path.dirname(os.path.dirname(__file__)), "paper_1703_10973_amd", "liblrsdp.so")
+
+
+@pytest.fixture(scope="module")
+def binding():
+    if not os.path.exists(LIB):
+        pytest.fail("liblrsdp.so is not built: run python -m paper_1703_10973_amd.build")
+    import paper_1703_10973_amd as pk
+    return pk
+
+
+def test_every_header_symbol_is_exported(binding):
+    names = binding.header_symbols()
+    assert len(names) >= 16
+    h = ctypes.CDLL(LIB)
+    for nm in names:
+        assert hasattr(h, nm), f"{nm} declared in include/lrsdp.h but not exported"
+
+
+def test_binding_covers_the_header(binding):
+    from paper_1703_10973_amd import _lib
+    assert set(binding.header_symbols()) == set(_lib._SIGS)
+
+
+def test_defaults_and_status_strings(binding):
+    o = binding.lrsdp_opts_default()
+    assert o.eps == 1e-8 and o.max_iter == 200 and o.deflate == 1 and o.dd_mode == 2
+    assert binding.status_string(0) == "OK"
+    assert binding.status_string(-2) == "DUPLICATE_PAIR"
+    assert binding.status_string(-99) == "UNKNOWN"
+
+
+def test_context_needs_a_device(binding):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(binding.LrsdpError):
+        binding.lrsdp_ctx_create(0)

@@ -1,0 +1,60 @@
+"""Full benchmark size (n = 1000, k = 5, m = 20000), in the configuration bench.py times."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import alg1, dd as ddo
+from synth import make_instance
+
+pytestmark = pytest.mark.gpu
+
+pk = pytest.importorskip("paper_1703_10973_amd")
+from gpu_util import host, problem_from, rel, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def problem(ctx):
+    inst = make_instance(1000, 5, 20000, 1e-2, seed=2001)
+    return problem_from(ctx, inst)
+
+
+MODES = {"mixed": dict(precision=pk.LRSDP_PREC_FP32, dd_mode=pk.LRSDP_DD_ON),
+         "fp64": dict(precision=pk.LRSDP_PREC_FP64, dd_mode=pk.LRSDP_DD_AUTO)}
+
+
+@pytest.mark.parametrize("mode", ["mixed", "fp64"])
+@pytest.mark.parametrize("mu", [1e-2, 1e-8])
+def test_full_size_solve_meets_target(problem, mode, mu):
+    inst = make_instance(1000, 5, 20000, mu, seed=2001)
+    F = pk.Factor(problem, to_dev(inst.W), inst.k)
+    y, ylo, st, info = F.solve(to_dev(inst.r), pk.opts(**MODES[mode]))
+    assert st == 0, info
+    yh, yl = host(y), host(ylo)
+    r_true, _ = ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val, inst.r, yh, yl)
+    assert r_true <= 1e-8
+    if mu == 1e-2:
+        C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
+        ref = alg1.solve(alg1.factor(C, inst.W, inst.k), inst.r, eps=1e-10)
+        assert rel(yh + yl, ref.y) <= 1e-6
+    assert info["iters"] <= 25 * max(1, info["outer_iters"])
+    F.close()
+
+
+def test_full_size_tau_and_top_eigenvalues(problem):
+    inst = make_instance(1000, 5, 20000, 1e-6, seed=2001)
+    F = pk.Factor(problem, to_dev(inst.W), inst.k)
+    ex = F.export()
+    lam = np.linalg.eigvalsh(inst.W)
+    assert abs(ex["tau"] - lam[0]) <= 1e-13 * lam[-1] * np.sqrt(1000)
+    np.testing.assert_allclose(ex["lam"][1:], lam[-5:], rtol=1e-12)
+    F.close()

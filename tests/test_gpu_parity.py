@@ -1,0 +1,206 @@
+"""HIP path vs the CPU oracle, through the C ABI (steps A0-A8)."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import alg1, dd as ddo, hessian as hs, refine
+from synth import make_instance
+
+pytestmark = pytest.mark.gpu
+
+pk = pytest.importorskip("paper_1703_10973_amd")
+from gpu_util import DEV, host, problem_from, rel, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+# ------------------------------------------------------------------ A0 ingest
+
+def test_ingest_pattern_and_errors(ctx):
+    inst = make_instance(50, 2, 300, 1e-2, seed=5)
+    P = problem_from(ctx, inst)
+    n, m, nnz = P.info()
+    assert (n, m, nnz) == (50, 300, 50 + 2 * 250)
+    con, row, col, val = inst.triplets()
+    # duplicate pair
+    row2, col2 = row.copy(), col.copy()
+    row2[-1], col2[-1] = row[-2], col[-2]
+    with pytest.raises(pk.LrsdpError) as e:
+        pk.Problem(ctx, 50, 300, to_dev(con, torch.int32), to_dev(row2, torch.int32),
+                   to_dev(col2, torch.int32), to_dev(val))
+    assert e.value.status == pk._lib.LRSDP_ERR_DUPLICATE_PAIR
+    # row > col
+    row3, col3 = row.copy(), col.copy()
+    row3[-1], col3[-1] = col[-1], row[-1]
+    with pytest.raises(pk.LrsdpError) as e:
+        pk.Problem(ctx, 50, 300, to_dev(con, torch.int32), to_dev(row3, torch.int32),
+                   to_dev(col3, torch.int32), to_dev(val))
+    assert e.value.status == pk._lib.LRSDP_ERR_INVALID_ARG
+    # a constraint given twice (overlapping supports)
+    con4 = con.copy()
+    con4[-1] = 0
+    with pytest.raises(pk.LrsdpError) as e:
+        pk.Problem(ctx, 50, 300, to_dev(con4, torch.int32), to_dev(row, torch.int32),
+                   to_dev(col, torch.int32), to_dev(val))
+    assert e.value.status == pk._lib.LRSDP_ERR_UNSUPPORTED
+    # the context is still usable
+    P2 = problem_from(ctx, inst)
+    assert P2.info()[2] == nnz
+
+
+# ------------------------------------------------------------------ A5 H v
+
+@pytest.mark.parametrize("shape", [(100, 2, 1000, 1e-4, 1001), (37, 3, 200, 1e-2, 3)])
+def test_hessian_apply_matches_dense(ctx, shape):
+    n, k, m, mu, seed = shape
+    inst = make_instance(n, k, m, mu, seed)
+    P = problem_from(ctx, inst)
+    H = hs.hessian_dense(inst.W, inst.a, inst.b, inst.val)
+    rng = np.random.default_rng(0)
+    for _ in range(3):
+        v = rng.standard_normal(m)
+        got = host(P.hessian_apply(to_dev(inst.W), to_dev(v)))
+        assert rel(got, H @ v) <= 1e-12
+
+
+def test_hessian_apply_full_size(ctx):
+    """The benchmark shape (n = 1000, m = 20000), against the oracle's matrix-free product."""
+    inst = make_instance(1000, 5, 20000, 1e-4, seed=2001)
+    P = problem_from(ctx, inst)
+    C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
+    v = np.random.default_rng(1).standard_normal(inst.m)
+    got = host(P.hessian_apply(to_dev(inst.W), to_dev(v)))
+    ref = alg1.hessian_apply_mf(C, inst.W, v)
+    assert rel(got, ref) <= 1e-12
+    # sampled outputs checked one by one against the closed form of H
+    idx = np.random.default_rng(2).choice(inst.m, 40, replace=False)
+    s = hs.half_scale(inst.a, inst.b, inst.val)
+    W = inst.W
+    for i in idx:
+        a, b = inst.a[i], inst.b[i]
+        row = 2 * s[i] * s * (W[a, inst.a] * W[b, inst.b] + W[a, inst.b] * W[b, inst.a])
+        assert abs(got[i] - row @ v) <= 1e-12 * np.abs(row) @ np.abs(v)
+
+
+# ------------------------------------------------------------------ A1-A4 factor
+
+@pytest.mark.parametrize("shape", [(100, 2, 1000, 1e-4, 1001), (64, 3, 600, 1e-2, 9),
+                                   (130, 1, 900, 1e-6, 4)])
+def test_factor_matches_oracle(ctx, shape):
+    n, k, m, mu, seed = shape
+    inst = make_instance(n, k, m, mu, seed)
+    P = problem_from(ctx, inst)
+    F = pk.Factor(P, to_dev(inst.W), k)
+    ex = F.export(U=True, W0=True, Z=True, Sinv=True)
+    C = alg1.Constraints(n, inst.a, inst.b, inst.val)
+    Fo = alg1.factor(C, inst.W, k)
+    lam = np.linalg.eigvalsh(inst.W)
+    nW = lam[-1]
+    assert abs(ex["tau"] - lam[0]) <= 1e-13 * nW * np.sqrt(n)
+    np.testing.assert_allclose(ex["lam"][1:], lam[n - k:], rtol=1e-12)
+    U = host(ex["U"]).T                                  # n x k
+    np.testing.assert_allclose(U @ U.T, Fo.split.U @ Fo.split.U.T, atol=1e-10 * nW)
+    W0 = host(ex["W0"])
+    assert np.max(np.abs(W0 - refine.dd_W0(inst.W, U))) <= 4e-16 * nW
+    Z = host(ex["Z"])
+    assert np.max(np.abs(np.triu(Z, 1))) == 0.0
+    Zin = 2 * W0 + U @ U.T
+    assert np.max(np.abs(Z @ Z.T - Zin)) <= 1e-13 * np.max(np.abs(Zin))
+    # bold S^{-1} against bold S formed by the oracle from the GPU's own U and Z
+    Sinv = host(ex["Sinv"])
+    S = alg1.schur_explicit(alg1.bold_U_explicit(C, Z, U), C.g, ex["tau"])
+    if k >= 2:
+        Q, _ = np.linalg.qr(alg1.null_basis(Z, U))
+        S = S + ex["shift"] * (Q @ Q.T)
+        assert abs(ex["shift"] - np.max(np.diag(alg1.schur_explicit(
+            alg1.bold_U_explicit(C, Z, U), C.g, ex["tau"])))) <= 1e-12 * ex["shift"]
+    resid = np.linalg.norm(Sinv @ S - np.eye(n * k), 2)
+    assert resid <= 1e-16 * np.linalg.cond(S) * n * k
+
+
+# ------------------------------------------------------------------ A6 preconditioner
+
+@pytest.mark.parametrize("mu", [1e-2, 1e-4])
+def test_precond_matches_oracle(ctx, mu):
+    inst = make_instance(100, 2, 1000, mu, seed=1001)
+    P = problem_from(ctx, inst)
+    F = pk.Factor(P, to_dev(inst.W), inst.k)
+    C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
+    Fo = alg1.factor(C, inst.W, inst.k)
+    v = np.random.default_rng(3).standard_normal(inst.m)
+    zo = alg1.precond_apply(Fo, v)
+    z = host(F.precond_apply(to_dev(v)))
+    zd = host(F.precond_apply(to_dev(v), dd=True))
+    assert rel(z, zo) <= 1e-7
+    assert rel(zd, zo) <= 1e-7
+    assert rel(zd, refine.dd_precond_apply(Fo, v)) <= 1e-7
+
+
+# ------------------------------------------------------------------ A7 split H v
+
+@pytest.mark.parametrize("mu", [1e-2, 1e-6])
+def test_split_hessian_apply(ctx, mu):
+    inst = make_instance(100, 2, 1000, mu, seed=1001)
+    P = problem_from(ctx, inst)
+    F = pk.Factor(P, to_dev(inst.W), inst.k)
+    H = hs.hessian_dense(inst.W, inst.a, inst.b, inst.val)
+    v = np.random.default_rng(4).standard_normal(inst.m)
+    ref = H @ v
+    vd = to_dev(v)
+    assert rel(host(F.hessian_apply_split(vd, pk.LRSDP_PREC_FP64)), ref) <= 1e-12
+    assert rel(host(F.hessian_apply_split(vd, pk.LRSDP_PREC_FP32)), ref) <= 1e-5
+    assert rel(host(F.hessian_apply_split(vd, pk.LRSDP_PREC_BF16)), ref) <= 3e-2
+
+
+# ------------------------------------------------------------------ A8 residual and solve
+
+def test_dd_residual_matches_oracle(ctx):
+    inst = make_instance(100, 2, 1000, 1e-6, seed=1001)
+    P = problem_from(ctx, inst)
+    F = pk.Factor(P, to_dev(inst.W), inst.k)
+    C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
+    out = refine.refine(alg1.factor(C, inst.W, inst.k), inst.r, eps=1e-10)
+    for yh, yl in [(out.yh, out.yl), (out.yh, None), (out.yh * (1 + 1e-9), None)]:
+        ro, _ = ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val, inst.r, yh, yl)
+        rg = F.residual_dd(to_dev(inst.r), to_dev(yh), None if yl is None else to_dev(yl))
+        assert abs(rg - ro) <= 1e-6 * ro + 1e-15
+
+
+@pytest.mark.parametrize("mu", [1e-2, 1e-4])
+def test_solve_fp64(ctx, mu):
+    inst = make_instance(100, 2, 1000, mu, seed=1001)
+    P = problem_from(ctx, inst)
+    F = pk.Factor(P, to_dev(inst.W), inst.k)
+    y, ylo, st, info = F.solve(to_dev(inst.r), pk.opts(dd_mode=pk.LRSDP_DD_OFF))
+    assert st == 0, info
+    assert info["iters"] <= 25
+    y = host(y)
+    H = hs.hessian_dense(inst.W, inst.a, inst.b, inst.val)
+    ystar = hs.solve_dense(H, inst.r)
+    assert rel(y, ystar) <= 1e-6
+    r_true, _ = ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val, inst.r, y)
+    assert r_true <= 1e-8
+
+
+@pytest.mark.parametrize("mu,prec", [(1e-6, 0), (1e-8, 0), (1e-4, 1), (1e-4, 2), (1e-8, 1)])
+def test_solve_refined(ctx, mu, prec):
+    inst = make_instance(100, 2, 1000, mu, seed=1001)
+    P = problem_from(ctx, inst)
+    F = pk.Factor(P, to_dev(inst.W), inst.k)
+    y, ylo, st, info = F.solve(to_dev(inst.r), pk.opts(dd_mode=pk.LRSDP_DD_ON, precision=prec))
+    assert st == 0, info
+    yh, yl = host(y), host(ylo)
+    r_true, _ = ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val, inst.r, yh, yl)
+    assert r_true <= 1e-8
+    C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
+    ref = refine.refine(alg1.factor(C, inst.W, inst.k), inst.r, eps=1e-10)
+    err = np.linalg.norm((yh - ref.yh) + (yl - ref.yl)) / np.linalg.norm(ref.yh)
+    assert err <= 1e-6

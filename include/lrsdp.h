@@ -84,7 +84,17 @@ typedef struct lrsdp_opts {
   double dd_auto_ratio;  /* spectral-gap threshold for LRSDP_DD_AUTO (default 2e-5)         */
   int dd_precond;        /* SMW pieces in double-double: 0 off, 1 on, 2 auto (default 2:    */
                          /* on when tau < 1e-7 lambda_max(W))                                */
+  int tau_rule;          /* LRSDP_TAU_* (default MEAN)                                      */
 } lrsdp_opts;
+
+/* The shift tau of the split W = W0 + U U^T (eq Wsplit2).  Algorithm 1 step 1a takes
+ * tau = lambda_min(W); Section 3.1 allows any tau in [lambda_min(Lambda_s), lambda_max(Lambda_s)),
+ * and Lemmas kappaW and Htilde hold for every such tau with the same kappa(W0). */
+#define LRSDP_TAU_MIN     0   /* lambda_min(W) (Householder tridiagonalization + bisection)     */
+#define LRSDP_TAU_MEAN    1   /* mean of the n-k smallest eigenvalues = (tr W - sum Lambda_l) /   */
+                              /* (n - k); the k largest pairs come from subspace iteration with   */
+                              /* Rayleigh-Ritz, falling back to the Householder path when W has  */
+                              /* no usable spectral gap                                          */
 
 typedef struct lrsdp_info {
   int status;            /* same as the return value                                        */
@@ -92,9 +102,10 @@ typedef struct lrsdp_info {
   int outer_iters;       /* refinement steps (0 when dd_mode resolved to OFF)               */
   int dd_used;           /* 1 if the answer is the pair y + y_lo                            */
   double relres;         /* final relative residual: recursive (OFF) or double-double true  */
-  double tau;            /* lambda_min(W)                                                   */
+  double tau;            /* the shift tau of the factor (see LRSDP_TAU_*)                  */
   double setup_ms;       /* time of the factor this solve used (Alg. 1 steps 1-2)           */
   double solve_ms;       /* wall time of this call                                          */
+  int eig_sweeps;        /* subspace-iteration sweeps of the factor (0: Householder path)   */
 } lrsdp_info;
 
 /* Fills *o with the defaults listed above.  o: host. */
@@ -151,8 +162,8 @@ LRSDP_API int lrsdp_hessian_apply(lrsdp_problem* p, const double* W, const doubl
 
 /* ------------------------------------------------------------------ A1-A4: setup */
 /* Algorithm 1 steps 1-2 for scaling matrix W (n x n symmetric positive definite, device,
- * copied) and rank k (1 <= k < n): eigendecomposition of W (lambda_min and the k largest
- * pairs), tau = lambda_min(W), U = V_l (Lambda_l - tau)^{1/2}, W0 = W - U U^T, Z = chol(2 W0
+ * copied) and rank k (1 <= k <= 16, k < n, n <= 4096 on the Householder path): the k largest
+ * eigenpairs of W and tau (opts->tau_rule), U = V_l (Lambda_l - tau)^{1/2}, W0 = W - U U^T, Z = chol(2 W0
  * + U U^T) (eqs Wsplit1, Wsplit2, hessExp2), bold S = tau^2 I + bold U^T (A^T A)^{-1} bold U
  * (eq SMW2), its deflation (opts->deflate) and Cholesky factor L, kept as the explicit
  * inverse bold S^{-1} = L^{-T} L^{-1}.  opts may be NULL (defaults).  Errors: INVALID_ARG,
@@ -162,7 +173,7 @@ LRSDP_API int lrsdp_factor_create(lrsdp_problem* p, const double* W, int32_t k, 
 LRSDP_API void lrsdp_factor_destroy(lrsdp_factor* f);
 
 /* Export of the setup results for parity checks.  Host outputs: tau, shift (the deflation
- * shift, 0 if none), lam[k + 1] = {lambda_min(W), then the k largest eigenvalues ascending},
+ * shift, 0 if none), lam[k + 1] = {tau, then the k largest eigenvalues ascending},
  * setup_ms.  Device outputs (each may be NULL): U (n x k), W0 (n x n), Z (n x n, lower, zero
  * above the diagonal), Sinv (nk x nk, full symmetric, nk index p + n j). */
 LRSDP_API int lrsdp_factor_export(const lrsdp_factor* f, double* tau, double* shift, double* lam,

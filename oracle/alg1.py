@@ -48,11 +48,21 @@ class Split:
     Z: np.ndarray          # n x n lower triangular, Z Z^T = 2 W0 + U U^T
 
 
-def formation(W, k):
-    """Algorithm 1 step 1 (eqs Wsplit1, Wsplit2, hessExp2)."""
+def formation(W, k, tau_rule="min"):
+    """Algorithm 1 step 1 (eqs Wsplit1, Wsplit2, hessExp2).
+
+    tau_rule "min": tau = lambda_min(W), as Algorithm 1 step 1a prints it.
+    tau_rule "mean": tau = the mean of the n - k smallest eigenvalues, i.e.
+    (tr W - sum of the k largest) / (n - k); Section 3.1 allows any tau with
+    lambda_min(Lambda_s) <= tau < lambda_max(Lambda_s), and the mean lies in that range."""
     n = W.shape[0]
     lam, V = np.linalg.eigh(W)
-    tau = float(lam[0])
+    if tau_rule == "min":
+        tau = float(lam[0])
+    elif tau_rule == "mean":
+        tau = float((np.trace(W) - lam[n - k:].sum()) / (n - k))
+    else:
+        raise ValueError(tau_rule)
     V_l = V[:, n - k:]
     lam_l = lam[n - k:]
     U = V_l * np.sqrt(lam_l - tau)[None, :]
@@ -202,9 +212,9 @@ class Factor:
         return self.split.tau
 
 
-def factor(C: Constraints, W, k, deflate=True, explicit=None):
+def factor(C: Constraints, W, k, deflate=True, explicit=None, tau_rule="min"):
     """Algorithm 1 steps 1 and 2."""
-    spl = formation(W, k)
+    spl = formation(W, k, tau_rule=tau_rule)
     if explicit is None:
         explicit = C.m * C.n * k <= 4_000_000
     bU = None

@@ -32,19 +32,20 @@ LRSDP_ERR_EIG = -11
 
 LRSDP_PREC_FP64, LRSDP_PREC_FP32, LRSDP_PREC_BF16 = 0, 1, 2
 LRSDP_DD_OFF, LRSDP_DD_ON, LRSDP_DD_AUTO = 0, 1, 2
+LRSDP_TAU_MIN, LRSDP_TAU_MEAN = 0, 1
 
 
 class lrsdp_opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int),
                 ("dd_mode", C.c_int), ("deflate", C.c_int), ("max_outer", C.c_int),
                 ("inner_eps", C.c_double), ("dd_auto_ratio", C.c_double),
-                ("dd_precond", C.c_int)]
+                ("dd_precond", C.c_int), ("tau_rule", C.c_int)]
 
 
 class lrsdp_info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("outer_iters", C.c_int),
                 ("dd_used", C.c_int), ("relres", C.c_double), ("tau", C.c_double),
-                ("setup_ms", C.c_double), ("solve_ms", C.c_double)]
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("eig_sweeps", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -95,7 +95,8 @@ struct DeviceGuard {
 bool opts_valid(const lrsdp_opts& o) {
   return o.eps > 0.0 && o.max_iter >= 1 && o.precision >= 0 && o.precision <= 2 &&
          o.dd_mode >= 0 && o.dd_mode <= 2 && o.max_outer >= 0 && o.inner_eps > 0.0 &&
-         o.inner_eps < 1.0 && o.dd_precond >= 0 && o.dd_precond <= 2;
+         o.inner_eps < 1.0 && o.dd_precond >= 0 && o.dd_precond <= 2 && o.tau_rule >= 0 &&
+         o.tau_rule <= 1;
 }
 
 }  // namespace
@@ -113,6 +114,7 @@ void lrsdp_opts_default(lrsdp_opts* o) {
   o->inner_eps = 1e-3;
   o->dd_auto_ratio = 2e-5;
   o->dd_precond = 2;
+  o->tau_rule = LRSDP_TAU_MEAN;
 }
 
 const char* lrsdp_status_string(int s) {

@@ -292,11 +292,16 @@ __global__ void k_Qc_dd(int N, int r, double shift, const double* Q, const doubl
   sl[i] = u.lo;
 }
 
+}  // namespace
+
 int rows_k(int n, int k, const double* A, int range, const double* X, double* out,
            hipStream_t s) {
   k_rows_k<<<(n + 3) / 4, kT, 0, s>>>(n, k, A, range, X, out);
   return LRSDP_OK;
 }
+
+namespace {
+
 int rows_k_dd(int n, int k, const double* A, int range, const double* Xh, const double* Xl,
               double* oh, double* ol, hipStream_t s) {
   k_rows_k_dd<<<(n + 3) / 4, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol);

@@ -23,6 +23,14 @@ namespace {
 
 constexpr int kT = 256;
 
+// lam[0] <- (tr W - sum of the k largest) / (n - k), tr W a double-double pair.
+__global__ void k_tau_mean(int n, int k, const double* tr, double* lam) {
+  if (threadIdx.x != 0) return;
+  double top = 0.0;
+  for (int i = 0; i < k; ++i) top += lam[1 + i];
+  lam[0] = ((tr[0] - top) + tr[1]) / (double)(n - k);
+}
+
 __global__ void k_make_U(int n, int k, const double* lam, const double* Vl, double* U) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * k) return;
@@ -247,12 +255,34 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
 
   LRSDP_HIP(hipMemcpyAsync(f->W, W, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
 
-  // ---- 1a: partial eigendecomposition (temporary workspace)
-  void* ews = nullptr;
-  const size_t ewb = eig_workspace_bytes(n, k);
-  LRSDP_TRY(dev_alloc(ctx, &ews, ewb));
+  // ---- 1a: the k largest eigenpairs and tau (temporary workspace).  lam_dev[0] = tau.
   double* Vl = f->U;  // eigenvectors land in U's buffer, scaled in place below
-  int rc = eig_top_and_min(f->W, n, k, ews, f->lam_dev, Vl, s);
+  int rc = LRSDP_ERR_EIG;
+  f->eig_sweeps = 0;
+  if (o.tau_rule == LRSDP_TAU_MEAN) {
+    void* sws = nullptr;
+    const size_t swb = spectral_workspace_bytes(n, k);
+    LRSDP_TRY(dev_alloc(ctx, &sws, swb));
+    int sweeps = 0;
+    rc = spectral_top(f->W, n, k, sws, f->lam_dev, Vl, nullptr, 40, nullptr, &sweeps, s);
+    (void)hipStreamSynchronize(s);
+    dev_free(ctx, sws, swb);
+    if (rc == LRSDP_OK) f->eig_sweeps = sweeps;
+    else if (rc != LRSDP_ERR_EIG) return rc;
+  }
+  if (rc != LRSDP_OK) {  // Householder path: exact lambda_min and the k largest pairs
+    void* ews = nullptr;
+    const size_t ewb = eig_workspace_bytes(n, k);
+    LRSDP_TRY(dev_alloc(ctx, &ews, ewb));
+    rc = eig_top_and_min(f->W, n, k, ews, f->lam_dev, Vl, s);
+    if (rc == LRSDP_OK && o.tau_rule == LRSDP_TAU_MEAN) {
+      double* tr = static_cast<double*>(ews);  // eigensolver scratch no longer needed
+      rc = trace_dd(f->W, n, tr, s);
+      if (rc == LRSDP_OK) k_tau_mean<<<1, 64, 0, s>>>(n, k, tr, f->lam_dev);
+    }
+    (void)hipStreamSynchronize(s);
+    dev_free(ctx, ews, ewb);
+  }
   if (rc == LRSDP_OK) {
     f->lam.assign(k + 1, 0.0);
     if (hipMemcpyAsync(f->lam.data(), f->lam_dev, (k + 1) * sizeof(double),
@@ -260,7 +290,6 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
         hipStreamSynchronize(s) != hipSuccess)
       rc = LRSDP_ERR_DEVICE;
   }
-  dev_free(ctx, ews, ewb);
   LRSDP_TRY(rc);
   f->tau = f->lam[0];
   for (double v : f->lam)

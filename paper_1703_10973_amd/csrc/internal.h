@@ -112,7 +112,8 @@ struct lrsdp_factor {
   lrsdp_problem* P = nullptr;
   int n = 0, k = 0, nk = 0, r = 0;   // r = k(k-1)/2 deflation directions kept
   double tau = 0.0, tau2 = 0.0, shift = 0.0, setup_ms = 0.0;
-  std::vector<double> lam;           // host copy: lambda_min, then the k largest ascending
+  int eig_sweeps = 0;                // subspace-iteration sweeps (0: Householder path)
+  std::vector<double> lam;           // host copy: tau, then the k largest ascending
   double* lam_dev = nullptr;         // k + 1
   double* W = nullptr;               // n x n, copy of the caller's W
   double* W0 = nullptr;              // n x n, W - U U^T rounded once from double-double
@@ -150,6 +151,10 @@ Work work_view(const lrsdp_factor* f);
 size_t work_doubles(int n, int m, int k);
 
 // ---------------------------------------------------------------- apply.hip
+// out[j][p] = sum_{q in range(p)} A[p][q] X[j][q], X and out k x n (k <= 16);
+// range 0 full, 1 q <= p (lower), 2 q >= p (upper).  One wavefront per row of A.
+int rows_k(int n, int k, const double* A, int range, const double* X, double* out,
+           hipStream_t s);
 int precond_apply_f64(const lrsdp_factor* f, const double* v, double* z, hipStream_t s,
                       int refine);
 int precond_apply_dd(const lrsdp_factor* f, const double* v, double* z, hipStream_t s,

@@ -197,6 +197,7 @@ int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lr
   lrsdp_info inf{};
   inf.tau = f->tau;
   inf.setup_ms = f->setup_ms;
+  inf.eig_sweeps = f->eig_sweeps;
 
   bool use_dd;
   if (o.dd_mode == LRSDP_DD_ON) use_dd = true;

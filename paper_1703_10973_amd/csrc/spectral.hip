@@ -1,0 +1,303 @@
+// Step A1, GEMM-based: the k largest eigenpairs of W by subspace iteration with
+// Rayleigh-Ritz, and tau from the trace.
+//
+// Algorithm 1 step 1a only consumes tau and (V_l, Lambda_l).  Section 3.1 allows any tau
+// with lambda_min(Lambda_s) <= tau < lambda_max(Lambda_s); the mean of the n - k smallest
+// eigenvalues, (tr W - sum Lambda_l) / (n - k), lies in that range, leaves kappa(W0) (and
+// so the bound of Lemma Htilde) unchanged, and needs no small eigenvalue.  Near the end of
+// an interior-point run W has the Theta(1/mu) gap of Proposition Weig, so a block of
+// b = k vectors converges at the rate lambda_{k+1} / lambda_k = O(mu) per sweep, each sweep
+// one W-times-block product (W read once).  The block is not oversampled: W X for vectors
+// beyond the k dominant directions is O(mu) against O(1), which leaves the Gram matrix of
+// the Cholesky QR numerically singular at small mu.  Without a gap the iteration stalls
+// and the caller falls back to the Householder path (eig.hip).
+//
+// One sweep (basis X: b orthonormal rows of length n):
+//   T = X W;  B = X T^T;  B = Q Theta Q^T (Jacobi);  X <- Q^T X, T <- Q^T T  (Ritz pairs)
+//   residuals ||T_i - theta_i X_i|| of the k largest; stop once all are at the FP64
+//   rounding level of the product (64 u theta_max sqrt(n)), so the pairs are as accurate
+//   as a dense eigensolver's
+//   X <- orth(T) by Cholesky QR, twice, after row normalization.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "dense.h"
+#include "eig.h"
+
+namespace lrsdp {
+namespace {
+
+constexpr int BMAX = 16;
+
+// G[i][j] = X_i . Y_j, one wavefront per entry (b x b entries).
+__global__ __launch_bounds__(64) void k_gram(int b, int n, const double* X, const double* Y,
+                                             double* G) {
+  const int i = blockIdx.x / b, j = blockIdx.x % b, lane = threadIdx.x;
+  double s = 0.0;
+  for (int q = lane; q < n; q += 64) s = fma(X[(size_t)i * n + q], Y[(size_t)j * n + q], s);
+  s = wave_sum(s);
+  if (lane == 0) G[i * b + j] = s;
+}
+
+// Scale each row of T to unit length (one wavefront per row).
+__global__ __launch_bounds__(64) void k_row_normalize(int n, double* T) {
+  const int i = blockIdx.x, lane = threadIdx.x;
+  double* t = T + (size_t)i * n;
+  double s = 0.0;
+  for (int q = lane; q < n; q += 64) s = fma(t[q], t[q], s);
+  s = wave_sum(s);
+  const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+  for (int q = lane; q < n; q += 64) t[q] *= inv;
+}
+
+// X[i][q] = sum_{j <= i} Linv[i][j] T[j][q]   (Linv: 64 x 64 block, lower)
+__global__ void k_lower_apply(int b, int n, const double* Linv, const double* T, double* X) {
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (idx >= (size_t)b * n) return;
+  const int i = (int)(idx / n), q = (int)(idx - (size_t)i * n);
+  double s = 0.0;
+  for (int j = 0; j <= i; ++j) s = fma(Linv[i * 64 + j], T[(size_t)j * n + q], s);
+  X[idx] = s;
+}
+
+// out[i][q] = sum_j Q[j][i] X[j][q]  (rows of out are the Ritz vectors)
+__global__ void k_rotate(int b, int n, const double* Q, const double* X, double* out) {
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (idx >= (size_t)b * n) return;
+  const int i = (int)(idx / n), q = (int)(idx - (size_t)i * n);
+  double s = 0.0;
+  for (int j = 0; j < b; ++j) s = fma(Q[j * b + i], X[(size_t)j * n + q], s);
+  out[idx] = s;
+}
+
+// res[i] = ||T_i - theta_i X_i|| (one wavefront per row)
+__global__ __launch_bounds__(64) void k_ritz_residual(int n, const double* T, const double* X,
+                                                      const double* theta, double* res) {
+  const int i = blockIdx.x, lane = threadIdx.x;
+  const double th = theta[i];
+  double s = 0.0;
+  for (int q = lane; q < n; q += 64) {
+    const double r = T[(size_t)i * n + q] - th * X[(size_t)i * n + q];
+    s = fma(r, r, s);
+  }
+  s = wave_sum(s);
+  if (lane == 0) res[i] = sqrt(s);
+}
+
+// Cyclic Jacobi on the symmetric b x b matrix B (b <= 16): B = Q diag(theta) Q^T, theta
+// ascending.  One wavefront; lane j owns column j of the working copies.
+__global__ __launch_bounds__(64) void k_jacobi(int b, const double* Bin, double* Q,
+                                               double* theta) {
+  __shared__ double A[BMAX][BMAX + 1];
+  __shared__ double V[BMAX][BMAX + 1];
+  __shared__ double cs[2];
+  const int t = threadIdx.x;
+  for (int e = t; e < BMAX * BMAX; e += 64) {
+    const int r = e / BMAX, c = e % BMAX;
+    A[r][c] = (r < b && c < b) ? 0.5 * (Bin[r * b + c] + Bin[c * b + r]) : 0.0;
+    V[r][c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, nrm = 0.0;
+    for (int e = t; e < b * b; e += 64) {
+      const int r = e / b, c = e % b;
+      const double v = A[r][c] * A[r][c];
+      nrm += v;
+      if (r != c) off += v;
+    }
+    off = wave_sum(off);
+    nrm = wave_sum(nrm);
+    if (off <= 1e-32 * nrm) break;
+    for (int p = 0; p < b - 1; ++p)
+      for (int q = p + 1; q < b; ++q) {
+        if (t == 0) {
+          const double apq = A[p][q];
+          double c = 1.0, s = 0.0;
+          if (apq != 0.0) {
+            const double theta_r = (A[q][q] - A[p][p]) / (2.0 * apq);
+            const double tt = (theta_r >= 0.0 ? 1.0 : -1.0) /
+                              (fabs(theta_r) + sqrt(1.0 + theta_r * theta_r));
+            c = 1.0 / sqrt(1.0 + tt * tt);
+            s = tt * c;
+          }
+          cs[0] = c;
+          cs[1] = s;
+        }
+        __syncthreads();
+        const double c = cs[0], s = cs[1];
+        if (t < b) {  // columns p, q of A and V
+          const double ap = A[t][p], aq = A[t][q];
+          A[t][p] = c * ap - s * aq;
+          A[t][q] = s * ap + c * aq;
+          const double vp = V[t][p], vq = V[t][q];
+          V[t][p] = c * vp - s * vq;
+          V[t][q] = s * vp + c * vq;
+        }
+        __syncthreads();
+        if (t < b) {  // rows p, q of A
+          const double ap = A[p][t], aq = A[q][t];
+          A[p][t] = c * ap - s * aq;
+          A[q][t] = s * ap + c * aq;
+        }
+        __syncthreads();
+      }
+  }
+  if (t == 0) {  // ascending order (selection sort of the columns)
+    int ord[BMAX];
+    for (int i = 0; i < b; ++i) ord[i] = i;
+    for (int i = 0; i < b; ++i)
+      for (int j = i + 1; j < b; ++j)
+        if (A[ord[j]][ord[j]] < A[ord[i]][ord[i]]) {
+          const int tmp = ord[i];
+          ord[i] = ord[j];
+          ord[j] = tmp;
+        }
+    for (int i = 0; i < b; ++i) {
+      theta[i] = A[ord[i]][ord[i]];
+      for (int r = 0; r < b; ++r) Q[r * b + i] = V[r][ord[i]];
+    }
+  }
+}
+
+// Trace of W in double-double (one block).
+__global__ __launch_bounds__(256) void k_trace_dd(int n, const double* W, double* out) {
+  __shared__ double hs[256], ls[256];
+  dd s = {0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += 256) s = dd_add_d(s, W[(size_t)i * n + i]);
+  hs[threadIdx.x] = s.hi;
+  ls[threadIdx.x] = s.lo;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dd acc = {0.0, 0.0};
+    for (int i = 0; i < 256; ++i) acc = dd_add(acc, {hs[i], ls[i]});
+    out[0] = acc.hi;
+    out[1] = acc.lo;
+  }
+}
+
+// lam = {tau, the k largest Ritz values ascending}, tau = (tr W - sum of them) / (n - k).
+__global__ void k_ritz_pack(int b, int k, int n, const double* theta, const double* tr,
+                            double* lam) {
+  if (threadIdx.x != 0) return;
+  double top = 0.0;
+  for (int i = b - k; i < b; ++i) top += theta[i];
+  lam[0] = ((tr[0] - top) + tr[1]) / (double)(n - k);
+  for (int i = 0; i < k; ++i) lam[1 + i] = theta[b - k + i];
+}
+
+__global__ void k_clear_flag(int* flag) {
+  if (threadIdx.x == 0) *flag = 0;
+}
+
+// Deterministic pseudo-random start block (rows).
+__global__ void k_start_block(int b, int n, double* X) {
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (idx >= (size_t)b * n) return;
+  uint32_t st = 0x243F6A88u ^ (uint32_t)(idx * 0x9E3779B9u + 0x7F4A7C15u);
+  st ^= st << 13;
+  st ^= st >> 17;
+  st ^= st << 5;
+  X[idx] = (double)(st & 0xFFFFFF) / (double)0x1000000 - 0.5;
+}
+
+}  // namespace
+
+size_t spectral_workspace_bytes(int n, int k) {
+  const int b = std::min(k, n);
+  return (size_t)(3 * b * (size_t)n + 4 * 64 * 64 + 4 * b * b + 4 * b + 16) * sizeof(double) +
+         64;
+}
+
+int trace_dd(const double* W, int n, double* out, hipStream_t s) {
+  k_trace_dd<<<1, 256, 0, s>>>(n, W, out);
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
+
+int spectral_top(const double* W, int n, int k, void* ws, double* lam_out, double* Vl_out,
+                 double* tr_out, int max_sweeps, double* host_res, int* sweeps_out,
+                 hipStream_t s) {
+  const int b = k;
+  if (k < 1 || k > BMAX || k >= n) return LRSDP_ERR_INVALID_ARG;
+  double* X = static_cast<double*>(ws);
+  double* T = X + (size_t)b * n;
+  double* Y = T + (size_t)b * n;
+  double* G = Y + (size_t)b * n;     // b x b (also B)
+  double* Qm = G + 64 * 64;          // b x b
+  double* Dinv = Qm + 64 * 64;       // 64 x 64
+  double* theta = Dinv + 64 * 64;    // b
+  double* res = theta + 64;          // b
+  double* tr = res + 64;             // 2
+  int* flag = reinterpret_cast<int*>(tr + 4);
+  const size_t bn = (size_t)b * n;
+  const int eg = grid_for((int64_t)bn, 256);
+
+  k_trace_dd<<<1, 256, 0, s>>>(n, W, tr);
+  k_clear_flag<<<1, 64, 0, s>>>(flag);
+  k_start_block<<<eg, 256, 0, s>>>(b, n, T);
+  // X <- orth(rows of T): row normalization, then Cholesky QR twice (T -> Y -> X)
+  auto orthonormalize = [&]() -> int {
+    k_row_normalize<<<b, 64, 0, s>>>(n, T);
+    for (int pass = 0; pass < 2; ++pass) {
+      const double* src = pass == 0 ? T : Y;
+      k_gram<<<b * b, 64, 0, s>>>(b, n, src, src, G);
+      LRSDP_TRY(potrf(G, b, b, flag, Dinv, s));
+      k_lower_apply<<<eg, 256, 0, s>>>(b, n, Dinv, src, pass == 0 ? Y : X);
+    }
+    return LRSDP_OK;
+  };
+  LRSDP_TRY(orthonormalize());
+  double best = 1e300;
+  int sweeps = 0;
+  int status = LRSDP_ERR_EIG;
+  std::vector<double> h(133);
+  for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
+    LRSDP_TRY(rows_k(n, b, W, 0, X, T, s));                  // T = X W
+    k_gram<<<b * b, 64, 0, s>>>(b, n, X, T, G);              // B = X T^T
+    k_jacobi<<<1, 64, 0, s>>>(b, G, Qm, theta);
+    k_rotate<<<eg, 256, 0, s>>>(b, n, Qm, X, Y);             // Ritz vectors
+    k_rotate<<<eg, 256, 0, s>>>(b, n, Qm, T, X);             // their images under W
+    std::swap(X, Y);                                         // X: Ritz vectors, Y: W X
+    std::swap(Y, T);                                         // T: W X, Y: free
+    k_ritz_residual<<<b, 64, 0, s>>>(n, T, X, theta, res);
+    LRSDP_HIP(hipGetLastError());
+    // theta, res, tr and the factorization flag are contiguous: one copy per sweep
+    LRSDP_HIP(hipMemcpyAsync(h.data(), theta, 133 * sizeof(double), hipMemcpyDeviceToHost, s));
+    LRSDP_HIP(hipStreamSynchronize(s));
+    const double* th = h.data();
+    const double* rs = h.data() + 64;
+    const double* trw = h.data() + 128;
+    int hflag = 0;
+    std::memcpy(&hflag, h.data() + 132, sizeof(int));
+    double sum_top = 0.0, rmax = 0.0;
+    bool finite = hflag == 0;
+    for (int i = b - k; i < b; ++i) {
+      sum_top += th[i];
+      finite = finite && std::isfinite(th[i]) && std::isfinite(rs[i]);
+      rmax = std::max(rmax, rs[i]);
+    }
+    if (!finite) break;  // lost rank in the Cholesky QR: no usable gap
+    const double tau = ((trw[0] - sum_top) + trw[1]) / (double)(n - k);
+    const double floor = 64.0 * 2.220446049250313e-16 * th[b - 1] * std::sqrt((double)n);
+    if (host_res) *host_res = rmax;
+    if (tau > 0.0 && rmax <= floor) {
+      status = LRSDP_OK;
+      break;
+    }
+    if (rmax < 0.5 * best) best = rmax;
+    else if (sweeps > 6 && rmax > 0.9 * best) break;  // stalled: no usable gap
+    LRSDP_TRY(orthonormalize());
+  }
+  if (sweeps_out) *sweeps_out = sweeps;
+  if (status != LRSDP_OK) return status;
+  // lam_out = {tau, top-k ascending}; Vl_out = the k top Ritz vectors (rows)
+  k_ritz_pack<<<1, 64, 0, s>>>(b, k, n, theta, tr, lam_out);
+  LRSDP_HIP(hipMemcpyAsync(Vl_out, X + (size_t)(b - k) * n, (size_t)k * n * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  if (tr_out) LRSDP_HIP(hipMemcpyAsync(tr_out, tr, 2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return LRSDP_OK;
+}
+
+}  // namespace lrsdp

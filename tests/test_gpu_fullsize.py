@@ -50,11 +50,19 @@ def test_full_size_solve_meets_target(problem, mode, mu):
     F.close()
 
 
-def test_full_size_tau_and_top_eigenvalues(problem):
+@pytest.mark.parametrize("rule", ["min", "mean"])
+def test_full_size_tau_and_top_eigenvalues(problem, rule):
     inst = make_instance(1000, 5, 20000, 1e-6, seed=2001)
-    F = pk.Factor(problem, to_dev(inst.W), inst.k)
-    ex = F.export()
+    F = pk.Factor(problem, to_dev(inst.W), inst.k,
+                  pk.opts(tau_rule={"min": 0, "mean": 1}[rule]))
+    ex = F.export(U=True)
     lam = np.linalg.eigvalsh(inst.W)
-    assert abs(ex["tau"] - lam[0]) <= 1e-13 * lam[-1] * np.sqrt(1000)
+    tau = lam[0] if rule == "min" else (np.trace(inst.W) - lam[-5:].sum()) / 995
+    assert abs(ex["tau"] - tau) <= 1e-12 * tau + 1e-15 * lam[-1] * np.sqrt(1000)
     np.testing.assert_allclose(ex["lam"][1:], lam[-5:], rtol=1e-12)
+    # the rows of U span the top invariant subspace: ||W u - u (lam + ...)|| small
+    U = host(ex["U"])                                     # k x n
+    V = U / np.linalg.norm(U, axis=1, keepdims=True)
+    R = V @ inst.W - np.asarray(ex["lam"])[1:, None] * V
+    assert np.max(np.linalg.norm(R, axis=1)) <= 1e-11 * lam[-1]
     F.close()

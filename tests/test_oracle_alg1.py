@@ -179,3 +179,27 @@ def test_fp64_solve_matches_dense_cholesky(mu):
     assert np.linalg.norm(out.y - ystar) <= 1e-6 * np.linalg.norm(ystar)
     rel, _ = dd.true_relative_residual(inst.W, inst.a, inst.b, inst.val, inst.r, out.y)
     assert rel <= 1e-8
+
+
+@pytest.mark.parametrize("mu", [1e-2, 1e-4])
+def test_mean_tau_rule(mu):
+    """tau = mean of the n - k smallest eigenvalues lies in the range Section 3.1 allows, gives
+    the same kappa(W0) (so Lemma Htilde's bound), keeps H~ SPD, and PCG still converges to the
+    same solution (the preconditioner does not change y*)."""
+    inst, C = setup(k=3, mu=mu)
+    lam = np.linalg.eigvalsh(inst.W)
+    n, k = inst.n, inst.k
+    s_min = alg1.formation(inst.W, k, "min")
+    s_mean = alg1.formation(inst.W, k, "mean")
+    assert lam[0] <= s_mean.tau < lam[n - k - 1]
+    np.testing.assert_allclose(s_mean.tau, lam[: n - k].mean(), rtol=1e-9)
+    l0 = np.linalg.eigvalsh(s_mean.W0)
+    l1 = np.linalg.eigvalsh(s_min.W0)
+    np.testing.assert_allclose(l0[-1] / l0[0], l1[-1] / l1[0], rtol=1e-6)
+    F = alg1.factor(C, inst.W, k, tau_rule="mean")
+    H = hs.hessian_dense(inst.W, inst.a, inst.b, inst.val)
+    g = sla.eigh(H, alg1.precond_dense(F), eigvals_only=True)
+    assert g[0] > 0 and g[-1] / g[0] <= (l0[-1] / l0[0]) ** 2 * (1 + 1e-8)
+    out = alg1.solve(F, inst.r, eps=1e-10, Hmul=lambda v: H @ v)
+    ref = alg1.solve(alg1.factor(C, inst.W, k), inst.r, eps=1e-10, Hmul=lambda v: H @ v)
+    assert np.linalg.norm(out.y - ref.y) <= 1e-6 * np.linalg.norm(ref.y)

@@ -335,7 +335,7 @@ int lrsdp_factor_export(const lrsdp_factor* f, double* tau, double* shift, doubl
   if (U) LRSDP_HIP(hipMemcpyAsync(U, f->U, nk * 8, hipMemcpyDeviceToDevice, s));
   if (W0) LRSDP_HIP(hipMemcpyAsync(W0, f->W0, nn * 8, hipMemcpyDeviceToDevice, s));
   if (Z) LRSDP_HIP(hipMemcpyAsync(Z, f->Z, nn * 8, hipMemcpyDeviceToDevice, s));
-  if (Sinv) LRSDP_HIP(hipMemcpyAsync(Sinv, f->Sinv, nk * nk * 8, hipMemcpyDeviceToDevice, s));
+  if (Sinv) LRSDP_TRY(export_sinv(f, Sinv, s));
   LRSDP_HIP(hipStreamSynchronize(s));
   return LRSDP_OK;
 }

@@ -43,63 +43,111 @@ __global__ void k_mval_dd(int nnz, const int32_t* src, const double* val, const 
 }
 
 // ---------------------------------------------------------------- M U (sparse x n x k)
-__global__ void k_spmm_U(int n, int k, const int32_t* rowptr, const int32_t* colidx,
-                         const double* mval, const double* U, double* out) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+// out[j][p] = sum_{e in row p} mval[e] U[j][col e].  Sixteen lanes share a row (fixed
+// lane-to-entry map, then an xor-shuffle tree), so the summation order is fixed.
+constexpr int kRL = 16;
+
+__global__ __launch_bounds__(kT) void k_spmm_U(int n, int k, const int32_t* __restrict__ rowptr,
+                                               const int32_t* __restrict__ colidx,
+                                               const double* __restrict__ mval,
+                                               const double* __restrict__ U,
+                                               double* __restrict__ out) {
+  const int p = blockIdx.x * (kT / kRL) + threadIdx.x / kRL;
+  const int sub = threadIdx.x & (kRL - 1);
+  const bool live = p < n;
   double acc[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
-  for (int e = rowptr[p]; e < rowptr[p + 1]; ++e) {
-    const int q = colidx[e];
-    const double mv = mval[e];
+  if (live) {
+    const int hi = rowptr[p + 1];
+    for (int e = rowptr[p] + sub; e < hi; e += kRL) {
+      const int q = colidx[e];
+      const double mv = mval[e];
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < k) acc[j] = fma(mv, U[(size_t)j * n + q], acc[j]);
+      for (int j = 0; j < KMAX; ++j)
+        if (j < k) acc[j] = fma(mv, U[(size_t)j * n + q], acc[j]);
+    }
   }
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j)
-    if (j < k) out[(size_t)j * n + p] = acc[j];
+  for (int j = 0; j < KMAX; ++j) {
+    if (j < k) {
+      double v = acc[j];
+#pragma unroll
+      for (int o = kRL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kRL);
+      if (live && sub == 0) out[(size_t)j * n + p] = v;
+    }
+  }
 }
 
-__global__ void k_spmm_U_dd(int n, int k, const int32_t* rowptr, const int32_t* colidx,
-                            const double* mh, const double* ml, const double* U, double* oh,
-                            double* ol) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n) return;
+__global__ __launch_bounds__(kT) void k_spmm_U_dd(int n, int k,
+                                                  const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colidx,
+                                                  const double* __restrict__ mh,
+                                                  const double* __restrict__ ml,
+                                                  const double* __restrict__ U,
+                                                  double* __restrict__ oh,
+                                                  double* __restrict__ ol) {
+  const int p = blockIdx.x * (kT / kRL) + threadIdx.x / kRL;
+  const int sub = threadIdx.x & (kRL - 1);
+  const bool live = p < n;
   dd acc[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) acc[j] = {0.0, 0.0};
-  for (int e = rowptr[p]; e < rowptr[p + 1]; ++e) {
-    const int q = colidx[e];
-    const double h = mh[e], l = ml[e];
+  if (live) {
+    const int hi = rowptr[p + 1];
+    for (int e = rowptr[p] + sub; e < hi; e += kRL) {
+      const int q = colidx[e];
+      const double h = mh[e], l = ml[e];
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < k) acc[j] = dd_fma2(acc[j], U[(size_t)j * n + q], h, l);
+      for (int j = 0; j < KMAX; ++j)
+        if (j < k) acc[j] = dd_fma2(acc[j], U[(size_t)j * n + q], h, l);
+    }
   }
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j)
+  for (int j = 0; j < KMAX; ++j) {
     if (j < k) {
-      oh[(size_t)j * n + p] = acc[j].hi;
-      ol[(size_t)j * n + p] = acc[j].lo;
+      dd v = acc[j];
+#pragma unroll
+      for (int o = kRL / 2; o > 0; o >>= 1)
+        v = dd_add(v, {__shfl_xor(v.hi, o, kRL), __shfl_xor(v.lo, o, kRL)});
+      if (live && sub == 0) {
+        oh[(size_t)j * n + p] = v.hi;
+        ol[(size_t)j * n + p] = v.lo;
+      }
     }
+  }
+}
+
+int spmm_U(const lrsdp_problem* P, int k, const double* U, double* out, hipStream_t s) {
+  k_spmm_U<<<(P->n + kT / kRL - 1) / (kT / kRL), kT, 0, s>>>(P->n, k, P->rowptr, P->colidx,
+                                                              P->mval, U, out);
+  return LRSDP_OK;
+}
+int spmm_U_dd(const lrsdp_problem* P, int k, const double* ml, const double* U, double* oh,
+              double* ol, hipStream_t s) {
+  k_spmm_U_dd<<<(P->n + kT / kRL - 1) / (kT / kRL), kT, 0, s>>>(P->n, k, P->rowptr, P->colidx,
+                                                                 P->mval, ml, U, oh, ol);
+  return LRSDP_OK;
 }
 
 // ---------------------------------------------------------------- dense n x n times n x k
 // out[j][p] = sum_{q in range(p)} A[p][q] X[j][q]; range: 0 full, 1 q <= p, 2 q >= p.
+// One workgroup per row p: its four wavefronts split the row, every load of a thread is in
+// flight at once, and the partial sums meet in a fixed order.
 __global__ __launch_bounds__(kT) void k_rows_k(int n, int k, const double* __restrict__ A,
                                                int range, const double* __restrict__ X,
                                                double* __restrict__ out) {
-  const int lane = threadIdx.x & 63;
-  const int p = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
-  if (p >= n) return;
+  __shared__ double red[kT / kWave][KMAX];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const int lane = t & (kWave - 1), wid = t / kWave;
   const int qlo = (range == 2) ? p : 0;
   const int qhi = (range == 1) ? p + 1 : n;
   const double* a = A + (size_t)p * n;
   double acc[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
-  for (int q = qlo + lane; q < qhi; q += 64) {
+#pragma unroll 4
+  for (int q = qlo + t; q < qhi; q += kT) {
     const double av = a[q];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j)
@@ -108,9 +156,11 @@ __global__ __launch_bounds__(kT) void k_rows_k(int n, int k, const double* __res
 #pragma unroll
   for (int j = 0; j < KMAX; ++j)
     if (j < k) {
-      const double s = wave_sum(acc[j]);
-      if (lane == 0) out[(size_t)j * n + p] = s;
+      const double v = wave_sum(acc[j]);
+      if (lane == 0) red[wid][j] = v;
     }
+  __syncthreads();
+  if (t < k) out[(size_t)t * n + p] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
 }
 
 __global__ __launch_bounds__(kT) void k_rows_k_dd(int n, int k, const double* __restrict__ A,
@@ -118,30 +168,40 @@ __global__ __launch_bounds__(kT) void k_rows_k_dd(int n, int k, const double* __
                                                   const double* __restrict__ Xl,
                                                   double* __restrict__ oh,
                                                   double* __restrict__ ol) {
-  const int lane = threadIdx.x & 63;
-  const int p = blockIdx.x * (kT / 64) + (threadIdx.x >> 6);
-  if (p >= n) return;
+  __shared__ double red[kT / kWave][KMAX][2];
+  const int p = blockIdx.x, t = threadIdx.x;
+  const int lane = t & (kWave - 1), wid = t / kWave;
   const int qlo = (range == 2) ? p : 0;
   const int qhi = (range == 1) ? p + 1 : n;
   const double* a = A + (size_t)p * n;
   dd acc[KMAX];
 #pragma unroll
   for (int j = 0; j < KMAX; ++j) acc[j] = {0.0, 0.0};
-  for (int q = qlo + lane; q < qhi; q += 64) {
+#pragma unroll 2
+  for (int q = qlo + t; q < qhi; q += kT) {
     const double av = a[q];
 #pragma unroll
     for (int j = 0; j < KMAX; ++j)
-      if (j < k) acc[j] = dd_fma2(acc[j], av, Xh[(size_t)j * n + q], Xl ? Xl[(size_t)j * n + q] : 0.0);
+      if (j < k)
+        acc[j] = dd_fma2(acc[j], av, Xh[(size_t)j * n + q], Xl ? Xl[(size_t)j * n + q] : 0.0);
   }
 #pragma unroll
   for (int j = 0; j < KMAX; ++j)
     if (j < k) {
-      const dd s = wave_sum_dd(acc[j]);
+      const dd v = wave_sum_dd(acc[j]);
       if (lane == 0) {
-        oh[(size_t)j * n + p] = s.hi;
-        ol[(size_t)j * n + p] = s.lo;
+        red[wid][j][0] = v.hi;
+        red[wid][j][1] = v.lo;
       }
     }
+  __syncthreads();
+  if (t < k) {
+    dd u = dd_add({red[0][t][0], red[0][t][1]}, {red[1][t][0], red[1][t][1]});
+    const dd w = dd_add({red[2][t][0], red[2][t][1]}, {red[3][t][0], red[3][t][1]});
+    u = dd_add(u, w);
+    oh[(size_t)t * n + p] = u.hi;
+    ol[(size_t)t * n + p] = u.lo;
+  }
 }
 
 // ---------------------------------------------------------------- sampled products
@@ -196,16 +256,16 @@ __global__ void k_scale_dd(int m, const double* ginv, double* yh, double* yl) {
   yl[i] = u.lo;
 }
 
-// K = U^T P (k x k) in double-double, then symmetrized and rounded: one wave per (j, l).
-__global__ __launch_bounds__(64) void k_UtP(int n, int k, const double* U, const double* Ph,
+// K = U^T P (k x k) in double-double, then symmetrized and rounded: one workgroup per (j, l).
+__global__ __launch_bounds__(kT) void k_UtP(int n, int k, const double* U, const double* Ph,
                                             const double* Pl, double* Kdd) {
+  __shared__ double scr[2 * kT / kWave];
   const int j = blockIdx.x / k, l = blockIdx.x % k;
-  const int lane = threadIdx.x;
   dd s = {0.0, 0.0};
-  for (int p = lane; p < n; p += 64)
+  for (int p = threadIdx.x; p < n; p += kT)
     s = dd_fma2(s, U[(size_t)j * n + p], Ph[(size_t)l * n + p], Pl[(size_t)l * n + p]);
-  s = wave_sum_dd(s);
-  if (lane == 0) {
+  s = block_sum_dd(s, scr);
+  if (threadIdx.x == 0) {
     Kdd[2 * (j * k + l)] = s.hi;
     Kdd[2 * (j * k + l) + 1] = s.lo;
   }
@@ -267,14 +327,15 @@ __global__ void k_dd_axpy_const(int N, double c, const double* th, const double*
   sh[i] = u.hi;
   sl[i] = u.lo;
 }
-// c = Q^T t  (r values, double-double), one wave per column of Q (nk x r row-major)
-__global__ __launch_bounds__(64) void k_Qt_dd(int N, int r, const double* Q, const double* th,
+// c = Q^T t  (r values, double-double), one workgroup per column of Q (nk x r row-major)
+__global__ __launch_bounds__(kT) void k_Qt_dd(int N, int r, const double* Q, const double* th,
                                               const double* tl, double* c) {
-  const int col = blockIdx.x, lane = threadIdx.x;
+  __shared__ double scr[2 * kT / kWave];
+  const int col = blockIdx.x;
   dd s = {0.0, 0.0};
-  for (int i = lane; i < N; i += 64) s = dd_fma2(s, Q[(size_t)i * r + col], th[i], tl[i]);
-  s = wave_sum_dd(s);
-  if (lane == 0) {
+  for (int i = threadIdx.x; i < N; i += kT) s = dd_fma2(s, Q[(size_t)i * r + col], th[i], tl[i]);
+  s = block_sum_dd(s, scr);
+  if (threadIdx.x == 0) {
     c[2 * col] = s.hi;
     c[2 * col + 1] = s.lo;
   }
@@ -296,7 +357,7 @@ __global__ void k_Qc_dd(int N, int r, double shift, const double* Q, const doubl
 
 int rows_k(int n, int k, const double* A, int range, const double* X, double* out,
            hipStream_t s) {
-  k_rows_k<<<(n + 3) / 4, kT, 0, s>>>(n, k, A, range, X, out);
+  k_rows_k<<<n, kT, 0, s>>>(n, k, A, range, X, out);
   return LRSDP_OK;
 }
 
@@ -304,7 +365,7 @@ namespace {
 
 int rows_k_dd(int n, int k, const double* A, int range, const double* Xh, const double* Xl,
               double* oh, double* ol, hipStream_t s) {
-  k_rows_k_dd<<<(n + 3) / 4, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol);
+  k_rows_k_dd<<<n, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol);
   return LRSDP_OK;
 }
 
@@ -321,13 +382,12 @@ int schur_apply_dd(const lrsdp_factor* f, const double* th, const double* tl, do
   // c. mat(A G^{-1} y) (dd)   d. P = M U (dd)   e. s = Z^T P (dd)
   k_mval_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, P->ginv, w.t0, w.t1,
                                                    P->mval, P->vec_scratch);
-  k_spmm_U_dd<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, P->mval,
-                                               P->vec_scratch, f->U, w.y, w.yl);
+  spmm_U_dd(P, k, P->vec_scratch, f->U, w.y, w.yl, s);
   rows_k_dd(n, k, f->Zt, 2, w.y, w.yl, sh, sl, s);
   // f. + tau^2 t + shift Q (Q^T t)
   k_dd_axpy_const<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->tau2, th, tl, sh, sl);
   if (f->r) {
-    k_Qt_dd<<<f->r, 64, 0, s>>>(nk, f->r, f->QN, th, tl, w.kk);
+    k_Qt_dd<<<f->r, kT, 0, s>>>(nk, f->r, f->QN, th, tl, w.kk);
     k_Qc_dd<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->r, f->shift, f->QN, w.kk, sh, sl);
   }
   LRSDP_HIP(hipGetLastError());
@@ -362,13 +422,14 @@ __global__ void k_add(int N, double* t, const double* d) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < N) t[i] += d[i];
 }
-__global__ __launch_bounds__(64) void k_Qt(int N, int r, const double* Q, const double* t,
+__global__ __launch_bounds__(kT) void k_Qt(int N, int r, const double* Q, const double* t,
                                            double* c) {
-  const int col = blockIdx.x, lane = threadIdx.x;
+  __shared__ double scr[kT / kWave];
+  const int col = blockIdx.x;
   double s = 0.0;
-  for (int i = lane; i < N; i += 64) s = fma(Q[(size_t)i * r + col], t[i], s);
-  s = wave_sum(s);
-  if (lane == 0) c[col] = s;
+  for (int i = threadIdx.x; i < N; i += kT) s = fma(Q[(size_t)i * r + col], t[i], s);
+  s = block_sum(s, scr);
+  if (threadIdx.x == 0) c[col] = s;
 }
 __global__ void k_Qc(int N, int r, double shift, const double* Q, const double* c, double* s) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -387,11 +448,11 @@ int schur_apply_f64(const lrsdp_factor* f, const double* t, double* sout, hipStr
   k_sampled_f64<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, P->ginv, w.y,
                                                   f->U, w.t0);             // G^{-1} bold U t
   k_mval<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, nullptr, w.t0, P->mval);
-  k_spmm_U<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, P->mval, f->U, w.y);
+  spmm_U(P, k, f->U, w.y, s);
   rows_k(n, k, f->Zt, 2, w.y, sout, s);                                    // Z^T M U
   k_axpy<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->tau2, t, sout);
   if (f->r) {
-    k_Qt<<<f->r, 64, 0, s>>>(nk, f->r, f->QN, t, w.kk);
+    k_Qt<<<f->r, kT, 0, s>>>(nk, f->r, f->QN, t, w.kk);
     k_Qc<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->r, f->shift, f->QN, w.kk, sout);
   }
   LRSDP_HIP(hipGetLastError());
@@ -411,13 +472,13 @@ int precond_apply_f64(const lrsdp_factor* f, const double* v, double* z, hipStre
   const int n = f->n, k = f->k, m = P->m, nk = f->nk;
   if (k > KMAX) return LRSDP_ERR_INVALID_ARG;
   k_mval<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, P->ginv, v, P->mval);
-  k_spmm_U<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, P->mval, f->U, w.y);
+  spmm_U(P, k, f->U, w.y, s);
   rows_k(n, k, f->Zt, 2, w.y, w.w, s);                    // w = vec(Z^T M U)
-  LRSDP_TRY(gemv(f->Sinv, nk, nk, w.w, w.t, s));           // t = bold S^{-1} w
+  LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.w, w.h, w.t, s));  // t = bold S^{-1} w
   if (refine) {
     LRSDP_TRY(schur_apply_f64(f, w.t, w.s, s));
     k_sub<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.s, w.g0);
-    LRSDP_TRY(gemv(f->Sinv, nk, nk, w.g0, w.g1, s));
+    LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.g0, w.h, w.g1, s));
     k_add<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.t, w.g1);
   }
   rows_k(n, k, f->Z, 1, w.t, w.y, s);                      // Y = Z T
@@ -436,17 +497,16 @@ int precond_apply_dd(const lrsdp_factor* f, const double* v, double* z, hipStrea
   // w = bold U^T G^{-1} v in double-double
   k_mval_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, P->ginv, v, nullptr,
                                                    P->mval, P->vec_scratch);
-  k_spmm_U_dd<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, P->mval,
-                                               P->vec_scratch, f->U, w.y, w.yl);
+  spmm_U_dd(P, k, P->vec_scratch, f->U, w.y, w.yl, s);
   rows_k_dd(n, k, f->Zt, 2, w.y, w.yl, w.w, w.wl, s);
   // t = bold S^{-1} w: FP64 inverse, refined against the matrix-free bold S in double-double
   k_dd_combine<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.wl, w.g0);
-  LRSDP_TRY(gemv(f->Sinv, nk, nk, w.g0, w.t, s));
+  LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.g0, w.h, w.t, s));
   LRSDP_HIP(hipMemsetAsync(w.tl, 0, (size_t)nk * sizeof(double), s));
   for (int it = 0; it < nref; ++it) {
     LRSDP_TRY(schur_apply_dd(f, w.t, w.tl, w.s, w.sl, s));
     k_dd_sub_round<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.wl, w.s, w.sl, w.g0);
-    LRSDP_TRY(gemv(f->Sinv, nk, nk, w.g0, w.g1, s));
+    LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.g0, w.h, w.g1, s));
     k_dd_accum<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.t, w.tl, w.g1);
   }
   // x = bold U t (dd);  z = (v - x) G^{-1} / tau^2
@@ -470,10 +530,9 @@ int split_apply(lrsdp_factor* f, const double* v, double* Hv, int precision, hip
   // P = M U (dd), Q = W0 P, K = U^T P (dd), then the sampled rank-k terms
   k_mval_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, nullptr, v, nullptr,
                                                    P->mval, P->vec_scratch);
-  k_spmm_U_dd<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, P->mval,
-                                               P->vec_scratch, f->U, w.g0, w.g1);
+  spmm_U_dd(P, k, P->vec_scratch, f->U, w.g0, w.g1, s);
   rows_k(n, k, f->W0, 0, w.g0, w.s, s);
-  k_UtP<<<k * k, 64, 0, s>>>(n, k, f->U, w.g0, w.g1, w.kk);
+  k_UtP<<<k * k, kT, 0, s>>>(n, k, f->U, w.g0, w.g1, w.kk);
   k_lowrank_add<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, f->U, w.s, w.kk,
                                                   Hv);
   LRSDP_HIP(hipGetLastError());

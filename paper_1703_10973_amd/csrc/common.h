@@ -158,6 +158,24 @@ __device__ __forceinline__ dd wave_sum_dd(dd v) {
   return v;
 }
 
+// Deterministic block sum in double-double; every thread gets the result.
+// scratch: >= 2 * blockDim/64 doubles.
+__device__ __forceinline__ dd block_sum_dd(dd v, double* scratch) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  v = wave_sum_dd(v);
+  __syncthreads();
+  if (lane == 0) {
+    scratch[2 * wid] = v.hi;
+    scratch[2 * wid + 1] = v.lo;
+  }
+  __syncthreads();
+  dd s = {0.0, 0.0};
+  for (int i = 0; i < nw; ++i) s = dd_add(s, {scratch[2 * i], scratch[2 * i + 1]});
+  return s;
+}
+
 // ------------------------------------------------------------------ bf16 helpers
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);

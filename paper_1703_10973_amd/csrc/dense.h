@@ -1,6 +1,6 @@
 // Dense FP64 kernels on the CDNA4 matrix cores (v_mfma_f64_16x16x4_f64), used by the
-// setup steps: Cholesky of 2 W0 + U U^T (size n) and of bold S (size nk), the explicit
-// bold S^{-1} = L^{-T} L^{-1}, and the GEMMs that form bold S.
+// setup steps: Cholesky of 2 W0 + U U^T (size n) and of bold S (size nk) with their inverse
+// factors, the explicit bold S^{-1} = L^{-T} L^{-1}, and the GEMMs that form bold S.
 #pragma once
 
 #include "internal.h"
@@ -37,17 +37,20 @@ struct GemmArgs {
 // C = alpha op(A) op(B) + beta C (row-major), FP64 MFMA.
 int gemm(const GemmArgs& g, hipStream_t s);
 
-// Inverted 64 x 64 diagonal blocks of a Cholesky factor (doubles needed for order N).
-size_t dinv_doubles(int N);
-// Cholesky A = L L^T in place (lower; the strict upper triangle of each 64-aligned diagonal
-// block is zeroed, the rest of the upper triangle is left as is).  dinv receives the inverses
-// of the 64-aligned diagonal blocks of L.  On a non-positive pivot *flag (device int) gets 1.
-int potrf(double* A, int N, int lda, int* flag, double* dinv, hipStream_t s);
-// B := B L^{-T}, B M x N, L N x N lower with its diagonal-block inverses dinv (from potrf).
-int trsm_rlt(double* B, int M, int N, int ldb, const double* L, int ldl, const double* dinv,
-             hipStream_t s);
-// L := L^{-1} in place (lower, upper triangle zero).  tmp: at least ceil(N/2)^2 doubles.
-int trtri(double* L, int N, int ldl, double* tmp, const double* dinv, hipStream_t s);
+// Cholesky A = L L^T and L^{-1} in one pass.  Li (N x N, distinct from A) receives L^{-1}
+// in its lower triangle with zeros above the diagonal inside each 64-aligned diagonal block
+// (the rest of the upper triangle is left as is).  With want_L, A's lower triangle receives
+// L under the same zero convention; without it, A is used as scratch and left undefined.
+// tmp: potrf_inv_tmp_doubles(N) doubles.  On a non-positive pivot *flag (device int) gets 1
+// and the result is garbage.
+size_t potrf_inv_tmp_doubles(int N);
+int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
+              bool want_L, hipStream_t s);
+// y = M_up (M_lo x) with M_lo the lower and M_up the upper triangle of M, both including the
+// diagonal (two row-wise triangular GEMVs; tmp: N doubles).  With L^{-1} in the lower
+// triangle and its transpose mirrored into the upper one this is y = L^{-T} L^{-1} x.
+int trmv_pair(const double* M, int N, int ld, const double* x, double* tmp, double* y,
+              hipStream_t s);
 // X := M^T M (lower part), M lower triangular N x N; X and M distinct.
 int lauum(const double* M, int N, int ldm, double* X, int ldx, hipStream_t s);
 // Copy the lower triangle into the upper one.

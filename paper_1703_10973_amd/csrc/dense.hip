@@ -1,14 +1,17 @@
 // Dense FP64 linear algebra on CDNA4 matrix cores for the setup of Algorithm 1.
 //
-// GEMM: 64 x 64 output tile per workgroup, four wavefronts each owning a 32 x 32 quarter
-// as 2 x 2 v_mfma_f64_16x16x4_f64 accumulators; K advances 16 at a time through LDS.
+// GEMM: 64 x 64 (or, for small products, 32 x 32) output tile per workgroup, each wavefront
+// owning a 32 x 32 block as 2 x 2 v_mfma_f64_16x16x4_f64 accumulators; K advances 16 at a
+// time through double-buffered LDS.
 // Operand fragments follow the MFMA register layout: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; the 16 x 16 result lives as D[l / 16 + 4 r][l % 16], r = 0..3
 // (rows interleaved across the four result registers).
 // Triangular operands skip whole zero tiles through per-tile K ranges (GemmFlags).
 //
-// POTRF / TRSM / TRTRI / LAUUM are recursive (split at a multiple of 64) so that nearly all
-// their flops land in that GEMM; the 64 x 64 leaves are single-workgroup LDS kernels.
+// The Cholesky factor and its inverse come out of one recursion (split at a multiple of 64):
+// [L11 0; L21 L22] with L21 = A21 L11^{-T}, L22 from A22 - L21 L21^T, and
+// (L^{-1})_21 = -L22^{-1} L21 L11^{-1}, so nearly all flops land in the GEMM and no
+// triangular solve is sequential beyond the 64 x 64 leaves (register-resident kernels).
 #include <algorithm>
 
 #include "dense.h"
@@ -18,14 +21,18 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int TM = 64, TN = 64, TK = 16;
-constexpr int PITCH = TM + 4;  // LDS row pitch (doubles) of the K-major operand tiles
-constexpr int NB = 64;         // leaf size of the recursive factorizations
+constexpr int TK = 16;
+constexpr int NB = 64;  // leaf size of the recursive factorizations
 
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ double As[2][TK][PITCH];
-  __shared__ double Bs[2][TK][PITCH];
+// Output tile (32 WM) x (32 WN) per workgroup of WM x WN wavefronts, each wavefront a
+// 32 x 32 block as 2 x 2 MFMA accumulators.  64 x 64 tiles for large products, 32 x 32
+// tiles (one wavefront) when the 64 x 64 grid would leave CUs idle.
+template <bool TA, bool TB, int WM, int WN>
+__global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
+  constexpr int TMv = 32 * WM, TNv = 32 * WN, NT = 64 * WM * WN;
+  constexpr int EA = TMv * TK / NT, EB = TNv * TK / NT;  // staged values per thread
+  __shared__ double As[2][TK][TMv + 4];
+  __shared__ double Bs[2][TK][TNv + 4];
   const double* __restrict__ Ap = g.A;
   const double* __restrict__ Bp = g.B;
   double* __restrict__ Cp = g.C;
@@ -35,76 +42,62 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     Bp += g.offs[3 * z + 1];
     Cp += g.offs[3 * z + 2];
   }
-  const int tiles_n = (g.N + TN - 1) / TN;
+  const int tiles_n = (g.N + TNv - 1) / TNv;
   const int ti = blockIdx.x / tiles_n;
   const int tj = blockIdx.x - ti * tiles_n;
-  const int i0 = ti * TM, j0 = tj * TN;
+  const int i0 = ti * TMv, j0 = tj * TNv;
   const bool lower = (g.flags & kLowerOut) != 0;
-  if (lower && j0 > i0 + TM - 1) return;
+  if (lower && j0 > i0 + TMv - 1) return;
   int klo = 0, khi = g.K;
   if (g.flags & kKFromRow) klo = max(klo, i0);
-  if (g.flags & kKToRow) khi = min(khi, i0 + TM);
+  if (g.flags & kKToRow) khi = min(khi, i0 + TMv);
   if (g.flags & kKFromCol) klo = max(klo, j0);
-  if (g.flags & kKToCol) khi = min(khi, j0 + TN);
+  if (g.flags & kKToCol) khi = min(khi, j0 + TNv);
 
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = t >> 6;
-  const int wm = w >> 1, wn = w & 1;
+  const int wm = w / WN, wn = w % WN;
   const int lr = lane & 15, lk = lane >> 4;
 
-  // each thread stages 4 values of op(A) and 4 of op(B) per K step
-  double ra[4], rb[4];
+  // staging map: consecutive threads walk the contiguous dimension of each operand
+  double ra[EA], rb[EB];
   auto load = [&](int k0) {
-    if (!TA) {
-      const int r = t >> 2, kq = (t & 3) * 4, i = i0 + r;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = k0 + kq + u;
+    for (int u = 0; u < EA; ++u) {
+      const int e = t + u * NT;
+      if (!TA) {
+        const int r = e / TK, kk = e % TK, i = i0 + r, k = k0 + kk;
         ra[u] = (i < g.M && k < khi) ? Ap[(size_t)i * g.lda + k] : 0.0;
-      }
-    } else {
-      const int kk = t >> 4, iq = (t & 15) * 4, k = k0 + kk;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int i = i0 + iq + u;
+      } else {
+        const int kk = e / TMv, r = e % TMv, i = i0 + r, k = k0 + kk;
         ra[u] = (i < g.M && k < khi) ? Ap[(size_t)k * g.lda + i] : 0.0;
       }
     }
-    if (!TB) {
-      const int kk = t >> 4, jq = (t & 15) * 4, k = k0 + kk;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = j0 + jq + u;
+    for (int u = 0; u < EB; ++u) {
+      const int e = t + u * NT;
+      if (!TB) {
+        const int kk = e / TNv, c = e % TNv, j = j0 + c, k = k0 + kk;
         rb[u] = (j < g.N && k < khi) ? Bp[(size_t)k * g.ldb + j] : 0.0;
-      }
-    } else {
-      const int r = t >> 2, kq = (t & 3) * 4, j = j0 + r;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int k = k0 + kq + u;
+      } else {
+        const int c = e / TK, kk = e % TK, j = j0 + c, k = k0 + kk;
         rb[u] = (j < g.N && k < khi) ? Bp[(size_t)j * g.ldb + k] : 0.0;
       }
     }
   };
   auto store = [&](int buf) {
-    if (!TA) {
-      const int r = t >> 2, kq = (t & 3) * 4;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) As[buf][kq + u][r] = ra[u];
-    } else {
-      const int kk = t >> 4, iq = (t & 15) * 4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) As[buf][kk][iq + u] = ra[u];
+    for (int u = 0; u < EA; ++u) {
+      const int e = t + u * NT;
+      if (!TA) As[buf][e % TK][e / TK] = ra[u];
+      else As[buf][e / TMv][e % TMv] = ra[u];
     }
-    if (!TB) {
-      const int kk = t >> 4, jq = (t & 15) * 4;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) Bs[buf][kk][jq + u] = rb[u];
-    } else {
-      const int r = t >> 2, kq = (t & 3) * 4;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) Bs[buf][kq + u][r] = rb[u];
+    for (int u = 0; u < EB; ++u) {
+      const int e = t + u * NT;
+      if (!TB) Bs[buf][e / TNv][e % TNv] = rb[u];
+      else Bs[buf][e % TK][e / TK] = rb[u];
     }
   };
 
@@ -155,63 +148,113 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
 }
 
-// ---------------------------------------------------------------- leaves (N <= 64)
+// ---------------------------------------------------------------- leaf (N <= 64)
 
-// Cholesky of a diagonal block (N <= 64) and the inverse of its factor, in LDS.
-// Right-looking: at step j every row i > j subtracts a_ij a_cj / a_jj from its trailing
-// entries c in (j, i], and the reduced identity rows Y (which become L^{-1}) subtract
-// l_ij (Y[j, :] / l_jj), the recurrence of forward substitution on L X = I.  Thread
-// (i = t % 64, g = t / 64) owns row i, columns c = g (mod 4): one barrier per step.
-// Rows beyond N are padded with the identity.  A non-positive pivot sets *flag.
-__global__ __launch_bounds__(256) void k_potrf_inv_leaf(double* A, int N, int lda, int* flag,
-                                                        double* Dinv) {
-  __shared__ double S[NB][NB + 1];
-  __shared__ double Y[NB][NB + 1];
-  const int t = threadIdx.x;
-  for (int e = t; e < NB * NB; e += 256) {
-    const int r = e >> 6, c = e & 63;
+constexpr int LW = 8;        // wavefronts of the leaf kernel
+constexpr int LQ = NB / LW;  // columns held per lane
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// 1/sqrt(x) for x > 0: hardware estimate plus two Newton steps (a few ulp; the
+// factorization does not need correct rounding).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
+// Cholesky factor L of a diagonal block (N <= 64) and L^{-1}, held in registers.
+// Lane i = t % 64 of every wavefront holds row i; wavefront g = t / 64 holds the columns
+// c = 8q + g (q = 0..7) of both the matrix being reduced and the identity being reduced
+// to L^{-1}.  Step j: the owner of column j takes the pivot from its lane j, scales the
+// column to l_cj and publishes it with 1 / l_jj through LDS (double-buffered, one barrier
+// per step); row i > j then subtracts l_ij l_cj from its columns c in (j, i] and
+// l_ij (row j of the reduced identity) / l_jj from its columns c <= j, that row coming
+// from lane j of its own wavefront.  Rows and columns beyond N are the identity.  A
+// non-positive pivot sets *flag and continues with pivot 1.  Writes L (lower, zero above
+// the diagonal) into A and L^{-1} (zero above the diagonal) into Li (li_rows x li_rows).
+__global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, int N, int lda,
+                                                       int* flag, double* __restrict__ Li,
+                                                       int ldi, int li_rows) {
+  __shared__ double col[2][NB];
+  __shared__ double sinv[2];
+  __shared__ double dsq[NB];
+  const int t = threadIdx.x, i = t & (NB - 1), g = t / NB;
+  double a[LQ], y[LQ];
+#pragma unroll
+  for (int q = 0; q < LQ; ++q) {
+    const int c = q * LW + g;
     double v = 0.0;
-    if (r < N && c <= r) v = A[(size_t)r * lda + c];
-    else if (r == c) v = 1.0;
-    S[r][c] = v;
-    Y[r][c] = (r == c) ? 1.0 : 0.0;
+    if (i < N && c <= i) v = A[(size_t)i * lda + c];
+    else if (i == c) v = 1.0;
+    a[q] = v;
+    y[q] = (i == c) ? 1.0 : 0.0;
   }
-  __syncthreads();
-  const int i = t & 63, g = t >> 6;
   for (int j = 0; j < NB; ++j) {
-    double piv = S[j][j];
-    if (!(piv > 0.0)) {
-      if (t == 0 && j < N) atomicOr(flag, 1);
-      piv = 1.0;
-    }
-    const double dj = sqrt(piv), inv_dj = 1.0 / dj;
-    if (i > j) {
-      const double lij = S[i][j] * inv_dj;
-      for (int c = j + 1 + ((g - (j + 1)) & 3); c <= i; c += 4)
-        S[i][c] = fma(-lij, S[c][j] * inv_dj, S[i][c]);
-      for (int c = g; c <= j; c += 4) Y[i][c] = fma(-lij, Y[j][c] * inv_dj, Y[i][c]);
+    const int qj = j / LW, gj = j % LW;
+    double* cj = col[j & 1];
+    if (g == gj) {  // owner wavefront of column j
+      double v = a[0];
+#pragma unroll
+      for (int q = 1; q < LQ; ++q)
+        if (q == qj) v = a[q];
+      double piv = readlane_d(v, j);
+      const bool bad = !(piv > 0.0);
+      if (bad) piv = 1.0;
+      const double inv = rsqrt_nr(piv);
+      cj[i] = v * inv;
+      if (i == 0) {
+        sinv[j & 1] = inv;
+        dsq[j] = piv * inv;
+        if (bad && j < N) atomicOr(flag, 1);
+      }
     }
     __syncthreads();
-  }
-  for (int e = t; e < NB * NB; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    const double dr = sqrt(S[r][r] > 0.0 ? S[r][r] : 1.0);
-    if (r < N && c < N) {
-      double l = 0.0;
-      if (c < r) l = S[r][c] / sqrt(S[c][c] > 0.0 ? S[c][c] : 1.0);
-      else if (c == r) l = dr;
-      A[(size_t)r * lda + c] = l;
+    // every LDS read of the step is issued before any use, and the updates are selects
+    const double inv = sinv[j & 1];
+    double cc[LQ];
+#pragma unroll
+    for (int q = 0; q < LQ; ++q) cc[q] = cj[q * LW + g];
+    const double mlij = -cj[i];
+    const bool below = i > j;
+#pragma unroll
+    for (int q = 0; q < LQ; ++q) {
+      const int c = q * LW + g;  // uniform over the wavefront
+      const double yj = readlane_d(y[q], j);
+      const double na = fma(mlij, cc[q], a[q]);
+      const double ny = fma(mlij, yj * inv, y[q]);
+      a[q] = (below && c > j && c <= i) ? na : a[q];
+      y[q] = (below && c <= j) ? ny : y[q];
     }
-    Dinv[e] = (c <= r) ? Y[r][c] / dr : 0.0;
+  }
+  __syncthreads();
+  const double di = dsq[i];
+#pragma unroll
+  for (int q = 0; q < LQ; ++q) {
+    const int c = q * LW + g;
+    if (i < N && c < N) {
+      double l = 0.0;
+      if (c < i) l = a[q] / dsq[c];
+      else if (c == i) l = di;
+      A[(size_t)i * lda + c] = l;
+    }
+    if (i < li_rows && c < li_rows) Li[(size_t)i * ldi + c] = (c <= i) ? y[q] / di : 0.0;
   }
 }
 
-// Copy the lower triangle of a 64 x 64 inverse block into an N x N diagonal block.
-__global__ void k_put_block(const double* D, double* L, int N, int ldl) {
-  for (int e = threadIdx.x; e < N * N; e += blockDim.x) {
-    const int r = e / N, c = e - r * N;
-    L[(size_t)r * ldl + c] = (c <= r) ? D[r * NB + c] : 0.0;
-  }
+__global__ void k_copy_block(const double* __restrict__ S, int lds, double* __restrict__ D,
+                             int ldd, int M, int N) {
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (idx >= (size_t)M * N) return;
+  const int i = (int)(idx / N), j = (int)(idx - (size_t)i * N);
+  D[(size_t)i * ldd + j] = S[(size_t)i * lds + j];
 }
 
 // ---------------------------------------------------------------- elementwise helpers
@@ -266,6 +309,22 @@ __global__ __launch_bounds__(256) void k_gemv(const double* __restrict__ A, int 
   if (lane == 0) y[row] = s;
 }
 
+// y = tri(A) x with tri the lower (upper = 0) or upper (upper = 1) triangle including the
+// diagonal; one wavefront per row.
+__global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, int N, int lda,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ y, int upper) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= N) return;
+  const double* a = A + (size_t)row * lda;
+  const int lo = upper ? row : 0, hi = upper ? N : row + 1;
+  double s = 0.0;
+  for (int c = lo + lane; c < hi; c += 64) s = fma(a[c], x[c], s);
+  s = wave_sum(s);
+  if (lane == 0) y[row] = s;
+}
+
 int split64(int N) {
   int h = (N + 1) / 2;
   int n1 = ((h + NB - 1) / NB) * NB;
@@ -275,21 +334,21 @@ int split64(int N) {
 
 }  // namespace
 
-// Flops of one GEMM call with its tile skipping, and its compulsory bytes.
-static void gemm_cost(const GemmArgs& g, double* flops, double* bytes) {
-  const int tm = (g.M + TM - 1) / TM, tn = (g.N + TN - 1) / TN;
+// Flops of one GEMM call with its tile skipping (tile edge te), and its compulsory bytes.
+static void gemm_cost(const GemmArgs& g, int te, double* flops, double* bytes) {
+  const int tm = (g.M + te - 1) / te, tn = (g.N + te - 1) / te;
   double f = 0.0;
   const bool lower = (g.flags & kLowerOut) != 0;
   for (int ti = 0; ti < tm; ++ti) {
-    const int i0 = ti * TM, ih = std::min(g.M, i0 + TM) - i0;
+    const int i0 = ti * te, ih = std::min(g.M, i0 + te) - i0;
     for (int tj = 0; tj < tn; ++tj) {
-      const int j0 = tj * TN, jh = std::min(g.N, j0 + TN) - j0;
-      if (lower && j0 > i0 + TM - 1) continue;
+      const int j0 = tj * te, jh = std::min(g.N, j0 + te) - j0;
+      if (lower && j0 > i0 + te - 1) continue;
       int klo = 0, khi = g.K;
       if (g.flags & kKFromRow) klo = std::max(klo, i0);
-      if (g.flags & kKToRow) khi = std::min(khi, i0 + TM);
+      if (g.flags & kKToRow) khi = std::min(khi, i0 + te);
       if (g.flags & kKFromCol) klo = std::max(klo, j0);
-      if (g.flags & kKToCol) khi = std::min(khi, j0 + TN);
+      if (g.flags & kKToCol) khi = std::min(khi, j0 + te);
       if (khi > klo) f += 2.0 * ih * jh * (khi - klo);
     }
   }
@@ -298,107 +357,122 @@ static void gemm_cost(const GemmArgs& g, double* flops, double* bytes) {
                   (double)g.M * g.N * (g.beta != 0.0 ? 2.0 : 1.0));
 }
 
+template <int WM, int WN>
+static void launch_gemm(const GemmArgs& g, hipStream_t s) {
+  constexpr int te_m = 32 * WM, te_n = 32 * WN;
+  const int tiles = ((g.M + te_m - 1) / te_m) * ((g.N + te_n - 1) / te_n);
+  const dim3 grid(tiles, g.offs ? g.batch : 1), block(64 * WM * WN);
+  if (!g.transA && !g.transB)
+    k_gemm<false, false, WM, WN><<<grid, block, 0, s>>>(g);
+  else if (!g.transA && g.transB)
+    k_gemm<false, true, WM, WN><<<grid, block, 0, s>>>(g);
+  else if (g.transA && !g.transB)
+    k_gemm<true, false, WM, WN><<<grid, block, 0, s>>>(g);
+  else
+    k_gemm<true, true, WM, WN><<<grid, block, 0, s>>>(g);
+}
+
 int gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return LRSDP_OK;
-  const int tiles = ((g.M + TM - 1) / TM) * ((g.N + TN - 1) / TN);
+  // 64 x 64 tiles once they alone give every CU a workgroup, else 32 x 32 tiles
+  const int64_t t64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * (g.offs ? g.batch : 1);
+  const int te = t64 >= 512 ? 64 : 32;
   ProfMark pm = prof_begin(LRSDP_K_GEMM, s);
-  const dim3 grid(tiles, g.offs ? g.batch : 1);
-  if (!g.transA && !g.transB)
-    k_gemm<false, false><<<grid, 256, 0, s>>>(g);
-  else if (!g.transA && g.transB)
-    k_gemm<false, true><<<grid, 256, 0, s>>>(g);
-  else if (g.transA && !g.transB)
-    k_gemm<true, false><<<grid, 256, 0, s>>>(g);
-  else
-    k_gemm<true, true><<<grid, 256, 0, s>>>(g);
+  if (te == 64) launch_gemm<2, 2>(g, s);
+  else launch_gemm<1, 1>(g, s);
   LRSDP_HIP(hipGetLastError());
   if (pm.kid >= 0) {
     double fl = 0.0, by = 0.0;
-    gemm_cost(g, &fl, &by);
+    gemm_cost(g, te, &fl, &by);
     const double nb = g.offs ? g.batch : 1;
     prof_end(pm, s, by * nb, fl * nb);
   }
   return LRSDP_OK;
 }
 
-size_t dinv_doubles(int N) { return (size_t)((N + NB - 1) / NB) * NB * NB; }
+size_t potrf_inv_tmp_doubles(int N) {
+  if (N <= NB) return 0;
+  const int N1 = split64(N), N2 = N - N1;
+  return std::max({(size_t)N1 * N2, potrf_inv_tmp_doubles(N1), potrf_inv_tmp_doubles(N2)});
+}
 
-int potrf(double* A, int N, int lda, int* flag, double* dinv, hipStream_t s) {
+int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
+              bool want_L, hipStream_t s) {
   if (N <= 0) return LRSDP_OK;
   if (N <= NB) {
-    k_potrf_inv_leaf<<<1, 256, 0, s>>>(A, N, lda, flag, dinv);
+    k_chol_leaf<<<1, NB * LW, 0, s>>>(A, N, lda, flag, Li, ldi, N);
     LRSDP_HIP(hipGetLastError());
     return LRSDP_OK;
   }
   const int N1 = split64(N), N2 = N - N1;
-  LRSDP_TRY(potrf(A, N1, lda, flag, dinv, s));
   double* A21 = A + (size_t)N1 * lda;
-  LRSDP_TRY(trsm_rlt(A21, N2, N1, lda, A, lda, dinv, s));
-  GemmArgs g;
-  g.M = N2; g.N = N2; g.K = N1;
-  g.A = A21; g.lda = lda; g.transA = false;
-  g.B = A21; g.ldb = lda; g.transB = true;
-  g.C = A21 + N1; g.ldc = lda;
-  g.alpha = -1.0; g.beta = 1.0; g.flags = kLowerOut;
-  LRSDP_TRY(gemm(g, s));
-  return potrf(A21 + N1, N2, lda, flag, dinv + (size_t)(N1 / NB) * NB * NB, s);
-}
-
-// The leaf B L^{-T} with N <= 64 is a GEMM against the stored inverse block; it may run in
-// place because a single column tile of C covers all N columns and every workgroup reads
-// only its own rows of B before it writes them.
-int trsm_rlt(double* B, int M, int N, int ldb, const double* L, int ldl, const double* dinv,
-             hipStream_t s) {
-  if (M <= 0 || N <= 0) return LRSDP_OK;
-  if (N <= NB) {
+  double* A22 = A21 + N1;
+  double* Li21 = Li + (size_t)N1 * ldi;
+  double* Li22 = Li21 + N1;
+  LRSDP_TRY(potrf_inv(A, N1, lda, Li, ldi, flag, tmp, want_L, s));
+  {  // tmp = L21 = A21 L11^{-T}
     GemmArgs g;
-    g.M = M; g.N = N; g.K = N;
-    g.A = B; g.lda = ldb;
-    g.B = dinv; g.ldb = NB; g.transB = true;
-    g.C = B; g.ldc = ldb;
-    return gemm(g, s);
+    g.M = N2; g.N = N1; g.K = N1;
+    g.A = A21; g.lda = lda;
+    g.B = Li; g.ldb = ldi; g.transB = true;  // op(B)[k][j] = L11^{-1}[j][k], zero for k > j
+    g.C = tmp; g.ldc = N1;
+    g.flags = kKToCol;
+    LRSDP_TRY(gemm(g, s));
   }
-  const int N1 = split64(N), N2 = N - N1;
-  LRSDP_TRY(trsm_rlt(B, M, N1, ldb, L, ldl, dinv, s));
-  GemmArgs g;
-  g.M = M; g.N = N2; g.K = N1;
-  g.A = B; g.lda = ldb; g.transA = false;
-  g.B = L + (size_t)N1 * ldl; g.ldb = ldl; g.transB = true;
-  g.C = B + N1; g.ldc = ldb;
-  g.alpha = -1.0; g.beta = 1.0;
-  LRSDP_TRY(gemm(g, s));
-  return trsm_rlt(B + N1, M, N2, ldb, L + (size_t)N1 * ldl + N1, ldl,
-                  dinv + (size_t)(N1 / NB) * NB * NB, s);
+  // L21 lives in A21 when the caller wants L (then P = L21 L11^{-1} waits in tmp, after the
+  // trailing factorization); otherwise L21 stays in tmp and P overwrites A21 at once.
+  const double* L21 = tmp;
+  int ld21 = N1;
+  if (want_L) {
+    const size_t cnt = (size_t)N2 * N1;
+    k_copy_block<<<(unsigned)((cnt + 255) / 256), 256, 0, s>>>(tmp, N1, A21, lda, N2, N1);
+    LRSDP_HIP(hipGetLastError());
+    L21 = A21;
+    ld21 = lda;
+  }
+  {  // A22 -= L21 L21^T (lower)
+    GemmArgs g;
+    g.M = N2; g.N = N2; g.K = N1;
+    g.A = L21; g.lda = ld21;
+    g.B = L21; g.ldb = ld21; g.transB = true;
+    g.C = A22; g.ldc = lda;
+    g.alpha = -1.0; g.beta = 1.0; g.flags = kLowerOut;
+    LRSDP_TRY(gemm(g, s));
+  }
+  GemmArgs pg;  // P = L21 L11^{-1}
+  pg.M = N2; pg.N = N1; pg.K = N1;
+  pg.A = L21; pg.lda = ld21;
+  pg.B = Li; pg.ldb = ldi;  // L11^{-1}[k][j], zero for k < j
+  pg.flags = kKFromCol;
+  if (!want_L) {
+    pg.C = A21; pg.ldc = lda;
+    LRSDP_TRY(gemm(pg, s));
+  }
+  LRSDP_TRY(potrf_inv(A22, N2, lda, Li22, ldi, flag, tmp, want_L, s));
+  if (want_L) {
+    pg.C = tmp; pg.ldc = N1;
+    LRSDP_TRY(gemm(pg, s));
+  }
+  {  // (L^{-1})_21 = -L22^{-1} P
+    GemmArgs g;
+    g.M = N2; g.N = N1; g.K = N2;
+    g.A = Li22; g.lda = ldi;  // zero for k > i
+    g.B = want_L ? tmp : A21; g.ldb = want_L ? N1 : lda;
+    g.C = Li21; g.ldc = ldi;
+    g.alpha = -1.0; g.flags = kKToRow;
+    LRSDP_TRY(gemm(g, s));
+  }
+  return LRSDP_OK;
 }
 
-int trtri(double* L, int N, int ldl, double* tmp, const double* dinv, hipStream_t s) {
-  if (N <= 0) return LRSDP_OK;
-  if (N <= NB) {
-    k_put_block<<<1, 256, 0, s>>>(dinv, L, N, ldl);
-    LRSDP_HIP(hipGetLastError());
-    return LRSDP_OK;
-  }
-  const int N1 = split64(N), N2 = N - N1;
-  double* L11 = L;
-  double* L21 = L + (size_t)N1 * ldl;
-  double* L22 = L21 + N1;
-  LRSDP_TRY(trtri(L11, N1, ldl, tmp, dinv, s));
-  LRSDP_TRY(trtri(L22, N2, ldl, tmp, dinv + (size_t)(N1 / NB) * NB * NB, s));
-  GemmArgs g;  // tmp = L21 L11^{-1}
-  g.M = N2; g.N = N1; g.K = N1;
-  g.A = L21; g.lda = ldl;
-  g.B = L11; g.ldb = ldl;
-  g.C = tmp; g.ldc = N1;
-  g.flags = kKFromCol;
-  LRSDP_TRY(gemm(g, s));
-  GemmArgs h;  // L21 = -L22^{-1} tmp
-  h.M = N2; h.N = N1; h.K = N2;
-  h.A = L22; h.lda = ldl;
-  h.B = tmp; h.ldb = N1;
-  h.C = L21; h.ldc = ldl;
-  h.alpha = -1.0; h.beta = 0.0;
-  h.flags = kKToRow;
-  return gemm(h, s);
+int trmv_pair(const double* M, int N, int ld, const double* x, double* tmp, double* y,
+              hipStream_t s) {
+  ProfMark pm = prof_begin(LRSDP_K_GEMV, s);
+  k_gemv_tri<<<(N + 3) / 4, 256, 0, s>>>(M, N, ld, x, tmp, 0);
+  k_gemv_tri<<<(N + 3) / 4, 256, 0, s>>>(M, N, ld, tmp, y, 1);
+  LRSDP_HIP(hipGetLastError());
+  prof_end(pm, s, 8.0 * (double)N * (N + 1) + 32.0 * N, 2.0 * (double)N * (N + 1));
+  return LRSDP_OK;
 }
 
 int lauum(const double* M, int N, int ldm, double* X, int ldx, hipStream_t s) {

@@ -167,7 +167,7 @@ int read_flag(lrsdp_ctx* ctx, int* out) {
 
 size_t work_doubles(int n, int m, int k) {
   const size_t nk = (size_t)n * k;
-  return 12 * (size_t)m + 10 * nk + 2 * (size_t)k * k + 8192;
+  return 12 * (size_t)m + 11 * nk + 2 * (size_t)k * k + 8192;
 }
 
 Work work_view(const lrsdp_factor* f) {
@@ -179,7 +179,7 @@ Work work_view(const lrsdp_factor* f) {
     *pp = b;
     b += m;
   }
-  double** kv[] = {&w.w, &w.wl, &w.t, &w.tl, &w.s, &w.sl, &w.y, &w.yl, &w.g0, &w.g1};
+  double** kv[] = {&w.w, &w.wl, &w.t, &w.tl, &w.s, &w.sl, &w.y, &w.yl, &w.g0, &w.g1, &w.h};
   for (auto pp : kv) {
     *pp = b;
     b += nk;
@@ -226,6 +226,23 @@ void factor_release(lrsdp_factor* f) {
   f->lam_dev = f->W = f->W0 = f->U = f->Z = f->Zt = f->Sinv = f->QN = f->work = f->sc = nullptr;
   f->W0f = nullptr;
   f->W0b = nullptr;
+}
+
+int export_sinv(const lrsdp_factor* f, double* out, hipStream_t s) {
+  lrsdp_ctx* ctx = f->P->ctx;
+  const int nk = f->nk;
+  double* Lt = nullptr;  // L^{-1} with an explicit zero upper triangle
+  LRSDP_TRY(dev_alloc_n(ctx, &Lt, (size_t)nk * nk));
+  int rc = LRSDP_OK;
+  if (hipMemcpyAsync(Lt, f->Sinv, (size_t)nk * nk * sizeof(double), hipMemcpyDeviceToDevice,
+                     s) != hipSuccess)
+    rc = LRSDP_ERR_DEVICE;
+  if (rc == LRSDP_OK) rc = zero_upper(Lt, nk, nk, s);
+  if (rc == LRSDP_OK) rc = lauum(Lt, nk, nk, out, nk, s);
+  if (rc == LRSDP_OK) rc = mirror_lower(out, nk, nk, s);
+  if (hipStreamSynchronize(s) != hipSuccess && rc == LRSDP_OK) rc = LRSDP_ERR_DEVICE;
+  dev_free(ctx, Lt, (size_t)nk * nk * sizeof(double));
+  return rc;
 }
 
 int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
@@ -308,10 +325,12 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
   struct Tmp {
     double* p = nullptr;
     size_t cnt = 0;
-  } dZ{nullptr, dinv_doubles(n)}, dS{nullptr, dinv_doubles(nk)}, Sb{nullptr, (size_t)nk * nk},
-      PJ{nullptr, (size_t)k * nn}, Rb{nullptr, pair_cap * nn}, dd_{nullptr, (size_t)npairs * n},
-      offs{nullptr, 3 * pair_cap};
-  Tmp* tmps[] = {&dZ, &dS, &Sb, &PJ, &Rb, &dd_, &offs};
+  } Zi{nullptr, nn}, ptmp{nullptr, std::max<size_t>(1, potrf_inv_tmp_doubles(nk))},
+      Sb{nullptr, (size_t)nk * nk}, PJ{nullptr, (size_t)k * nn},
+      Rb{nullptr, std::max(pair_cap * nn, (size_t)nk + 2 * (size_t)r * r)},
+      dd_{nullptr, (size_t)npairs * n}, offs{nullptr, 3 * pair_cap},
+      Q2{nullptr, std::max<size_t>(1, (size_t)nk * r)};
+  Tmp* tmps[] = {&Zi, &ptmp, &Sb, &PJ, &Rb, &dd_, &offs, &Q2};
   for (Tmp* t : tmps) {
     if ((rc = dev_alloc_n(ctx, &t->p, t->cnt)) < 0) break;
   }
@@ -328,7 +347,7 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
       rc = LRSDP_ERR_DEVICE;
       break;
     }
-    if ((rc = potrf(f->Z, n, n, ctx->d_flag, dZ.p, s))) break;
+    if ((rc = potrf_inv(f->Z, n, n, Zi.p, n, ctx->d_flag, ptmp.p, true, s))) break;
     if ((rc = zero_upper(f->Z, n, n, s))) break;
     int flag = 0;
     if ((rc = read_flag(ctx, &flag))) break;
@@ -393,25 +412,36 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
                                                    f->tau2);
     // ---- deflation of null(bold U) directions
     if (r) {
-      double* Yt = Rb.p;  // k x n: (Z^{-1} U)^T = U^T Z^{-T}
-      if (hipMemcpyAsync(Yt, f->U, (size_t)nk * sizeof(double), hipMemcpyDeviceToDevice, s) !=
-          hipSuccess) {
-        rc = LRSDP_ERR_DEVICE;
-        break;
+      double* Yt = Rb.p;  // k x n: (Z^{-1} U)^T = U Z^{-T}
+      {
+        GemmArgs g;
+        g.M = k; g.N = n; g.K = n;
+        g.A = f->U; g.lda = n;
+        g.B = Zi.p; g.ldb = n; g.transB = true;  // op(B)[q][p] = Z^{-1}[p][q], zero for q > p
+        g.C = Yt; g.ldc = n;
+        g.flags = kKToCol;
+        if ((rc = gemm(g, s))) break;
       }
-      if ((rc = trsm_rlt(Yt, k, n, n, f->Z, n, dZ.p, s))) break;
-      double* G = Rb.p + nk;   // r x r Gram matrix
-      double* dG = PJ.p;       // its inverse diagonal blocks (P_J no longer needed)
+      double* G = Rb.p + nk;        // r x r Gram matrix
+      double* Gi = G + (size_t)r * r;  // the inverse of its Cholesky factor
       k_null_basis<<<grid_for((int64_t)nk * r, 256), 256, 0, s>>>(n, k, r, Yt, f->QN);
       for (int pass = 0; pass < 2 && rc == LRSDP_OK; ++pass) {  // Cholesky QR, twice
+        double* Qin = pass == 0 ? f->QN : Q2.p;
+        double* Qout = pass == 0 ? Q2.p : f->QN;
         GemmArgs g;
         g.M = r; g.N = r; g.K = nk;
-        g.A = f->QN; g.lda = r; g.transA = true;
-        g.B = f->QN; g.ldb = r;
+        g.A = Qin; g.lda = r; g.transA = true;
+        g.B = Qin; g.ldb = r;
         g.C = G; g.ldc = r;
         if ((rc = gemm(g, s))) break;
-        if ((rc = potrf(G, r, r, ctx->d_flag, dG, s))) break;
-        if ((rc = trsm_rlt(f->QN, nk, r, r, G, r, dG, s))) break;
+        if ((rc = potrf_inv(G, r, r, Gi, r, ctx->d_flag, ptmp.p, true, s))) break;
+        GemmArgs h;  // Q <- Q R^{-1} = Q (L^{-1})^T
+        h.M = nk; h.N = r; h.K = r;
+        h.A = Qin; h.lda = r;
+        h.B = Gi; h.ldb = r; h.transB = true;
+        h.C = Qout; h.ldc = r;
+        h.flags = kKToCol;
+        if ((rc = gemm(h, s))) break;
       }
       if (rc) break;
       k_max_diag<<<1, kT, 0, s>>>(S, nk, nk, f->sc);
@@ -436,16 +466,15 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
       rc = LRSDP_ERR_DEVICE;
       break;
     }
-    if ((rc = potrf(S, nk, nk, ctx->d_flag, dS.p, s))) break;
-    if ((rc = zero_upper(S, nk, nk, s))) break;
+    // the factor keeps L^{-1} in the lower triangle and L^{-T} in the upper one, so that
+    // bold S^{-1} w = L^{-T} (L^{-1} w) is two row-wise triangular GEMVs
+    if ((rc = potrf_inv(S, nk, nk, f->Sinv, nk, ctx->d_flag, ptmp.p, false, s))) break;
     int fl = 0;
     if ((rc = read_flag(ctx, &fl))) break;
     if (fl) {
       rc = LRSDP_ERR_CHOL_S;
       break;
     }
-    if ((rc = trtri(S, nk, nk, f->Sinv, dS.p, s))) break;
-    if ((rc = lauum(S, nk, nk, f->Sinv, nk, s))) break;
     if ((rc = mirror_lower(f->Sinv, nk, nk, s))) break;
     if (hipStreamSynchronize(s) != hipSuccess) rc = LRSDP_ERR_DEVICE;
   } while (0);

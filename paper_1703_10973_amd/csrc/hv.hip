@@ -14,8 +14,8 @@
 namespace lrsdp {
 namespace {
 
-constexpr int kThreads = 256;
-constexpr size_t kLdsBudget = 64 * 1024;  // two blocks per CU
+constexpr int kThreads = 1024;
+constexpr size_t kLdsBudget = 80 * 1024;  // two workgroups of 16 wavefronts per CU
 
 __global__ void k_scatter(int nnz, const int32_t* __restrict__ src,
                           const double* __restrict__ val, const double* __restrict__ v,
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_hv_fused(
     const TW* wa = W + (size_t)a * n;
     const TA* tt = Tt + c * ldn;
     TA s = TA(0);
-#pragma unroll 4
+#pragma unroll 8
     for (int p = lane; p < n; p += kWave) s = fma(load_w<TW, TA>(wa, p), tt[p], s);
     s = wave_sum(s);
     if (lane == 0) {
@@ -145,6 +145,9 @@ int launch_hv(const lrsdp_problem* P, const TW* W, const double* v, double* Hv, 
     if (cb < 1) return LRSDP_ERR_INVALID_ARG;
   }
   cb = cb >= 8 ? 8 : cb >= 4 ? 4 : cb >= 2 ? 2 : 1;
+  // at least ~200 workgroups so that every CU gets one; fewer rows per workgroup cost only
+  // extra (L2-resident) passes over the pattern
+  while (cb > 1 && (n + cb - 1) / cb < 200) cb >>= 1;
   const size_t smem = (size_t)cb * row_bytes;
   const int grid = (n + cb - 1) / cb;
   ProfMark pm = prof_begin(LRSDP_K_HV, s);
@@ -290,6 +293,7 @@ int hv_residual_dd(const lrsdp_problem* P, const double* W, const double* r, con
     if (cb < 1) return LRSDP_ERR_INVALID_ARG;
   }
   cb = cb >= 4 ? 4 : cb >= 2 ? 2 : 1;
+  while (cb > 1 && (n + cb - 1) / cb < 200) cb >>= 1;
   const size_t smem = (size_t)cb * row_bytes;
   const int grid = (n + cb - 1) / cb;
   ProfMark pm = prof_begin(LRSDP_K_RESDD, s);

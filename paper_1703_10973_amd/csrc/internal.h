@@ -122,7 +122,7 @@ struct lrsdp_factor {
   double* U = nullptr;               // k x n (n x k column-major)
   double* Z = nullptr;               // n x n lower, Z Z^T = 2 W0 + U U^T
   double* Zt = nullptr;              // n x n, Z^T
-  double* Sinv = nullptr;            // nk x nk, full symmetric bold S^{-1}
+  double* Sinv = nullptr;            // nk x nk: L^{-1} (lower) and L^{-T} (upper), bold S = L L^T
   double* QN = nullptr;              // nk x r orthonormal deflation basis
   // per-solve work vectors (allocated with the factor)
   double* work = nullptr;            // see factor.hip for the carve-up
@@ -136,13 +136,15 @@ namespace lrsdp {
 int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o);
 void factor_release(lrsdp_factor* f);
 int ensure_lowprec(lrsdp_factor* f, int precision, hipStream_t s);
+// bold S^{-1} = L^{-T} L^{-1} as a full symmetric nk x nk matrix (parity export)
+int export_sinv(const lrsdp_factor* f, double* out, hipStream_t s);
 
 // Work-vector views (each m or nk long) inside f->work.
 struct Work {
   // m-vectors
   double *x, *r, *z, *p, *q, *t0, *t1, *t2, *t3, *ylo, *dd0, *dd1;
   // nk-vectors / k x n blocks
-  double *w, *wl, *t, *tl, *s, *sl, *y, *yl, *g0, *g1;
+  double *w, *wl, *t, *tl, *s, *sl, *y, *yl, *g0, *g1, *h;
   // small
   double *kk;     // k x k
   double *part;   // reduction partials

@@ -243,7 +243,7 @@ int spectral_top(const double* W, int n, int k, void* ws, double* lam_out, doubl
     for (int pass = 0; pass < 2; ++pass) {
       const double* src = pass == 0 ? T : Y;
       k_gram<<<b * b, 64, 0, s>>>(b, n, src, src, G);
-      LRSDP_TRY(potrf(G, b, b, flag, Dinv, s));
+      LRSDP_TRY(potrf_inv(G, b, b, Dinv, 64, flag, nullptr, true, s));
       k_lower_apply<<<eg, 256, 0, s>>>(b, n, Dinv, src, pass == 0 ? Y : X);
     }
     return LRSDP_OK;

@@ -150,8 +150,6 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
 
 // ---------------------------------------------------------------- leaf (N <= 64)
 
-constexpr int LW = 8;        // wavefronts of the leaf kernel
-constexpr int LQ = NB / LW;  // columns held per lane
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
@@ -170,82 +168,98 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   return y;
 }
 
-// Cholesky factor L of a diagonal block (N <= 64) and L^{-1}, held in registers.
+// Cholesky factor L of a diagonal block (N <= 64) and L^{-1}, by 8-column panels.
 // Lane i = t % 64 of every wavefront holds row i; wavefront g = t / 64 holds the columns
-// c = 8q + g (q = 0..7) of both the matrix being reduced and the identity being reduced
-// to L^{-1}.  Step j: the owner of column j takes the pivot from its lane j, scales the
-// column to l_cj and publishes it with 1 / l_jj through LDS (double-buffered, one barrier
-// per step); row i > j then subtracts l_ij l_cj from its columns c in (j, i] and
-// l_ij (row j of the reduced identity) / l_jj from its columns c <= j, that row coming
-// from lane j of its own wavefront.  Rows and columns beyond N are the identity.  A
-// non-positive pivot sets *flag and continues with pivot 1.  Writes L (lower, zero above
-// the diagonal) into A and L^{-1} (zero above the diagonal) into Li (li_rows x li_rows).
+// [8g, 8g + 8) of the matrix being reduced and of the identity being reduced to L^{-1}.
+// Panel P: wavefront P factors its eight columns alone (pivots and l_cj by cross-lane reads,
+// no barrier) and publishes them to LDS; after one barrier the wavefronts right of the
+// panel apply its rank-8 update to their columns, and the wavefronts at or left of it
+// apply the panel's eight forward-substitution steps to their identity columns (row j
+// comes from lane j).  Eight barriers in all; each update keeps the order of the
+// unblocked algorithm.  Rows and columns beyond N are the identity.  A non-positive pivot
+// sets *flag and continues with pivot 1.  Writes L (lower, zero above the diagonal) into A
+// and L^{-1} (zero above the diagonal) into Li (li_rows x li_rows).
+constexpr int LW = NB / 8;   // wavefronts of the leaf kernel
+constexpr int LP = NB / LW;  // panel width = columns per wavefront
+
 __global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, int N, int lda,
                                                        int* flag, double* __restrict__ Li,
                                                        int ldi, int li_rows) {
-  __shared__ double col[2][NB];
-  __shared__ double sinv[2];
-  __shared__ double dsq[NB];
+  __shared__ double Ls[NB][NB + 1];
+  __shared__ double dinv[NB];
   const int t = threadIdx.x, i = t & (NB - 1), g = t / NB;
-  double a[LQ], y[LQ];
+  double a[LP], y[LP];
 #pragma unroll
-  for (int q = 0; q < LQ; ++q) {
-    const int c = q * LW + g;
+  for (int q = 0; q < LP; ++q) {
+    const int c = g * LP + q;
     double v = 0.0;
     if (i < N && c <= i) v = A[(size_t)i * lda + c];
     else if (i == c) v = 1.0;
     a[q] = v;
     y[q] = (i == c) ? 1.0 : 0.0;
   }
-  for (int j = 0; j < NB; ++j) {
-    const int qj = j / LW, gj = j % LW;
-    double* cj = col[j & 1];
-    if (g == gj) {  // owner wavefront of column j
-      double v = a[0];
+  for (int P = 0; P < LW; ++P) {
+    const int j0 = P * LP;
+    if (g == P) {  // factor the panel in this wavefront
 #pragma unroll
-      for (int q = 1; q < LQ; ++q)
-        if (q == qj) v = a[q];
-      double piv = readlane_d(v, j);
-      const bool bad = !(piv > 0.0);
-      if (bad) piv = 1.0;
-      const double inv = rsqrt_nr(piv);
-      cj[i] = v * inv;
-      if (i == 0) {
-        sinv[j & 1] = inv;
-        dsq[j] = piv * inv;
-        if (bad && j < N) atomicOr(flag, 1);
+      for (int jj = 0; jj < LP; ++jj) {
+        const int j = j0 + jj;
+        double piv = readlane_d(a[jj], j);
+        const bool bad = !(piv > 0.0);
+        if (bad) piv = 1.0;
+        const double inv = rsqrt_nr(piv);
+        if (i == 0) {
+          dinv[j] = inv;
+          if (bad && j < N) atomicOr(flag, 1);
+        }
+        const double l = (i >= j) ? a[jj] * inv : 0.0;  // column j of L
+        a[jj] = l;
+#pragma unroll
+        for (int qq = jj + 1; qq < LP; ++qq) {
+          const int c = j0 + qq;
+          const double lc = readlane_d(l, c);  // l_cj
+          const double na = fma(-l, lc, a[qq]);
+          a[qq] = (i >= c) ? na : a[qq];
+        }
       }
+#pragma unroll
+      for (int q = 0; q < LP; ++q) Ls[i][j0 + q] = a[q];
     }
     __syncthreads();
-    // every LDS read of the step is issued before any use, and the updates are selects
-    const double inv = sinv[j & 1];
-    double cc[LQ];
+    if (g > P) {  // rank-8 update of this wavefront's columns
+      double li[LP];
 #pragma unroll
-    for (int q = 0; q < LQ; ++q) cc[q] = cj[q * LW + g];
-    const double mlij = -cj[i];
-    const bool below = i > j;
+      for (int jj = 0; jj < LP; ++jj) li[jj] = Ls[i][j0 + jj];
 #pragma unroll
-    for (int q = 0; q < LQ; ++q) {
-      const int c = q * LW + g;  // uniform over the wavefront
-      const double yj = readlane_d(y[q], j);
-      const double na = fma(mlij, cc[q], a[q]);
-      const double ny = fma(mlij, yj * inv, y[q]);
-      a[q] = (below && c > j && c <= i) ? na : a[q];
-      y[q] = (below && c <= j) ? ny : y[q];
+      for (int q = 0; q < LP; ++q) {
+        const int c = g * LP + q;
+        double acc = a[q];
+#pragma unroll
+        for (int jj = 0; jj < LP; ++jj) acc = fma(-li[jj], Ls[c][j0 + jj], acc);
+        a[q] = (i >= c) ? acc : a[q];
+      }
+    } else {  // forward substitution steps j0..j0+7 on this wavefront's identity columns
+#pragma unroll
+      for (int jj = 0; jj < LP; ++jj) {
+        const int j = j0 + jj;
+        const double mlij = -Ls[i][j], dj = dinv[j];
+#pragma unroll
+        for (int q = 0; q < LP; ++q) {
+          if (g * LP + q <= j) {  // uniform over the wavefront
+            const double yj = readlane_d(y[q], j) * dj;
+            const double ny = fma(mlij, yj, y[q]);
+            y[q] = (i > j) ? ny : y[q];
+          }
+        }
+      }
     }
   }
-  __syncthreads();
-  const double di = dsq[i];
+  const double di = dinv[i];
 #pragma unroll
-  for (int q = 0; q < LQ; ++q) {
-    const int c = q * LW + g;
-    if (i < N && c < N) {
-      double l = 0.0;
-      if (c < i) l = a[q] / dsq[c];
-      else if (c == i) l = di;
-      A[(size_t)i * lda + c] = l;
-    }
-    if (i < li_rows && c < li_rows) Li[(size_t)i * ldi + c] = (c <= i) ? y[q] / di : 0.0;
+  for (int q = 0; q < LP; ++q) {
+    const int c = g * LP + q;
+    if (i < N && c < N) A[(size_t)i * lda + c] = (c <= i) ? a[q] : 0.0;
+    if (i < li_rows && c < li_rows) Li[(size_t)i * ldi + c] = (c <= i) ? y[q] * di : 0.0;
   }
 }
 

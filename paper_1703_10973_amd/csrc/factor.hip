@@ -135,6 +135,18 @@ __global__ void k_null_basis(int n, int k, int r, const double* Yt, double* N) {
   N[idx] = v;
 }
 
+// G = Q^T Q (r x r), Q N x r row-major: one workgroup per entry, fixed summation order.
+__global__ __launch_bounds__(kT) void k_gram_cols(int N, int r, const double* __restrict__ Q,
+                                                  double* __restrict__ G) {
+  __shared__ double red[kT / kWave];
+  const int a = blockIdx.x / r, b = blockIdx.x % r;
+  double s = 0.0;
+  for (int p = threadIdx.x; p < N; p += kT)
+    s = fma(Q[(size_t)p * r + a], Q[(size_t)p * r + b], s);
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) G[a * r + b] = s;
+}
+
 __global__ __launch_bounds__(kT) void k_max_diag(const double* S, int N, int ld, double* out) {
   __shared__ double red[kT];
   double m = 0.0;
@@ -413,27 +425,15 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
     // ---- deflation of null(bold U) directions
     if (r) {
       double* Yt = Rb.p;  // k x n: (Z^{-1} U)^T = U Z^{-T}
-      {
-        GemmArgs g;
-        g.M = k; g.N = n; g.K = n;
-        g.A = f->U; g.lda = n;
-        g.B = Zi.p; g.ldb = n; g.transB = true;  // op(B)[q][p] = Z^{-1}[p][q], zero for q > p
-        g.C = Yt; g.ldc = n;
-        g.flags = kKToCol;
-        if ((rc = gemm(g, s))) break;
-      }
+      // Yt[j][p] = sum_{q <= p} Z^{-1}[p][q] U[j][q]
+      if ((rc = rows_k(n, k, Zi.p, 1, f->U, Yt, s))) break;
       double* G = Rb.p + nk;        // r x r Gram matrix
       double* Gi = G + (size_t)r * r;  // the inverse of its Cholesky factor
       k_null_basis<<<grid_for((int64_t)nk * r, 256), 256, 0, s>>>(n, k, r, Yt, f->QN);
       for (int pass = 0; pass < 2 && rc == LRSDP_OK; ++pass) {  // Cholesky QR, twice
         double* Qin = pass == 0 ? f->QN : Q2.p;
         double* Qout = pass == 0 ? Q2.p : f->QN;
-        GemmArgs g;
-        g.M = r; g.N = r; g.K = nk;
-        g.A = Qin; g.lda = r; g.transA = true;
-        g.B = Qin; g.ldb = r;
-        g.C = G; g.ldc = r;
-        if ((rc = gemm(g, s))) break;
+        k_gram_cols<<<r * r, kT, 0, s>>>(nk, r, Qin, G);
         if ((rc = potrf_inv(G, r, r, Gi, r, ctx->d_flag, ptmp.p, true, s))) break;
         GemmArgs h;  // Q <- Q R^{-1} = Q (L^{-1})^T
         h.M = nk; h.N = r; h.K = r;

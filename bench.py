@@ -130,8 +130,11 @@ def main():
     def summ(name):
         r = results[name]
         nsolve = len(r["lat"])
+        setup = [i["setup_ms"] for i in r["infos"]]
+        solve = [i["solve_ms"] for i in r["infos"]]
         return dict(value=nsolve / r["elapsed"], p50_ms=float(np.percentile(r["lat"], 50)),
                     p99_ms=float(np.percentile(r["lat"], 99)),
+                    setup_ms_mean=float(np.mean(setup)), pcg_ms_mean=float(np.mean(solve)),
                     ms_per_step=r["elapsed"] / args.steps * 1e3,
                     relres_max=float(max(checks[name]["relres"])),
                     iters=checks[name]["iters"], outer=checks[name]["outer"],
@@ -180,8 +183,10 @@ def main():
         "relres_max": mixed["relres_max"],
         "pcg_iters": mixed["iters"],
         "outer_iters": mixed["outer"],
+        "setup_ms_mean": mixed["setup_ms_mean"],
+        "pcg_ms_mean": mixed["pcg_ms_mean"],
         "fp64": {k: fp64[k] for k in ("value", "p50_ms", "p99_ms", "ms_per_step", "relres_max",
-                                      "iters", "outer")},
+                                      "iters", "outer", "setup_ms_mean", "pcg_ms_mean")},
         "mixed_over_fp64": mixed["value"] / fp64["value"],
         "kernel_profile_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         "roofline": roof,

@@ -223,6 +223,7 @@ void lrsdp_problem_destroy(lrsdp_problem* p) {
   dev_free(c, p->own_ptr, (n + 1) * 4);
   dev_free(c, p->own_con, m * 4);
   dev_free(c, p->own_oth, m * 4);
+  dev_free(c, p->pat, 2 * m * 4);
   dev_free(c, p->colidx, nnz * 4);
   dev_free(c, p->src, nnz * 4);
   dev_free(c, p->mval, nnz * 8);
@@ -256,6 +257,7 @@ int lrsdp_problem_create(lrsdp_ctx* c, int64_t n, int64_t m, int64_t nnz, const 
     if ((rc = dev_alloc_n(c, &p->own_ptr, (size_t)n + 1))) break;
     if ((rc = dev_alloc_n(c, &p->own_con, (size_t)m))) break;
     if ((rc = dev_alloc_n(c, &p->own_oth, (size_t)m))) break;
+    if ((rc = dev_alloc_n(c, &p->pat, 2 * (size_t)m))) break;
     if ((rc = dev_alloc_n(c, &p->vec_scratch, 4 * (size_t)m))) break;
     ProfScope ps(c);
     rc = ingest(c, p, con, row, col, val, nnz);

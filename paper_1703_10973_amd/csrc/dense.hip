@@ -24,15 +24,16 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int TK = 16;
 constexpr int NB = 64;  // leaf size of the recursive factorizations
 
-// Output tile (32 WM) x (32 WN) per workgroup of WM x WN wavefronts, each wavefront a
-// 32 x 32 block as 2 x 2 MFMA accumulators.  64 x 64 tiles for large products, 32 x 32
-// tiles (one wavefront) when the 64 x 64 grid would leave CUs idle.
-template <bool TA, bool TB, int WM, int WN>
-__global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
-  constexpr int TMv = 32 * WM, TNv = 32 * WN, NT = 64 * WM * WN;
-  constexpr int EA = TMv * TK / NT, EB = TNv * TK / NT;  // staged values per thread
-  __shared__ double As[2][TK][TMv + 4];
-  __shared__ double Bs[2][TK][TNv + 4];
+// Output tile (32 WM) x (32 WN) per workgroup; each of WM x WN wavefront positions owns a
+// 32 x 32 block as 2 x 2 MFMA accumulators, and KS wavefronts share each position by
+// splitting every K chunk of 16 KS columns (intra-workgroup split-K), so one load latency
+// covers KS times more K; the KS partial blocks are summed through LDS in a fixed order.
+template <bool TA, bool TB, int WM, int WN, int KS>
+__global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
+  constexpr int TMv = 32 * WM, TNv = 32 * WN, NT = 64 * WM * WN * KS, TKc = TK * KS;
+  constexpr int EA = TMv * TKc / NT, EB = TNv * TKc / NT;  // staged values per thread
+  __shared__ double As[2][TKc][TMv + 4];
+  __shared__ double Bs[2][TKc][TNv + 4];
   const double* __restrict__ Ap = g.A;
   const double* __restrict__ Bp = g.B;
   double* __restrict__ Cp = g.C;
@@ -57,7 +58,8 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
   const int t = threadIdx.x;
   const int lane = t & 63;
   const int w = t >> 6;
-  const int wm = w / WN, wn = w % WN;
+  const int ks = w / (WM * WN), wmn = w % (WM * WN);
+  const int wm = wmn / WN, wn = wmn % WN;
   const int lr = lane & 15, lk = lane >> 4;
 
   // staging map: consecutive threads walk the contiguous dimension of each operand
@@ -67,7 +69,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
     for (int u = 0; u < EA; ++u) {
       const int e = t + u * NT;
       if (!TA) {
-        const int r = e / TK, kk = e % TK, i = i0 + r, k = k0 + kk;
+        const int r = e / TKc, kk = e % TKc, i = i0 + r, k = k0 + kk;
         ra[u] = (i < g.M && k < khi) ? Ap[(size_t)i * g.lda + k] : 0.0;
       } else {
         const int kk = e / TMv, r = e % TMv, i = i0 + r, k = k0 + kk;
@@ -81,7 +83,7 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
         const int kk = e / TNv, c = e % TNv, j = j0 + c, k = k0 + kk;
         rb[u] = (j < g.N && k < khi) ? Bp[(size_t)k * g.ldb + j] : 0.0;
       } else {
-        const int c = e / TK, kk = e % TK, j = j0 + c, k = k0 + kk;
+        const int c = e / TKc, kk = e % TKc, j = j0 + c, k = k0 + kk;
         rb[u] = (j < g.N && k < khi) ? Bp[(size_t)j * g.ldb + k] : 0.0;
       }
     }
@@ -90,14 +92,14 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
 #pragma unroll
     for (int u = 0; u < EA; ++u) {
       const int e = t + u * NT;
-      if (!TA) As[buf][e % TK][e / TK] = ra[u];
+      if (!TA) As[buf][e % TKc][e / TKc] = ra[u];
       else As[buf][e / TMv][e % TMv] = ra[u];
     }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const int e = t + u * NT;
       if (!TB) Bs[buf][e / TNv][e % TNv] = rb[u];
-      else Bs[buf][e % TK][e / TK] = rb[u];
+      else Bs[buf][e % TKc][e / TKc] = rb[u];
     }
   };
 
@@ -113,15 +115,16 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
   }
   __syncthreads();
   int buf = 0;
-  for (int k0 = klo; k0 < khi; k0 += TK) {
-    const bool more = k0 + TK < khi;
-    if (more) load(k0 + TK);  // next tile's global loads in flight during the MFMAs
+  for (int k0 = klo; k0 < khi; k0 += TKc) {
+    const bool more = k0 + TKc < khi;
+    if (more) load(k0 + TKc);  // next chunk's global loads in flight during the MFMAs
 #pragma unroll
     for (int k4 = 0; k4 < TK; k4 += 4) {
-      const double a0 = As[buf][k4 + lk][wm * 32 + lr];
-      const double a1 = As[buf][k4 + lk][wm * 32 + 16 + lr];
-      const double b0 = Bs[buf][k4 + lk][wn * 32 + lr];
-      const double b1 = Bs[buf][k4 + lk][wn * 32 + 16 + lr];
+      const int kr = ks * TK + k4 + lk;
+      const double a0 = As[buf][kr][wm * 32 + lr];
+      const double a1 = As[buf][kr][wm * 32 + 16 + lr];
+      const double b0 = Bs[buf][kr][wn * 32 + lr];
+      const double b1 = Bs[buf][kr][wn * 32 + 16 + lr];
       acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
       acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
       acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -130,6 +133,32 @@ __global__ __launch_bounds__(64 * WM * WN) void k_gemm(GemmArgs g) {
     if (more) store(buf ^ 1);
     __syncthreads();
     buf ^= 1;
+  }
+
+  if constexpr (KS > 1) {  // fold the K slices: wavefronts ks > 0 park their blocks in LDS
+    static_assert((KS - 1) * WM * WN * 64 * 16 <= 2 * TKc * (TMv + 4), "LDS too small");
+    double* park = &As[0][0][0];
+    if (ks > 0) {
+      double* mine = park + ((size_t)(ks - 1) * WM * WN + wmn) * 64 * 16;
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) mine[((mi * 2 + ni) * 4 + r) * 64 + lane] = acc[mi][ni][r];
+    }
+    __syncthreads();
+    if (ks > 0) return;
+#pragma unroll
+    for (int o = 1; o < KS; ++o) {
+      const double* theirs = park + ((size_t)(o - 1) * WM * WN + wmn) * 64 * 16;
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[mi][ni][r] += theirs[((mi * 2 + ni) * 4 + r) * 64 + lane];
+    }
   }
 
 #pragma unroll
@@ -371,29 +400,31 @@ static void gemm_cost(const GemmArgs& g, int te, double* flops, double* bytes) {
                   (double)g.M * g.N * (g.beta != 0.0 ? 2.0 : 1.0));
 }
 
-template <int WM, int WN>
+template <int WM, int WN, int KS>
 static void launch_gemm(const GemmArgs& g, hipStream_t s) {
   constexpr int te_m = 32 * WM, te_n = 32 * WN;
   const int tiles = ((g.M + te_m - 1) / te_m) * ((g.N + te_n - 1) / te_n);
-  const dim3 grid(tiles, g.offs ? g.batch : 1), block(64 * WM * WN);
+  const dim3 grid(tiles, g.offs ? g.batch : 1), block(64 * WM * WN * KS);
   if (!g.transA && !g.transB)
-    k_gemm<false, false, WM, WN><<<grid, block, 0, s>>>(g);
+    k_gemm<false, false, WM, WN, KS><<<grid, block, 0, s>>>(g);
   else if (!g.transA && g.transB)
-    k_gemm<false, true, WM, WN><<<grid, block, 0, s>>>(g);
+    k_gemm<false, true, WM, WN, KS><<<grid, block, 0, s>>>(g);
   else if (g.transA && !g.transB)
-    k_gemm<true, false, WM, WN><<<grid, block, 0, s>>>(g);
+    k_gemm<true, false, WM, WN, KS><<<grid, block, 0, s>>>(g);
   else
-    k_gemm<true, true, WM, WN><<<grid, block, 0, s>>>(g);
+    k_gemm<true, true, WM, WN, KS><<<grid, block, 0, s>>>(g);
 }
 
 int gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return LRSDP_OK;
-  // 64 x 64 tiles once they alone give every CU a workgroup, else 32 x 32 tiles
+  // 64 x 64 tiles once they alone give every CU a few workgroups; below that 32 x 32 tiles
+  // with four wavefronts splitting K
   const int64_t t64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * (g.offs ? g.batch : 1);
   const int te = t64 >= 512 ? 64 : 32;
   ProfMark pm = prof_begin(LRSDP_K_GEMM, s);
-  if (te == 64) launch_gemm<2, 2>(g, s);
-  else launch_gemm<1, 1>(g, s);
+  if (t64 >= 1024) launch_gemm<2, 2, 1>(g, s);
+  else if (t64 >= 512) launch_gemm<2, 2, 2>(g, s);
+  else launch_gemm<1, 1, 4>(g, s);
   LRSDP_HIP(hipGetLastError());
   if (pm.kid >= 0) {
     double fl = 0.0, by = 0.0;

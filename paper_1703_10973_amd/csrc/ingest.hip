@@ -4,6 +4,8 @@
 // A^T A is diagonal (Assumption 2): g_i = val_i^2 (a == b) or 2 val_i^2.  mat(A v) lives on
 // the symmetric pattern Obar = {(a,b), (b,a)}, stored as CSR with sorted columns so that every
 // product with it accumulates in a fixed order.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace lrsdp {
@@ -111,43 +113,51 @@ __global__ void k_fill(int m, const int32_t* a, const int32_t* b, const int32_t*
   own_oth[op] = oth;
 }
 
-// Sort each CSR row by column (insertion sort: rows are short) and flag duplicates.
-__global__ void k_sort_rows(int n, const int32_t* rowptr, int32_t* colidx, int32_t* src,
-                            int* flag) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
+// Sort each CSR row by column, one wavefront per row: every entry's destination is its
+// rank (entries with a smaller column, ties broken by position), so the result does not
+// depend on scheduling.  Equal columns (a pair given twice) raise kFlagDup.  Sorted keys and
+// payloads go to k2 / p2 and are copied back by the caller.
+__global__ __launch_bounds__(256) void k_rank_sort(int n, const int32_t* __restrict__ ptr,
+                                                   const int32_t* __restrict__ key,
+                                                   const int32_t* __restrict__ pay,
+                                                   int32_t* __restrict__ k2,
+                                                   int32_t* __restrict__ p2, int* flag,
+                                                   int dup_flag) {
+  const int r = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
   if (r >= n) return;
-  int lo = rowptr[r], hi = rowptr[r + 1];
-  for (int i = lo + 1; i < hi; ++i) {
-    int c = colidx[i], s = src[i];
-    int j = i - 1;
-    while (j >= lo && colidx[j] > c) {
-      colidx[j + 1] = colidx[j];
-      src[j + 1] = src[j];
-      --j;
+  const int lo = ptr[r], hi = ptr[r + 1];
+  for (int e = lo + lane; e < hi; e += 64) {
+    const int c = key[e];
+    int rank = 0;
+    bool dup = false;
+    for (int f = lo; f < hi; ++f) {
+      const int d = key[f];
+      rank += (d < c || (d == c && f < e)) ? 1 : 0;
+      dup = dup || (d == c && f != e);
     }
-    colidx[j + 1] = c;
-    src[j + 1] = s;
+    k2[lo + rank] = c;
+    p2[lo + rank] = pay[e];
+    if (dup && dup_flag) atomicOr(flag, dup_flag);
   }
-  for (int i = lo + 1; i < hi; ++i)
-    if (colidx[i] == colidx[i - 1]) atomicOr(flag, kFlagDup);
 }
 
-// Sort each owner list by constraint id so that the work assignment is reproducible.
-__global__ void k_sort_owned(int n, const int32_t* optr, int32_t* con, int32_t* oth) {
-  int r = blockIdx.x * blockDim.x + threadIdx.x;
+// pat[2 i] / pat[2 i + 1]: the pattern entries (a_i, b_i) and (b_i, a_i) of constraint i
+// (the second is -1 on the diagonal).  One thread per row.
+__global__ void k_pattern_map(int n, const int32_t* __restrict__ rowptr,
+                              const int32_t* __restrict__ src, const int32_t* __restrict__ a,
+                              int32_t* __restrict__ pat) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
-  int lo = optr[r], hi = optr[r + 1];
-  for (int i = lo + 1; i < hi; ++i) {
-    int c = con[i], o = oth[i];
-    int j = i - 1;
-    while (j >= lo && con[j] > c) {
-      con[j + 1] = con[j];
-      oth[j + 1] = oth[j];
-      --j;
-    }
-    con[j + 1] = c;
-    oth[j + 1] = o;
+  for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+    const int i = src[e];
+    if (r == a[i]) pat[2 * i] = e;
+    else pat[2 * i + 1] = e;
   }
+}
+
+__global__ void k_fill_i32(int cnt, int32_t* p, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < cnt) p[i] = v;
 }
 
 }  // namespace
@@ -211,8 +221,35 @@ int ingest(lrsdp_ctx* ctx, lrsdp_problem* P, const int32_t* con, const int32_t* 
     if (e3 < 0) { rc = e3; break; }
     k_fill<<<grid_for(m, T), T, 0, s>>>(m, P->a, P->b, P->rowptr, fill, P->colidx, P->src,
                                          P->own_ptr, ofill, P->own_con, P->own_oth);
-    k_sort_rows<<<grid_for(n, 128), 128, 0, s>>>(n, P->rowptr, P->colidx, P->src, ctx->d_flag);
-    k_sort_owned<<<grid_for(n, 128), 128, 0, s>>>(n, P->own_ptr, P->own_con, P->own_oth);
+    {
+      int32_t* tmp = nullptr;  // sorted copies, then copied back
+      const size_t cap = 2 * (size_t)std::max(nnz, m);
+      if ((rc = dev_alloc_n(ctx, &tmp, cap)) < 0) break;
+      k_rank_sort<<<(n + 3) / 4, 256, 0, s>>>(n, P->rowptr, P->colidx, P->src, tmp, tmp + nnz,
+                                               ctx->d_flag, kFlagDup);
+      bool ok = hipMemcpyAsync(P->colidx, tmp, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s) ==
+                    hipSuccess &&
+                hipMemcpyAsync(P->src, tmp + nnz, (size_t)nnz * 4, hipMemcpyDeviceToDevice, s) ==
+                    hipSuccess;
+      if (ok) {
+        k_rank_sort<<<(n + 3) / 4, 256, 0, s>>>(n, P->own_ptr, P->own_con, P->own_oth, tmp,
+                                                 tmp + m, ctx->d_flag, 0);
+        ok = hipMemcpyAsync(P->own_con, tmp, (size_t)m * 4, hipMemcpyDeviceToDevice, s) ==
+                 hipSuccess &&
+             hipMemcpyAsync(P->own_oth, tmp + m, (size_t)m * 4, hipMemcpyDeviceToDevice, s) ==
+                 hipSuccess;
+      }
+      if (ok) {
+        k_fill_i32<<<grid_for(2 * m, T), T, 0, s>>>(2 * m, P->pat, -1);
+        k_pattern_map<<<grid_for(n, 128), 128, 0, s>>>(n, P->rowptr, P->src, P->a, P->pat);
+      }
+      if (hipStreamSynchronize(s) != hipSuccess) ok = false;
+      dev_free(ctx, tmp, cap * sizeof(int32_t));
+      if (!ok) {
+        rc = LRSDP_ERR_DEVICE;
+        break;
+      }
+    }
     if (hipMemcpyAsync(&flag, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess) {

@@ -50,6 +50,7 @@ struct lrsdp_problem {
   int32_t* own_ptr = nullptr;       // n + 1, constraints grouped by the index that computes them
   int32_t* own_con = nullptr;       // m, constraint id
   int32_t* own_oth = nullptr;       // m, the other index of the pair
+  int32_t* pat = nullptr;           // 2 m, pattern entries (a,b) and (b,a) of each constraint
   double* mval = nullptr;           // nnz scratch: values of mat(A v) in pattern order
   double* vec_scratch = nullptr;    // 4 m scratch for parity hooks
   size_t bytes = 0;

@@ -58,6 +58,7 @@ extern "C" {
 #define LRSDP_ERR_INDEFINITE_PRECOND -9   /* PCG met r^T z <= 0 or p^T H p <= 0                */
 #define LRSDP_ERR_DEVICE            -10   /* a HIP runtime call failed                          */
 #define LRSDP_ERR_EIG               -11   /* the symmetric eigensolver did not converge         */
+#define LRSDP_PENDING                 2   /* lrsdp_server_poll: the request has not finished   */
 
 /* ------------------------------------------------------------------ handles */
 typedef struct lrsdp_ctx lrsdp_ctx;          /* device, stream, HBM budget                     */
@@ -128,13 +129,16 @@ LRSDP_API int lrsdp_ctx_memory(const lrsdp_ctx* ctx, size_t* in_use, size_t* bud
  * class.  `enable` is a bit mask of classes (bit LRSDP_K_*; -1 all, 0 off); every call resets
  * the counters.  Used by benchmarks to compute roofline fractions. */
 #define LRSDP_K_HV      0   /* fused scatter -> SpMM -> sampled-gather H v kernel (A5/A7)     */
-#define LRSDP_K_GEMM    1   /* FP64 MFMA GEMM (bold S formation, POTRF/TRTRI/LAUUM updates)   */
+#define LRSDP_K_GEMM    1   /* FP64 MFMA GEMM (bold S formation, Cholesky/inverse updates)    */
 #define LRSDP_K_TRI     2   /* Householder tridiagonalization step (A1)                       */
-#define LRSDP_K_GEMV    3   /* bold S^{-1} w GEMV (A6)                                         */
+#define LRSDP_K_GEMV    3   /* bold S^{-1} w = L^{-T} (L^{-1} w), two triangular GEMVs (A6)    */
 #define LRSDP_K_BZ      4   /* sparse B_JL Z pass of bold S formation (A3)                    */
 #define LRSDP_K_RESDD   5   /* double-double residual r - H y (A8)                            */
 #define LRSDP_K_COUNT   6
 LRSDP_API int lrsdp_ctx_profile(lrsdp_ctx* ctx, int enable);
+/* Time only one launch in `every` (>= 1) of each enabled class, so that a timed run is not
+ * slowed by the events; counts restart.  Default 1. */
+LRSDP_API int lrsdp_ctx_profile_sample(lrsdp_ctx* ctx, int every);
 /* Counters of one kernel class; every output is host and may be NULL. */
 LRSDP_API int lrsdp_ctx_profile_read(const lrsdp_ctx* ctx, int kernel_class, int64_t* launches,
                                      double* total_ms, double* bytes, double* flops);
@@ -203,6 +207,57 @@ LRSDP_API int lrsdp_residual_dd(lrsdp_factor* f, const double* r, const double* 
  * NOT_CONVERGED, STAGNATED, INDEFINITE_PRECOND, INVALID_ARG or DEVICE. */
 LRSDP_API int lrsdp_solve(lrsdp_factor* f, const double* r, double* y, double* y_lo,
                 const lrsdp_opts* opts, lrsdp_info* info);
+
+/* ------------------------------------------------------------------ many instances */
+/* One Hessian-equation instance: the constraint triplets (as for lrsdp_problem_create), the
+ * scaling matrix W (n x n), k, the right-hand side r (m) and the outputs y, y_lo (m; y_lo may
+ * be NULL when the options never ask for the double-double pair).  Every pointer is a device
+ * pointer owned by the caller; inputs must be complete before submission and stay unchanged,
+ * and outputs untouched, until the instance has finished. */
+typedef struct lrsdp_instance {
+  int64_t n, m;
+  int32_t k;
+  const int32_t* con;
+  const int32_t* row;
+  const int32_t* col;
+  const double* val;
+  const double* W;
+  const double* r;
+  double* y;
+  double* y_lo;
+} lrsdp_instance;
+
+/* Independent instances (a batch of interior-point solves, or one per outer iteration of
+ * several SDPs): each is A0 + Algorithm 1 steps 1-3, run concurrently by `workers` host
+ * threads, each with its own stream on ctx's device.  Results are bitwise the same as those of
+ * lrsdp_problem_create + lrsdp_factor_create + lrsdp_solve on one instance alone.  status and
+ * info (host arrays of length count; info may be NULL) receive each instance's outcome.
+ * Returns OK once every instance has finished (whatever its status), INVALID_ARG or DEVICE. */
+LRSDP_API int lrsdp_solve_batch(lrsdp_ctx* ctx, int count, const lrsdp_instance* inst,
+                                const lrsdp_opts* opts, int workers, int* status,
+                                lrsdp_info* info);
+
+/* Serving: requests are queued and taken by `workers` host threads (own streams) as they
+ * arrive, each while the estimated device memory of the instances in flight stays within
+ * hbm_budget_bytes (0: no cap; a request larger than the cap runs alone).  submit copies the
+ * instance descriptor and options and returns a ticket (host); poll reports LRSDP_PENDING
+ * until the request has finished, then OK with its status and info (host, may be NULL).
+ * With wait != 0 poll blocks until the request finishes.  A ticket is released by the poll
+ * that returns OK.  destroy waits for every submitted request. */
+typedef struct lrsdp_server lrsdp_server;
+LRSDP_API int lrsdp_server_create(lrsdp_ctx* ctx, int workers, size_t hbm_budget_bytes,
+                                  lrsdp_server** out);
+LRSDP_API int lrsdp_server_submit(lrsdp_server* srv, const lrsdp_instance* inst,
+                                  const lrsdp_opts* opts, uint64_t* ticket);
+LRSDP_API int lrsdp_server_poll(lrsdp_server* srv, uint64_t ticket, int wait, int* status,
+                                lrsdp_info* info);
+/* Requests queued, running and finished-but-unpolled, and the estimated bytes in flight;
+ * every output is host and may be NULL. */
+LRSDP_API int lrsdp_server_stats(lrsdp_server* srv, int* queued, int* running, int* done,
+                                 size_t* bytes_in_flight);
+LRSDP_API void lrsdp_server_destroy(lrsdp_server* srv);
+/* Device bytes one instance is estimated to hold at its peak (setup). */
+LRSDP_API size_t lrsdp_instance_bytes(int64_t n, int64_t m, int32_t k);
 
 #ifdef __cplusplus
 }

@@ -18,11 +18,15 @@ from ._lib import (  # noqa: F401
     LRSDP_DD_AUTO, LRSDP_DD_OFF, LRSDP_DD_ON, LRSDP_PREC_BF16, LRSDP_PREC_FP32, LRSDP_TAU_MEAN,
     LRSDP_TAU_MIN,
     LRSDP_PREC_FP64, LrsdpError, header_symbols, lib, lrsdp_ctx_create, lrsdp_ctx_destroy,
-    lrsdp_ctx_memory, lrsdp_ctx_profile, lrsdp_ctx_profile_read, LRSDP_K_NAMES,
+    lrsdp_ctx_memory, lrsdp_ctx_profile, lrsdp_ctx_profile_read, lrsdp_ctx_profile_sample,
+    LRSDP_K_NAMES,
     lrsdp_factor_create, lrsdp_factor_destroy, lrsdp_factor_export,
     lrsdp_hessian_apply, lrsdp_hessian_apply_split, lrsdp_info, lrsdp_opts,
     lrsdp_opts_default, lrsdp_precond_apply, lrsdp_problem_create, lrsdp_problem_destroy,
-    lrsdp_problem_info, lrsdp_residual_dd, lrsdp_solve, status_string)
+    lrsdp_problem_info, lrsdp_residual_dd, lrsdp_solve, status_string, lrsdp_instance,
+    make_instance, lrsdp_solve_batch, lrsdp_server_create, lrsdp_server_submit,
+    lrsdp_server_poll, lrsdp_server_stats, lrsdp_server_destroy, lrsdp_instance_bytes,
+    LRSDP_PENDING)
 
 
 def opts(**kw):
@@ -48,7 +52,9 @@ class Context:
     def memory(self):
         return lrsdp_ctx_memory(self.handle)
 
-    def profile(self, enable=True):
+    def profile(self, enable=True, every=1):
+        """Time kernel classes (bit mask) with HIP events, one launch in `every`."""
+        lrsdp_ctx_profile_sample(self.handle, every)
         lrsdp_ctx_profile(self.handle, enable)
 
     def profile_read(self):
@@ -149,3 +155,50 @@ class Factor:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Request server over the C ABI: submit instances, poll their results.  Each request
+    keeps references to its tensors until its result has been polled."""
+
+    def __init__(self, ctx: "Context", workers=8, hbm_budget_bytes=0):
+        self.ctx = ctx
+        self.handle = None
+        self.handle = lrsdp_server_create(ctx.handle, workers, hbm_budget_bytes)
+        self._keep = {}
+        ctx._children.add(self)
+
+    def submit(self, n, k, con, row, col, val, W, r, y, y_lo=None, options=None):
+        inst = make_instance(n, k, con, row, col, val, W, r, y, y_lo)
+        t = lrsdp_server_submit(self.handle, inst, options)
+        self._keep[t] = (con, row, col, val, W, r, y, y_lo)
+        return t
+
+    def poll(self, ticket, wait=False):
+        out = lrsdp_server_poll(self.handle, ticket, wait)
+        if out is not None:
+            self._keep.pop(ticket, None)
+        return out
+
+    def stats(self):
+        return lrsdp_server_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            lrsdp_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_batch(ctx: "Context", instances, options=None, workers=8):
+    """instances: list of dicts with n, k, con, row, col, val, W, r, y and optionally y_lo
+    (torch device tensors).  Returns (statuses, infos)."""
+    insts = [make_instance(d["n"], d["k"], d["con"], d["row"], d["col"], d["val"], d["W"],
+                           d["r"], d["y"], d.get("y_lo")) for d in instances]
+    return lrsdp_solve_batch(ctx.handle, insts, options, workers)

@@ -29,6 +29,7 @@ LRSDP_ERR_STAGNATED = -8
 LRSDP_ERR_INDEFINITE_PRECOND = -9
 LRSDP_ERR_DEVICE = -10
 LRSDP_ERR_EIG = -11
+LRSDP_PENDING = 2
 
 LRSDP_PREC_FP64, LRSDP_PREC_FP32, LRSDP_PREC_BF16 = 0, 1, 2
 LRSDP_DD_OFF, LRSDP_DD_ON, LRSDP_DD_AUTO = 0, 1, 2
@@ -51,6 +52,12 @@ class lrsdp_info(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class lrsdp_instance(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("k", C.c_int32), ("con", C.c_void_p),
+                ("row", C.c_void_p), ("col", C.c_void_p), ("val", C.c_void_p),
+                ("W", C.c_void_p), ("r", C.c_void_p), ("y", C.c_void_p), ("y_lo", C.c_void_p)]
+
+
 class LrsdpError(RuntimeError):
     def __init__(self, status, where):
         self.status = status
@@ -67,6 +74,7 @@ _SIGS = {
     "lrsdp_ctx_destroy": (None, [_P]),
     "lrsdp_ctx_memory": (C.c_int, [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "lrsdp_ctx_profile": (C.c_int, [_P, C.c_int]),
+    "lrsdp_ctx_profile_sample": (C.c_int, [_P, C.c_int]),
     "lrsdp_ctx_profile_read": (C.c_int, [_P, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "lrsdp_problem_create": (C.c_int, [_P, C.c_int64, C.c_int64, C.c_int64, _P, _P, _P, _P,
@@ -84,6 +92,17 @@ _SIGS = {
     "lrsdp_precond_apply": (C.c_int, [_P, _P, _P, C.c_int]),
     "lrsdp_residual_dd": (C.c_int, [_P, _P, _P, _P, _P, C.POINTER(C.c_double)]),
     "lrsdp_solve": (C.c_int, [_P, _P, _P, _P, C.POINTER(lrsdp_opts), C.POINTER(lrsdp_info)]),
+    "lrsdp_solve_batch": (C.c_int, [_P, C.c_int, C.POINTER(lrsdp_instance), C.POINTER(lrsdp_opts),
+                                    C.c_int, C.POINTER(C.c_int), C.POINTER(lrsdp_info)]),
+    "lrsdp_server_create": (C.c_int, [_P, C.c_int, C.c_size_t, C.POINTER(_P)]),
+    "lrsdp_server_submit": (C.c_int, [_P, C.POINTER(lrsdp_instance), C.POINTER(lrsdp_opts),
+                                      C.POINTER(C.c_uint64)]),
+    "lrsdp_server_poll": (C.c_int, [_P, C.c_uint64, C.c_int, C.POINTER(C.c_int),
+                                    C.POINTER(lrsdp_info)]),
+    "lrsdp_server_stats": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                     C.POINTER(C.c_int), C.POINTER(C.c_size_t)]),
+    "lrsdp_server_destroy": (None, [_P]),
+    "lrsdp_instance_bytes": (C.c_size_t, [C.c_int64, C.c_int64, C.c_int32]),
 }
 
 
@@ -181,6 +200,10 @@ def lrsdp_ctx_profile(ctx, enable):
     _ok(lib().lrsdp_ctx_profile(ctx, int(enable)), "lrsdp_ctx_profile")
 
 
+def lrsdp_ctx_profile_sample(ctx, every):
+    _ok(lib().lrsdp_ctx_profile_sample(ctx, int(every)), "lrsdp_ctx_profile_sample")
+
+
 def lrsdp_ctx_profile_read(ctx, kernel_class):
     n, ms, by, fl = C.c_int64(), C.c_double(), C.c_double(), C.c_double()
     _ok(lib().lrsdp_ctx_profile_read(ctx, int(kernel_class), C.byref(n), C.byref(ms), C.byref(by),
@@ -271,3 +294,68 @@ def lrsdp_solve(f, r, y, y_lo=None, opts=None):
     if st < 0 and st != LRSDP_ERR_STAGNATED:
         raise LrsdpError(st, "lrsdp_solve")
     return st, info.as_dict()
+
+
+# ----------------------------------------------------------------- many instances
+
+def make_instance(n, k, con, row, col, val, W, r, y, y_lo=None):
+    """An lrsdp_instance over torch device tensors (the caller keeps them alive)."""
+    m = r.numel()
+    return lrsdp_instance(int(n), int(m), int(k), _ptr(con, torch.int32, m, "con"),
+                          _ptr(row, torch.int32, m, "row"), _ptr(col, torch.int32, m, "col"),
+                          _ptr(val, torch.float64, m, "val"),
+                          _ptr(W, torch.float64, int(n) * int(n), "W"),
+                          _ptr(r, torch.float64, m, "r"), _ptr(y, torch.float64, m, "y"),
+                          _ptr(y_lo, torch.float64, m, "y_lo"))
+
+
+def lrsdp_solve_batch(ctx, instances, opts=None, workers=8):
+    """Solve every instance; returns (statuses, infos)."""
+    cnt = len(instances)
+    arr = (lrsdp_instance * max(cnt, 1))(*instances)
+    st = (C.c_int * max(cnt, 1))()
+    inf = (lrsdp_info * max(cnt, 1))()
+    _ok(lib().lrsdp_solve_batch(ctx, cnt, arr, C.byref(opts) if opts is not None else None,
+                                int(workers), st, inf), "lrsdp_solve_batch")
+    return [st[i] for i in range(cnt)], [inf[i].as_dict() for i in range(cnt)]
+
+
+def lrsdp_server_create(ctx, workers=8, hbm_budget_bytes=0):
+    out = _P()
+    _ok(lib().lrsdp_server_create(ctx, int(workers), int(hbm_budget_bytes), C.byref(out)),
+        "lrsdp_server_create")
+    return out
+
+
+def lrsdp_server_submit(srv, inst, opts=None):
+    t = C.c_uint64()
+    _ok(lib().lrsdp_server_submit(srv, C.byref(inst), C.byref(opts) if opts is not None else None,
+                                  C.byref(t)), "lrsdp_server_submit")
+    return t.value
+
+
+def lrsdp_server_poll(srv, ticket, wait=False):
+    """None while pending, else (status, info)."""
+    st = C.c_int()
+    inf = lrsdp_info()
+    rc = lib().lrsdp_server_poll(srv, C.c_uint64(ticket), int(bool(wait)), C.byref(st), C.byref(inf))
+    if rc == LRSDP_PENDING:
+        return None
+    _ok(rc, "lrsdp_server_poll")
+    return st.value, inf.as_dict()
+
+
+def lrsdp_server_stats(srv):
+    q, r, d, b = C.c_int(), C.c_int(), C.c_int(), C.c_size_t()
+    _ok(lib().lrsdp_server_stats(srv, C.byref(q), C.byref(r), C.byref(d), C.byref(b)),
+        "lrsdp_server_stats")
+    return dict(queued=q.value, running=r.value, done=d.value, bytes_in_flight=b.value)
+
+
+def lrsdp_server_destroy(srv):
+    if srv:
+        lib().lrsdp_server_destroy(srv)
+
+
+def lrsdp_instance_bytes(n, m, k):
+    return int(lib().lrsdp_instance_bytes(int(n), int(m), int(k)))

@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblrsdp.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["api.hip", "ingest.hip", "hv.hip", "dense.hip", "eig.hip", "spectral.hip", "factor.hip",
+SOURCES = ["api.hip", "ingest.hip", "hv.hip", "dense.hip", "eig.hip", "spectral.hip", "serve.hip", "factor.hip",
            "apply.hip", "pcg.hip"]
 
 HIP_FLAGS = [

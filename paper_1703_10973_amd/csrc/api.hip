@@ -1,5 +1,6 @@
 // The C ABI declared in include/lrsdp.h: handles, validation, budget accounting.
 #include <chrono>
+#include <iterator>
 #include <cstring>
 #include <new>
 
@@ -7,23 +8,60 @@
 
 namespace lrsdp {
 
+// Device memory is cached per context: a freed block returns to a free list keyed by its
+// rounded size and is handed out again by a later request of that size.  hipFree (which
+// waits for the whole device) then runs only when the cache outgrows its cap or the context
+// ends, so concurrent contexts do not stall each other, and stream order on the context's one
+// stream makes reuse safe.  The budget counts the bytes held by live handles.
+static size_t pool_size_class(size_t bytes) {
+  const size_t q = bytes >= ((size_t)1 << 20) ? ((size_t)1 << 20) : 4096;
+  return (bytes + q - 1) / q * q;
+}
+
+static void pool_trim(lrsdp_ctx* ctx, size_t keep) {
+  for (auto it = ctx->pool.begin(); it != ctx->pool.end() && ctx->pooled > keep;) {
+    while (!it->second.empty() && ctx->pooled > keep) {
+      (void)hipFree(it->second.back());
+      it->second.pop_back();
+      ctx->pooled -= it->first;
+    }
+    it = it->second.empty() ? ctx->pool.erase(it) : std::next(it);
+  }
+}
+
 int dev_alloc(lrsdp_ctx* ctx, void** p, size_t bytes) {
   *p = nullptr;
   if (bytes == 0) return LRSDP_OK;
-  if (ctx->budget && ctx->in_use + bytes > ctx->budget) return LRSDP_ERR_OUT_OF_BUDGET;
-  if (hipMalloc(p, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return LRSDP_ERR_OUT_OF_BUDGET;
+  const size_t sz = pool_size_class(bytes);
+  if (ctx->budget && ctx->in_use + sz > ctx->budget) return LRSDP_ERR_OUT_OF_BUDGET;
+  auto it = ctx->pool.find(sz);
+  if (it != ctx->pool.end() && !it->second.empty()) {
+    *p = it->second.back();
+    it->second.pop_back();
+    ctx->pooled -= sz;
+    ctx->in_use += sz;
+    return LRSDP_OK;
   }
-  ctx->in_use += bytes;
+  if (hipMalloc(p, sz) != hipSuccess) {
+    (void)hipGetLastError();
+    pool_trim(ctx, 0);  // give the cache back and try once more
+    if (hipMalloc(p, sz) != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return LRSDP_ERR_OUT_OF_BUDGET;
+    }
+  }
+  ctx->in_use += sz;
   return LRSDP_OK;
 }
 
 void dev_free(lrsdp_ctx* ctx, void* p, size_t bytes) {
   if (!p) return;
-  (void)hipFree(p);
-  ctx->in_use -= bytes;
+  const size_t sz = pool_size_class(bytes);
+  ctx->pool[sz].push_back(p);
+  ctx->pooled += sz;
+  ctx->in_use -= sz;
+  if (ctx->pooled > ctx->pool_cap) pool_trim(ctx, ctx->pool_cap / 2);
 }
 
 thread_local Profiler* tls_prof = nullptr;
@@ -42,6 +80,7 @@ static hipEvent_t prof_event(Profiler* p) {
 ProfMark prof_begin(int kid, hipStream_t s) {
   ProfMark mk;
   if (!prof_on() || !(tls_prof->mask & (1u << kid))) return mk;
+  if (tls_prof->seen[kid]++ % tls_prof->every != 0) return mk;
   mk.a = prof_event(tls_prof);
   if (!mk.a || hipEventRecord(mk.a, s) != hipSuccess) {
     mk.a = nullptr;
@@ -173,6 +212,7 @@ void lrsdp_ctx_destroy(lrsdp_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   prof_flush(&c->prof);
   for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+  pool_trim(c, 0);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->d_flag) (void)hipFree(c->d_flag);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -187,6 +227,14 @@ int lrsdp_ctx_profile(lrsdp_ctx* c, int enable) {
   for (auto& st : c->prof.stat) st = ProfStat();
   c->prof.enabled = enable != 0;
   c->prof.mask = static_cast<unsigned>(enable);
+  for (auto& v : c->prof.seen) v = 0;
+  return LRSDP_OK;
+}
+
+int lrsdp_ctx_profile_sample(lrsdp_ctx* c, int every) {
+  if (!c || every < 1) return LRSDP_ERR_INVALID_ARG;
+  c->prof.every = every;
+  for (auto& v : c->prof.seen) v = 0;
   return LRSDP_OK;
 }
 

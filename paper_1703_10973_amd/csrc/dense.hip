@@ -198,24 +198,27 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 }
 
 // Cholesky factor L of a diagonal block (N <= 64) and L^{-1}, by 8-column panels.
-// Lane i = t % 64 of every wavefront holds row i; wavefront g = t / 64 holds the columns
-// [8g, 8g + 8) of the matrix being reduced and of the identity being reduced to L^{-1}.
-// Panel P: wavefront P factors its eight columns alone (pivots and l_cj by cross-lane reads,
-// no barrier) and publishes them to LDS; after one barrier the wavefronts right of the
-// panel apply its rank-8 update to their columns, and the wavefronts at or left of it
-// apply the panel's eight forward-substitution steps to their identity columns (row j
-// comes from lane j).  Eight barriers in all; each update keeps the order of the
-// unblocked algorithm.  Rows and columns beyond N are the identity.  A non-positive pivot
-// sets *flag and continues with pivot 1.  Writes L (lower, zero above the diagonal) into A
-// and L^{-1} (zero above the diagonal) into Li (li_rows x li_rows).
+// The matrix being reduced sits in registers as rows: lane i = t % 64 holds row i, and
+// wavefront g = t / 64 the columns [8g, 8g + 8).  L^{-1} is built by forward substitution
+// on the identity in the transposed layout: lane c holds column c and wavefront g the rows
+// [8g, 8g + 8).  Panel P:
+//   wavefront P factors its eight columns alone (pivots and l_cj by cross-lane reads, no
+//   barrier), finishes rows [8P, 8P + 8) of L^{-1} (an 8 x 8 forward substitution whose
+//   coefficients are the panel's own l values, uniform across lanes), and publishes both;
+//   after one barrier every wavefront g > P applies the panel's rank-8 update to its columns
+//   of the matrix and to its rows of L^{-1}.
+// Eight barriers in all; every update keeps the order of the unblocked algorithm.  Rows and
+// columns beyond N are the identity.  A non-positive pivot sets *flag and continues with
+// pivot 1.  Writes L (lower, zero above the diagonal) into A and L^{-1} (zero above the
+// diagonal) into Li (li_rows x li_rows).
 constexpr int LW = NB / 8;   // wavefronts of the leaf kernel
-constexpr int LP = NB / LW;  // panel width = columns per wavefront
+constexpr int LP = NB / LW;  // panel width = columns (rows of L^{-1}) per wavefront
 
 __global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, int N, int lda,
                                                        int* flag, double* __restrict__ Li,
                                                        int ldi, int li_rows) {
-  __shared__ double Ls[NB][NB + 1];
-  __shared__ double dinv[NB];
+  __shared__ double Ls[NB][NB + 1];  // L, published panel by panel
+  __shared__ double Xs[NB][NB];      // finished rows of L^{-1}
   const int t = threadIdx.x, i = t & (NB - 1), g = t / NB;
   double a[LP], y[LP];
 #pragma unroll
@@ -225,23 +228,21 @@ __global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, i
     if (i < N && c <= i) v = A[(size_t)i * lda + c];
     else if (i == c) v = 1.0;
     a[q] = v;
-    y[q] = (i == c) ? 1.0 : 0.0;
+    y[q] = (c == i) ? 1.0 : 0.0;  // row c = 8g + q, column i (lane) of the identity
   }
   for (int P = 0; P < LW; ++P) {
     const int j0 = P * LP;
-    if (g == P) {  // factor the panel in this wavefront
+    if (g == P) {  // factor the panel, then finish rows j0..j0+7 of L^{-1}
+      double inv[LP];
 #pragma unroll
       for (int jj = 0; jj < LP; ++jj) {
         const int j = j0 + jj;
         double piv = readlane_d(a[jj], j);
         const bool bad = !(piv > 0.0);
         if (bad) piv = 1.0;
-        const double inv = rsqrt_nr(piv);
-        if (i == 0) {
-          dinv[j] = inv;
-          if (bad && j < N) atomicOr(flag, 1);
-        }
-        const double l = (i >= j) ? a[jj] * inv : 0.0;  // column j of L
+        inv[jj] = rsqrt_nr(piv);
+        if (bad && i == 0 && j < N) atomicOr(flag, 1);
+        const double l = (i >= j) ? a[jj] * inv[jj] : 0.0;  // column j of L
         a[jj] = l;
 #pragma unroll
         for (int qq = jj + 1; qq < LP; ++qq) {
@@ -252,43 +253,47 @@ __global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, i
         }
       }
 #pragma unroll
-      for (int q = 0; q < LP; ++q) Ls[i][j0 + q] = a[q];
-    }
-    __syncthreads();
-    if (g > P) {  // rank-8 update of this wavefront's columns
-      double li[LP];
+      for (int jj = 0; jj < LP; ++jj) {
+        y[jj] *= inv[jj];  // row j of L^{-1} is final
 #pragma unroll
-      for (int jj = 0; jj < LP; ++jj) li[jj] = Ls[i][j0 + jj];
+        for (int kk = jj + 1; kk < LP; ++kk)
+          y[kk] = fma(-readlane_d(a[jj], j0 + kk), y[jj], y[kk]);
+      }
 #pragma unroll
       for (int q = 0; q < LP; ++q) {
-        const int c = g * LP + q;
-        double acc = a[q];
-#pragma unroll
-        for (int jj = 0; jj < LP; ++jj) acc = fma(-li[jj], Ls[c][j0 + jj], acc);
-        a[q] = (i >= c) ? acc : a[q];
+        Ls[i][j0 + q] = a[q];
+        Xs[j0 + q][i] = y[q];
       }
-    } else {  // forward substitution steps j0..j0+7 on this wavefront's identity columns
+    }
+    __syncthreads();
+    if (g > P) {  // rank-8 updates of this wavefront's matrix columns and L^{-1} rows
+      double li[LP], xj[LP];
 #pragma unroll
       for (int jj = 0; jj < LP; ++jj) {
-        const int j = j0 + jj;
-        const double mlij = -Ls[i][j], dj = dinv[j];
+        li[jj] = Ls[i][j0 + jj];
+        xj[jj] = Xs[j0 + jj][i];
+      }
 #pragma unroll
-        for (int q = 0; q < LP; ++q) {
-          if (g * LP + q <= j) {  // uniform over the wavefront
-            const double yj = readlane_d(y[q], j) * dj;
-            const double ny = fma(mlij, yj, y[q]);
-            y[q] = (i > j) ? ny : y[q];
-          }
+      for (int q = 0; q < LP; ++q) {
+        const int c = g * LP + q;  // matrix column c / L^{-1} row c (uniform)
+        double acc = a[q], yacc = y[q];
+#pragma unroll
+        for (int jj = 0; jj < LP; ++jj) {
+          const double lcj = Ls[c][j0 + jj];
+          acc = fma(-li[jj], lcj, acc);
+          yacc = fma(-lcj, xj[jj], yacc);
         }
+        a[q] = (i >= c) ? acc : a[q];
+        y[q] = yacc;
       }
     }
   }
-  const double di = dinv[i];
 #pragma unroll
   for (int q = 0; q < LP; ++q) {
     const int c = g * LP + q;
     if (i < N && c < N) A[(size_t)i * lda + c] = (c <= i) ? a[q] : 0.0;
-    if (i < li_rows && c < li_rows) Li[(size_t)i * ldi + c] = (c <= i) ? y[q] * di : 0.0;
+    // lane i holds column i of row c of L^{-1}
+    if (c < li_rows && i < li_rows) Li[(size_t)c * ldi + i] = (i <= c) ? y[q] : 0.0;
   }
 }
 
@@ -417,13 +422,14 @@ static void launch_gemm(const GemmArgs& g, hipStream_t s) {
 
 int gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return LRSDP_OK;
-  // 64 x 64 tiles once they alone give every CU a few workgroups; below that 32 x 32 tiles
-  // with four wavefronts splitting K
+  // 32 x 32 tiles with four wavefronts splitting K for small products, 64 x 64 tiles with
+  // two for medium ones, plain 64 x 64 tiles once they alone fill the chip several times
   const int64_t t64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * (g.offs ? g.batch : 1);
-  const int te = t64 >= 512 ? 64 : 32;
+  // (thresholds from a sweep of the factorization's shapes)
+  const int te = t64 >= 320 ? 64 : 32;
   ProfMark pm = prof_begin(LRSDP_K_GEMM, s);
-  if (t64 >= 1024) launch_gemm<2, 2, 1>(g, s);
-  else if (t64 >= 512) launch_gemm<2, 2, 2>(g, s);
+  if (t64 >= 2048) launch_gemm<2, 2, 1>(g, s);
+  else if (t64 >= 320) launch_gemm<2, 2, 2>(g, s);
   else launch_gemm<1, 1, 4>(g, s);
   LRSDP_HIP(hipGetLastError());
   if (pm.kid >= 0) {

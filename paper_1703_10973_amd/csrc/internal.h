@@ -1,6 +1,9 @@
 // Handles and kernel launchers of the Hessian-equation solver (internal).
 #pragma once
 
+#include <unordered_map>
+#include <vector>
+
 #include "common.h"
 
 namespace lrsdp {
@@ -13,6 +16,8 @@ struct ProfStat {
 struct Profiler {
   bool enabled = false;
   unsigned mask = 0;  // bit i: time kernel class i
+  int every = 1;      // time one launch in `every` of each class
+  int64_t seen[LRSDP_K_COUNT] = {};
   ProfStat stat[LRSDP_K_COUNT];
   struct Pending {
     int kid;
@@ -32,6 +37,9 @@ struct lrsdp_ctx {
   bool own_stream = false;
   size_t budget = 0;   // 0: unlimited
   size_t in_use = 0;
+  std::unordered_map<size_t, std::vector<void*>> pool;  // cached device blocks by size
+  size_t pooled = 0;                       // bytes in the cache
+  size_t pool_cap = (size_t)16 << 30;      // the cache is trimmed beyond this
   double* h_pinned = nullptr;   // small pinned host staging area (scalars)
   int* d_flag = nullptr;        // device error/status word
 };

@@ -1,0 +1,129 @@
+"""Many independent instances through the C ABI: the batch call and the request server.
+
+An instance solved in a batch or by the server must give bitwise the answer it gets alone
+(same kernels, same launch shapes, no cross-instance reductions), and every answer must meet
+the true-residual target checked by the oracle's double-double residual.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import dd as ddo
+from synth import batch_instances, draw_serving_shape, make_instance
+
+pytestmark = pytest.mark.gpu
+
+pk = pytest.importorskip("paper_1703_10973_amd")
+from gpu_util import host, to_dev  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = pk.Context(0)
+    yield c
+    c.close()
+
+
+def _device_instance(inst):
+    con, row, col, val = inst.triplets()
+    d = dict(n=inst.n, k=inst.k, con=to_dev(con, torch.int32), row=to_dev(row, torch.int32),
+             col=to_dev(col, torch.int32), val=to_dev(val), W=to_dev(inst.W), r=to_dev(inst.r))
+    d["y"] = torch.zeros(inst.m, dtype=torch.float64, device="cuda")
+    d["y_lo"] = torch.zeros(inst.m, dtype=torch.float64, device="cuda")
+    return d
+
+
+def _alone(ctx, inst, opts):
+    d = _device_instance(inst)
+    P = pk.Problem(ctx, inst.n, inst.m, d["con"], d["row"], d["col"], d["val"])
+    F = pk.Factor(P, d["W"], inst.k, opts)
+    y, ylo, st, info = F.solve(d["r"], opts)
+    out = (host(y), host(ylo), st)
+    F.close()
+    P.close()
+    return out
+
+
+def _check_residual(inst, yh, yl):
+    r_true, _ = ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val, inst.r, yh, yl)
+    assert r_true <= 1e-8, (inst.n, inst.k, inst.m, inst.mu, r_true)
+
+
+def test_batch_matches_alone(ctx):
+    """Batched-workload shapes (n in [64, 512], k in 1..4, mu = 1e-6): a batch of 10 on four
+    workers, each instance bitwise equal to its solve alone."""
+    insts = batch_instances(10, base_seed=3000)
+    opts = pk.opts(dd_mode=pk.LRSDP_DD_AUTO)
+    devs = [_device_instance(i) for i in insts]
+    torch.cuda.synchronize()
+    st, info = pk.solve_batch(ctx, devs, opts, workers=4)
+    assert all(s == 0 for s in st), st
+    for inst, d, inf in zip(insts, devs, info):
+        yh, yl = host(d["y"]), host(d["y_lo"])
+        ya, yla, sta = _alone(ctx, inst, opts)
+        assert sta == 0
+        assert np.array_equal(yh, ya) and np.array_equal(yl, yla), (inst.n, inst.k)
+        assert inf["iters"] > 0
+        _check_residual(inst, yh, yl)
+
+
+def test_batch_empty_and_errors(ctx):
+    assert pk.solve_batch(ctx, [], None, workers=2) == ([], [])
+    inst = make_instance(40, 2, 200, 1e-2, seed=3)
+    d = _device_instance(inst)
+    d["k"] = 40  # k must be below n
+    st, _ = pk.solve_batch(ctx, [d], None, workers=1)
+    assert st == [pk._lib.LRSDP_ERR_INVALID_ARG]
+
+
+@pytest.mark.parametrize("budget", [0, 1])
+def test_server_mixed_stream(ctx, budget):
+    """Serving-style requests of mixed shape and mu submitted at once; budget 1 byte admits
+    one request at a time.  Every result equals the instance solved alone."""
+    shapes = []
+    for s in range(50000, 50040):
+        n, k, m, mu = draw_serving_shape(s)
+        if n <= 400:           # keep the test small
+            shapes.append((n, k, m, mu, s))
+        if len(shapes) == 6:
+            break
+    insts = [make_instance(n, k, m, mu, seed=s) for (n, k, m, mu, s) in shapes]
+    opts = pk.opts(dd_mode=pk.LRSDP_DD_AUTO)
+    srv = pk.Server(ctx, workers=3, hbm_budget_bytes=budget)
+    devs = [_device_instance(i) for i in insts]
+    torch.cuda.synchronize()
+    tickets = [srv.submit(d["n"], d["k"], d["con"], d["row"], d["col"], d["val"], d["W"],
+                          d["r"], d["y"], d["y_lo"], opts) for d in devs]
+    peak = 0
+    for t in tickets:
+        out = srv.poll(t, wait=True)
+        assert out is not None
+        st, info = out
+        assert st == 0, info
+        peak = max(peak, srv.stats()["bytes_in_flight"])
+    assert srv.stats() == dict(queued=0, running=0, done=0, bytes_in_flight=0)
+    srv.close()
+    for inst, d in zip(insts, devs):
+        yh, yl = host(d["y"]), host(d["y_lo"])
+        ya, yla, _ = _alone(ctx, inst, opts)
+        assert np.array_equal(yh, ya) and np.array_equal(yl, yla)
+        _check_residual(inst, yh, yl)
+
+
+def test_server_poll_pending_and_unknown_ticket(ctx):
+    inst = make_instance(300, 3, 4000, 1e-4, seed=11)
+    d = _device_instance(inst)
+    srv = pk.Server(ctx, workers=1)
+    torch.cuda.synchronize()
+    t = srv.submit(d["n"], d["k"], d["con"], d["row"], d["col"], d["val"], d["W"], d["r"],
+                   d["y"], d["y_lo"])
+    first = srv.poll(t)        # may or may not have finished yet
+    if first is None:
+        first = srv.poll(t, wait=True)
+    assert first[0] == 0
+    with pytest.raises(pk.LrsdpError):
+        srv.poll(t)            # released by the poll that returned the result
+    srv.close()

@@ -41,12 +41,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mu-path",
-                    choices=["mu-path", "batch", "serving", "large", "copy-calibration"],
+                    choices=["mu-path", "batch", "serving", "large", "single",
+                             "copy-calibration"],
                     help="mu-path (default): the headline line; batch: 256 independent "
                          "instances (n in [64, 512], k in 1..4, mu = 1e-6); serving: Poisson "
                          "request stream (n in [200, 3000], k in 1..8, mu in [1e-8, 1e-2]); "
-                         "large: n=4000 k=10 m=400000 mu=1e-8; copy-calibration: a plain "
-                         "device copy of known size, for scaling HBM counters")
+                         "large: n=4000 k=10 m=400000 mu=1e-8; single: one mixed-mode solve "
+                         "of the mu=1e-2 instance of the default workload, untimed (for counter "
+                         "runs); copy-calibration: a plain device copy of known size, for "
+                         "scaling HBM counters")
     ap.add_argument("--count", type=int, default=0, help="instances / requests (batch, serving)")
     ap.add_argument("--qps", type=float, default=4.0, help="serving arrival rate")
     ap.add_argument("--workers", type=int, default=16)
@@ -61,7 +64,7 @@ def main():
         sys.exit(2)
     if args.workload != "mu-path":
         return {"batch": run_batch, "serving": run_serving, "large": run_large,
-                "copy-calibration": run_copy}[args.workload](args)
+                "single": run_single, "copy-calibration": run_copy}[args.workload](args)
     import torch
 
     import paper_1703_10973_amd as pk
@@ -180,6 +183,8 @@ def main():
                     launches=dstat["launches"], avg_us=avg_ms * 1e3,
                     profiled_ms_per_step=prof_ms_per_step)
 
+    roof["traffic"] = hbm_traffic(dom)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(insts, args.cpu_seconds)
@@ -216,6 +221,24 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+
+
+def hbm_traffic(kernel_class):
+    """HBM bytes per launch of a kernel class from the committed hardware-counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None when the class
+    was not measured or its source has changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)["classes"][kernel_class]
+        src = os.path.join(ROOT, "paper_1703_10973_amd", "csrc", rec["source"])
+        with open(src, "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def _device_inputs(inst, torch, dev):
@@ -356,6 +379,29 @@ def run_large(args):
     ctx.close()
 
 
+def run_single(args):
+    """One mixed-mode solve (A0 + Algorithm 1) of the mu = 1e-2 instance of the default
+    workload, after one warm-up solve; prints its status (for hardware-counter runs)."""
+    import torch
+
+    import paper_1703_10973_amd as pk
+    from synth import make_instance
+    dev = torch.device("cuda", 0)
+    inst = make_instance(N, K, M, MUS[0], SEED)
+    d = _device_inputs(inst, torch, dev)
+    ctx = pk.Context(0)
+    opts = pk.opts(precision=pk.LRSDP_PREC_FP32, dd_mode=pk.LRSDP_DD_ON)
+    for _ in range(2):
+        P = pk.Problem(ctx, inst.n, inst.m, d["con"], d["row"], d["col"], d["val"])
+        F = pk.Factor(P, d["W"], inst.k, opts)
+        y, ylo, st, info = F.solve(d["r"], opts)
+        F.close()
+        P.close()
+    torch.cuda.synchronize()
+    print(json.dumps({"status": st, "iters": info["iters"], "outer_iters": info["outer_iters"]}))
+    ctx.close()
+
+
 def run_copy(args):
     """A plain device copy of 1 GiB, five times (scale reference for HBM byte counters)."""
     import torch
@@ -384,7 +430,7 @@ def cpu_baseline(insts, budget_s):
             solved += 1
             if len(res) < len(easy):
                 res.append(out.iters)
-        if time.perf_counter() - t0 > budget_s * 0.5 or solved >= 8:
+        if time.perf_counter() - t0 > budget_s * 0.5 or solved >= 12:
             break
     el = time.perf_counter() - t0
     try:

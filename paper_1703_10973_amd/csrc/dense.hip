@@ -358,7 +358,8 @@ __global__ __launch_bounds__(256) void k_gemv(const double* __restrict__ A, int 
 }
 
 // y = tri(A) x with tri the lower (upper = 0) or upper (upper = 1) triangle including the
-// diagonal; one wavefront per row.
+// diagonal; one wavefront per row, eight independent accumulators so that eight loads per
+// lane are in flight (the rows are long and the product is bound by HBM).
 __global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, int N, int lda,
                                                   const double* __restrict__ x,
                                                   double* __restrict__ y, int upper) {
@@ -367,10 +368,16 @@ __global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, 
   if (row >= N) return;
   const double* a = A + (size_t)row * lda;
   const int lo = upper ? row : 0, hi = upper ? N : row + 1;
-  double s = 0.0;
-  for (int c = lo + lane; c < hi; c += 64) s = fma(a[c], x[c], s);
-  s = wave_sum(s);
-  if (lane == 0) y[row] = s;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int c = lo + lane;
+  for (; c + 7 * 64 < hi; c += 8 * 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] = fma(a[c + u * 64], x[c + u * 64], s[u]);
+  }
+  for (int u = 0; c < hi; c += 64, ++u) s[u] = fma(a[c], x[c], s[u]);
+  double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  t = wave_sum(t);
+  if (lane == 0) y[row] = t;
 }
 
 int split64(int N) {

@@ -85,18 +85,21 @@ __global__ __launch_bounds__(kT) void k_PJ(int n, int k, const int32_t* rowptr,
 }
 
 // d_JL[a] = sum_{b in Obar(a)} u_J[b] u_L[b] for every pair J >= L (pair index J(J+1)/2 + L).
-__global__ void k_dJL(int n, int k, const int32_t* rowptr, const int32_t* colidx,
-                      const double* U, double* d) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= n) return;
+// One wavefront per row a; its lanes share the row's entries, then a wave reduction per pair.
+__global__ __launch_bounds__(256) void k_dJL(int n, int k, const int32_t* rowptr,
+                                             const int32_t* colidx, const double* U, double* d) {
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (a >= n) return;  // whole wavefront
+  const int lo = rowptr[a], hi = rowptr[a + 1];
   for (int J = 0; J < k; ++J)
     for (int L = 0; L <= J; ++L) {
       double s = 0.0;
-      for (int e = rowptr[a]; e < rowptr[a + 1]; ++e) {
+      for (int e = lo + lane; e < hi; e += 64) {
         const int b = colidx[e];
         s = fma(U[(size_t)J * n + b], U[(size_t)L * n + b], s);
       }
-      d[(size_t)(J * (J + 1) / 2 + L) * n + a] = s;
+      s = wave_sum(s);
+      if (lane == 0) d[(size_t)(J * (J + 1) / 2 + L) * n + a] = s;
     }
 }
 
@@ -279,6 +282,7 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
   f->work_doubles = work_doubles(n, P->m, k);
   LRSDP_TRY(dev_alloc_n(ctx, &f->work, f->work_doubles));
   LRSDP_TRY(dev_alloc_n(ctx, &f->sc, (size_t)64));
+  LRSDP_HIP(hipMemsetAsync(f->sc, 0, 64 * sizeof(double), ctx->stream));  // scalars, counters
   f->bytes = (k + 1 + 5 * nn + (size_t)nk + (size_t)nk * nk + (size_t)nk * r + f->work_doubles +
               64) * sizeof(double);
 
@@ -375,7 +379,7 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
     {
       ProfMark pm = prof_begin(LRSDP_K_BZ, s);
       k_PJ<<<dim3(n, (n + kT - 1) / kT), kT, 0, s>>>(n, k, P->rowptr, P->colidx, f->U, f->Z, PJ.p);
-      k_dJL<<<grid_for(n, 128), 128, 0, s>>>(n, k, P->rowptr, P->colidx, f->U, dd_.p);
+      k_dJL<<<(n + 3) / 4, 256, 0, s>>>(n, k, P->rowptr, P->colidx, f->U, dd_.p);
       prof_end(pm, s, 8.0 * ((double)k + 1) * nn + 12.0 * P->nnz,
                2.0 * (double)P->nnz * n * k);
     }

@@ -21,28 +21,50 @@ constexpr int kT = 256;
 constexpr int kG = 256;  // partial sums per reduction
 
 // scalar slots
-enum : int { kRho0 = 0, kRho1 = 1, kPQ = 2, kRR = 3, kRR0 = 4, kMisc = 8 };
+enum : int { kRho0 = 0, kRho1 = 1, kPQ = 2, kRR = 3, kRR0 = 4, kMisc = 8, kCounter = 32 };
 
-__global__ __launch_bounds__(kT) void k_dot_part(int m, const double* a, const double* b,
-                                                 double* part) {
+// True in every thread of the workgroup that finishes last.  Each workgroup's partial is
+// written before its arrival is counted (release); the last one then reads all partials
+// (acquire) and sums them in index order, so the result does not depend on scheduling.
+__device__ __forceinline__ bool arrive_last(int* counter) {
+  __shared__ int last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(counter, 1) == (int)gridDim.x - 1;
+    if (last) __threadfence();
+  }
+  __syncthreads();
+  return last != 0;
+}
+
+// *out = sum of part[0..kG) (called by the last workgroup), counter reset for the next use
+__device__ __forceinline__ void finish_sum(const double* part, int* counter, double* out,
+                                           double* red) {
+  const volatile double* vp = part;
+  double s = (threadIdx.x < kG) ? vp[threadIdx.x] : 0.0;
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    *out = s;
+    *counter = 0;
+  }
+}
+
+// *out = a . b in one launch: per-workgroup partials, summed by the last workgroup
+__global__ __launch_bounds__(kT) void k_dot(int m, const double* a, const double* b,
+                                            double* part, int* counter, double* out) {
   __shared__ double red[kT / kWave];
   double s = 0.0;
   for (int i = blockIdx.x * kT + threadIdx.x; i < m; i += kG * kT) s = fma(a[i], b[i], s);
   s = block_sum(s, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (arrive_last(counter)) finish_sum(part, counter, out, red);
 }
 
-__global__ __launch_bounds__(kT) void k_dot_final(const double* part, double* out) {
-  __shared__ double red[kT / kWave];
-  double s = (threadIdx.x < kG) ? part[threadIdx.x] : 0.0;
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) *out = s;
-}
-
-// alpha = rho / pq;  y += alpha p;  r -= alpha q;  partial sums of r.r
-__global__ __launch_bounds__(kT) void k_update_xr(int m, const double* sc, int rho_slot,
-                                                  double* x, double* r, const double* p,
-                                                  const double* q, double* part) {
+// alpha = rho / pq;  y += alpha p;  r -= alpha q;  sc[kRR] = r.r
+__global__ __launch_bounds__(kT) void k_update_xr(int m, double* sc, int rho_slot, double* x,
+                                                  double* r, const double* p, const double* q,
+                                                  double* part, int* counter) {
   __shared__ double red[kT / kWave];
   const double alpha = sc[rho_slot] / sc[kPQ];
   double s = 0.0;
@@ -54,6 +76,7 @@ __global__ __launch_bounds__(kT) void k_update_xr(int m, const double* sc, int r
   }
   s = block_sum(s, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
+  if (arrive_last(counter)) finish_sum(part, counter, sc + kRR, red);
 }
 
 // p = z + (rho_new / rho_old) p
@@ -88,9 +111,13 @@ __global__ void k_round_pair(int m, double* yh, const double* yl) {
     yh[i] = yh[i] + yl[i];
 }
 
-int dot(int m, const double* a, const double* b, double* part, double* out, hipStream_t s) {
-  k_dot_part<<<kG, kT, 0, s>>>(m, a, b, part);
-  k_dot_final<<<1, kT, 0, s>>>(part, out);
+// The reduction counter lives in the factor's scalar block (zeroed at setup, reset by every
+// reduction's last workgroup).
+int* red_counter(const lrsdp_factor* f) { return reinterpret_cast<int*>(f->sc + kCounter); }
+
+int dot(const lrsdp_factor* f, int m, const double* a, const double* b, double* part,
+        double* out, hipStream_t s) {
+  k_dot<<<kG, kT, 0, s>>>(m, a, b, part, red_counter(f), out);
   return LRSDP_OK;
 }
 
@@ -120,9 +147,9 @@ int pcg(lrsdp_factor* f, const double* b, double eps, int max_iter, HM Hmul, PM 
   const int vg = grid_for(m, kT, 1024);
   k_zero<<<vg, kT, 0, s>>>(m, w.x);
   k_copy<<<vg, kT, 0, s>>>(m, b, w.r);
-  LRSDP_TRY(dot(m, w.r, w.r, w.part, sc + kRR0, s));
+  LRSDP_TRY(dot(f, m, w.r, w.r, w.part, sc + kRR0, s));
   LRSDP_TRY(Pinv(w.r, w.z));
-  LRSDP_TRY(dot(m, w.r, w.z, w.part, sc + kRho0, s));
+  LRSDP_TRY(dot(f, m, w.r, w.z, w.part, sc + kRho0, s));
   k_copy<<<vg, kT, 0, s>>>(m, w.z, w.p);
   double h[8];
   LRSDP_TRY(read_scalars(ctx, sc, 8, h));
@@ -142,9 +169,8 @@ int pcg(lrsdp_factor* f, const double* b, double eps, int max_iter, HM Hmul, PM 
   int cur = kRho0, nxt = kRho1;
   for (int it = 1; it <= max_iter; ++it) {
     LRSDP_TRY(Hmul(w.p, w.q));
-    LRSDP_TRY(dot(m, w.p, w.q, w.part, sc + kPQ, s));
-    k_update_xr<<<kG, kT, 0, s>>>(m, sc, cur, w.x, w.r, w.p, w.q, w.part);
-    k_dot_final<<<1, kT, 0, s>>>(w.part, sc + kRR);
+    LRSDP_TRY(dot(f, m, w.p, w.q, w.part, sc + kPQ, s));
+    k_update_xr<<<kG, kT, 0, s>>>(m, sc, cur, w.x, w.r, w.p, w.q, w.part, red_counter(f));
     LRSDP_TRY(read_scalars(ctx, sc, 8, h));
     out->iters = it;
     const double rel = std::sqrt(std::fmax(h[kRR], 0.0) / rr0);
@@ -158,7 +184,7 @@ int pcg(lrsdp_factor* f, const double* b, double eps, int max_iter, HM Hmul, PM 
       return LRSDP_OK;
     }
     LRSDP_TRY(Pinv(w.r, w.z));
-    LRSDP_TRY(dot(m, w.r, w.z, w.part, sc + nxt, s));
+    LRSDP_TRY(dot(f, m, w.r, w.z, w.part, sc + nxt, s));
     k_update_p<<<vg, kT, 0, s>>>(m, sc, nxt, cur, w.z, w.p);
     std::swap(cur, nxt);
   }
@@ -174,8 +200,8 @@ int residual_dd(lrsdp_factor* f, const double* r, const double* y, const double*
   const Work w = work_view(f);
   const int m = f->P->m;
   LRSDP_TRY(hv_residual_dd(f->P, f->W, r, y, ylo, res, res_lo, s));
-  LRSDP_TRY(dot(m, res, res, w.part, f->sc + kMisc, s));
-  LRSDP_TRY(dot(m, r, r, w.part, f->sc + kMisc + 1, s));
+  LRSDP_TRY(dot(f, m, res, res, w.part, f->sc + kMisc, s));
+  LRSDP_TRY(dot(f, m, r, r, w.part, f->sc + kMisc + 1, s));
   double h[2];
   LRSDP_HIP(hipMemcpyAsync(ctx->h_pinned, f->sc + kMisc, 2 * sizeof(double),
                            hipMemcpyDeviceToHost, s));

@@ -40,6 +40,47 @@ __global__ __launch_bounds__(64) void k_gram(int b, int n, const double* X, cons
   if (lane == 0) G[i * b + j] = s;
 }
 
+// Cholesky G = L L^T of the b x b Gram matrix (b <= 16) and L^{-1} into Linv (row pitch 64),
+// in one wavefront: lane i holds row i; pivots and column values come by cross-lane reads.
+// A non-positive pivot sets *flag.
+__global__ __launch_bounds__(64) void k_small_chol_inv(int b, const double* G, double* Linv,
+                                                       int* flag) {
+  const int i = threadIdx.x;
+  double a[BMAX], y[BMAX];
+#pragma unroll
+  for (int c = 0; c < BMAX; ++c) {
+    a[c] = (i < b && c < b && c <= i) ? G[i * b + c] : (i == c ? 1.0 : 0.0);
+    y[c] = (i == c) ? 1.0 : 0.0;
+  }
+#pragma unroll
+  for (int j = 0; j < BMAX; ++j) {
+    if (j >= b) break;
+    double piv = __shfl(a[j], j);
+    if (!(piv > 0.0)) {
+      if (i == 0) atomicOr(flag, 1);
+      piv = 1.0;
+    }
+    const double inv = 1.0 / sqrt(piv);
+    const double l = (i >= j) ? a[j] * inv : 0.0;  // column j of L
+    a[j] = l;
+#pragma unroll
+    for (int c = j + 1; c < BMAX; ++c) {
+      const double lc = __shfl(l, c);
+      if (i >= c) a[c] = fma(-l, lc, a[c]);
+    }
+    // forward substitution on the identity: row j of L^{-1} is y_j / l_jj
+#pragma unroll
+    for (int c = 0; c <= j; ++c) {
+      const double yj = __shfl(y[c], j) * inv;
+      if (i == j) y[c] = yj;
+      else if (i > j) y[c] = fma(-l, yj, y[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < BMAX; ++c)
+    if (i < b && c < b) Linv[i * 64 + c] = (c <= i) ? y[c] : 0.0;
+}
+
 // Scale each row of T to unit length (one wavefront per row).
 __global__ __launch_bounds__(64) void k_row_normalize(int n, double* T) {
   const int i = blockIdx.x, lane = threadIdx.x;
@@ -243,7 +284,7 @@ int spectral_top(const double* W, int n, int k, void* ws, double* lam_out, doubl
     for (int pass = 0; pass < 2; ++pass) {
       const double* src = pass == 0 ? T : Y;
       k_gram<<<b * b, 64, 0, s>>>(b, n, src, src, G);
-      LRSDP_TRY(potrf_inv(G, b, b, Dinv, 64, flag, nullptr, true, s));
+      k_small_chol_inv<<<1, 64, 0, s>>>(b, G, Dinv, flag);
       k_lower_apply<<<eg, 256, 0, s>>>(b, n, Dinv, src, pass == 0 ? Y : X);
     }
     return LRSDP_OK;

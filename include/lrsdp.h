@@ -69,6 +69,8 @@ typedef struct lrsdp_factor lrsdp_factor;    /* W and the preconditioner factors
 #define LRSDP_PREC_FP64   0   /* H v with W in FP64                                            */
 #define LRSDP_PREC_FP32   1   /* split H v: W0 part in FP32 (FP32 accumulation), rest FP64/dd  */
 #define LRSDP_PREC_BF16   2   /* split H v: W0 part with BF16 operands, FP32 accumulation      */
+#define LRSDP_PREC_AUTO   3   /* FP32 split when the solve refines in double-double anyway     */
+                              /* (mu small, see dd_mode), else plain FP64 PCG                   */
 
 #define LRSDP_DD_OFF      0   /* plain PCG in FP64, answer in y only                            */
 #define LRSDP_DD_ON       1   /* outer refinement with double-double residual, answer y + y_lo  */

@@ -31,7 +31,7 @@ LRSDP_ERR_DEVICE = -10
 LRSDP_ERR_EIG = -11
 LRSDP_PENDING = 2
 
-LRSDP_PREC_FP64, LRSDP_PREC_FP32, LRSDP_PREC_BF16 = 0, 1, 2
+LRSDP_PREC_FP64, LRSDP_PREC_FP32, LRSDP_PREC_BF16, LRSDP_PREC_AUTO = 0, 1, 2, 3
 LRSDP_DD_OFF, LRSDP_DD_ON, LRSDP_DD_AUTO = 0, 1, 2
 LRSDP_TAU_MIN, LRSDP_TAU_MEAN = 0, 1
 

@@ -64,6 +64,21 @@ void dev_free(lrsdp_ctx* ctx, void* p, size_t bytes) {
   if (ctx->pooled > ctx->pool_cap) pool_trim(ctx, ctx->pool_cap / 2);
 }
 
+int ctx_side(lrsdp_ctx* ctx, SideStream* out) {
+  if (!ctx->side) {
+    if (hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking) != hipSuccess) {
+      ctx->side = nullptr;
+      return LRSDP_ERR_DEVICE;
+    }
+    for (hipEvent_t& e : ctx->side_ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return LRSDP_ERR_DEVICE;
+  }
+  out->stream = ctx->side;
+  out->ev = ctx->side_ev;
+  out->depths = (int)(sizeof(ctx->side_ev) / sizeof(ctx->side_ev[0])) / 2;
+  return LRSDP_OK;
+}
+
 thread_local Profiler* tls_prof = nullptr;
 
 static hipEvent_t prof_event(Profiler* p) {
@@ -132,7 +147,7 @@ struct DeviceGuard {
 };
 
 bool opts_valid(const lrsdp_opts& o) {
-  return o.eps > 0.0 && o.max_iter >= 1 && o.precision >= 0 && o.precision <= 2 &&
+  return o.eps > 0.0 && o.max_iter >= 1 && o.precision >= 0 && o.precision <= 3 &&
          o.dd_mode >= 0 && o.dd_mode <= 2 && o.max_outer >= 0 && o.inner_eps > 0.0 &&
          o.inner_eps < 1.0 && o.dd_precond >= 0 && o.dd_precond <= 2 && o.tau_rule >= 0 &&
          o.tau_rule <= 1;
@@ -212,6 +227,12 @@ void lrsdp_ctx_destroy(lrsdp_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   prof_flush(&c->prof);
   for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    for (hipEvent_t e : c->side_ev)
+      if (e) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(c->side);
+  }
   pool_trim(c, 0);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->d_flag) (void)hipFree(c->d_flag);

@@ -43,9 +43,19 @@ int gemm(const GemmArgs& g, hipStream_t s);
 // L under the same zero convention; without it, A is used as scratch and left undefined.
 // tmp: potrf_inv_tmp_doubles(N) doubles.  On a non-positive pivot *flag (device int) gets 1
 // and the result is garbage.
+// A second stream on which the factorization runs the one product per recursion node that
+// the rest of the node does not wait for (P = L21 L11^{-1}, needed only at the node's end),
+// with events to join it back; ev holds two events per recursion depth.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t* ev = nullptr;
+  int depths = 0;
+};
+// The context's side stream and events (created on first use).
+int ctx_side(lrsdp_ctx* ctx, SideStream* out);
 size_t potrf_inv_tmp_doubles(int N);
 int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
-              bool want_L, hipStream_t s);
+              bool want_L, hipStream_t s, const SideStream* side = nullptr);
 // y = M_up (M_lo x) with M_lo the lower and M_up the upper triangle of M, both including the
 // diagonal (two row-wise triangular GEMVs; tmp: N doubles).  With L^{-1} in the lower
 // triangle and its transpose mirrored into the upper one this is y = L^{-T} L^{-1} x.

@@ -448,14 +448,21 @@ int gemm(const GemmArgs& g, hipStream_t s) {
   return LRSDP_OK;
 }
 
+// Scratch: a node keeps its L21 in tmp[0, N1 N2) while its trailing factorization runs on
+// tmp beyond it (the side-stream product may still be reading L21 then).
 size_t potrf_inv_tmp_doubles(int N) {
   if (N <= NB) return 0;
   const int N1 = split64(N), N2 = N - N1;
-  return std::max({(size_t)N1 * N2, potrf_inv_tmp_doubles(N1), potrf_inv_tmp_doubles(N2)});
+  return (size_t)N1 * N2 + std::max(potrf_inv_tmp_doubles(N1), potrf_inv_tmp_doubles(N2));
 }
 
-int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
-              bool want_L, hipStream_t s) {
+// nodes at least this large move P to the side stream (below it the events cost more than
+// the overlap gains)
+constexpr int kSideMin = 512;
+
+static int potrf_inv_rec(double* A, int N, int lda, double* Li, int ldi, int* flag,
+                         double* tmp, bool want_L, hipStream_t s, const SideStream* side,
+                         int depth) {
   if (N <= 0) return LRSDP_OK;
   if (N <= NB) {
     k_chol_leaf<<<1, NB * LW, 0, s>>>(A, N, lda, flag, Li, ldi, N);
@@ -467,7 +474,8 @@ int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double*
   double* A22 = A21 + N1;
   double* Li21 = Li + (size_t)N1 * ldi;
   double* Li22 = Li21 + N1;
-  LRSDP_TRY(potrf_inv(A, N1, lda, Li, ldi, flag, tmp, want_L, s));
+  double* sub = tmp + (size_t)N1 * N2;  // the children's scratch
+  LRSDP_TRY(potrf_inv_rec(A, N1, lda, Li, ldi, flag, tmp, want_L, s, side, depth + 1));
   {  // tmp = L21 = A21 L11^{-T}
     GemmArgs g;
     g.M = N2; g.N = N1; g.K = N1;
@@ -478,7 +486,8 @@ int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double*
     LRSDP_TRY(gemm(g, s));
   }
   // L21 lives in A21 when the caller wants L (then P = L21 L11^{-1} waits in tmp, after the
-  // trailing factorization); otherwise L21 stays in tmp and P overwrites A21 at once.
+  // trailing factorization); otherwise L21 stays in tmp and P overwrites A21 at once, on
+  // the side stream when there is one.
   const double* L21 = tmp;
   int ld21 = N1;
   if (want_L) {
@@ -487,6 +496,25 @@ int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double*
     LRSDP_HIP(hipGetLastError());
     L21 = A21;
     ld21 = lda;
+  }
+  GemmArgs pg;  // P = L21 L11^{-1}
+  pg.M = N2; pg.N = N1; pg.K = N1;
+  pg.A = L21; pg.lda = ld21;
+  pg.B = Li; pg.ldb = ldi;  // L11^{-1}[k][j], zero for k < j
+  pg.flags = kKFromCol;
+  const bool use_side = !want_L && side && side->stream && N >= kSideMin && depth < side->depths;
+  hipEvent_t ev_in = use_side ? side->ev[2 * depth] : nullptr;
+  hipEvent_t ev_out = use_side ? side->ev[2 * depth + 1] : nullptr;
+  if (!want_L) {
+    pg.C = A21; pg.ldc = lda;
+    if (use_side) {
+      LRSDP_HIP(hipEventRecord(ev_in, s));
+      LRSDP_HIP(hipStreamWaitEvent(side->stream, ev_in, 0));
+      LRSDP_TRY(gemm(pg, side->stream));
+      LRSDP_HIP(hipEventRecord(ev_out, side->stream));
+    } else {
+      LRSDP_TRY(gemm(pg, s));
+    }
   }
   {  // A22 -= L21 L21^T (lower)
     GemmArgs g;
@@ -497,20 +525,12 @@ int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double*
     g.alpha = -1.0; g.beta = 1.0; g.flags = kLowerOut;
     LRSDP_TRY(gemm(g, s));
   }
-  GemmArgs pg;  // P = L21 L11^{-1}
-  pg.M = N2; pg.N = N1; pg.K = N1;
-  pg.A = L21; pg.lda = ld21;
-  pg.B = Li; pg.ldb = ldi;  // L11^{-1}[k][j], zero for k < j
-  pg.flags = kKFromCol;
-  if (!want_L) {
-    pg.C = A21; pg.ldc = lda;
-    LRSDP_TRY(gemm(pg, s));
-  }
-  LRSDP_TRY(potrf_inv(A22, N2, lda, Li22, ldi, flag, tmp, want_L, s));
+  LRSDP_TRY(potrf_inv_rec(A22, N2, lda, Li22, ldi, flag, sub, want_L, s, side, depth + 1));
   if (want_L) {
     pg.C = tmp; pg.ldc = N1;
     LRSDP_TRY(gemm(pg, s));
   }
+  if (use_side) LRSDP_HIP(hipStreamWaitEvent(s, ev_out, 0));
   {  // (L^{-1})_21 = -L22^{-1} P
     GemmArgs g;
     g.M = N2; g.N = N1; g.K = N2;
@@ -521,6 +541,11 @@ int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double*
     LRSDP_TRY(gemm(g, s));
   }
   return LRSDP_OK;
+}
+
+int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
+              bool want_L, hipStream_t s, const SideStream* side) {
+  return potrf_inv_rec(A, N, lda, Li, ldi, flag, tmp, want_L, s, side, 0);
 }
 
 int trmv_pair(const double* M, int N, int ld, const double* x, double* tmp, double* y,

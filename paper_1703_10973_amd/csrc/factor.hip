@@ -472,7 +472,9 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
     }
     // the factor keeps L^{-1} in the lower triangle and L^{-T} in the upper one, so that
     // bold S^{-1} w = L^{-T} (L^{-1} w) is two row-wise triangular GEMVs
-    if ((rc = potrf_inv(S, nk, nk, f->Sinv, nk, ctx->d_flag, ptmp.p, false, s))) break;
+    SideStream side;
+    if ((rc = ctx_side(ctx, &side))) break;
+    if ((rc = potrf_inv(S, nk, nk, f->Sinv, nk, ctx->d_flag, ptmp.p, false, s, &side))) break;
     int fl = 0;
     if ((rc = read_flag(ctx, &fl))) break;
     if (fl) {

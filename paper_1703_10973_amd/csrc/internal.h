@@ -40,6 +40,8 @@ struct lrsdp_ctx {
   std::unordered_map<size_t, std::vector<void*>> pool;  // cached device blocks by size
   size_t pooled = 0;                       // bytes in the cache
   size_t pool_cap = (size_t)16 << 30;      // the cache is trimmed beyond this
+  hipStream_t side = nullptr;   // second stream of the factorization (created on first use)
+  hipEvent_t side_ev[48] = {};  // its join events, two per recursion depth
   double* h_pinned = nullptr;   // small pinned host staging area (scalars)
   int* d_flag = nullptr;        // device error/status word
 };

@@ -229,7 +229,11 @@ int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lr
   if (o.dd_mode == LRSDP_DD_ON) use_dd = true;
   else if (o.dd_mode == LRSDP_DD_OFF) use_dd = false;
   else use_dd = f->tau < o.dd_auto_ratio * f->lam[1];
-  const bool refine = use_dd || o.precision != LRSDP_PREC_FP64;
+  // AUTO: the low-precision W0 product pays only inside refinement, which the solve needs
+  // anyway once the answer is a double-double pair; otherwise plain FP64 PCG is cheaper
+  const int prec = o.precision == LRSDP_PREC_AUTO ? (use_dd ? LRSDP_PREC_FP32 : LRSDP_PREC_FP64)
+                                                  : o.precision;
+  const bool refine = use_dd || prec != LRSDP_PREC_FP64;
   // SMW pieces: double-double when tau^2 is within a few units of u ||bold S|| (dd_precond on
   // or auto with tau < 1e-7 lambda_max), else FP64 with one refinement step of bold S^{-1} w
   // once tau / lambda_max < 1e-3 (where the explicit inverse alone loses definiteness).
@@ -259,7 +263,7 @@ int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lr
     k_zero<<<vg, kT, 0, s>>>(m, y);
     k_zero<<<vg, kT, 0, s>>>(m, yl);
     auto Hm = [&](const double* v, double* out) -> int {
-      return split_apply(f, v, out, o.precision, s);
+      return split_apply(f, v, out, prec, s);
     };
     double best = 1e300;
     int stall = 0;

@@ -40,21 +40,21 @@ __global__ __launch_bounds__(64) void k_gram(int b, int n, const double* X, cons
   if (lane == 0) G[i * b + j] = s;
 }
 
-// Cholesky G = L L^T of the b x b Gram matrix (b <= 16) and L^{-1} into Linv (row pitch 64),
+// Cholesky G = L L^T of the B x B Gram matrix (B <= 16) and L^{-1} into Linv (row pitch 64),
 // in one wavefront: lane i holds row i; pivots and column values come by cross-lane reads.
+// B is a template parameter so that every register index is fixed at compile time.
 // A non-positive pivot sets *flag.
-__global__ __launch_bounds__(64) void k_small_chol_inv(int b, const double* G, double* Linv,
-                                                       int* flag) {
+template <int B>
+__global__ __launch_bounds__(64) void k_small_chol_inv(const double* G, double* Linv, int* flag) {
   const int i = threadIdx.x;
-  double a[BMAX], y[BMAX];
+  double a[B], y[B];
 #pragma unroll
-  for (int c = 0; c < BMAX; ++c) {
-    a[c] = (i < b && c < b && c <= i) ? G[i * b + c] : (i == c ? 1.0 : 0.0);
+  for (int c = 0; c < B; ++c) {
+    a[c] = (i < B && c <= i) ? G[i * B + c] : (i == c ? 1.0 : 0.0);
     y[c] = (i == c) ? 1.0 : 0.0;
   }
 #pragma unroll
-  for (int j = 0; j < BMAX; ++j) {
-    if (j >= b) break;
+  for (int j = 0; j < B; ++j) {
     double piv = __shfl(a[j], j);
     if (!(piv > 0.0)) {
       if (i == 0) atomicOr(flag, 1);
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(64) void k_small_chol_inv(int b, const double* G, d
     const double l = (i >= j) ? a[j] * inv : 0.0;  // column j of L
     a[j] = l;
 #pragma unroll
-    for (int c = j + 1; c < BMAX; ++c) {
+    for (int c = j + 1; c < B; ++c) {
       const double lc = __shfl(l, c);
       if (i >= c) a[c] = fma(-l, lc, a[c]);
     }
@@ -77,8 +77,21 @@ __global__ __launch_bounds__(64) void k_small_chol_inv(int b, const double* G, d
     }
   }
 #pragma unroll
-  for (int c = 0; c < BMAX; ++c)
-    if (i < b && c < b) Linv[i * 64 + c] = (c <= i) ? y[c] : 0.0;
+  for (int c = 0; c < B; ++c)
+    if (i < B) Linv[i * 64 + c] = (c <= i) ? y[c] : 0.0;
+}
+
+void small_chol_inv(int b, const double* G, double* Linv, int* flag, hipStream_t s) {
+  switch (b) {
+#define LRSDP_SC(B) \
+  case B:           \
+    k_small_chol_inv<B><<<1, 64, 0, s>>>(G, Linv, flag); \
+    break;
+    LRSDP_SC(1) LRSDP_SC(2) LRSDP_SC(3) LRSDP_SC(4) LRSDP_SC(5) LRSDP_SC(6) LRSDP_SC(7)
+    LRSDP_SC(8) LRSDP_SC(9) LRSDP_SC(10) LRSDP_SC(11) LRSDP_SC(12) LRSDP_SC(13) LRSDP_SC(14)
+    LRSDP_SC(15) LRSDP_SC(16)
+#undef LRSDP_SC
+  }
 }
 
 // Scale each row of T to unit length (one wavefront per row).
@@ -284,7 +297,7 @@ int spectral_top(const double* W, int n, int k, void* ws, double* lam_out, doubl
     for (int pass = 0; pass < 2; ++pass) {
       const double* src = pass == 0 ? T : Y;
       k_gram<<<b * b, 64, 0, s>>>(b, n, src, src, G);
-      k_small_chol_inv<<<1, 64, 0, s>>>(b, G, Dinv, flag);
+      small_chol_inv(b, G, Dinv, flag, s);
       k_lower_apply<<<eg, 256, 0, s>>>(b, n, Dinv, src, pass == 0 ? Y : X);
     }
     return LRSDP_OK;

@@ -28,11 +28,12 @@ def problem(ctx):
     return problem_from(ctx, inst)
 
 
-MODES = {"mixed": dict(precision=pk.LRSDP_PREC_FP32, dd_mode=pk.LRSDP_DD_ON),
+MODES = {"mixed": dict(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO),
+         "fp32-refined": dict(precision=pk.LRSDP_PREC_FP32, dd_mode=pk.LRSDP_DD_ON),
          "fp64": dict(precision=pk.LRSDP_PREC_FP64, dd_mode=pk.LRSDP_DD_AUTO)}
 
 
-@pytest.mark.parametrize("mode", ["mixed", "fp64"])
+@pytest.mark.parametrize("mode", ["mixed", "fp32-refined", "fp64"])
 @pytest.mark.parametrize("mu", [1e-2, 1e-8])
 def test_full_size_solve_meets_target(problem, mode, mu):
     inst = make_instance(1000, 5, 20000, mu, seed=2001)

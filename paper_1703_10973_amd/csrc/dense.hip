@@ -43,11 +43,25 @@ __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
     Bp += g.offs[3 * z + 1];
     Cp += g.offs[3 * z + 2];
   }
-  const int tiles_n = (g.N + TNv - 1) / TNv;
-  const int ti = blockIdx.x / tiles_n;
-  const int tj = blockIdx.x - ti * tiles_n;
-  const int i0 = ti * TMv, j0 = tj * TNv;
+  const int tiles_m = (g.M + TMv - 1) / TMv, tiles_n = (g.N + TNv - 1) / TNv;
   const bool lower = (g.flags & kLowerOut) != 0;
+  // (workgroups are dealt to the eight XCDs in turn, which spreads tiles of unequal K
+  // ranges evenly over them; a contiguous tile range per XCD measured slower here)
+  const int tile = blockIdx.x;
+  int ti, tj;
+  if (lower && tiles_m == tiles_n) {  // the grid covers only the lower triangle of tiles
+    ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
+    while (ti * (ti + 1) / 2 > tile) --ti;
+    tj = tile - ti * (ti + 1) / 2;
+  } else {
+    ti = tile / tiles_n;
+    tj = tile - ti * tiles_n;
+  }
+  // triangular operands: start with the tiles whose K range is longest
+  if (g.flags & kKToCol) tj = tiles_n - 1 - tj;
+  if (g.flags & kKToRow) ti = tiles_m - 1 - ti;
+  const int i0 = ti * TMv, j0 = tj * TNv;
   if (lower && j0 > i0 + TMv - 1) return;
   int klo = 0, khi = g.K;
   if (g.flags & kKFromRow) klo = max(klo, i0);
@@ -415,7 +429,9 @@ static void gemm_cost(const GemmArgs& g, int te, double* flops, double* bytes) {
 template <int WM, int WN, int KS>
 static void launch_gemm(const GemmArgs& g, hipStream_t s) {
   constexpr int te_m = 32 * WM, te_n = 32 * WN;
-  const int tiles = ((g.M + te_m - 1) / te_m) * ((g.N + te_n - 1) / te_n);
+  const int tm = (g.M + te_m - 1) / te_m, tn = (g.N + te_n - 1) / te_n;
+  // a lower-triangular output of a square tile grid launches only its lower tiles
+  const int tiles = ((g.flags & kLowerOut) && tm == tn) ? tm * (tm + 1) / 2 : tm * tn;
   const dim3 grid(tiles, g.offs ? g.batch : 1), block(64 * WM * WN * KS);
   if (!g.transA && !g.transB)
     k_gemm<false, false, WM, WN, KS><<<grid, block, 0, s>>>(g);

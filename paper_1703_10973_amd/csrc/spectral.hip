@@ -17,7 +17,7 @@
 //   residuals ||T_i - theta_i X_i|| of the k largest; stop once all are at the FP64
 //   rounding level of the product (64 u theta_max sqrt(n)), so the pairs are as accurate
 //   as a dense eigensolver's
-//   X <- orth(T) by Cholesky QR, twice, after row normalization.
+//   X <- orth(T W) by Cholesky QR, twice, after row normalization (each sweep applies W^2).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -342,6 +342,10 @@ int spectral_top(const double* W, int n, int k, void* ws, double* lam_out, doubl
     }
     if (rmax < 0.5 * best) best = rmax;
     else if (sweeps > 6 && rmax > 0.9 * best) break;  // stalled: no usable gap
+    // the next basis spans W^2 times the Ritz vectors: one more W-times-block product
+    // squares the convergence factor of the sweep
+    LRSDP_TRY(rows_k(n, b, W, 0, T, Y, s));
+    std::swap(T, Y);
     LRSDP_TRY(orthonormalize());
   }
   if (sweeps_out) *sweeps_out = sweeps;

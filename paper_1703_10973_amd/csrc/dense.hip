@@ -54,6 +54,9 @@ __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
     while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
     while (ti * (ti + 1) / 2 > tile) --ti;
     tj = tile - ti * (ti + 1) / 2;
+  } else if ((g.flags & (kKToCol | kKFromCol)) && !(g.flags & (kKToRow | kKFromRow))) {
+    tj = tile / tiles_m;  // the K range follows the tile column: walk the grid column by column
+    ti = tile - tj * tiles_m;
   } else {
     ti = tile / tiles_n;
     tj = tile - ti * tiles_n;
@@ -215,15 +218,20 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // The matrix being reduced sits in registers as rows: lane i = t % 64 holds row i, and
 // wavefront g = t / 64 the columns [8g, 8g + 8).  L^{-1} is built by forward substitution
 // on the identity in the transposed layout: lane c holds column c and wavefront g the rows
-// [8g, 8g + 8).  Panel P:
-//   wavefront P factors its eight columns alone (pivots and l_cj by cross-lane reads, no
-//   barrier), finishes rows [8P, 8P + 8) of L^{-1} (an 8 x 8 forward substitution whose
-//   coefficients are the panel's own l values, uniform across lanes), and publishes both;
-//   after one barrier every wavefront g > P applies the panel's rank-8 update to its columns
-//   of the matrix and to its rows of L^{-1}.
-// Eight barriers in all; every update keeps the order of the unblocked algorithm.  Rows and
-// columns beyond N are the identity.  A non-positive pivot sets *flag and continues with
-// pivot 1.  Writes L (lower, zero above the diagonal) into A and L^{-1} (zero above the
+// [8g, 8g + 8).  Between barrier P - 1 and barrier P:
+//   wavefront P factors panel P alone (pivots and l_cj by cross-lane reads) and publishes
+//   its columns;
+//   wavefront P - 1 finishes rows [8(P-1), 8P) of L^{-1} (an 8 x 8 forward substitution
+//   whose coefficients are its panel's l values) and publishes them.
+// After barrier P every wavefront g > P applies panel P's rank-8 update to its matrix
+// columns, and the wavefronts g >= P apply panel P - 1's update to their rows of L^{-1};
+// the wavefront that factors panel P + 1 defers that one until after the next barrier.  So the chain from
+// one factorization to the next holds one rank-8 update of eight columns and no L^{-1}
+// work.  Only the lower triangle of the registers is L: the updates are not masked, the
+// entries above the diagonal collect values that are never read as L (panels are published
+// with zeros there).  Every update keeps the order of the unblocked algorithm.  Rows and
+// columns beyond N are the identity.  A non-positive pivot sets *flag (the result is then
+// garbage).  Writes L (lower, zero above the diagonal) into A and L^{-1} (zero above the
 // diagonal) into Li (li_rows x li_rows).
 constexpr int LW = NB / 8;   // wavefronts of the leaf kernel
 constexpr int LP = NB / LW;  // panel width = columns (rows of L^{-1}) per wavefront
@@ -231,8 +239,8 @@ constexpr int LP = NB / LW;  // panel width = columns (rows of L^{-1}) per wavef
 __global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, int N, int lda,
                                                        int* flag, double* __restrict__ Li,
                                                        int ldi, int li_rows) {
-  __shared__ double Ls[NB][NB + 1];  // L, published panel by panel
-  __shared__ double Xs[NB][NB];      // finished rows of L^{-1}
+  __shared__ double Ls[4][NB][LP + 1];  // panel P's columns of L, row-indexed (buffer P % 4)
+  __shared__ double Xs[2][LP][NB];      // panel P's rows of L^{-1} (buffer P % 2)
   const int t = threadIdx.x, i = t & (NB - 1), g = t / NB;
   double a[LP], y[LP];
 #pragma unroll
@@ -244,64 +252,72 @@ __global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, i
     a[q] = v;
     y[q] = (c == i) ? 1.0 : 0.0;  // row c = 8g + q, column i (lane) of the identity
   }
-  for (int P = 0; P < LW; ++P) {
+  bool bad = false;
+  double inv[LP];  // 1 / l_jj of this wavefront's panel
+  // this wavefront's rows of L^{-1} -= (panel p's l_cj) x (panel p's rows of L^{-1})
+  auto y_update = [&](int p) {
+    const int lb = p & 3, xb = p & 1;
+    double xj[LP];
+#pragma unroll
+    for (int jj = 0; jj < LP; ++jj) xj[jj] = Xs[xb][jj][i];
+#pragma unroll
+    for (int q = 0; q < LP; ++q) {
+      const int c = g * LP + q;
+      double yacc = y[q];
+#pragma unroll
+      for (int jj = 0; jj < LP; ++jj) yacc = fma(-Ls[lb][c][jj], xj[jj], yacc);
+      y[q] = yacc;
+    }
+  };
+  for (int P = 0; P <= LW; ++P) {
     const int j0 = P * LP;
-    if (g == P) {  // factor the panel, then finish rows j0..j0+7 of L^{-1}
-      double inv[LP];
+    if (P < LW && g == P) {  // factor panel P: every update from panels < P is in
+      const int jl0 = __builtin_amdgcn_readfirstlane(j0);
 #pragma unroll
       for (int jj = 0; jj < LP; ++jj) {
-        const int j = j0 + jj;
-        double piv = readlane_d(a[jj], j);
-        const bool bad = !(piv > 0.0);
-        if (bad) piv = 1.0;
+        const double piv = readlane_d(a[jj], jl0 + jj);
+        bad |= !(piv > 0.0) && (j0 + jj < N);
         inv[jj] = rsqrt_nr(piv);
-        if (bad && i == 0 && j < N) atomicOr(flag, 1);
-        const double l = (i >= j) ? a[jj] * inv[jj] : 0.0;  // column j of L
+        const double l = a[jj] * inv[jj];
         a[jj] = l;
 #pragma unroll
-        for (int qq = jj + 1; qq < LP; ++qq) {
-          const int c = j0 + qq;
-          const double lc = readlane_d(l, c);  // l_cj
-          const double na = fma(-l, lc, a[qq]);
-          a[qq] = (i >= c) ? na : a[qq];
-        }
+        for (int qq = jj + 1; qq < LP; ++qq) a[qq] = fma(-l, readlane_d(l, jl0 + qq), a[qq]);
       }
 #pragma unroll
+      for (int q = 0; q < LP; ++q) Ls[P & 3][i][q] = (i >= j0 + q) ? a[q] : 0.0;
+    }
+    if (P >= 1 && g == P - 1) {  // rows of L^{-1} of panel P - 1: all updates are in
+      const int jl0 = __builtin_amdgcn_readfirstlane(j0 - LP);
+#pragma unroll
       for (int jj = 0; jj < LP; ++jj) {
-        y[jj] *= inv[jj];  // row j of L^{-1} is final
+        y[jj] *= inv[jj];
 #pragma unroll
         for (int kk = jj + 1; kk < LP; ++kk)
-          y[kk] = fma(-readlane_d(a[jj], j0 + kk), y[jj], y[kk]);
+          y[kk] = fma(-readlane_d(a[jj], jl0 + kk), y[jj], y[kk]);
       }
 #pragma unroll
-      for (int q = 0; q < LP; ++q) {
-        Ls[i][j0 + q] = a[q];
-        Xs[j0 + q][i] = y[q];
-      }
+      for (int q = 0; q < LP; ++q) Xs[(P - 1) & 1][q][i] = y[q];
     }
+    if (P == LW) break;
     __syncthreads();
-    if (g > P) {  // rank-8 updates of this wavefront's matrix columns and L^{-1} rows
-      double li[LP], xj[LP];
+    if (g > P) {  // rank-8 update of this wavefront's matrix columns with panel P
+      const int lb = P & 3;
+      double li[LP];
 #pragma unroll
-      for (int jj = 0; jj < LP; ++jj) {
-        li[jj] = Ls[i][j0 + jj];
-        xj[jj] = Xs[j0 + jj][i];
-      }
+      for (int jj = 0; jj < LP; ++jj) li[jj] = Ls[lb][i][jj];
 #pragma unroll
       for (int q = 0; q < LP; ++q) {
-        const int c = g * LP + q;  // matrix column c / L^{-1} row c (uniform)
-        double acc = a[q], yacc = y[q];
+        const int c = g * LP + q;
+        double acc = a[q];
 #pragma unroll
-        for (int jj = 0; jj < LP; ++jj) {
-          const double lcj = Ls[c][j0 + jj];
-          acc = fma(-li[jj], lcj, acc);
-          yacc = fma(-lcj, xj[jj], yacc);
-        }
-        a[q] = (i >= c) ? acc : a[q];
-        y[q] = yacc;
+        for (int jj = 0; jj < LP; ++jj) acc = fma(-li[jj], Ls[lb][c][jj], acc);
+        a[q] = acc;
       }
     }
+    if (g == P && P >= 2) y_update(P - 2);  // deferred while this wavefront factored
+    if (P >= 1 && g >= P && g != P + 1) y_update(P - 1);
   }
+  if (bad && i == 0) atomicOr(flag, 1);
 #pragma unroll
   for (int q = 0; q < LP; ++q) {
     const int c = g * LP + q;
@@ -309,6 +325,158 @@ __global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, i
     // lane i holds column i of row c of L^{-1}
     if (c < li_rows && i < li_rows) Li[(size_t)c * ldi + i] = (i <= c) ? y[q] : 0.0;
   }
+}
+
+// ---------------------------------------------------------------- right-looking node
+// Below a few thousand rows the recursion's cost is its chain of small launches, not its
+// flops.  There a node is factored right-looking by 64-blocks, three launches per block
+// column j: the leaf (L_jj, L_jj^{-1}), a panel step and a trailing step.  L^{-1} = X is
+// built alongside from its block recurrence X_ik = -L_ii^{-1} sum_{k <= m < i} L_im X_mk:
+// the sums Y_ik accumulate in Li as the block columns m finish, and X_ik = L_ii^{-1} Y_ik is
+// formed once L_ii^{-1} is known.  Every block product is one 64 x 64 x 64 MFMA tile.
+enum { kRLPanel = 0, kRLTrail = 1 };
+
+__device__ __forceinline__ int rl_rows(int b, int N) { return min(64, N - 64 * b); }
+
+// One block product per workgroup, C = alpha P op(Q) + beta C on 64 x 64 blocks (entries past
+// the node edge read as zero and are not written).  With r = nb - 1 - j, step j:
+//   panel: tiles t < r:        L_ij = A_ij L_jj^{-T}, i = j + 1 + t (in place in A);
+//          tiles r <= t < r+j: X_jk = L_jj^{-1} Y_jk, k = t - r (in place in Li);
+//   trail: tiles t < r(r+1)/2: A_ik -= L_ij L_kj^T for j < k <= i;
+//          the rest:           Y_ik = [k < j] Y_ik - L_ij X_jk for i > j, k <= j.
+// The operands of a tile are never written by another tile of the same launch, and a tile
+// that updates one of its own operands loads both before it stores.
+template <int MODE>
+__global__ __launch_bounds__(512) void k_rl_step(double* __restrict__ A, int lda,
+                                                 double* __restrict__ Li, int ldi, int N,
+                                                 int j) {
+  __shared__ double Ps[64][68];  // Ps[k][m] = P[m][k]
+  __shared__ double Qs[64][68];  // Qs[k][n] = op(Q)[k][n]
+  const int nb = (N + 63) >> 6, r = nb - 1 - j, t = blockIdx.x;
+  const double* P;
+  const double* Q;
+  double* C;
+  int ldp, ldq, ldc, Mv, Nv, Kv;
+  bool qT;
+  double alpha = 1.0, beta = 0.0;
+  if (MODE == kRLPanel) {
+    if (t < r) {
+      const int i = j + 1 + t;
+      P = A + (size_t)(64 * i) * lda + 64 * j; ldp = lda;
+      Q = Li + (size_t)(64 * j) * ldi + 64 * j; ldq = ldi; qT = true;
+      C = A + (size_t)(64 * i) * lda + 64 * j; ldc = lda;
+      Mv = rl_rows(i, N); Nv = 64; Kv = 64;
+    } else {
+      const int k = t - r;
+      P = Li + (size_t)(64 * j) * ldi + 64 * j; ldp = ldi;
+      Q = Li + (size_t)(64 * j) * ldi + 64 * k; ldq = ldi; qT = false;
+      C = Li + (size_t)(64 * j) * ldi + 64 * k; ldc = ldi;
+      Mv = rl_rows(j, N); Nv = 64; Kv = rl_rows(j, N);
+    }
+  } else {
+    // block (i, k) of A (k > j) or of Y (k <= j) that this tile updates
+    const int ta = r * (r + 1) / 2;
+    const bool yt = t >= ta;
+    int i, k;
+    if (!yt) {
+      int ii = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+      while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+      while (ii * (ii + 1) / 2 > t) --ii;
+      i = j + 1 + ii;
+      k = j + 1 + (t - ii * (ii + 1) / 2);
+    } else {
+      i = j + 1 + (t - ta) / (j + 1);
+      k = (t - ta) % (j + 1);
+    }
+    if (!yt) {
+      P = A + (size_t)(64 * i) * lda + 64 * j; ldp = lda;
+      Q = A + (size_t)(64 * k) * lda + 64 * j; ldq = lda; qT = true;
+      C = A + (size_t)(64 * i) * lda + 64 * k; ldc = lda;
+      Mv = rl_rows(i, N); Nv = rl_rows(k, N); Kv = 64;
+      alpha = -1.0; beta = 1.0;
+    } else {
+      P = A + (size_t)(64 * i) * lda + 64 * j; ldp = lda;
+      Q = Li + (size_t)(64 * j) * ldi + 64 * k; ldq = ldi; qT = false;
+      C = Li + (size_t)(64 * i) * ldi + 64 * k; ldc = ldi;
+      Mv = rl_rows(i, N); Nv = 64; Kv = 64;
+      alpha = -1.0; beta = (k < j) ? 1.0 : 0.0;
+    }
+  }
+  // 512 threads: wavefront w computes the 32 x 32 quadrant (w >> 1) & 1, w & 1 over the K half
+  // w >> 2; the upper half parks its partial sums in LDS for the lower one to add and store
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, kh = w >> 2, wm = (w >> 1) & 1, wn = w & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  double cv[2][2][4];  // the old C values this thread stores back into (beta != 0)
+  if (kh == 0 && beta != 0.0) {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int i = wm * 32 + mi * 16 + lk + 4 * q, c = wn * 32 + ni * 16 + lr;
+          cv[mi][ni][q] = (i < Mv && c < Nv) ? C[(size_t)i * ldc + c] : 0.0;
+        }
+  }
+  double pv[8], qv[8];  // all loads in flight before the first LDS store
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int rr = w + 8 * u, cc = lane;
+    pv[u] = (rr < Mv && cc < Kv) ? P[(size_t)rr * ldp + cc] : 0.0;
+    qv[u] = (qT ? (rr < Nv && cc < Kv) : (rr < Kv && cc < Nv)) ? Q[(size_t)rr * ldq + cc] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int rr = w + 8 * u, cc = lane;
+    Ps[cc][rr] = pv[u];
+    if (qT) Qs[cc][rr] = qv[u];
+    else Qs[rr][cc] = qv[u];
+  }
+  __syncthreads();
+  v4d acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k4 = 0; k4 < 32; k4 += 4) {
+    const int kr = 32 * kh + k4 + lk;
+    const double a0 = Ps[kr][wm * 32 + lr];
+    const double a1 = Ps[kr][wm * 32 + 16 + lr];
+    const double b0 = Qs[kr][wn * 32 + lr];
+    const double b1 = Qs[kr][wn * 32 + 16 + lr];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+  __syncthreads();  // every wavefront is done with Ps: reuse it for the upper half's sums
+  double* park = &Ps[0][0] + (size_t)(w & 3) * 64 * 16;
+  if (kh == 1) {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) park[((mi * 2 + ni) * 4 + q) * 64 + lane] = acc[mi][ni][q];
+  }
+  __syncthreads();
+  if (kh == 1) return;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = wm * 32 + mi * 16 + lk + 4 * q;
+        const int c = wn * 32 + ni * 16 + lr;
+        if (i < Mv && c < Nv) {
+          double v = alpha * (acc[mi][ni][q] + park[((mi * 2 + ni) * 4 + q) * 64 + lane]);
+          if (beta != 0.0) v = fma(beta, cv[mi][ni][q], v);
+          C[(size_t)i * ldc + c] = v;
+        }
+      }
 }
 
 __global__ void k_copy_block(const double* __restrict__ S, int lds, double* __restrict__ D,
@@ -466,8 +634,11 @@ int gemm(const GemmArgs& g, hipStream_t s) {
 
 // Scratch: a node keeps its L21 in tmp[0, N1 N2) while its trailing factorization runs on
 // tmp beyond it (the side-stream product may still be reading L21 then).
+// nodes up to this size are factored right-looking (no scratch)
+constexpr int kRLMax = 1280;
+
 size_t potrf_inv_tmp_doubles(int N) {
-  if (N <= NB) return 0;
+  if (N <= kRLMax) return 0;
   const int N1 = split64(N), N2 = N - N1;
   return (size_t)N1 * N2 + std::max(potrf_inv_tmp_doubles(N1), potrf_inv_tmp_doubles(N2));
 }
@@ -476,15 +647,36 @@ size_t potrf_inv_tmp_doubles(int N) {
 // the overlap gains)
 constexpr int kSideMin = 512;
 
+// Right-looking factorization of a node of N <= kRLMax rows (L into A's lower triangle,
+// L^{-1} into Li's), 64-block columns in order.  (Splitting off the trailing tiles that the
+// next column waits for, onto a second stream, measured slower: the cross-stream waits
+// cost more than the overlap gains at this size.)
+static int rl_factor(double* A, int N, int lda, double* Li, int ldi, int* flag, hipStream_t s) {
+  const int nb = (N + NB - 1) / NB;
+  for (int j = 0; j < nb; ++j) {
+    const int nj = std::min(NB, N - NB * j);
+    k_chol_leaf<<<1, NB * LW, 0, s>>>(A + (size_t)(NB * j) * lda + NB * j, nj, lda, flag,
+                                      Li + (size_t)(NB * j) * ldi + NB * j, ldi, nj);
+    LRSDP_HIP(hipGetLastError());
+    const int r = nb - 1 - j;
+    if (r + j > 0) {
+      k_rl_step<kRLPanel><<<r + j, 512, 0, s>>>(A, lda, Li, ldi, N, j);
+      LRSDP_HIP(hipGetLastError());
+    }
+    const int tiles = r * (r + 1) / 2 + r * (j + 1);
+    if (tiles > 0) {
+      k_rl_step<kRLTrail><<<tiles, 512, 0, s>>>(A, lda, Li, ldi, N, j);
+      LRSDP_HIP(hipGetLastError());
+    }
+  }
+  return LRSDP_OK;
+}
+
 static int potrf_inv_rec(double* A, int N, int lda, double* Li, int ldi, int* flag,
                          double* tmp, bool want_L, hipStream_t s, const SideStream* side,
                          int depth) {
   if (N <= 0) return LRSDP_OK;
-  if (N <= NB) {
-    k_chol_leaf<<<1, NB * LW, 0, s>>>(A, N, lda, flag, Li, ldi, N);
-    LRSDP_HIP(hipGetLastError());
-    return LRSDP_OK;
-  }
+  if (N <= kRLMax) return rl_factor(A, N, lda, Li, ldi, flag, s);
   const int N1 = split64(N), N2 = N - N1;
   double* A21 = A + (size_t)N1 * lda;
   double* A22 = A21 + N1;

@@ -55,11 +55,93 @@ def parse():
     ap.add_argument("--count", type=int, default=0, help="instances / requests (batch, serving)")
     ap.add_argument("--qps", type=float, default=4.0, help="serving arrival rate")
     ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--summarize-traffic", nargs=4, metavar="DIR",
+                    help="no GPU: read four rocprofv3 --pmc output folders (FETCH_SIZE and "
+                         "WRITE_SIZE of --workload single, then of --workload "
+                         "copy-calibration), print the per-kernel HBM table and write "
+                         "profiles/hbm_traffic.json")
     return ap.parse_args()
+
+
+# kernel class (as profiled by the library) -> kernel names counted in it; a class launch is
+# one launch of the first name
+TRAFFIC_CLASSES = {
+    "gemm": ("k_gemm",), "hv": ("k_hv_fused",), "gemv": ("k_gemv_tri",),
+    "resdd": ("k_residual_dd",), "bz": ("k_PJ", "k_dJL"), "leaf": ("k_chol_leaf",),
+    "tile": ("k_rl_step",),
+}
+CLASS_SOURCE = {"gemm": "dense.hip", "hv": "hv.hip", "gemv": "dense.hip", "resdd": "hv.hip",
+                "bz": "factor.hip", "leaf": "dense.hip", "tile": "dense.hip"}
+
+
+def summarize_traffic(dirs):
+    """HBM bytes per kernel of the second (warm) solve of --workload single, from FETCH_SIZE
+    and WRITE_SIZE counter runs, each scaled by what the counter reads for a 1 GiB copy."""
+    import csv
+    import glob
+    import hashlib
+    import re
+
+    def rows(d):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)[0]
+        with open(f) as fh:
+            out = [(int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]))
+                   for r in csv.DictReader(fh)]
+        return sorted(out)
+
+    def short(name):
+        name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+        return re.sub(r"\(.*", "", name.replace("lrsdp::", ""))
+
+    def warm(rs):  # from the last problem validation on: the second solve
+        start = max(i for i, r in enumerate(rs) if short(r[1]) == "k_validate")
+        return rs[start:]
+
+    fetch, write = warm(rows(dirs[0])), warm(rows(dirs[1]))
+    copy_bytes = float(1 << 30)
+    cf = sorted(v for _, _, v in rows(dirs[2]))[-5:]
+    cw = sorted(v for _, _, v in rows(dirs[3]))[-5:]
+    fscale = copy_bytes / (np.mean(cf) * 1024.0)
+    wscale = copy_bytes / (np.mean(cw) * 1024.0)
+    per = {}
+    for tag, rs, sc in (("f", fetch, fscale), ("w", write, wscale)):
+        for _, name, v in rs:
+            k = short(name)
+            e = per.setdefault(k, {"n": 0, "f": 0.0, "w": 0.0})
+            if tag == "f":
+                e["n"] += 1
+            e[tag] += v * 1024.0 * sc
+    print(f"# calibration: a 1 GiB device copy reads FETCH_SIZE {np.mean(cf):.1f} KiB and "
+          f"WRITE_SIZE {np.mean(cw):.1f} KiB,")
+    print(f"# so fetched bytes = FETCH_SIZE x 1024 x {fscale:.4f} and written bytes = "
+          f"WRITE_SIZE x 1024 x {wscale:.4f}")
+    print(f"{'kernel':40s} {'launches':>8s} {'fetch_MB':>10s} {'write_MB':>10s} {'MB/launch':>10s}")
+    for k, e in sorted(per.items(), key=lambda kv: -(kv[1]["f"] + kv[1]["w"])):
+        print(f"{k[:40]:40s} {e['n']:8d} {e['f'] / 1e6:10.2f} {e['w'] / 1e6:10.2f} "
+              f"{(e['f'] + e['w']) / 1e6 / max(e['n'], 1):10.3f}")
+    classes = {}
+    for cls, names in TRAFFIC_CLASSES.items():
+        hit = [(k, e) for k, e in per.items() if any(k.startswith(nm) for nm in names)]
+        launches = sum(e["n"] for k, e in hit if k.startswith(names[0]))
+        if not launches:
+            continue
+        src = os.path.join(ROOT, "paper_1703_10973_amd", "csrc", CLASS_SOURCE[cls])
+        with open(src, "rb") as fh:
+            sha = hashlib.sha256(fh.read()).hexdigest()
+        classes[cls] = {
+            "launches": launches,
+            "fetch_bytes_per_launch": sum(e["f"] for _, e in hit) / launches,
+            "write_bytes_per_launch": sum(e["w"] for _, e in hit) / launches,
+            "source": CLASS_SOURCE[cls], "source_sha256": sha}
+    with open(os.path.join(ROOT, "profiles", "hbm_traffic.json"), "w") as fh:
+        json.dump({"fetch_scale": fscale, "write_scale": wscale, "classes": classes}, fh,
+                  indent=1)
 
 
 def main():
     args = parse()
+    if args.summarize_traffic:
+        return summarize_traffic(args.summarize_traffic)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the per-GPU "
               "shard of this workload is one independent instance stream", file=sys.stderr)
@@ -172,10 +254,17 @@ def main():
 
     # ---- roofline of the dominant kernel class, from the events of the timed region
     avg_ms = dstat["ms"] / max(dstat["launches"], 1)
-    if dom in ("gemm",):
+    if dom in ("gemm", "tile"):
         per = dstat["flops"] / max(dstat["launches"], 1)
         achieved = per / (avg_ms * 1e-3) / 1e12
         roof = dict(bound="mfma", achieved=achieved, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
+                    frac=achieved / (FP64_PEAK / 1e12), traffic=None, kernel=dom,
+                    launches=dstat["launches"], avg_us=avg_ms * 1e3,
+                    profiled_ms_per_step=prof_ms_per_step)
+    elif dom == "leaf":  # latency-bound FP64 vector arithmetic
+        per = dstat["flops"] / max(dstat["launches"], 1)
+        achieved = per / (avg_ms * 1e-3) / 1e12
+        roof = dict(bound="alu", achieved=achieved, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
                     frac=achieved / (FP64_PEAK / 1e12), traffic=None, kernel=dom,
                     launches=dstat["launches"], avg_us=avg_ms * 1e3,
                     profiled_ms_per_step=prof_ms_per_step)
@@ -385,17 +474,17 @@ def run_large(args):
 
 
 def run_single(args):
-    """One mixed-mode solve (A0 + Algorithm 1) of the mu = 1e-2 instance of the default
+    """One mixed-mode solve (A0 + Algorithm 1) of the mu = 1e-6 instance of the default
     workload, after one warm-up solve; prints its status (for hardware-counter runs)."""
     import torch
 
     import paper_1703_10973_amd as pk
     from synth import make_instance
     dev = torch.device("cuda", 0)
-    inst = make_instance(N, K, M, MUS[0], SEED)
+    inst = make_instance(N, K, M, MUS[2], SEED)
     d = _device_inputs(inst, torch, dev)
     ctx = pk.Context(0)
-    opts = pk.opts(precision=pk.LRSDP_PREC_FP32, dd_mode=pk.LRSDP_DD_ON)
+    opts = pk.opts(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO)
     for _ in range(2):
         P = pk.Problem(ctx, inst.n, inst.m, d["con"], d["row"], d["col"], d["val"])
         F = pk.Factor(P, d["W"], inst.k, opts)

@@ -136,7 +136,9 @@ LRSDP_API int lrsdp_ctx_memory(const lrsdp_ctx* ctx, size_t* in_use, size_t* bud
 #define LRSDP_K_GEMV    3   /* bold S^{-1} w = L^{-T} (L^{-1} w), two triangular GEMVs (A6)    */
 #define LRSDP_K_BZ      4   /* sparse B_JL Z pass of bold S formation (A3)                    */
 #define LRSDP_K_RESDD   5   /* double-double residual r - H y (A8)                            */
-#define LRSDP_K_COUNT   6
+#define LRSDP_K_LEAF    6   /* 64 x 64 Cholesky and inverse of a diagonal block (A2/A4)       */
+#define LRSDP_K_TILE    7   /* 64 x 64 MFMA block steps of the right-looking factorization    */
+#define LRSDP_K_COUNT   8
 LRSDP_API int lrsdp_ctx_profile(lrsdp_ctx* ctx, int enable);
 /* Time only one launch in `every` (>= 1) of each enabled class, so that a timed run is not
  * slowed by the events; counts restart.  Default 1. */

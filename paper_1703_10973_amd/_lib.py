@@ -193,7 +193,7 @@ def lrsdp_ctx_memory(ctx):
     return a.value, b.value
 
 
-LRSDP_K_NAMES = ["hv", "gemm", "tri", "gemv", "bz", "resdd"]
+LRSDP_K_NAMES = ["hv", "gemm", "tri", "gemv", "bz", "resdd", "leaf", "tile"]
 
 
 def lrsdp_ctx_profile(ctx, enable):

@@ -653,20 +653,28 @@ constexpr int kSideMin = 512;
 // cost more than the overlap gains at this size.)
 static int rl_factor(double* A, int N, int lda, double* Li, int ldi, int* flag, hipStream_t s) {
   const int nb = (N + NB - 1) / NB;
+  const double tile_flops = 2.0 * NB * NB * NB, tile_bytes = 4.0 * NB * NB * 8;
   for (int j = 0; j < nb; ++j) {
     const int nj = std::min(NB, N - NB * j);
+    ProfMark pm = prof_begin(LRSDP_K_LEAF, s);
     k_chol_leaf<<<1, NB * LW, 0, s>>>(A + (size_t)(NB * j) * lda + NB * j, nj, lda, flag,
                                       Li + (size_t)(NB * j) * ldi + NB * j, ldi, nj);
     LRSDP_HIP(hipGetLastError());
+    // Cholesky nj^3 / 3 and triangular inverse nj^3 / 3 flops; A read, L and L^{-1} written
+    prof_end(pm, s, 3.0 * 8 * nj * nj, 2.0 * nj * nj * nj / 3.0);
     const int r = nb - 1 - j;
     if (r + j > 0) {
+      pm = prof_begin(LRSDP_K_TILE, s);
       k_rl_step<kRLPanel><<<r + j, 512, 0, s>>>(A, lda, Li, ldi, N, j);
       LRSDP_HIP(hipGetLastError());
+      prof_end(pm, s, (r + j) * tile_bytes, (r + j) * tile_flops);
     }
     const int tiles = r * (r + 1) / 2 + r * (j + 1);
     if (tiles > 0) {
+      pm = prof_begin(LRSDP_K_TILE, s);
       k_rl_step<kRLTrail><<<tiles, 512, 0, s>>>(A, lda, Li, ldi, N, j);
       LRSDP_HIP(hipGetLastError());
+      prof_end(pm, s, tiles * tile_bytes, tiles * tile_flops);
     }
   }
   return LRSDP_OK;

@@ -132,37 +132,9 @@ int spmm_U_dd(const lrsdp_problem* P, int k, const double* ml, const double* U, 
 
 // ---------------------------------------------------------------- dense n x n times n x k
 // out[j][p] = sum_{q in range(p)} A[p][q] X[j][q]; range: 0 full, 1 q <= p, 2 q >= p.
-// One workgroup per row p: its four wavefronts split the row, every load of a thread is in
-// flight at once, and the partial sums meet in a fixed order.
-__global__ __launch_bounds__(kT) void k_rows_k(int n, int k, const double* __restrict__ A,
-                                               int range, const double* __restrict__ X,
-                                               double* __restrict__ out) {
-  __shared__ double red[kT / kWave][KMAX];
-  const int p = blockIdx.x, t = threadIdx.x;
-  const int lane = t & (kWave - 1), wid = t / kWave;
-  const int qlo = (range == 2) ? p : 0;
-  const int qhi = (range == 1) ? p + 1 : n;
-  const double* a = A + (size_t)p * n;
-  double acc[KMAX];
-#pragma unroll
-  for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
-#pragma unroll 4
-  for (int q = qlo + t; q < qhi; q += kT) {
-    const double av = a[q];
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j)
-      if (j < k) acc[j] = fma(av, X[(size_t)j * n + q], acc[j]);
-  }
-#pragma unroll
-  for (int j = 0; j < KMAX; ++j)
-    if (j < k) {
-      const double v = wave_sum(acc[j]);
-      if (lane == 0) red[wid][j] = v;
-    }
-  __syncthreads();
-  if (t < k) out[(size_t)t * n + p] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
-}
-
+// (FP64: k_rows_kr below.)  The double-double form takes one workgroup per row p: its four
+// wavefronts split the row, every load of a thread is in flight at once, and the partial
+// sums meet in a fixed order.
 __global__ __launch_bounds__(kT) void k_rows_k_dd(int n, int k, const double* __restrict__ A,
                                                   int range, const double* __restrict__ Xh,
                                                   const double* __restrict__ Xl,
@@ -353,11 +325,79 @@ __global__ void k_Qc_dd(int N, int r, double shift, const double* Q, const doubl
   sl[i] = u.lo;
 }
 
+// out[j][p] = sum_{q in range(p)} A[p][q] X[j][q] for R rows p per workgroup: every X value
+// loaded serves R rows, so X (k x n, L2-resident) is read n / R times instead of n times.
+// KC >= k bounds the accumulators; rows past n and q outside a row's range add nothing.
+template <int R, int KC>
+__global__ __launch_bounds__(kT) void k_rows_kr(int n, int k, const double* __restrict__ A,
+                                                int range, const double* __restrict__ X,
+                                                double* __restrict__ out) {
+  __shared__ double red[kT / kWave][R * KC];
+  const int p0 = blockIdx.x * R, t = threadIdx.x;
+  const int lane = t & (kWave - 1), wid = t / kWave;
+  int lo[R], hi[R];
+  int qlo = n, qhi = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int p = p0 + r;
+    lo[r] = (range == 2) ? p : 0;
+    hi[r] = p >= n ? 0 : (range == 1) ? p + 1 : n;
+    if (hi[r] > lo[r]) {
+      qlo = min(qlo, lo[r]);
+      qhi = max(qhi, hi[r]);
+    }
+  }
+  double acc[R][KC];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < KC; ++j) acc[r][j] = 0.0;
+  constexpr int U = 4;  // columns per thread in flight at once
+  for (int q0 = qlo + t; q0 < qhi; q0 += U * kT) {
+    double xv[U][KC], av[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int q = q0 + u * kT;
+#pragma unroll
+      for (int j = 0; j < KC; ++j) xv[u][j] = (q < qhi && j < k) ? X[(size_t)j * n + q] : 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        av[u][r] = (q >= lo[r] && q < hi[r]) ? A[(size_t)(p0 + r) * n + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int j = 0; j < KC; ++j) acc[r][j] = fma(av[u][r], xv[u][j], acc[r][j]);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int j = 0; j < KC; ++j)
+      if (j < k) {
+        const double v = wave_sum(acc[r][j]);
+        if (lane == 0) red[wid][r * KC + j] = v;
+      }
+  __syncthreads();
+  if (t < R * KC) {
+    const int r = t / KC, j = t - r * KC, p = p0 + r;
+    if (p < n && j < k) out[(size_t)j * n + p] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+  }
+}
+
 }  // namespace
 
 int rows_k(int n, int k, const double* A, int range, const double* X, double* out,
            hipStream_t s) {
-  k_rows_k<<<n, kT, 0, s>>>(n, k, A, range, X, out);
+  if (n <= 0 || k <= 0) return LRSDP_OK;
+  if (k > KMAX) return LRSDP_ERR_INVALID_ARG;
+  constexpr int R = 4;
+  const int grid = (n + R - 1) / R;
+  if (k <= 4) k_rows_kr<R, 4><<<grid, kT, 0, s>>>(n, k, A, range, X, out);
+  else if (k <= 8) k_rows_kr<R, 8><<<grid, kT, 0, s>>>(n, k, A, range, X, out);
+  else k_rows_kr<R, 16><<<grid, kT, 0, s>>>(n, k, A, range, X, out);
+  LRSDP_HIP(hipGetLastError());
   return LRSDP_OK;
 }
 

@@ -24,13 +24,15 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 constexpr int TK = 16;
 constexpr int NB = 64;  // leaf size of the recursive factorizations
 
-// Output tile (32 WM) x (32 WN) per workgroup; each of WM x WN wavefront positions owns a
-// 32 x 32 block as 2 x 2 MFMA accumulators, and KS wavefronts share each position by
-// splitting every K chunk of 16 KS columns (intra-workgroup split-K), so one load latency
-// covers KS times more K; the KS partial blocks are summed through LDS in a fixed order.
-template <bool TA, bool TB, int WM, int WN, int KS>
+// Output tile (16 FM WM) x (16 FN WN) per workgroup; each of WM x WN wavefront positions
+// owns a (16 FM) x (16 FN) block as FM x FN MFMA accumulators, and KS wavefronts share each
+// position by splitting every K chunk of 16 KS columns (intra-workgroup split-K), so one load
+// latency covers KS times more K; the KS partial blocks are summed through LDS in a fixed
+// order.  Larger blocks per wavefront reuse each LDS operand read for more MFMAs and larger
+// tiles re-read less of A and B.
+template <bool TA, bool TB, int WM, int WN, int KS, int FM, int FN>
 __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
-  constexpr int TMv = 32 * WM, TNv = 32 * WN, NT = 64 * WM * WN * KS, TKc = TK * KS;
+  constexpr int TMv = 16 * FM * WM, TNv = 16 * FN * WN, NT = 64 * WM * WN * KS, TKc = TK * KS;
   constexpr int EA = TMv * TKc / NT, EB = TNv * TKc / NT;  // staged values per thread
   __shared__ double As[2][TKc][TMv + 4];
   __shared__ double Bs[2][TKc][TNv + 4];
@@ -120,11 +122,11 @@ __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
     }
   };
 
-  v4d acc[2][2];
+  v4d acc[FM][FN];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < FN; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
 
   if (klo < khi) {
     load(klo);
@@ -138,14 +140,16 @@ __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
 #pragma unroll
     for (int k4 = 0; k4 < TK; k4 += 4) {
       const int kr = ks * TK + k4 + lk;
-      const double a0 = As[buf][kr][wm * 32 + lr];
-      const double a1 = As[buf][kr][wm * 32 + 16 + lr];
-      const double b0 = Bs[buf][kr][wn * 32 + lr];
-      const double b1 = Bs[buf][kr][wn * 32 + 16 + lr];
-      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+      double av[FM], bv[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) av[a] = As[buf][kr][wm * 16 * FM + 16 * a + lr];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) bv[b] = Bs[buf][kr][wn * 16 * FN + 16 * b + lr];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
     if (more) store(buf ^ 1);
     __syncthreads();
@@ -153,39 +157,40 @@ __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
   }
 
   if constexpr (KS > 1) {  // fold the K slices: wavefronts ks > 0 park their blocks in LDS
-    static_assert((KS - 1) * WM * WN * 64 * 16 <= 2 * TKc * (TMv + 4), "LDS too small");
+    constexpr int PB = 64 * 4 * FM * FN;  // doubles parked per wavefront
+    static_assert((KS - 1) * WM * WN * PB <= 2 * TKc * (TMv + 4), "LDS too small");
     double* park = &As[0][0][0];
     if (ks > 0) {
-      double* mine = park + ((size_t)(ks - 1) * WM * WN + wmn) * 64 * 16;
+      double* mine = park + ((size_t)(ks - 1) * WM * WN + wmn) * PB;
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
+        for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) mine[((mi * 2 + ni) * 4 + r) * 64 + lane] = acc[mi][ni][r];
+          for (int r = 0; r < 4; ++r) mine[((mi * FN + ni) * 4 + r) * 64 + lane] = acc[mi][ni][r];
     }
     __syncthreads();
     if (ks > 0) return;
 #pragma unroll
     for (int o = 1; o < KS; ++o) {
-      const double* theirs = park + ((size_t)(o - 1) * WM * WN + wmn) * 64 * 16;
+      const double* theirs = park + ((size_t)(o - 1) * WM * WN + wmn) * PB;
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
+        for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc[mi][ni][r] += theirs[((mi * 2 + ni) * 4 + r) * 64 + lane];
+          for (int r = 0; r < 4; ++r) acc[mi][ni][r] += theirs[((mi * FN + ni) * 4 + r) * 64 + lane];
     }
   }
 
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < FM; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+    for (int ni = 0; ni < FN; ++ni)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = i0 + wm * 32 + mi * 16 + lk + 4 * r;
-        const int j = j0 + wn * 32 + ni * 16 + lr;
+        const int i = i0 + wm * 16 * FM + mi * 16 + lk + 4 * r;
+        const int j = j0 + wn * 16 * FN + ni * 16 + lr;
         if (i < g.M && j < g.N && (!lower || j <= i)) {
           double c = g.alpha * acc[mi][ni][r];
           if (g.beta != 0.0) c = fma(g.beta, Cp[(size_t)i * g.ldc + j], c);
@@ -236,18 +241,25 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 constexpr int LW = NB / 8;   // wavefronts of the leaf kernel
 constexpr int LP = NB / LW;  // panel width = columns (rows of L^{-1}) per wavefront
 
-__global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, int N, int lda,
-                                                       int* flag, double* __restrict__ Li,
-                                                       int ldi, int li_rows) {
-  __shared__ double Ls[4][NB][LP + 1];  // panel P's columns of L, row-indexed (buffer P % 4)
-  __shared__ double Xs[2][LP][NB];      // panel P's rows of L^{-1} (buffer P % 2)
+// LDS of the leaf: Ls[4][NB][LP + 1] (panel P's columns of L, row-indexed, buffer P % 4)
+// and Xs[2][LP][NB] (panel P's rows of L^{-1}, buffer P % 2).
+constexpr int kLeafLds = 4 * NB * (LP + 1) + 2 * LP * NB;  // doubles
+
+// The leaf's work by its NB * LW threads.  The block comes from A (global, row pitch lda) or,
+// when Ain is given, from LDS (row pitch NB + 1); L goes to A in either case.
+__device__ __forceinline__ void leaf_factor(double* __restrict__ A, int N, int lda,
+                                            const double* Ain, int* flag,
+                                            double* __restrict__ Li, int ldi, int li_rows,
+                                            double* lds) {
+  double(*Ls)[NB][LP + 1] = reinterpret_cast<double(*)[NB][LP + 1]>(lds);
+  double(*Xs)[LP][NB] = reinterpret_cast<double(*)[LP][NB]>(lds + 4 * NB * (LP + 1));
   const int t = threadIdx.x, i = t & (NB - 1), g = t / NB;
   double a[LP], y[LP];
 #pragma unroll
   for (int q = 0; q < LP; ++q) {
     const int c = g * LP + q;
     double v = 0.0;
-    if (i < N && c <= i) v = A[(size_t)i * lda + c];
+    if (i < N && c <= i) v = Ain ? Ain[i * (NB + 1) + c] : A[(size_t)i * lda + c];
     else if (i == c) v = 1.0;
     a[q] = v;
     y[q] = (c == i) ? 1.0 : 0.0;  // row c = 8g + q, column i (lane) of the identity
@@ -327,6 +339,13 @@ __global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, i
   }
 }
 
+__global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, int N, int lda,
+                                                       int* flag, double* __restrict__ Li,
+                                                       int ldi, int li_rows) {
+  __shared__ double lds[kLeafLds];
+  leaf_factor(A, N, lda, nullptr, flag, Li, ldi, li_rows, lds);
+}
+
 // ---------------------------------------------------------------- right-looking node
 // Below a few thousand rows the recursion's cost is its chain of small launches, not its
 // flops.  There a node is factored right-looking by 64-blocks, three launches per block
@@ -338,18 +357,86 @@ enum { kRLPanel = 0, kRLTrail = 1 };
 
 __device__ __forceinline__ int rl_rows(int b, int N) { return min(64, N - 64 * b); }
 
+// acc = P op(Q) for 64 x 64 blocks (entries past Mv rows / Nv columns / Kv of K read as
+// zero) by 512 threads: wavefront w computes the 32 x 32 quadrant ((w >> 1) & 1, w & 1) over
+// the K half w >> 2, and the upper half parks its partial sums in LDS for the lower one to
+// add.  Returns true on the lower four wavefronts, which then hold the product.  Ps, Qs:
+// LDS, 64 x 68 doubles each; Ps is reused for the parked sums.
+__device__ __forceinline__ bool tile_product(const double* P, int ldp, const double* Q,
+                                             int ldq, bool qT, int Mv, int Nv, int Kv,
+                                             double (*Ps)[68], double (*Qs)[68],
+                                             v4d (&acc)[2][2]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, kh = w >> 2, wm = (w >> 1) & 1, wn = w & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+  double pv[8], qv[8];  // all loads in flight before the first LDS store
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int rr = w + 8 * u, cc = lane;
+    pv[u] = (rr < Mv && cc < Kv) ? P[(size_t)rr * ldp + cc] : 0.0;
+    qv[u] = (qT ? (rr < Nv && cc < Kv) : (rr < Kv && cc < Nv)) ? Q[(size_t)rr * ldq + cc] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int rr = w + 8 * u, cc = lane;
+    Ps[cc][rr] = pv[u];
+    if (qT) Qs[cc][rr] = qv[u];
+    else Qs[rr][cc] = qv[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k4 = 0; k4 < 32; k4 += 4) {
+    const int kr = 32 * kh + k4 + lk;
+    const double a0 = Ps[kr][wm * 32 + lr];
+    const double a1 = Ps[kr][wm * 32 + 16 + lr];
+    const double b0 = Qs[kr][wn * 32 + lr];
+    const double b1 = Qs[kr][wn * 32 + 16 + lr];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+  __syncthreads();  // every wavefront is done with Ps: reuse it for the upper half's sums
+  double* park = &Ps[0][0] + (size_t)(w & 3) * 64 * 16;
+  if (kh == 1) {
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) park[((mi * 2 + ni) * 4 + q) * 64 + lane] = acc[mi][ni][q];
+  }
+  __syncthreads();
+  if (kh == 1) return false;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[mi][ni][q] += park[((mi * 2 + ni) * 4 + q) * 64 + lane];
+  return true;
+}
+
 // One block product per workgroup, C = alpha P op(Q) + beta C on 64 x 64 blocks (entries past
 // the node edge read as zero and are not written).  With r = nb - 1 - j, step j:
 //   panel: tiles t < r:        L_ij = A_ij L_jj^{-T}, i = j + 1 + t (in place in A);
 //          tiles r <= t < r+j: X_jk = L_jj^{-1} Y_jk, k = t - r (in place in Li);
 //   trail: tiles t < r(r+1)/2: A_ik -= L_ij L_kj^T for j < k <= i;
-//          the rest:           Y_ik = [k < j] Y_ik - L_ij X_jk for i > j, k <= j.
+//          the rest:           Y_ik = [k < j] Y_ik - L_ij X_jk for i > j, k <= j;
+//          tile 0, the diagonal block (j + 1, j + 1), is updated into LDS and workgroup 0 goes
+//          on to the leaf of block column j + 1 (its Cholesky factor and inverse), so the
+//          next column's leaf runs beside the trailing update instead of after it.
 // The operands of a tile are never written by another tile of the same launch, and a tile
 // that updates one of its own operands loads both before it stores.
 template <int MODE>
 __global__ __launch_bounds__(512) void k_rl_step(double* __restrict__ A, int lda,
                                                  double* __restrict__ Li, int ldi, int N,
-                                                 int j) {
+                                                 int j, int* flag) {
+  static_assert(NB == 64 && NB * LW == 512 && kLeafLds <= 64 * 68, "leaf inside a tile step");
   __shared__ double Ps[64][68];  // Ps[k][m] = P[m][k]
   __shared__ double Qs[64][68];  // Qs[k][n] = op(Q)[k][n]
   const int nb = (N + 63) >> 6, r = nb - 1 - j, t = blockIdx.x;
@@ -374,6 +461,43 @@ __global__ __launch_bounds__(512) void k_rl_step(double* __restrict__ A, int lda
       Mv = rl_rows(j, N); Nv = 64; Kv = rl_rows(j, N);
     }
   } else {
+    if (t == 0) {  // A_dd -= L_dj L_dj^T, then the leaf of block d
+      const int d = j + 1, nd = rl_rows(d, N);
+      const double* Pd = A + (size_t)(64 * d) * lda + 64 * j;
+      double* Add = A + (size_t)(64 * d) * lda + 64 * d;
+      const int tid = threadIdx.x;
+      const int lane = tid & 63, w = tid >> 6, kh = w >> 2, wm = (w >> 1) & 1, wn = w & 1;
+      const int lr = lane & 15, lk = lane >> 4;
+      double cv[2][2][4];
+      if (kh == 0) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int i = wm * 32 + mi * 16 + lk + 4 * q, c = wn * 32 + ni * 16 + lr;
+              cv[mi][ni][q] = (i < nd && c <= i) ? Add[(size_t)i * lda + c] : 0.0;
+            }
+      }
+      v4d acc[2][2];
+      double* Al = &Qs[0][0];  // the updated block, row pitch NB + 1
+      if (tile_product(Pd, lda, Pd, lda, true, nd, nd, 64, Ps, Qs, acc)) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+          for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int i = wm * 32 + mi * 16 + lk + 4 * q, c = wn * 32 + ni * 16 + lr;
+              Al[i * (NB + 1) + c] = cv[mi][ni][q] - acc[mi][ni][q];
+            }
+      }
+      __syncthreads();
+      leaf_factor(Add, nd, lda, Al, flag, Li + (size_t)(64 * d) * ldi + 64 * d, ldi, nd,
+                  &Ps[0][0]);
+      return;
+    }
     // block (i, k) of A (k > j) or of Y (k <= j) that this tile updates
     const int ta = r * (r + 1) / 2;
     const bool yt = t >= ta;
@@ -402,8 +526,6 @@ __global__ __launch_bounds__(512) void k_rl_step(double* __restrict__ A, int lda
       alpha = -1.0; beta = (k < j) ? 1.0 : 0.0;
     }
   }
-  // 512 threads: wavefront w computes the 32 x 32 quadrant (w >> 1) & 1, w & 1 over the K half
-  // w >> 2; the upper half parks its partial sums in LDS for the lower one to add and store
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, kh = w >> 2, wm = (w >> 1) & 1, wn = w & 1;
   const int lr = lane & 15, lk = lane >> 4;
@@ -419,50 +541,8 @@ __global__ __launch_bounds__(512) void k_rl_step(double* __restrict__ A, int lda
           cv[mi][ni][q] = (i < Mv && c < Nv) ? C[(size_t)i * ldc + c] : 0.0;
         }
   }
-  double pv[8], qv[8];  // all loads in flight before the first LDS store
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int rr = w + 8 * u, cc = lane;
-    pv[u] = (rr < Mv && cc < Kv) ? P[(size_t)rr * ldp + cc] : 0.0;
-    qv[u] = (qT ? (rr < Nv && cc < Kv) : (rr < Kv && cc < Nv)) ? Q[(size_t)rr * ldq + cc] : 0.0;
-  }
-#pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int rr = w + 8 * u, cc = lane;
-    Ps[cc][rr] = pv[u];
-    if (qT) Qs[cc][rr] = qv[u];
-    else Qs[rr][cc] = qv[u];
-  }
-  __syncthreads();
   v4d acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-  for (int k4 = 0; k4 < 32; k4 += 4) {
-    const int kr = 32 * kh + k4 + lk;
-    const double a0 = Ps[kr][wm * 32 + lr];
-    const double a1 = Ps[kr][wm * 32 + 16 + lr];
-    const double b0 = Qs[kr][wn * 32 + lr];
-    const double b1 = Qs[kr][wn * 32 + 16 + lr];
-    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
-  }
-  __syncthreads();  // every wavefront is done with Ps: reuse it for the upper half's sums
-  double* park = &Ps[0][0] + (size_t)(w & 3) * 64 * 16;
-  if (kh == 1) {
-#pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-      for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) park[((mi * 2 + ni) * 4 + q) * 64 + lane] = acc[mi][ni][q];
-  }
-  __syncthreads();
-  if (kh == 1) return;
+  if (!tile_product(P, ldp, Q, ldq, qT, Mv, Nv, Kv, Ps, Qs, acc)) return;
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -472,7 +552,7 @@ __global__ __launch_bounds__(512) void k_rl_step(double* __restrict__ A, int lda
         const int i = wm * 32 + mi * 16 + lk + 4 * q;
         const int c = wn * 32 + ni * 16 + lr;
         if (i < Mv && c < Nv) {
-          double v = alpha * (acc[mi][ni][q] + park[((mi * 2 + ni) * 4 + q) * 64 + lane]);
+          double v = alpha * acc[mi][ni][q];
           if (beta != 0.0) v = fma(beta, cv[mi][ni][q], v);
           C[(size_t)i * ldc + c] = v;
         }
@@ -594,21 +674,21 @@ static void gemm_cost(const GemmArgs& g, int te, double* flops, double* bytes) {
                   (double)g.M * g.N * (g.beta != 0.0 ? 2.0 : 1.0));
 }
 
-template <int WM, int WN, int KS>
+template <int WM, int WN, int KS, int FM = 2, int FN = 2>
 static void launch_gemm(const GemmArgs& g, hipStream_t s) {
-  constexpr int te_m = 32 * WM, te_n = 32 * WN;
+  constexpr int te_m = 16 * FM * WM, te_n = 16 * FN * WN;
   const int tm = (g.M + te_m - 1) / te_m, tn = (g.N + te_n - 1) / te_n;
   // a lower-triangular output of a square tile grid launches only its lower tiles
   const int tiles = ((g.flags & kLowerOut) && tm == tn) ? tm * (tm + 1) / 2 : tm * tn;
   const dim3 grid(tiles, g.offs ? g.batch : 1), block(64 * WM * WN * KS);
   if (!g.transA && !g.transB)
-    k_gemm<false, false, WM, WN, KS><<<grid, block, 0, s>>>(g);
+    k_gemm<false, false, WM, WN, KS, FM, FN><<<grid, block, 0, s>>>(g);
   else if (!g.transA && g.transB)
-    k_gemm<false, true, WM, WN, KS><<<grid, block, 0, s>>>(g);
+    k_gemm<false, true, WM, WN, KS, FM, FN><<<grid, block, 0, s>>>(g);
   else if (g.transA && !g.transB)
-    k_gemm<true, false, WM, WN, KS><<<grid, block, 0, s>>>(g);
+    k_gemm<true, false, WM, WN, KS, FM, FN><<<grid, block, 0, s>>>(g);
   else
-    k_gemm<true, true, WM, WN, KS><<<grid, block, 0, s>>>(g);
+    k_gemm<true, true, WM, WN, KS, FM, FN><<<grid, block, 0, s>>>(g);
 }
 
 int gemm(const GemmArgs& g, hipStream_t s) {
@@ -654,27 +734,29 @@ constexpr int kSideMin = 512;
 static int rl_factor(double* A, int N, int lda, double* Li, int ldi, int* flag, hipStream_t s) {
   const int nb = (N + NB - 1) / NB;
   const double tile_flops = 2.0 * NB * NB * NB, tile_bytes = 4.0 * NB * NB * 8;
-  for (int j = 0; j < nb; ++j) {
-    const int nj = std::min(NB, N - NB * j);
+  const double leaf_flops = 2.0 * NB * NB * NB / 3.0, leaf_bytes = 3.0 * 8 * NB * NB;
+  {  // the first block column's leaf; every later one runs inside the previous trail step
+    const int n0 = std::min(NB, N);
     ProfMark pm = prof_begin(LRSDP_K_LEAF, s);
-    k_chol_leaf<<<1, NB * LW, 0, s>>>(A + (size_t)(NB * j) * lda + NB * j, nj, lda, flag,
-                                      Li + (size_t)(NB * j) * ldi + NB * j, ldi, nj);
+    k_chol_leaf<<<1, NB * LW, 0, s>>>(A, n0, lda, flag, Li, ldi, n0);
     LRSDP_HIP(hipGetLastError());
-    // Cholesky nj^3 / 3 and triangular inverse nj^3 / 3 flops; A read, L and L^{-1} written
-    prof_end(pm, s, 3.0 * 8 * nj * nj, 2.0 * nj * nj * nj / 3.0);
+    // Cholesky n0^3 / 3 and triangular inverse n0^3 / 3 flops; A read, L and L^{-1} written
+    prof_end(pm, s, 3.0 * 8 * n0 * n0, 2.0 * n0 * n0 * n0 / 3.0);
+  }
+  for (int j = 0; j < nb; ++j) {
     const int r = nb - 1 - j;
     if (r + j > 0) {
-      pm = prof_begin(LRSDP_K_TILE, s);
-      k_rl_step<kRLPanel><<<r + j, 512, 0, s>>>(A, lda, Li, ldi, N, j);
+      ProfMark pm = prof_begin(LRSDP_K_TILE, s);
+      k_rl_step<kRLPanel><<<r + j, 512, 0, s>>>(A, lda, Li, ldi, N, j, flag);
       LRSDP_HIP(hipGetLastError());
       prof_end(pm, s, (r + j) * tile_bytes, (r + j) * tile_flops);
     }
-    const int tiles = r * (r + 1) / 2 + r * (j + 1);
-    if (tiles > 0) {
-      pm = prof_begin(LRSDP_K_TILE, s);
-      k_rl_step<kRLTrail><<<tiles, 512, 0, s>>>(A, lda, Li, ldi, N, j);
+    if (r > 0) {
+      const int tiles = r * (r + 1) / 2 + r * (j + 1);
+      ProfMark pm = prof_begin(LRSDP_K_TILE, s);
+      k_rl_step<kRLTrail><<<tiles, 512, 0, s>>>(A, lda, Li, ldi, N, j, flag);
       LRSDP_HIP(hipGetLastError());
-      prof_end(pm, s, tiles * tile_bytes, tiles * tile_flops);
+      prof_end(pm, s, tiles * tile_bytes + leaf_bytes, tiles * tile_flops + leaf_flops);
     }
   }
   return LRSDP_OK;

@@ -40,17 +40,18 @@ __global__ __launch_bounds__(64) void k_gram(int b, int n, const double* X, cons
   if (lane == 0) G[i * b + j] = s;
 }
 
-// Cholesky G = L L^T of the B x B Gram matrix (B <= 16) and L^{-1} into Linv (row pitch 64),
-// in one wavefront: lane i holds row i; pivots and column values come by cross-lane reads.
-// B is a template parameter so that every register index is fixed at compile time.
-// A non-positive pivot sets *flag.
+// Cholesky G = L L^T of the B x B Gram matrix (B <= 16, row pitch ldg) and L^{-1} into Linv
+// (row pitch ldl), by one wavefront: lane i holds row i; pivots and column values come by
+// cross-lane reads.  B is a template parameter so that every register index is fixed at
+// compile time.  A non-positive pivot sets *flag.
 template <int B>
-__global__ __launch_bounds__(64) void k_small_chol_inv(const double* G, double* Linv, int* flag) {
-  const int i = threadIdx.x;
+__device__ __forceinline__ void chol_inv_wave(const double* G, int ldg, double* Linv, int ldl,
+                                              int* flag) {
+  const int i = threadIdx.x & 63;
   double a[B], y[B];
 #pragma unroll
   for (int c = 0; c < B; ++c) {
-    a[c] = (i < B && c <= i) ? G[i * B + c] : (i == c ? 1.0 : 0.0);
+    a[c] = (i < B && c <= i) ? G[i * ldg + c] : (i == c ? 1.0 : 0.0);
     y[c] = (i == c) ? 1.0 : 0.0;
   }
 #pragma unroll
@@ -78,7 +79,12 @@ __global__ __launch_bounds__(64) void k_small_chol_inv(const double* G, double* 
   }
 #pragma unroll
   for (int c = 0; c < B; ++c)
-    if (i < B) Linv[i * 64 + c] = (c <= i) ? y[c] : 0.0;
+    if (i < B) Linv[i * ldl + c] = (c <= i) ? y[c] : 0.0;
+}
+
+template <int B>
+__global__ __launch_bounds__(64) void k_small_chol_inv(const double* G, double* Linv, int* flag) {
+  chol_inv_wave<B>(G, B, Linv, 64, flag);
 }
 
 void small_chol_inv(int b, const double* G, double* Linv, int* flag, hipStream_t s) {
@@ -139,20 +145,25 @@ __global__ __launch_bounds__(64) void k_ritz_residual(int n, const double* T, co
   if (lane == 0) res[i] = sqrt(s);
 }
 
-// Cyclic Jacobi on the symmetric b x b matrix B (b <= 16): B = Q diag(theta) Q^T, theta
-// ascending.  One wavefront; lane j owns column j of the working copies.
-__global__ __launch_bounds__(64) void k_jacobi(int b, const double* Bin, double* Q,
-                                               double* theta) {
-  __shared__ double A[BMAX][BMAX + 1];
-  __shared__ double V[BMAX][BMAX + 1];
-  __shared__ double cs[2];
-  const int t = threadIdx.x;
+// Orders the LDS accesses of one wavefront's lanes (the only wavefront taking part).
+#define LRSDP_WAVE_SYNC()                                   \
+  do {                                                      \
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");  \
+    __builtin_amdgcn_wave_barrier();                        \
+  } while (0)
+
+// Cyclic Jacobi on the symmetric b x b matrix sym(B) = (B + B^T) / 2 (b <= 16, row pitch ldb):
+// sym(B) = Q diag(theta) Q^T, theta ascending.  Run by one wavefront (lane j owns column j of
+// the working copies A, V in LDS; cs: two doubles of LDS).
+__device__ void jacobi_wave(int b, const double* Bin, int ldb, double* Q, double* theta,
+                            double (*A)[BMAX + 1], double (*V)[BMAX + 1], double* cs) {
+  const int t = threadIdx.x & 63;
   for (int e = t; e < BMAX * BMAX; e += 64) {
     const int r = e / BMAX, c = e % BMAX;
-    A[r][c] = (r < b && c < b) ? 0.5 * (Bin[r * b + c] + Bin[c * b + r]) : 0.0;
+    A[r][c] = (r < b && c < b) ? 0.5 * (Bin[r * ldb + c] + Bin[c * ldb + r]) : 0.0;
     V[r][c] = (r == c) ? 1.0 : 0.0;
   }
-  __syncthreads();
+  LRSDP_WAVE_SYNC();
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, nrm = 0.0;
     for (int e = t; e < b * b; e += 64) {
@@ -179,7 +190,7 @@ __global__ __launch_bounds__(64) void k_jacobi(int b, const double* Bin, double*
           cs[0] = c;
           cs[1] = s;
         }
-        __syncthreads();
+        LRSDP_WAVE_SYNC();
         const double c = cs[0], s = cs[1];
         if (t < b) {  // columns p, q of A and V
           const double ap = A[t][p], aq = A[t][q];
@@ -189,13 +200,13 @@ __global__ __launch_bounds__(64) void k_jacobi(int b, const double* Bin, double*
           V[t][p] = c * vp - s * vq;
           V[t][q] = s * vp + c * vq;
         }
-        __syncthreads();
+        LRSDP_WAVE_SYNC();
         if (t < b) {  // rows p, q of A
           const double ap = A[p][t], aq = A[q][t];
           A[p][t] = c * ap - s * aq;
           A[q][t] = s * ap + c * aq;
         }
-        __syncthreads();
+        LRSDP_WAVE_SYNC();
       }
   }
   if (t == 0) {  // ascending order (selection sort of the columns)
@@ -212,6 +223,183 @@ __global__ __launch_bounds__(64) void k_jacobi(int b, const double* Bin, double*
       theta[i] = A[ord[i]][ord[i]];
       for (int r = 0; r < b; ++r) Q[r * b + i] = V[r][ord[i]];
     }
+  }
+  LRSDP_WAVE_SYNC();
+}
+
+__global__ __launch_bounds__(64) void k_jacobi(int b, const double* Bin, double* Q,
+                                               double* theta) {
+  __shared__ double A[BMAX][BMAX + 1];
+  __shared__ double V[BMAX][BMAX + 1];
+  __shared__ double cs[2];
+  jacobi_wave(b, Bin, b, Q, theta, A, V, cs);
+}
+
+// ---------------------------------------------------------------- fused sweep kernels
+// When b n doubles fit the LDS budget, one workgroup holds the whole block and a sweep
+// takes two launches besides the products with W: Rayleigh-Ritz (Gram, Jacobi, rotation,
+// residuals) and the orthonormalization (row scaling, Cholesky QR twice).
+constexpr int kFT = 512;                   // threads of the fused kernels
+constexpr size_t kFusedLds = 96 * 1024;    // their dynamic LDS budget (Rayleigh-Ritz: 2 b n)
+
+// v[0..16) summed over the workgroup into out[0..16) (LDS); red: kFT / 64 x 16 doubles.
+__device__ __forceinline__ void wg_sum16(double (&v)[16], double* red, double* out) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const double sm = wave_sum(v[m]);
+    if (lane == 0) red[w * 16 + m] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x < 16) {
+    double sm = 0.0;
+    for (int ww = 0; ww < kFT / 64; ++ww) sm += red[ww * 16 + threadIdx.x];
+    out[threadIdx.x] = sm;
+  }
+  __syncthreads();
+}
+
+// G[i][j] = sum_q A[i][q] C[j][q], i, j < B (row pitch 16); SYM: the lower triangle, mirrored.
+template <int B, bool SYM>
+__device__ void wg_gram(int n, const double* A, const double* C, double* red, double* ch,
+                        double* G) {
+  constexpr int NE = SYM ? B * (B + 1) / 2 : B * B;
+  for (int c0 = 0; c0 < NE; c0 += 16) {
+    double v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m] = 0.0;
+    for (int q = threadIdx.x; q < n; q += kFT) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int e = c0 + m;
+        if (e < NE) {
+          int i, j;
+          if (SYM) {
+            i = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+            while ((i + 1) * (i + 2) / 2 <= e) ++i;
+            while (i * (i + 1) / 2 > e) --i;
+            j = e - i * (i + 1) / 2;
+          } else {
+            i = e / B;
+            j = e - i * B;
+          }
+          v[m] = fma(A[i * n + q], C[j * n + q], v[m]);
+        }
+      }
+    }
+    wg_sum16(v, red, ch);
+    if (threadIdx.x < 16 && c0 + threadIdx.x < NE) {
+      const int e = c0 + threadIdx.x;
+      int i, j;
+      if (SYM) {
+        i = (int)((sqrtf(8.0f * e + 1.0f) - 1.0f) * 0.5f);
+        while ((i + 1) * (i + 2) / 2 <= e) ++i;
+        while (i * (i + 1) / 2 > e) --i;
+        j = e - i * (i + 1) / 2;
+      } else {
+        i = e / B;
+        j = e - i * B;
+      }
+      G[i * 16 + j] = ch[threadIdx.x];
+      if (SYM) G[j * 16 + i] = ch[threadIdx.x];
+    }
+    __syncthreads();
+  }
+}
+
+// X <- orth(rows of Y): row normalization, then Cholesky QR twice; one workgroup, Y (b x n)
+// staged in LDS.  Same arithmetic as the multi-kernel path up to summation order.
+template <int B>
+__global__ __launch_bounds__(kFT) void k_orth_fused(int n, const double* __restrict__ Y,
+                                                    double* __restrict__ X, int* flag) {
+  extern __shared__ __align__(16) double xl[];  // B x n
+  __shared__ double red[kFT / 64 * 16], ch[16], G[16 * 16], Li[16 * 16];
+  const int t = threadIdx.x;
+  for (int e = t; e < B * n; e += kFT) xl[e] = Y[e];
+  __syncthreads();
+  {  // unit rows
+    double v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m] = 0.0;
+    for (int q = t; q < n; q += kFT)
+#pragma unroll
+      for (int i = 0; i < B; ++i) v[i] = fma(xl[i * n + q], xl[i * n + q], v[i]);
+    wg_sum16(v, red, ch);
+    for (int q = t; q < n; q += kFT)
+#pragma unroll
+      for (int i = 0; i < B; ++i) xl[i * n + q] *= ch[i] > 0.0 ? 1.0 / sqrt(ch[i]) : 0.0;
+    __syncthreads();
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    wg_gram<B, true>(n, xl, xl, red, ch, G);
+    if (t < 64) chol_inv_wave<B>(G, 16, Li, 16, flag);
+    __syncthreads();
+    for (int q = t; q < n; q += kFT) {
+      double col[B];
+#pragma unroll
+      for (int j = 0; j < B; ++j) col[j] = xl[j * n + q];
+#pragma unroll
+      for (int i = 0; i < B; ++i) {
+        double sm = 0.0;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) sm = fma(Li[i * 16 + j], col[j], sm);
+        xl[i * n + q] = sm;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < B * n; e += kFT) X[e] = xl[e];
+}
+
+// Rayleigh-Ritz on the block X with T = X W: B = X T^T, B = Q diag(theta) Q^T (Jacobi),
+// X <- Q^T X, T <- Q^T T (in place), res_i = ||T_i - theta_i X_i||.  One workgroup.
+template <int B>
+__global__ __launch_bounds__(kFT) void k_rr_fused(int n, double* __restrict__ X,
+                                                  double* __restrict__ T,
+                                                  double* __restrict__ theta,
+                                                  double* __restrict__ res) {
+  extern __shared__ __align__(16) double sm[];  // X then T, B x n each
+  __shared__ double red[kFT / 64 * 16], ch[16], G[16 * 16], Qm[BMAX * BMAX];
+  __shared__ double JA[BMAX][BMAX + 1], JV[BMAX][BMAX + 1], cs[2], th[BMAX];
+  double* xl = sm;
+  double* tl = sm + (size_t)B * n;
+  const int t = threadIdx.x;
+  for (int e = t; e < B * n; e += kFT) {
+    xl[e] = X[e];
+    tl[e] = T[e];
+  }
+  __syncthreads();
+  wg_gram<B, false>(n, xl, tl, red, ch, G);
+  if (t < 64) jacobi_wave(B, G, 16, Qm, th, JA, JV, cs);
+  __syncthreads();
+  double v[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) v[m] = 0.0;
+  for (int q = t; q < n; q += kFT) {
+    double xc[B], tc[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+      xc[j] = xl[j * n + q];
+      tc[j] = tl[j * n + q];
+    }
+#pragma unroll
+    for (int i = 0; i < B; ++i) {
+      double xs = 0.0, ts = 0.0;
+#pragma unroll
+      for (int j = 0; j < B; ++j) {
+        xs = fma(Qm[j * B + i], xc[j], xs);
+        ts = fma(Qm[j * B + i], tc[j], ts);
+      }
+      X[(size_t)i * n + q] = xs;
+      T[(size_t)i * n + q] = ts;
+      const double r = ts - th[i] * xs;
+      v[i] = fma(r, r, v[i]);
+    }
+  }
+  wg_sum16(v, red, ch);
+  if (t < B) {
+    theta[t] = th[t];
+    res[t] = sqrt(ch[t]);
   }
 }
 
@@ -291,8 +479,23 @@ int spectral_top(const double* W, int n, int k, void* ws, double* lam_out, doubl
   k_trace_dd<<<1, 256, 0, s>>>(n, W, tr);
   k_clear_flag<<<1, 64, 0, s>>>(flag);
   k_start_block<<<eg, 256, 0, s>>>(b, n, T);
+  // (the fused kernels keep b-sized register blocks: up to b = 8 they stay in registers)
+  const bool fused = b <= 8 && 2 * bn * sizeof(double) <= kFusedLds;
   // X <- orth(rows of T): row normalization, then Cholesky QR twice (T -> Y -> X)
   auto orthonormalize = [&]() -> int {
+    if (fused) {
+      switch (b) {
+#define LRSDP_ORTH(B)                                                            \
+  case B:                                                                        \
+    k_orth_fused<B><<<1, kFT, bn * sizeof(double), s>>>(n, T, X, flag); \
+    break;
+        LRSDP_ORTH(1) LRSDP_ORTH(2) LRSDP_ORTH(3) LRSDP_ORTH(4) LRSDP_ORTH(5) LRSDP_ORTH(6)
+        LRSDP_ORTH(7) LRSDP_ORTH(8)
+#undef LRSDP_ORTH
+      }
+      LRSDP_HIP(hipGetLastError());
+      return LRSDP_OK;
+    }
     k_row_normalize<<<b, 64, 0, s>>>(n, T);
     for (int pass = 0; pass < 2; ++pass) {
       const double* src = pass == 0 ? T : Y;
@@ -309,13 +512,25 @@ int spectral_top(const double* W, int n, int k, void* ws, double* lam_out, doubl
   std::vector<double> h(133);
   for (sweeps = 1; sweeps <= max_sweeps; ++sweeps) {
     LRSDP_TRY(rows_k(n, b, W, 0, X, T, s));                  // T = X W
-    k_gram<<<b * b, 64, 0, s>>>(b, n, X, T, G);              // B = X T^T
-    k_jacobi<<<1, 64, 0, s>>>(b, G, Qm, theta);
-    k_rotate<<<eg, 256, 0, s>>>(b, n, Qm, X, Y);             // Ritz vectors
-    k_rotate<<<eg, 256, 0, s>>>(b, n, Qm, T, X);             // their images under W
-    std::swap(X, Y);                                         // X: Ritz vectors, Y: W X
-    std::swap(Y, T);                                         // T: W X, Y: free
-    k_ritz_residual<<<b, 64, 0, s>>>(n, T, X, theta, res);
+    if (fused) {  // X <- Ritz vectors, T <- W X, theta, res: one launch
+      switch (b) {
+#define LRSDP_RR(B)                                                                     \
+  case B:                                                                               \
+    k_rr_fused<B><<<1, kFT, 2 * bn * sizeof(double), s>>>(n, X, T, theta, res); \
+    break;
+        LRSDP_RR(1) LRSDP_RR(2) LRSDP_RR(3) LRSDP_RR(4) LRSDP_RR(5) LRSDP_RR(6) LRSDP_RR(7)
+        LRSDP_RR(8)
+#undef LRSDP_RR
+      }
+    } else {
+      k_gram<<<b * b, 64, 0, s>>>(b, n, X, T, G);              // B = X T^T
+      k_jacobi<<<1, 64, 0, s>>>(b, G, Qm, theta);
+      k_rotate<<<eg, 256, 0, s>>>(b, n, Qm, X, Y);             // Ritz vectors
+      k_rotate<<<eg, 256, 0, s>>>(b, n, Qm, T, X);             // their images under W
+      std::swap(X, Y);                                         // X: Ritz vectors, Y: W X
+      std::swap(Y, T);                                         // T: W X, Y: free
+      k_ritz_residual<<<b, 64, 0, s>>>(n, T, X, theta, res);
+    }
     LRSDP_HIP(hipGetLastError());
     // theta, res, tr and the factorization flag are contiguous: one copy per sweep
     LRSDP_HIP(hipMemcpyAsync(h.data(), theta, 133 * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -103,19 +103,42 @@ __global__ __launch_bounds__(256) void k_dJL(int n, int k, const int32_t* rowptr
     }
 }
 
-// R_JL = B_JL Z = 1/2 (diag(d_JL) Z + D_{u_L} P_J)
-__global__ void k_R_pair(int n, int J, int L, const double* Z, const double* U,
-                         const double* PJ, const double* dJL, double* R) {
-  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
-  const size_t nn = (size_t)n * n;
-  if (idx >= nn) return;
-  const int a = (int)(idx / n);
-  R[idx] = 0.5 * fma(dJL[a], Z[idx], U[(size_t)L * n + a] * PJ[J * nn + idx]);
+// Block pair p = J (J + 1) / 2 + L (L <= J) of the lower block triangle of bold S.
+__device__ __forceinline__ void pair_of(int p, int* J, int* L) {
+  int j = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+  while ((j + 1) * (j + 2) / 2 <= p) ++j;
+  while (j * (j + 1) / 2 > p) --j;
+  *J = j;
+  *L = p - j * (j + 1) / 2;
 }
 
+// R_JL = B_JL Z = 1/2 (diag(d_JL) Z + D_{u_L} P_J) for the pairs q0 + y, y < gridDim.y, into
+// R + y n^2; and (thread 0 of column 0) the batched-GEMM offsets of those pairs:
+// A at 0, B at y n^2, C at block (J, L) of bold S (row pitch nk).
+__global__ void k_R_pairs(int n, int nk, int q0, const double* Z, const double* U,
+                          const double* PJ, const double* dd, double* R, int64_t* offs) {
+  const int y = blockIdx.y, p = q0 + y;
+  int J, L;
+  pair_of(p, &J, &L);
+  const size_t nn = (size_t)n * n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    offs[3 * y] = 0;
+    offs[3 * y + 1] = (int64_t)y * (int64_t)nn;
+    offs[3 * y + 2] = (int64_t)n * J * nk + (int64_t)n * L;
+  }
+  const double* dJL = dd + (size_t)p * n;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < nn;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int a = (int)(idx / n);
+    R[y * nn + idx] = 0.5 * fma(dJL[a], Z[idx], U[(size_t)L * n + a] * PJ[J * nn + idx]);
+  }
+}
+
+// S_JJ += v I for the k diagonal blocks (block J = blockIdx.y).
 __global__ void k_add_diag(double* S, int n, int ld, double v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) S[(size_t)i * ld + i] += v;
+  const size_t o = (size_t)n * blockIdx.y * ld + (size_t)n * blockIdx.y;
+  if (i < n) S[o + (size_t)i * ld + i] += v;
 }
 
 // N (nk x r): column c <-> pair (i < j): block j holds y_i, block i holds -y_j, y = rows of Yt.
@@ -383,34 +406,12 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
       prof_end(pm, s, 8.0 * ((double)k + 1) * nn + 12.0 * P->nnz,
                2.0 * (double)P->nnz * n * k);
     }
-    std::vector<int> pj, pl;
-    for (int J = 0; J < k; ++J)
-      for (int L = 0; L <= J; ++L) {
-        pj.push_back(J);
-        pl.push_back(L);
-      }
+    // chunks of pair_cap pairs (R_JL buffers); stream order keeps a chunk's R and offsets
+    // from being overwritten before its GEMM has read them
     for (int q0 = 0; q0 < npairs && rc == LRSDP_OK; q0 += (int)pair_cap) {
       const int cnt = std::min<int>((int)pair_cap, npairs - q0);
-      std::vector<int64_t> ho(3 * cnt);
-      for (int q = 0; q < cnt; ++q) {
-        const int J = pj[q0 + q], L = pl[q0 + q];
-        ho[3 * q] = 0;
-        ho[3 * q + 1] = (int64_t)q * nn;
-        ho[3 * q + 2] = (int64_t)n * J * nk + (int64_t)n * L;
-      }
-      if (hipMemcpyAsync(offs.p, ho.data(), ho.size() * sizeof(int64_t), hipMemcpyHostToDevice,
-                         s) != hipSuccess ||
-          hipStreamSynchronize(s) != hipSuccess) {
-        rc = LRSDP_ERR_DEVICE;
-        break;
-      }
-      for (int q = 0; q < cnt; ++q) {
-        const int J = pj[q0 + q], L = pl[q0 + q];
-        const int pidx = J * (J + 1) / 2 + L;
-        k_R_pair<<<grid_for((int64_t)nn, 256), 256, 0, s>>>(n, J, L, f->Z, f->U, PJ.p,
-                                                            dd_.p + (size_t)pidx * n,
-                                                            Rb.p + (size_t)q * nn);
-      }
+      k_R_pairs<<<dim3(std::min<int64_t>(grid_for((int64_t)nn, 256), 1024), cnt), 256, 0, s>>>(
+          n, nk, q0, f->Z, f->U, PJ.p, dd_.p, Rb.p, reinterpret_cast<int64_t*>(offs.p));
       GemmArgs g;
       g.M = n; g.N = n; g.K = n;
       g.A = f->Z; g.lda = n; g.transA = true;  // op(A) = Z^T, zero below its diagonal
@@ -420,12 +421,9 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
       g.batch = cnt;
       g.offs = reinterpret_cast<const int64_t*>(offs.p);
       rc = gemm(g, s);
-      if (rc == LRSDP_OK && hipStreamSynchronize(s) != hipSuccess) rc = LRSDP_ERR_DEVICE;
     }
     if (rc != LRSDP_OK) break;
-    for (int J = 0; J < k; ++J)
-      k_add_diag<<<grid_for(n, 256), 256, 0, s>>>(S + (size_t)n * J * nk + (size_t)n * J, n, nk,
-                                                   f->tau2);
+    k_add_diag<<<dim3(grid_for(n, 256), k), 256, 0, s>>>(S, n, nk, f->tau2);
     // ---- deflation of null(bold U) directions
     if (r) {
       double* Yt = Rb.p;  // k x n: (Z^{-1} U)^T = U Z^{-T}

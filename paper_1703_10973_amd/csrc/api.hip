@@ -212,7 +212,7 @@ int lrsdp_ctx_create(int device, void* stream, size_t budget, lrsdp_ctx** out) {
   }
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_pinned), 64 * sizeof(double),
                     hipHostMallocDefault) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&c->d_flag), sizeof(int)) != hipSuccess) {
+      hipMalloc(reinterpret_cast<void**>(&c->d_flag), 4 * sizeof(int)) != hipSuccess) {
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return LRSDP_ERR_DEVICE;

@@ -29,6 +29,7 @@ struct GemmArgs {
   double* C = nullptr;
   int ldc = 0;
   double alpha = 1.0, beta = 0.0;
+  const double* alpha_dev = nullptr;  // device scalar that replaces alpha when given
   unsigned flags = 0;
   int batch = 1;                  // with offs: number of products (grid.y)
   const int64_t* offs = nullptr;  // device, 3 x batch element offsets of A, B, C

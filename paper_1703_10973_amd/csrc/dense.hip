@@ -192,7 +192,7 @@ __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
         const int i = i0 + wm * 16 * FM + mi * 16 + lk + 4 * r;
         const int j = j0 + wn * 16 * FN + ni * 16 + lr;
         if (i < g.M && j < g.N && (!lower || j <= i)) {
-          double c = g.alpha * acc[mi][ni][r];
+          double c = (g.alpha_dev ? *g.alpha_dev : g.alpha) * acc[mi][ni][r];
           if (g.beta != 0.0) c = fma(g.beta, Cp[(size_t)i * g.ldc + j], c);
           Cp[(size_t)i * g.ldc + j] = c;
         }

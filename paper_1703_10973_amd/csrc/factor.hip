@@ -195,12 +195,6 @@ __global__ void k_f64_to_bf16(size_t cnt, const double* a, uint16_t* b) {
   if (i < cnt) b[i] = f32_to_bf16_rne(static_cast<float>(a[i]));
 }
 
-int read_flag(lrsdp_ctx* ctx, int* out) {
-  LRSDP_HIP(hipMemcpyAsync(out, ctx->d_flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  LRSDP_HIP(hipStreamSynchronize(ctx->stream));
-  return LRSDP_OK;
-}
-
 }  // namespace
 
 size_t work_doubles(int n, int m, int k) {
@@ -321,8 +315,7 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
     LRSDP_TRY(dev_alloc(ctx, &sws, swb));
     int sweeps = 0;
     rc = spectral_top(f->W, n, k, sws, f->lam_dev, Vl, nullptr, 40, nullptr, &sweeps, s);
-    (void)hipStreamSynchronize(s);
-    dev_free(ctx, sws, swb);
+    dev_free(ctx, sws, swb);  // the pool hands it out again only in stream order
     if (rc == LRSDP_OK) f->eig_sweeps = sweeps;
     else if (rc != LRSDP_ERR_EIG) return rc;
   }
@@ -381,19 +374,18 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
     free_tmp();
     return rc;
   }
+  // the flags of the two factorizations are read once, at the end: a failed Z only makes
+  // the steps after it compute garbage, which is discarded
+  int* flag_S = ctx->d_flag;
+  int* flag_Z = ctx->d_flag + 1;
+  int* flag_scratch = ctx->d_flag + 2;
   do {
-    if (hipMemsetAsync(ctx->d_flag, 0, sizeof(int), s) != hipSuccess) {
+    if (hipMemsetAsync(ctx->d_flag, 0, 3 * sizeof(int), s) != hipSuccess) {
       rc = LRSDP_ERR_DEVICE;
       break;
     }
-    if ((rc = potrf_inv(f->Z, n, n, Zi.p, n, ctx->d_flag, ptmp.p, true, s))) break;
+    if ((rc = potrf_inv(f->Z, n, n, Zi.p, n, flag_Z, ptmp.p, true, s))) break;
     if ((rc = zero_upper(f->Z, n, n, s))) break;
-    int flag = 0;
-    if ((rc = read_flag(ctx, &flag))) break;
-    if (flag) {
-      rc = LRSDP_ERR_CHOL_Z;
-      break;
-    }
     if ((rc = transpose(f->Z, n, n, f->Zt, n, s))) break;
 
     // ---- 2: bold S (lower block triangle).  P_J = Obar D_{u_J} Z for every J in one sparse
@@ -436,7 +428,7 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
         double* Qin = pass == 0 ? f->QN : Q2.p;
         double* Qout = pass == 0 ? Q2.p : f->QN;
         k_gram_cols<<<r * r, kT, 0, s>>>(nk, r, Qin, G);
-        if ((rc = potrf_inv(G, r, r, Gi, r, ctx->d_flag, ptmp.p, true, s))) break;
+        if ((rc = potrf_inv(G, r, r, Gi, r, flag_scratch, ptmp.p, true, s))) break;
         GemmArgs h;  // Q <- Q R^{-1} = Q (L^{-1})^T
         h.M = nk; h.N = r; h.K = r;
         h.A = Qin; h.lda = r;
@@ -446,41 +438,36 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
         if ((rc = gemm(h, s))) break;
       }
       if (rc) break;
-      k_max_diag<<<1, kT, 0, s>>>(S, nk, nk, f->sc);
-      double shift = 0.0;
-      if (hipMemcpyAsync(&shift, f->sc, sizeof(double), hipMemcpyDeviceToHost, s) !=
-              hipSuccess ||
-          hipStreamSynchronize(s) != hipSuccess) {
-        rc = LRSDP_ERR_DEVICE;
-        break;
-      }
-      f->shift = shift;
+      k_max_diag<<<1, kT, 0, s>>>(S, nk, nk, f->sc);  // the shift, kept on the device
       GemmArgs g;
       g.M = nk; g.N = nk; g.K = r;
       g.A = f->QN; g.lda = r;
       g.B = f->QN; g.ldb = r; g.transB = true;
       g.C = S; g.ldc = nk;
-      g.alpha = shift; g.beta = 1.0; g.flags = kLowerOut;
+      g.alpha_dev = f->sc; g.beta = 1.0; g.flags = kLowerOut;
       if ((rc = gemm(g, s))) break;
     }
     // ---- L L^T = bold S, then bold S^{-1} = L^{-T} L^{-1}
-    if (hipMemsetAsync(ctx->d_flag, 0, sizeof(int), s) != hipSuccess) {
-      rc = LRSDP_ERR_DEVICE;
-      break;
-    }
     // the factor keeps L^{-1} in the lower triangle and L^{-T} in the upper one, so that
     // bold S^{-1} w = L^{-T} (L^{-1} w) is two row-wise triangular GEMVs
     SideStream side;
     if ((rc = ctx_side(ctx, &side))) break;
-    if ((rc = potrf_inv(S, nk, nk, f->Sinv, nk, ctx->d_flag, ptmp.p, false, s, &side))) break;
-    int fl = 0;
-    if ((rc = read_flag(ctx, &fl))) break;
-    if (fl) {
-      rc = LRSDP_ERR_CHOL_S;
+    if ((rc = potrf_inv(S, nk, nk, f->Sinv, nk, flag_S, ptmp.p, false, s, &side))) break;
+    if ((rc = mirror_lower(f->Sinv, nk, nk, s))) break;
+    // one host read for both flags and the shift
+    int fl[2] = {0, 0};
+    double shift = 0.0;
+    if (hipMemcpyAsync(fl, ctx->d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        (r && hipMemcpyAsync(&shift, f->sc, sizeof(double), hipMemcpyDeviceToHost, s) !=
+                  hipSuccess) ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
       break;
     }
-    if ((rc = mirror_lower(f->Sinv, nk, nk, s))) break;
-    if (hipStreamSynchronize(s) != hipSuccess) rc = LRSDP_ERR_DEVICE;
+    f->shift = shift;
+    if (fl[1]) rc = LRSDP_ERR_CHOL_Z;
+    else if (fl[0]) rc = LRSDP_ERR_CHOL_S;
   } while (0);
   free_tmp();
   LRSDP_TRY(rc);

@@ -43,7 +43,8 @@ struct lrsdp_ctx {
   hipStream_t side = nullptr;   // second stream of the factorization (created on first use)
   hipEvent_t side_ev[48] = {};  // its join events, two per recursion depth
   double* h_pinned = nullptr;   // small pinned host staging area (scalars)
-  int* d_flag = nullptr;        // device error/status word
+  int* d_flag = nullptr;        // device error/status words: [0] general and bold S, [1] Z,
+                                // [2] scratch for factorizations whose failure is not an error
 };
 
 struct lrsdp_problem {

@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--count", type=int, default=0, help="instances / requests (batch, serving)")
     ap.add_argument("--qps", type=float, default=4.0, help="serving arrival rate")
     ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--summarize-stats", metavar="DIR",
+                    help="no GPU: print the top kernels of a rocprofv3 --kernel-trace --stats "
+                         "-f csv output folder as a text table")
     ap.add_argument("--summarize-traffic", nargs=4, metavar="DIR",
                     help="no GPU: read four rocprofv3 --pmc output folders (FETCH_SIZE and "
                          "WRITE_SIZE of --workload single, then of --workload "
@@ -138,8 +141,32 @@ def summarize_traffic(dirs):
                   indent=1)
 
 
+def summarize_stats(d, top=30):
+    """Top kernels by total time from a rocprofv3 kernel_stats.csv (durations in us)."""
+    import csv
+    import glob
+    import re
+    f = glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)[0]
+    with open(f) as fh:
+        rows = list(csv.DictReader(fh))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    print(f"{'kernel':60s} {'calls':>7s} {'total_us':>11s} {'avg_us':>9s} {'min_us':>8s} "
+          f"{'max_us':>8s} {'pct':>6s}")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows[:top]:
+        nm = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+        nm = re.sub(r"\(.*", "", nm.replace("lrsdp::", ""))
+        t = float(r["TotalDurationNs"])
+        print(f"{nm[:60]:60s} {int(r['Calls']):7d} {t / 1e3:11.1f} "
+              f"{float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:8.2f} "
+              f"{float(r['MaxNs']) / 1e3:8.2f} {100 * t / tot:6.2f}")
+    print(f"# all kernels: {tot / 1e6:.3f} ms in {sum(int(r['Calls']) for r in rows)} dispatches")
+
+
 def main():
     args = parse()
+    if args.summarize_stats:
+        return summarize_stats(args.summarize_stats)
     if args.summarize_traffic:
         return summarize_traffic(args.summarize_traffic)
     if args.gpus != 1:

@@ -34,8 +34,8 @@ template <bool TA, bool TB, int WM, int WN, int KS, int FM, int FN>
 __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
   constexpr int TMv = 16 * FM * WM, TNv = 16 * FN * WN, NT = 64 * WM * WN * KS, TKc = TK * KS;
   constexpr int EA = TMv * TKc / NT, EB = TNv * TKc / NT;  // staged values per thread
-  __shared__ double As[2][TKc][TMv + 4];
-  __shared__ double Bs[2][TKc][TNv + 4];
+  __shared__ double As[2][TKc][TMv + 1];  // odd row pitch: the transposed stores and the
+  __shared__ double Bs[2][TKc][TNv + 1];  // MFMA operand reads spread over the banks
   const double* __restrict__ Ap = g.A;
   const double* __restrict__ Bp = g.B;
   double* __restrict__ Cp = g.C;
@@ -158,7 +158,7 @@ __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
 
   if constexpr (KS > 1) {  // fold the K slices: wavefronts ks > 0 park their blocks in LDS
     constexpr int PB = 64 * 4 * FM * FN;  // doubles parked per wavefront
-    static_assert((KS - 1) * WM * WN * PB <= 2 * TKc * (TMv + 4), "LDS too small");
+    static_assert((KS - 1) * WM * WN * PB <= 2 * TKc * (TMv + 1), "LDS too small");
     double* park = &As[0][0][0];
     if (ks > 0) {
       double* mine = park + ((size_t)(ks - 1) * WM * WN + wmn) * PB;
@@ -361,10 +361,10 @@ __device__ __forceinline__ int rl_rows(int b, int N) { return min(64, N - 64 * b
 // zero) by 512 threads: wavefront w computes the 32 x 32 quadrant ((w >> 1) & 1, w & 1) over
 // the K half w >> 2, and the upper half parks its partial sums in LDS for the lower one to
 // add.  Returns true on the lower four wavefronts, which then hold the product.  Ps, Qs:
-// LDS, 64 x 68 doubles each; Ps is reused for the parked sums.
+// LDS, 64 x 65 doubles each; Ps is reused for the parked sums.
 __device__ __forceinline__ bool tile_product(const double* P, int ldp, const double* Q,
                                              int ldq, bool qT, int Mv, int Nv, int Kv,
-                                             double (*Ps)[68], double (*Qs)[68],
+                                             double (*Ps)[65], double (*Qs)[65],
                                              v4d (&acc)[2][2]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, w = tid >> 6, kh = w >> 2, wm = (w >> 1) & 1, wn = w & 1;
@@ -436,9 +436,9 @@ template <int MODE>
 __global__ __launch_bounds__(512) void k_rl_step(double* __restrict__ A, int lda,
                                                  double* __restrict__ Li, int ldi, int N,
                                                  int j, int* flag) {
-  static_assert(NB == 64 && NB * LW == 512 && kLeafLds <= 64 * 68, "leaf inside a tile step");
-  __shared__ double Ps[64][68];  // Ps[k][m] = P[m][k]
-  __shared__ double Qs[64][68];  // Qs[k][n] = op(Q)[k][n]
+  static_assert(NB == 64 && NB * LW == 512 && kLeafLds <= 64 * 65, "leaf inside a tile step");
+  __shared__ double Ps[64][65];  // Ps[k][m] = P[m][k] (odd row pitch against bank conflicts)
+  __shared__ double Qs[64][65];  // Qs[k][n] = op(Q)[k][n]
   const int nb = (N + 63) >> 6, r = nb - 1 - j, t = blockIdx.x;
   const double* P;
   const double* Q;

@@ -49,11 +49,13 @@ def parse():
                          "instances (n in [64, 512], k in 1..4, mu = 1e-6); serving: Poisson "
                          "request stream (n in [200, 3000], k in 1..8, mu in [1e-8, 1e-2]); "
                          "large: n=4000 k=10 m=400000 mu=1e-8; single: one mixed-mode solve "
-                         "of the mu=1e-2 instance of the default workload, untimed (for counter "
+                         "of the mu=1e-6 instance of the default workload, untimed (for counter "
                          "runs); copy-calibration: a plain device copy of known size, for "
                          "scaling HBM counters")
     ap.add_argument("--count", type=int, default=0, help="instances / requests (batch, serving)")
     ap.add_argument("--qps", type=float, default=4.0, help="serving arrival rate")
+    ap.add_argument("--qps-sweep", action="store_true",
+                    help="serving: measure capacity, then 0.25x to 1x of it")
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="no GPU: print the top kernels of a rocprofv3 --kernel-trace --stats "
@@ -241,23 +243,39 @@ def main():
     # ---- the dominant kernel class, timed live with HIP events on the library's stream over
     #      a further timed region of the same steps (mixed mode); kept apart from the region
     #      that gives `value` because the events add host work per launch
-    ctx.profile(1 << dom_id)
+    hv_id = pk.LRSDP_K_NAMES.index("hv")
+    ctx.profile((1 << dom_id) | (1 << hv_id))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         one_step(modes["mixed"])
     torch.cuda.synchronize()
     prof_ms_per_step = (time.perf_counter() - t0) / args.steps * 1e3
-    dstat = ctx.profile_read()[dom]
+    pstat = ctx.profile_read()
+    dstat, hstat = pstat[dom], pstat["hv"]
     ctx.profile(0)
 
     # ---- accuracy of the returned answers (untimed): GPU double-double true residual
-    checks = {}
+    # ---- PCG only, with the factors resident (several right-hand sides per W): each kept
+    #      factor solves the same right-hand side `reps` times
+    checks, pcg_only, answers = {}, {}, {}
+    reps = 5
     for name, opts in modes.items():
         _, infos, outs, P = one_step(opts, keep=True)
         rr = []
         for (F, y, ylo) in outs:
             rr.append(F.residual_dd(d_r, y, ylo))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for (F, _, _) in outs:
+            for _ in range(reps):
+                F.solve(d_r, opts)
+        torch.cuda.synchronize()
+        pcg_only[name] = len(outs) * reps / (time.perf_counter() - t0)
+        if name == "mixed":
+            answers = {mu: (y.cpu().numpy(), ylo.cpu().numpy())
+                       for mu, (_, y, ylo) in zip(MUS, outs)}
+        for (F, _, _) in outs:
             F.close()
         P.close()
         checks[name] = dict(relres=rr, iters=[i["iters"] for i in infos],
@@ -272,6 +290,9 @@ def main():
         return dict(value=nsolve / r["elapsed"], p50_ms=float(np.percentile(r["lat"], 50)),
                     p99_ms=float(np.percentile(r["lat"], 99)),
                     setup_ms_mean=float(np.mean(setup)), pcg_ms_mean=float(np.mean(solve)),
+                    phase_ms_mean=dict(zip(("eig", "split_and_Z", "S_formation", "S_factor"),
+                                           np.mean([i["phase_ms"] for i in r["infos"]],
+                                                   axis=0).round(4).tolist())),
                     ms_per_step=r["elapsed"] / args.steps * 1e3,
                     relres_max=float(max(checks[name]["relres"])),
                     iters=checks[name]["iters"], outer=checks[name]["outer"],
@@ -305,9 +326,37 @@ def main():
 
     roof["traffic"] = hbm_traffic(dom)
 
+    # ---- H v (A5/A7) against the HBM roof: its compulsory bytes per launch (W once, the
+    #      pattern, and per constraint its owner entry, coefficient and output) over the
+    #      event-timed launch duration, in the same timed region
+    hv_ms = hstat["ms"] / max(hstat["launches"], 1)
+    hv_ach = hstat["bytes"] / max(hstat["launches"], 1) / (hv_ms * 1e-3) / 1e9
+    hv_roof = dict(bound="hbm", achieved=hv_ach, peak=HBM_PEAK / 1e9, unit="GB/s",
+                   frac=hv_ach / (HBM_PEAK / 1e9), traffic=hbm_traffic("hv"), kernel="hv",
+                   launches=hstat["launches"], avg_us=hv_ms * 1e3,
+                   bytes_per_launch=hstat["bytes"] / max(hstat["launches"], 1),
+                   tflops=hstat["flops"] / max(hstat["ms"], 1e-9) / 1e9)
+
+    # ---- the whole solve against its roofline: setup flops at the FP64 matrix peak plus,
+    #      per PCG iteration (inner iterations and outer residual evaluations), the compulsory
+    #      bytes of H v, two passes over L^{-1}, Z twice and ~10 m-vectors at the HBM peak
+    nnz = 2 * M - N
+    nk = N * K
+    f_setup = nk ** 3 / 3 + N ** 3 / 3 + K * (K + 1) / 2 * 2 * N ** 3 + 2 * nnz * N * K
+    b_hv = 32 * N * N + 24 * M + 20 * nnz
+    b_iter = b_hv + 8 * nk * nk + 16 * N * N + 80 * M
+    t_roof = [f_setup / FP64_PEAK + (it + out) * b_iter / HBM_PEAK
+              for it, out in zip(mixed["iters"], mixed["outer"])]
+    t_meas = [i["setup_ms"] + i["solve_ms"] for i in results["mixed"]["infos"]]
+    t_meas = [float(np.mean(t_meas[j::len(MUS)])) * 1e-3 for j in range(len(MUS))]
+    solve_roof = dict(t_roof_ms=[round(x * 1e3, 4) for x in t_roof],
+                      t_measured_ms=[round(x * 1e3, 4) for x in t_meas],
+                      frac=float(np.sum(t_roof) / np.sum(t_meas)),
+                      setup_flops=f_setup, bytes_per_iter=b_iter)
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(insts, args.cpu_seconds)
+        cpu = cpu_baseline(insts, args.cpu_seconds, answers)
 
     line = {
         "metric": METRIC,
@@ -333,12 +382,16 @@ def main():
         "pcg_iters": mixed["iters"],
         "outer_iters": mixed["outer"],
         "setup_ms_mean": mixed["setup_ms_mean"],
+        "setup_phase_ms_mean": mixed["phase_ms_mean"],
         "pcg_ms_mean": mixed["pcg_ms_mean"],
         "fp64": {k: fp64[k] for k in ("value", "p50_ms", "p99_ms", "ms_per_step", "relres_max",
                                       "iters", "outer", "setup_ms_mean", "pcg_ms_mean")},
         "mixed_over_fp64": mixed["value"] / fp64["value"],
+        "pcg_only_solves_per_s": {k: v for k, v in pcg_only.items()},
         "kernel_profile_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         "roofline": roof,
+        "hv_roofline": hv_roof,
+        "solve_roofline": solve_roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
@@ -393,47 +446,49 @@ def run_batch(args):
     insts = batch_instances(count, base_seed=3000)
     devs = [_device_inputs(i, torch, dev) for i in insts]
     ctx = pk.Context(0)
-    opts = pk.opts(dd_mode=pk.LRSDP_DD_AUTO)
-    torch.cuda.synchronize()
-    pk.solve_batch(ctx, devs[:min(8, count)], opts, workers=args.workers)  # warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st, info = pk.solve_batch(ctx, devs, opts, workers=args.workers)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    rr = _sample_residuals(insts, devs, 8)
+    modes = {"mixed": pk.opts(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO),
+             "fp64": pk.opts(precision=pk.LRSDP_PREC_FP64, dd_mode=pk.LRSDP_DD_AUTO)}
+    out = {}
+    for name, opts in modes.items():
+        torch.cuda.synchronize()
+        pk.solve_batch(ctx, devs[:min(8, count)], opts, workers=args.workers)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = pk.solve_batch(ctx, devs, opts, workers=args.workers)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rr = _sample_residuals(insts, devs, 8)
+        out[name] = dict(value=count / el, ms_total=el * 1e3,
+                         statuses_ok=int(sum(1 for x in st if x == 0)),
+                         relres_sampled_max=max(rr),
+                         iters_mean=float(np.mean([i["iters"] for i in info])),
+                         outer_mean=float(np.mean([i["outer_iters"] for i in info])))
+    m = out["mixed"]
     print(json.dumps({
         "metric": "batched Hessian-eq solves/s (A0 + Alg.1 each) at 1e-8 rel. residual",
-        "value": count / el, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
-        "ms_total": el * 1e3, "workers": args.workers, "dtype": "f64+dd",
-        "data": "synthetic", "statuses_ok": int(sum(1 for x in st if x == 0)),
-        "relres_sampled_max": max(rr), "iters_mean": float(np.mean([i["iters"] for i in info])),
+        "value": m["value"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "ms_total": m["ms_total"], "workers": args.workers, "dtype": "f32+f64+dd",
+        "data": "synthetic", "statuses_ok": m["statuses_ok"],
+        "relres_sampled_max": m["relres_sampled_max"], "iters_mean": m["iters_mean"],
+        "outer_mean": m["outer_mean"], "fp64": out["fp64"],
+        "mixed_over_fp64": m["value"] / out["fp64"]["value"],
         "config": {"workload": f"{count} instances, n log-uniform [64,512], k 1..4, "
-                               "m = min(n(n+1)/2, 3nk ln n), mu=1e-6, seeds 3000+"}}))
+                               "m = min(n(n+1)/2, 3nk ln n), mu=1e-6, seeds 3000+",
+                   "precision": "W0 part of H v in FP32 inside double-double refinement"}}))
     ctx.close()
 
 
-def run_serving(args):
-    """Serving workload: requests arrive as a Poisson stream and are submitted at their
-    arrival times; latency = completion - arrival.  Inputs are placed in HBM beforehand."""
-    import torch
-
-    import paper_1703_10973_amd as pk
-    from synth import make_instance, serving_requests
-    count = args.count or 48
-    dev = torch.device("cuda", 0)
-    shapes, arrive = serving_requests(count, base_seed=50000, qps=args.qps)
-    insts = [make_instance(n, k, m, mu, seed=50000 + i) for i, (n, k, m, mu) in enumerate(shapes)]
-    devs = [_device_inputs(i, torch, dev) for i in insts]
-    ctx = pk.Context(0)
-    srv = pk.Server(ctx, workers=args.workers)
-    opts = pk.opts(dd_mode=pk.LRSDP_DD_AUTO)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+def _serve_stream(pk, ctx, devs, arrive, opts, workers):
+    """Submits request i at arrive[i] seconds after the start and polls until all are done;
+    returns the latencies (completion - arrival, ms) and the wall time to the last result."""
+    import time as _t
+    count = len(devs)
+    srv = pk.Server(ctx, workers=workers)
+    t0 = _t.perf_counter()
     pending, done_t, lat = {}, {}, {}
     nxt = 0
     while len(done_t) < count:
-        now = time.perf_counter() - t0
+        now = _t.perf_counter() - t0
         while nxt < count and arrive[nxt] <= now:
             d = devs[nxt]
             pending[srv.submit(d["n"], d["k"], d["con"], d["row"], d["col"], d["val"], d["W"],
@@ -443,24 +498,64 @@ def run_serving(args):
             out = srv.poll(tk)
             if out is not None:
                 i = pending.pop(tk)
-                done_t[i] = time.perf_counter() - t0
+                done_t[i] = _t.perf_counter() - t0
                 lat[i] = (done_t[i] - arrive[i]) * 1e3
                 assert out[0] == 0, out
-        time.sleep(0.0005)
-    el = max(done_t.values())
+        _t.sleep(0.0005)
     srv.close()
+    return np.array([lat[i] for i in range(count)]), max(done_t.values())
+
+
+def run_serving(args):
+    """Serving workload: requests arrive as a Poisson stream and are submitted at their
+    arrival times; latency = completion - arrival.  Inputs are placed in HBM beforehand.
+    With --qps-sweep: capacity first (every request submitted at once), then the stream at
+    0.25, 0.5, 0.75 and 1.0 times that rate."""
+    import torch
+
+    import paper_1703_10973_amd as pk
+    from synth import make_instance, serving_requests
+    count = args.count or 48
+    dev = torch.device("cuda", 0)
+    shapes, arrive = serving_requests(count, base_seed=50000, qps=1.0)  # unit-rate arrivals
+    insts = [make_instance(n, k, m, mu, seed=50000 + i) for i, (n, k, m, mu) in enumerate(shapes)]
+    devs = [_device_inputs(i, torch, dev) for i in insts]
+    ctx = pk.Context(0)
+    opts = pk.opts(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO)
+    torch.cuda.synchronize()
+    cfg = {"workload": f"{count} requests, Poisson arrivals, n log-uniform [200,3000], k 1..8, "
+                       "m = min(n(n+1)/2, 3nk ln n), mu log-uniform [1e-8,1e-2], seeds 50000+, "
+                       "arrivals seed 59999"}
+    if args.qps_sweep:
+        _, el = _serve_stream(pk, ctx, devs, np.zeros(count), opts, args.workers)
+        cap = count / el
+        points = []
+        for frac in (0.25, 0.5, 0.75, 1.0):
+            q = frac * cap
+            L, el = _serve_stream(pk, ctx, devs, arrive / q, opts, args.workers)
+            points.append(dict(qps=q, load=frac, p50_ms=float(np.percentile(L, 50)),
+                               p99_ms=float(np.percentile(L, 99)), solves_per_s=count / el))
+            print(f"# qps {q:.2f}: p50 {points[-1]['p50_ms']:.1f} ms, p99 "
+                  f"{points[-1]['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        rr = _sample_residuals(insts, devs, 6)
+        print(json.dumps({
+            "metric": "serving Hessian-eq solves: latency p50/p99 ms against arrival rate",
+            "value": points[-1]["p50_ms"], "unit": "ms (p50 latency at capacity)",
+            "n_gpus": 1, "higher_is_better": False, "capacity_solves_per_s": cap,
+            "points": points, "requests": count, "workers": args.workers,
+            "dtype": "f32+f64+dd", "data": "synthetic", "relres_sampled_max": max(rr),
+            "config": cfg}))
+        ctx.close()
+        return
+    L, el = _serve_stream(pk, ctx, devs, arrive / args.qps, opts, args.workers)
     rr = _sample_residuals(insts, devs, 6)
-    L = np.array([lat[i] for i in range(count)])
     print(json.dumps({
         "metric": "serving Hessian-eq solves: latency p50/p99 ms at a Poisson arrival rate",
         "value": float(np.percentile(L, 50)), "unit": "ms (p50 latency)", "n_gpus": 1,
         "higher_is_better": False, "p99_ms": float(np.percentile(L, 99)),
         "solves_per_s": count / el, "qps": args.qps, "requests": count,
-        "workers": args.workers, "dtype": "f64+dd", "data": "synthetic",
-        "relres_sampled_max": max(rr),
-        "config": {"workload": f"{count} requests, Poisson {args.qps}/s, n log-uniform "
-                               "[200,3000], k 1..8, m = min(n(n+1)/2, 3nk ln n), mu log-uniform "
-                               "[1e-8,1e-2], seeds 50000+, arrivals seed 59999"}}))
+        "workers": args.workers, "dtype": "f32+f64+dd", "data": "synthetic",
+        "relres_sampled_max": max(rr), "config": cfg}))
     ctx.close()
 
 
@@ -494,7 +589,10 @@ def run_large(args):
         "metric": "Hessian-eq solve time (setup + PCG) at 1e-8 rel. residual", "value": el * 1e3,
         "unit": "ms", "n_gpus": 1, "higher_is_better": False, "status": st,
         "setup_ms": info["setup_ms"], "pcg_ms": info["solve_ms"], "iters": info["iters"],
-        "outer_iters": info["outer_iters"], "relres": rel, "dtype": "f64+dd", "data": "synthetic",
+        "outer_iters": info["outer_iters"], "relres": rel,
+        "setup_phase_ms": dict(zip(("eig", "split_and_Z", "S_formation", "S_factor"),
+                                   info["phase_ms"])),
+        "pcg_ms_per_inner_iter": info["solve_ms"] / max(info["iters"], 1), "dtype": "f64+dd", "data": "synthetic",
         "config": {"workload": "n=4000 k=10 m=400000 mu=1e-8 seed 4001"}}))
     P.close()
     ctx.close()
@@ -535,22 +633,23 @@ def run_copy(args):
                       "launches": 5}))
 
 
-def cpu_baseline(insts, budget_s):
-    """The oracle (Algorithm 1 in numpy FP64) on a bounded sample of the same workload."""
+def cpu_baseline(insts, budget_s, answers=None):
+    """The oracle (Algorithm 1 in numpy FP64) on a bounded sample of the same workload; the
+    library's answers for those instances (mixed mode) are compared with the oracle's."""
     from oracle import alg1
-    from oracle import dd as ddo
     easy = [i for i in insts if i.mu >= 1e-4]
     t0 = time.perf_counter()
     solved = 0
-    res = []
+    err = {}
     while True:
         for inst in easy:
             C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
             F = alg1.factor(C, inst.W, inst.k)
             out = alg1.solve(F, inst.r, eps=1e-8)
             solved += 1
-            if len(res) < len(easy):
-                res.append(out.iters)
+            if answers and inst.mu in answers and f"{inst.mu:g}" not in err:
+                yh, yl = answers[inst.mu]
+                err[f"{inst.mu:g}"] = float(np.linalg.norm(yh + yl - out.y) / np.linalg.norm(out.y))
         if time.perf_counter() - t0 > budget_s * 0.5 or solved >= 12:
             break
     el = time.perf_counter() - t0
@@ -563,7 +662,7 @@ def cpu_baseline(insts, budget_s):
             "sample": f"{solved} FP64 Algorithm-1 solves (setup + PCG) of the n=1000 k=5 m=20000 "
                       f"instance at mu=1e-2 and 1e-4 only (numpy/scipy, all host BLAS threads); "
                       f"the mu<=1e-6 solves need the double-double oracle, minutes each",
-            "seconds": el}
+            "seconds": el, "gpu_rel_err_vs_oracle": err}
 
 
 if __name__ == "__main__":

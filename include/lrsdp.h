@@ -109,6 +109,10 @@ typedef struct lrsdp_info {
   double setup_ms;       /* time of the factor this solve used (Alg. 1 steps 1-2)           */
   double solve_ms;       /* wall time of this call                                          */
   int eig_sweeps;        /* subspace-iteration sweeps of the factor (0: Householder path)   */
+  double phase_ms[4];    /* the factor's setup by phase, device time between events on its  */
+                         /* stream: [0] eigen step (step 1a), [1] U, W0 and Z with Z^{-1}    */
+                         /* (step 1b), [2] bold S formation and deflation (step 2), [3] the  */
+                         /* Cholesky factor of bold S and its inverse (step 2)                */
 } lrsdp_info;
 
 /* Fills *o with the defaults listed above.  o: host. */

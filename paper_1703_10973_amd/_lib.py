@@ -46,10 +46,13 @@ class lrsdp_opts(C.Structure):
 class lrsdp_info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("outer_iters", C.c_int),
                 ("dd_used", C.c_int), ("relres", C.c_double), ("tau", C.c_double),
-                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("eig_sweeps", C.c_int)]
+                ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("eig_sweeps", C.c_int),
+                ("phase_ms", C.c_double * 4)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["phase_ms"] = list(d["phase_ms"])
+        return d
 
 
 class lrsdp_instance(C.Structure):

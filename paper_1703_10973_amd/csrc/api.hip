@@ -213,9 +213,17 @@ int lrsdp_ctx_create(int device, void* stream, size_t budget, lrsdp_ctx** out) {
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_pinned), 64 * sizeof(double),
                     hipHostMallocDefault) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&c->d_flag), 4 * sizeof(int)) != hipSuccess) {
+    if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return LRSDP_ERR_DEVICE;
+  }
+  for (hipEvent_t& e : c->phase_ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      e = nullptr;
+      lrsdp_ctx_destroy(c);
+      return LRSDP_ERR_DEVICE;
+    }
   }
   *out = c;
   return LRSDP_OK;
@@ -234,6 +242,8 @@ void lrsdp_ctx_destroy(lrsdp_ctx* c) {
     (void)hipStreamDestroy(c->side);
   }
   pool_trim(c, 0);
+  for (hipEvent_t e : c->phase_ev)
+    if (e) (void)hipEventDestroy(e);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->d_flag) (void)hipFree(c->d_flag);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);

@@ -304,6 +304,8 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
               64) * sizeof(double);
 
   LRSDP_HIP(hipMemcpyAsync(f->W, W, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+  hipEvent_t* ev = ctx->phase_ev;  // phase boundaries, read after the final synchronization
+  LRSDP_HIP(hipEventRecord(ev[0], s));
 
   // ---- 1a: the k largest eigenpairs and tau (temporary workspace).  lam_dev[0] = tau.
   double* Vl = f->U;  // eigenvectors land in U's buffer, scaled in place below
@@ -347,6 +349,7 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
   f->tau2 = f->tau * f->tau;
 
   // ---- 1b: U, W0, Z
+  LRSDP_HIP(hipEventRecord(ev[1], s));
   k_make_U<<<grid_for((int64_t)nk, 256), 256, 0, s>>>(n, k, f->lam_dev, Vl, f->U);
   k_make_W0<<<grid_for((int64_t)nn, 256), 256, 0, s>>>(n, k, f->W, f->U, f->W0, f->Z);
   LRSDP_HIP(hipGetLastError());
@@ -387,6 +390,10 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
     if ((rc = potrf_inv(f->Z, n, n, Zi.p, n, flag_Z, ptmp.p, true, s))) break;
     if ((rc = zero_upper(f->Z, n, n, s))) break;
     if ((rc = transpose(f->Z, n, n, f->Zt, n, s))) break;
+    if (hipEventRecord(ev[2], s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
 
     // ---- 2: bold S (lower block triangle).  P_J = Obar D_{u_J} Z for every J in one sparse
     //      pass, R_JL = 1/2 (diag(d_JL) Z + D_{u_L} P_J), then batched GEMMs Z^T R_JL.
@@ -450,10 +457,18 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
     // ---- L L^T = bold S, then bold S^{-1} = L^{-T} L^{-1}
     // the factor keeps L^{-1} in the lower triangle and L^{-T} in the upper one, so that
     // bold S^{-1} w = L^{-T} (L^{-1} w) is two row-wise triangular GEMVs
+    if (hipEventRecord(ev[3], s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
     SideStream side;
     if ((rc = ctx_side(ctx, &side))) break;
     if ((rc = potrf_inv(S, nk, nk, f->Sinv, nk, flag_S, ptmp.p, false, s, &side))) break;
     if ((rc = mirror_lower(f->Sinv, nk, nk, s))) break;
+    if (hipEventRecord(ev[4], s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
     // one host read for both flags and the shift
     int fl[2] = {0, 0};
     double shift = 0.0;
@@ -471,6 +486,10 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
   } while (0);
   free_tmp();
   LRSDP_TRY(rc);
+  for (int i = 0; i < 4; ++i) {
+    float ms = 0.0f;
+    f->phase_ms[i] = hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess ? ms : 0.0;
+  }
   auto t_end = std::chrono::steady_clock::now();
   f->setup_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
   return LRSDP_OK;

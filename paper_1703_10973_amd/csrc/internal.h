@@ -43,6 +43,7 @@ struct lrsdp_ctx {
   hipStream_t side = nullptr;   // second stream of the factorization (created on first use)
   hipEvent_t side_ev[48] = {};  // its join events, two per recursion depth
   double* h_pinned = nullptr;   // small pinned host staging area (scalars)
+  hipEvent_t phase_ev[5] = {};  // boundaries of the setup phases of a factor
   int* d_flag = nullptr;        // device error/status words: [0] general and bold S, [1] Z,
                                 // [2] scratch for factorizations whose failure is not an error
 };
@@ -124,6 +125,7 @@ struct lrsdp_factor {
   lrsdp_problem* P = nullptr;
   int n = 0, k = 0, nk = 0, r = 0;   // r = k(k-1)/2 deflation directions kept
   double tau = 0.0, tau2 = 0.0, shift = 0.0, setup_ms = 0.0;
+  double phase_ms[4] = {0.0, 0.0, 0.0, 0.0};  // setup phases (see lrsdp_info)
   int eig_sweeps = 0;                // subspace-iteration sweeps (0: Householder path)
   std::vector<double> lam;           // host copy: tau, then the k largest ascending
   double* lam_dev = nullptr;         // k + 1

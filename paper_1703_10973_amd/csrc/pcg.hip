@@ -224,6 +224,7 @@ int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lr
   inf.tau = f->tau;
   inf.setup_ms = f->setup_ms;
   inf.eig_sweeps = f->eig_sweeps;
+  for (int i = 0; i < 4; ++i) inf.phase_ms[i] = f->phase_ms[i];
 
   bool use_dd;
   if (o.dd_mode == LRSDP_DD_ON) use_dd = true;

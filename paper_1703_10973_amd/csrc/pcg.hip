@@ -9,6 +9,7 @@
 // Refinement (double-double mode): y <- y + PCG(H_split, r - H y) with y kept as a
 // double-double pair and r - H y evaluated in double-double from the plain definition of
 // H; the inner H v is the split form with the W0 part in FP64, FP32 or BF16.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 
@@ -38,11 +39,12 @@ __device__ __forceinline__ bool arrive_last(int* counter) {
   return last != 0;
 }
 
-// *out = sum of part[0..kG) (called by the last workgroup), counter reset for the next use
+// *out = sum of part[0..gridDim.x) (called by the last workgroup), counter reset for the next
+// use
 __device__ __forceinline__ void finish_sum(const double* part, int* counter, double* out,
                                            double* red) {
   const volatile double* vp = part;
-  double s = (threadIdx.x < kG) ? vp[threadIdx.x] : 0.0;
+  double s = (threadIdx.x < gridDim.x) ? vp[threadIdx.x] : 0.0;
   s = block_sum(s, red);
   if (threadIdx.x == 0) {
     *out = s;
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(kT) void k_dot(int m, const double* a, const double
                                             double* part, int* counter, double* out) {
   __shared__ double red[kT / kWave];
   double s = 0.0;
-  for (int i = blockIdx.x * kT + threadIdx.x; i < m; i += kG * kT) s = fma(a[i], b[i], s);
+  for (int i = blockIdx.x * kT + threadIdx.x; i < m; i += gridDim.x * kT) s = fma(a[i], b[i], s);
   s = block_sum(s, red);
   if (threadIdx.x == 0) part[blockIdx.x] = s;
   if (arrive_last(counter)) finish_sum(part, counter, out, red);
@@ -68,7 +70,7 @@ __global__ __launch_bounds__(kT) void k_update_xr(int m, double* sc, int rho_slo
   __shared__ double red[kT / kWave];
   const double alpha = sc[rho_slot] / sc[kPQ];
   double s = 0.0;
-  for (int i = blockIdx.x * kT + threadIdx.x; i < m; i += kG * kT) {
+  for (int i = blockIdx.x * kT + threadIdx.x; i < m; i += gridDim.x * kT) {
     x[i] = fma(alpha, p[i], x[i]);
     const double ri = fma(-alpha, q[i], r[i]);
     r[i] = ri;
@@ -115,9 +117,13 @@ __global__ void k_round_pair(int m, double* yh, const double* yl) {
 // reduction's last workgroup).
 int* red_counter(const lrsdp_factor* f) { return reinterpret_cast<int*>(f->sc + kCounter); }
 
+// workgroups of a one-launch reduction over m values: one per kT values, at most kG (the
+// partials then stay few, and the grid depends only on m, so the sum order does too)
+int red_grid(int m) { return std::max(1, std::min(kG, (m + kT - 1) / kT)); }
+
 int dot(const lrsdp_factor* f, int m, const double* a, const double* b, double* part,
         double* out, hipStream_t s) {
-  k_dot<<<kG, kT, 0, s>>>(m, a, b, part, red_counter(f), out);
+  k_dot<<<red_grid(m), kT, 0, s>>>(m, a, b, part, red_counter(f), out);
   return LRSDP_OK;
 }
 
@@ -170,7 +176,8 @@ int pcg(lrsdp_factor* f, const double* b, double eps, int max_iter, HM Hmul, PM 
   for (int it = 1; it <= max_iter; ++it) {
     LRSDP_TRY(Hmul(w.p, w.q));
     LRSDP_TRY(dot(f, m, w.p, w.q, w.part, sc + kPQ, s));
-    k_update_xr<<<kG, kT, 0, s>>>(m, sc, cur, w.x, w.r, w.p, w.q, w.part, red_counter(f));
+    k_update_xr<<<red_grid(m), kT, 0, s>>>(m, sc, cur, w.x, w.r, w.p, w.q, w.part,
+                                          red_counter(f));
     LRSDP_TRY(read_scalars(ctx, sc, 8, h));
     out->iters = it;
     const double rel = std::sqrt(std::fmax(h[kRR], 0.0) / rr0);

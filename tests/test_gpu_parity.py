@@ -210,6 +210,9 @@ def test_solve_fp64(ctx, mu):
     assert st == 0, info
     assert info["iters"] <= 25
     assert info["eig_sweeps"] > 0          # the default tau rule takes the subspace iteration
+    # the setup phases are device time between events inside the setup's wall time
+    assert all(t > 0.0 for t in info["phase_ms"]), info["phase_ms"]
+    assert sum(info["phase_ms"]) <= info["setup_ms"] * 1.001 + 0.05, info
     y = host(y)
     H = hs.hessian_dense(inst.W, inst.a, inst.b, inst.val)
     ystar = hs.solve_dense(H, inst.r)

@@ -19,17 +19,8 @@ constexpr int KMAX = 16;
 constexpr int kT = 256;
 
 // ---------------------------------------------------------------- mat(A v) values
-// mval[e] = val_i * scale_i * v_i, i = src[e]  (scale = 1/g when ginv != nullptr)
-__global__ void k_mval(int nnz, const int32_t* src, const double* val, const double* ginv,
-                       const double* v, double* mval) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nnz) return;
-  const int i = src[e];
-  const double u = ginv ? v[i] * ginv[i] : v[i];
-  mval[e] = val[i] * u;
-}
-
-// double-double version, v may carry a low part
+// (mh, ml)[e] = val_i * scale_i * (vh_i + vl_i) in double-double, i = src[e] (scale = 1/g
+// when ginv != nullptr; vl may be nullptr)
 __global__ void k_mval_dd(int nnz, const int32_t* src, const double* val, const double* ginv,
                           const double* vh, const double* vl, double* mh, double* ml) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,13 +34,17 @@ __global__ void k_mval_dd(int nnz, const int32_t* src, const double* val, const 
 }
 
 // ---------------------------------------------------------------- M U (sparse x n x k)
-// out[j][p] = sum_{e in row p} mval[e] U[j][col e].  Sixteen lanes share a row (fixed
+// out[j][p] = sum_{e in row p} M_e U[j][col e], M_e = val_i * (scale_i * v_i) formed on the
+// fly (i = src[e], scale = 1/g when ginv != nullptr).  Sixteen lanes share a row (fixed
 // lane-to-entry map, then an xor-shuffle tree), so the summation order is fixed.
 constexpr int kRL = 16;
 
 __global__ __launch_bounds__(kT) void k_spmm_U(int n, int k, const int32_t* __restrict__ rowptr,
                                                const int32_t* __restrict__ colidx,
-                                               const double* __restrict__ mval,
+                                               const int32_t* __restrict__ src,
+                                               const double* __restrict__ val,
+                                               const double* __restrict__ ginv,
+                                               const double* __restrict__ v,
                                                const double* __restrict__ U,
                                                double* __restrict__ out) {
   const int p = blockIdx.x * (kT / kRL) + threadIdx.x / kRL;
@@ -62,7 +57,8 @@ __global__ __launch_bounds__(kT) void k_spmm_U(int n, int k, const int32_t* __re
     const int hi = rowptr[p + 1];
     for (int e = rowptr[p] + sub; e < hi; e += kRL) {
       const int q = colidx[e];
-      const double mv = mval[e];
+      const int i = src[e];
+      const double mv = val[i] * (ginv ? v[i] * ginv[i] : v[i]);
 #pragma unroll
       for (int j = 0; j < KMAX; ++j)
         if (j < k) acc[j] = fma(mv, U[(size_t)j * n + q], acc[j]);
@@ -118,9 +114,11 @@ __global__ __launch_bounds__(kT) void k_spmm_U_dd(int n, int k,
   }
 }
 
-int spmm_U(const lrsdp_problem* P, int k, const double* U, double* out, hipStream_t s) {
+// out = M U with M = mat(A (ginv o v)) (ginv may be nullptr)
+int spmm_U(const lrsdp_problem* P, int k, const double* ginv, const double* v, const double* U,
+           double* out, hipStream_t s) {
   k_spmm_U<<<(P->n + kT / kRL - 1) / (kT / kRL), kT, 0, s>>>(P->n, k, P->rowptr, P->colidx,
-                                                              P->mval, U, out);
+                                                              P->src, P->val, ginv, v, U, out);
   return LRSDP_OK;
 }
 int spmm_U_dd(const lrsdp_problem* P, int k, const double* ml, const double* U, double* oh,
@@ -328,10 +326,12 @@ __global__ void k_Qc_dd(int N, int r, double shift, const double* Q, const doubl
 // out[j][p] = sum_{q in range(p)} A[p][q] X[j][q] for R rows p per workgroup: every X value
 // loaded serves R rows, so X (k x n, L2-resident) is read n / R times instead of n times.
 // KC >= k bounds the accumulators; rows past n and q outside a row's range add nothing.
+// With tadd != nullptr the result is fma(c, tadd, product) (an axpy folded in).
 template <int R, int KC>
 __global__ __launch_bounds__(kT) void k_rows_kr(int n, int k, const double* __restrict__ A,
                                                 int range, const double* __restrict__ X,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out, double c,
+                                                const double* __restrict__ tadd) {
   __shared__ double red[kT / kWave][R * KC];
   const int p0 = blockIdx.x * R, t = threadIdx.x;
   const int lane = t & (kWave - 1), wid = t / kWave;
@@ -382,23 +382,31 @@ __global__ __launch_bounds__(kT) void k_rows_kr(int n, int k, const double* __re
   __syncthreads();
   if (t < R * KC) {
     const int r = t / KC, j = t - r * KC, p = p0 + r;
-    if (p < n && j < k) out[(size_t)j * n + p] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+    if (p < n && j < k) {
+      const double v = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+      out[(size_t)j * n + p] = tadd ? fma(c, tadd[(size_t)j * n + p], v) : v;
+    }
   }
 }
 
 }  // namespace
 
-int rows_k(int n, int k, const double* A, int range, const double* X, double* out,
-           hipStream_t s) {
+int rows_k_axpy(int n, int k, const double* A, int range, const double* X, double* out,
+                double c, const double* tadd, hipStream_t s) {
   if (n <= 0 || k <= 0) return LRSDP_OK;
   if (k > KMAX) return LRSDP_ERR_INVALID_ARG;
   constexpr int R = 4;
   const int grid = (n + R - 1) / R;
-  if (k <= 4) k_rows_kr<R, 4><<<grid, kT, 0, s>>>(n, k, A, range, X, out);
-  else if (k <= 8) k_rows_kr<R, 8><<<grid, kT, 0, s>>>(n, k, A, range, X, out);
-  else k_rows_kr<R, 16><<<grid, kT, 0, s>>>(n, k, A, range, X, out);
+  if (k <= 4) k_rows_kr<R, 4><<<grid, kT, 0, s>>>(n, k, A, range, X, out, c, tadd);
+  else if (k <= 8) k_rows_kr<R, 8><<<grid, kT, 0, s>>>(n, k, A, range, X, out, c, tadd);
+  else k_rows_kr<R, 16><<<grid, kT, 0, s>>>(n, k, A, range, X, out, c, tadd);
   LRSDP_HIP(hipGetLastError());
   return LRSDP_OK;
+}
+
+int rows_k(int n, int k, const double* A, int range, const double* X, double* out,
+           hipStream_t s) {
+  return rows_k_axpy(n, k, A, range, X, out, 0.0, nullptr, s);
 }
 
 namespace {
@@ -450,18 +458,6 @@ __global__ void k_sampled_f64(int m, int n, int k, const int32_t* a, const int32
   }
   x[i] = 0.5 * coef[i] * s * (scale ? scale[i] : 1.0);
 }
-__global__ void k_axpy(int N, double c, const double* t, double* s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) s[i] = fma(c, t[i], s[i]);
-}
-__global__ void k_sub(int N, const double* a, const double* b, double* out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) out[i] = a[i] - b[i];
-}
-__global__ void k_add(int N, double* t, const double* d) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) t[i] += d[i];
-}
 __global__ __launch_bounds__(kT) void k_Qt(int N, int r, const double* Q, const double* t,
                                            double* c) {
   __shared__ double scr[kT / kWave];
@@ -487,10 +483,8 @@ int schur_apply_f64(const lrsdp_factor* f, const double* t, double* sout, hipStr
   rows_k(n, k, f->Z, 1, t, w.y, s);                                        // Z T
   k_sampled_f64<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, P->ginv, w.y,
                                                   f->U, w.t0);             // G^{-1} bold U t
-  k_mval<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, nullptr, w.t0, P->mval);
-  spmm_U(P, k, f->U, w.y, s);
-  rows_k(n, k, f->Zt, 2, w.y, sout, s);                                    // Z^T M U
-  k_axpy<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->tau2, t, sout);
+  spmm_U(P, k, nullptr, w.t0, f->U, w.y, s);
+  rows_k_axpy(n, k, f->Zt, 2, w.y, sout, f->tau2, t, s);  // Z^T M U + tau^2 t
   if (f->r) {
     k_Qt<<<f->r, kT, 0, s>>>(nk, f->r, f->QN, t, w.kk);
     k_Qc<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->r, f->shift, f->QN, w.kk, sout);
@@ -511,15 +505,12 @@ int precond_apply_f64(const lrsdp_factor* f, const double* v, double* z, hipStre
   const Work w = work_view(f);
   const int n = f->n, k = f->k, m = P->m, nk = f->nk;
   if (k > KMAX) return LRSDP_ERR_INVALID_ARG;
-  k_mval<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, P->ginv, v, P->mval);
-  spmm_U(P, k, f->U, w.y, s);
+  spmm_U(P, k, P->ginv, v, f->U, w.y, s);                // M U, M = mat(A G^{-1} v)
   rows_k(n, k, f->Zt, 2, w.y, w.w, s);                    // w = vec(Z^T M U)
   LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.w, w.h, w.t, s));  // t = bold S^{-1} w
-  if (refine) {
+  if (refine) {                                           // t += bold S^{-1} (w - bold S t)
     LRSDP_TRY(schur_apply_f64(f, w.t, w.s, s));
-    k_sub<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.s, w.g0);
-    LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.g0, w.h, w.g1, s));
-    k_add<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.t, w.g1);
+    LRSDP_TRY(trmv_pair_ex(f->Sinv, nk, nk, w.w, w.s, w.h, w.t, true, s));
   }
   rows_k(n, k, f->Z, 1, w.t, w.y, s);                      // Y = Z T
   k_smw_out<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, P->ginv,

@@ -62,6 +62,10 @@ int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double*
 // triangle and its transpose mirrored into the upper one this is y = L^{-T} L^{-1} x.
 int trmv_pair(const double* M, int N, int ld, const double* x, double* tmp, double* y,
               hipStream_t s);
+// y (+)= L^{-T} (L^{-1} (x - xsub)) with the same two passes; xsub may be nullptr, and with
+// accumulate the result is added to y.
+int trmv_pair_ex(const double* M, int N, int ld, const double* x, const double* xsub,
+                 double* tmp, double* y, bool accumulate, hipStream_t s);
 // X := M^T M (lower part), M lower triangular N x N; X and M distinct.
 int lauum(const double* M, int N, int ldm, double* X, int ldx, hipStream_t s);
 // Copy the lower triangle into the upper one.

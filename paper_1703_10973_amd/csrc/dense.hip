@@ -622,24 +622,28 @@ __global__ __launch_bounds__(256) void k_gemv(const double* __restrict__ A, int 
 // y = tri(A) x with tri the lower (upper = 0) or upper (upper = 1) triangle including the
 // diagonal; one wavefront per row, eight independent accumulators so that eight loads per
 // lane are in flight (the rows are long and the product is bound by HBM).
+// kSub: the vector is x - xs (each difference rounded once); kAcc: y += the product.
+template <bool kSub, bool kAcc>
 __global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, int N, int lda,
                                                   const double* __restrict__ x,
+                                                  const double* __restrict__ xs,
                                                   double* __restrict__ y, int upper) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (row >= N) return;
   const double* a = A + (size_t)row * lda;
   const int lo = upper ? row : 0, hi = upper ? N : row + 1;
+  auto xv = [&](int c) { return kSub ? x[c] - xs[c] : x[c]; };
   double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int c = lo + lane;
   for (; c + 7 * 64 < hi; c += 8 * 64) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] = fma(a[c + u * 64], x[c + u * 64], s[u]);
+    for (int u = 0; u < 8; ++u) s[u] = fma(a[c + u * 64], xv(c + u * 64), s[u]);
   }
-  for (int u = 0; c < hi; c += 64, ++u) s[u] = fma(a[c], x[c], s[u]);
+  for (int u = 0; c < hi; c += 64, ++u) s[u] = fma(a[c], xv(c), s[u]);
   double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   t = wave_sum(t);
-  if (lane == 0) y[row] = t;
+  if (lane == 0) y[row] = kAcc ? y[row] + t : t;
 }
 
 int split64(int N) {
@@ -846,14 +850,22 @@ int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double*
   return potrf_inv_rec(A, N, lda, Li, ldi, flag, tmp, want_L, s, side, 0);
 }
 
-int trmv_pair(const double* M, int N, int ld, const double* x, double* tmp, double* y,
-              hipStream_t s) {
+int trmv_pair_ex(const double* M, int N, int ld, const double* x, const double* xsub,
+                 double* tmp, double* y, bool accumulate, hipStream_t s) {
   ProfMark pm = prof_begin(LRSDP_K_GEMV, s);
-  k_gemv_tri<<<(N + 3) / 4, 256, 0, s>>>(M, N, ld, x, tmp, 0);
-  k_gemv_tri<<<(N + 3) / 4, 256, 0, s>>>(M, N, ld, tmp, y, 1);
+  const int grid = (N + 3) / 4;
+  if (xsub) k_gemv_tri<true, false><<<grid, 256, 0, s>>>(M, N, ld, x, xsub, tmp, 0);
+  else k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, ld, x, nullptr, tmp, 0);
+  if (accumulate) k_gemv_tri<false, true><<<grid, 256, 0, s>>>(M, N, ld, tmp, nullptr, y, 1);
+  else k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, ld, tmp, nullptr, y, 1);
   LRSDP_HIP(hipGetLastError());
   prof_end(pm, s, 8.0 * (double)N * (N + 1) + 32.0 * N, 2.0 * (double)N * (N + 1));
   return LRSDP_OK;
+}
+
+int trmv_pair(const double* M, int N, int ld, const double* x, double* tmp, double* y,
+              hipStream_t s) {
+  return trmv_pair_ex(M, N, ld, x, nullptr, tmp, y, false, s);
 }
 
 int lauum(const double* M, int N, int ldm, double* X, int ldx, hipStream_t s) {

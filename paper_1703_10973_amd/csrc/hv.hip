@@ -165,9 +165,11 @@ int launch_hv(const lrsdp_problem* P, const TW* W, const double* v, double* Hv, 
   }
 #undef LRSDP_HV_CASE
   LRSDP_HIP(hipGetLastError());
-  // compulsory traffic of the fused kernel: W once, the pattern (column + value), and per
-  // constraint its owner entry, coefficient and output; flops 2 (nnz + m) n
-  prof_end(pm, s, (double)sizeof(TW) * n * n + 12.0 * P->nnz + 24.0 * P->m,
+  // algorithmic bytes of H v as a two-pass product: W read by both passes, T = M W written
+  // once and read once (2 (s_W + s_T) n^2), 24 bytes per constraint and 20 per pattern entry;
+  // the fused kernel keeps T on chip, so it moves less than this.  Flops 2 (nnz + m) n.
+  prof_end(pm, s,
+           2.0 * ((double)sizeof(TW) + sizeof(TA)) * n * n + 24.0 * P->m + 20.0 * P->nnz,
            2.0 * ((double)P->nnz + P->m) * n);
   return LRSDP_OK;
 }

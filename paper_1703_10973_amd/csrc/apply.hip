@@ -18,21 +18,6 @@ namespace {
 constexpr int KMAX = 16;
 constexpr int kT = 256;
 
-// ---------------------------------------------------------------- mat(A v) values
-// (mh, ml)[e] = val_i * scale_i * (vh_i + vl_i) in double-double, i = src[e] (scale = 1/g
-// when ginv != nullptr; vl may be nullptr)
-__global__ void k_mval_dd(int nnz, const int32_t* src, const double* val, const double* ginv,
-                          const double* vh, const double* vl, double* mh, double* ml) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nnz) return;
-  const int i = src[e];
-  dd u = {vh[i], vl ? vl[i] : 0.0};
-  if (ginv) u = dd_mul_d(u, ginv[i]);
-  u = dd_mul_d(u, val[i]);
-  mh[e] = u.hi;
-  ml[e] = u.lo;
-}
-
 // ---------------------------------------------------------------- M U (sparse x n x k)
 // out[j][p] = sum_{e in row p} M_e U[j][col e], M_e = val_i * (scale_i * v_i) formed on the
 // fly (i = src[e], scale = 1/g when ginv != nullptr).  Sixteen lanes share a row (fixed
@@ -75,11 +60,15 @@ __global__ __launch_bounds__(kT) void k_spmm_U(int n, int k, const int32_t* __re
   }
 }
 
+// double-double version: M_e = (vh_i + vl_i) * scale_i * val_i, each product in double-double
 __global__ __launch_bounds__(kT) void k_spmm_U_dd(int n, int k,
                                                   const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colidx,
-                                                  const double* __restrict__ mh,
-                                                  const double* __restrict__ ml,
+                                                  const int32_t* __restrict__ src,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ ginv,
+                                                  const double* __restrict__ vh,
+                                                  const double* __restrict__ vl,
                                                   const double* __restrict__ U,
                                                   double* __restrict__ oh,
                                                   double* __restrict__ ol) {
@@ -93,10 +82,13 @@ __global__ __launch_bounds__(kT) void k_spmm_U_dd(int n, int k,
     const int hi = rowptr[p + 1];
     for (int e = rowptr[p] + sub; e < hi; e += kRL) {
       const int q = colidx[e];
-      const double h = mh[e], l = ml[e];
+      const int i = src[e];
+      dd u = {vh[i], vl ? vl[i] : 0.0};
+      if (ginv) u = dd_mul_d(u, ginv[i]);
+      u = dd_mul_d(u, val[i]);
 #pragma unroll
       for (int j = 0; j < KMAX; ++j)
-        if (j < k) acc[j] = dd_fma2(acc[j], U[(size_t)j * n + q], h, l);
+        if (j < k) acc[j] = dd_fma2(acc[j], U[(size_t)j * n + q], u.hi, u.lo);
     }
   }
 #pragma unroll
@@ -121,10 +113,11 @@ int spmm_U(const lrsdp_problem* P, int k, const double* ginv, const double* v, c
                                                               P->src, P->val, ginv, v, U, out);
   return LRSDP_OK;
 }
-int spmm_U_dd(const lrsdp_problem* P, int k, const double* ml, const double* U, double* oh,
-              double* ol, hipStream_t s) {
-  k_spmm_U_dd<<<(P->n + kT / kRL - 1) / (kT / kRL), kT, 0, s>>>(P->n, k, P->rowptr, P->colidx,
-                                                                 P->mval, ml, U, oh, ol);
+// (oh, ol) = M U in double-double, M = mat(A G^{-1} (vh + vl)) (ginv, vl may be nullptr)
+int spmm_U_dd(const lrsdp_problem* P, int k, const double* ginv, const double* vh,
+              const double* vl, const double* U, double* oh, double* ol, hipStream_t s) {
+  k_spmm_U_dd<<<(P->n + kT / kRL - 1) / (kT / kRL), kT, 0, s>>>(
+      P->n, k, P->rowptr, P->colidx, P->src, P->val, ginv, vh, vl, U, oh, ol);
   return LRSDP_OK;
 }
 
@@ -137,7 +130,9 @@ __global__ __launch_bounds__(kT) void k_rows_k_dd(int n, int k, const double* __
                                                   int range, const double* __restrict__ Xh,
                                                   const double* __restrict__ Xl,
                                                   double* __restrict__ oh,
-                                                  double* __restrict__ ol) {
+                                                  double* __restrict__ ol, double c,
+                                                  const double* __restrict__ th,
+                                                  const double* __restrict__ tl) {
   __shared__ double red[kT / kWave][KMAX][2];
   const int p = blockIdx.x, t = threadIdx.x;
   const int lane = t & (kWave - 1), wid = t / kWave;
@@ -169,6 +164,7 @@ __global__ __launch_bounds__(kT) void k_rows_k_dd(int n, int k, const double* __
     dd u = dd_add({red[0][t][0], red[0][t][1]}, {red[1][t][0], red[1][t][1]});
     const dd w = dd_add({red[2][t][0], red[2][t][1]}, {red[3][t][0], red[3][t][1]});
     u = dd_add(u, w);
+    if (th) u = dd_add(u, dd_mul_d({th[(size_t)t * n + p], tl[(size_t)t * n + p]}, c));
     oh[(size_t)t * n + p] = u.hi;
     ol[(size_t)t * n + p] = u.lo;
   }
@@ -288,15 +284,6 @@ __global__ void k_dd_accum(int N, double* th, double* tl, const double* d) {
   th[i] = u.hi;
   tl[i] = u.lo;
 }
-// s += tau2 * t  (all double-double, tau2 an FP64 constant)
-__global__ void k_dd_axpy_const(int N, double c, const double* th, const double* tl, double* sh,
-                                double* sl) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  dd u = dd_add({sh[i], sl[i]}, dd_mul_d({th[i], tl[i]}, c));
-  sh[i] = u.hi;
-  sl[i] = u.lo;
-}
 // c = Q^T t  (r values, double-double), one workgroup per column of Q (nk x r row-major)
 __global__ __launch_bounds__(kT) void k_Qt_dd(int N, int r, const double* Q, const double* th,
                                               const double* tl, double* c) {
@@ -411,9 +398,11 @@ int rows_k(int n, int k, const double* A, int range, const double* X, double* ou
 
 namespace {
 
+// (oh, ol) = rows of A times X in double-double; with th != nullptr, + c (th, tl)
 int rows_k_dd(int n, int k, const double* A, int range, const double* Xh, const double* Xl,
-              double* oh, double* ol, hipStream_t s) {
-  k_rows_k_dd<<<n, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol);
+              double* oh, double* ol, hipStream_t s, double c = 0.0,
+              const double* th = nullptr, const double* tl = nullptr) {
+  k_rows_k_dd<<<n, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol, c, th, tl);
   return LRSDP_OK;
 }
 
@@ -428,12 +417,9 @@ int schur_apply_dd(const lrsdp_factor* f, const double* th, const double* tl, do
   k_sampled_dd<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, w.y, w.yl, f->U,
                                                  w.t0, w.t1, nullptr, nullptr, 0.0, nullptr);
   // c. mat(A G^{-1} y) (dd)   d. P = M U (dd)   e. s = Z^T P (dd)
-  k_mval_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, P->ginv, w.t0, w.t1,
-                                                   P->mval, P->vec_scratch);
-  spmm_U_dd(P, k, P->vec_scratch, f->U, w.y, w.yl, s);
-  rows_k_dd(n, k, f->Zt, 2, w.y, w.yl, sh, sl, s);
-  // f. + tau^2 t + shift Q (Q^T t)
-  k_dd_axpy_const<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->tau2, th, tl, sh, sl);
+  spmm_U_dd(P, k, P->ginv, w.t0, w.t1, f->U, w.y, w.yl, s);
+  // f. s = Z^T P + tau^2 t (one launch), + shift Q (Q^T t)
+  rows_k_dd(n, k, f->Zt, 2, w.y, w.yl, sh, sl, s, f->tau2, th, tl);
   if (f->r) {
     k_Qt_dd<<<f->r, kT, 0, s>>>(nk, f->r, f->QN, th, tl, w.kk);
     k_Qc_dd<<<grid_for(nk, 256), 256, 0, s>>>(nk, f->r, f->shift, f->QN, w.kk, sh, sl);
@@ -526,9 +512,7 @@ int precond_apply_dd(const lrsdp_factor* f, const double* v, double* z, hipStrea
   const int n = f->n, k = f->k, m = P->m, nk = f->nk;
   if (k > KMAX) return LRSDP_ERR_INVALID_ARG;
   // w = bold U^T G^{-1} v in double-double
-  k_mval_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, P->ginv, v, nullptr,
-                                                   P->mval, P->vec_scratch);
-  spmm_U_dd(P, k, P->vec_scratch, f->U, w.y, w.yl, s);
+  spmm_U_dd(P, k, P->ginv, v, nullptr, f->U, w.y, w.yl, s);
   rows_k_dd(n, k, f->Zt, 2, w.y, w.yl, w.w, w.wl, s);
   // t = bold S^{-1} w: FP64 inverse, refined against the matrix-free bold S in double-double
   k_dd_combine<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.wl, w.g0);
@@ -559,9 +543,7 @@ int split_apply(lrsdp_factor* f, const double* v, double* Hv, int precision, hip
   else if (precision == LRSDP_PREC_BF16) LRSDP_TRY(hv_apply_bf16(P, f->W0b, v, Hv, s));
   else LRSDP_TRY(hv_apply_f64(P, f->W0, v, Hv, s));
   // P = M U (dd), Q = W0 P, K = U^T P (dd), then the sampled rank-k terms
-  k_mval_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, nullptr, v, nullptr,
-                                                   P->mval, P->vec_scratch);
-  spmm_U_dd(P, k, P->vec_scratch, f->U, w.g0, w.g1, s);
+  spmm_U_dd(P, k, nullptr, v, nullptr, f->U, w.g0, w.g1, s);
   rows_k(n, k, f->W0, 0, w.g0, w.s, s);
   k_UtP<<<k * k, kT, 0, s>>>(n, k, f->U, w.g0, w.g1, w.kk);
   k_lowrank_add<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, f->U, w.s, w.kk,

@@ -73,7 +73,7 @@ def parse():
 TRAFFIC_CLASSES = {
     "gemm": ("k_gemm",), "hv": ("k_hv_fused",), "gemv": ("k_gemv_tri",),
     "resdd": ("k_residual_dd",), "bz": ("k_PJ", "k_dJL"), "leaf": ("k_chol_leaf",),
-    "tile": ("k_rl_step",),
+    "tile": ("k_rl_fused", "k_rl_panel"),
 }
 CLASS_SOURCE = {"gemm": "dense.hip", "hv": "hv.hip", "gemv": "dense.hip", "resdd": "hv.hip",
                 "bz": "factor.hip", "leaf": "dense.hip", "tile": "dense.hip"}

@@ -348,27 +348,27 @@ __global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, i
 
 // ---------------------------------------------------------------- right-looking node
 // Below a few thousand rows the recursion's cost is its chain of small launches, not its
-// flops.  There a node is factored right-looking by 64-blocks, three launches per block
-// column j: the leaf (L_jj, L_jj^{-1}), a panel step and a trailing step.  L^{-1} = X is
-// built alongside from its block recurrence X_ik = -L_ii^{-1} sum_{k <= m < i} L_im X_mk:
-// the sums Y_ik accumulate in Li as the block columns m finish, and X_ik = L_ii^{-1} Y_ik is
-// formed once L_ii^{-1} is known.  Every block product is one 64 x 64 x 64 MFMA tile.
-enum { kRLPanel = 0, kRLTrail = 1 };
+// flops.  There a node is factored right-looking by 64-blocks, one launch per block column
+// j.  L^{-1} = X is built alongside from its block recurrence
+// X_ik = -L_ii^{-1} sum_{k <= m < i} L_im X_mk: the sums Y_ik accumulate in Li as the block
+// columns m finish, and X_ik = L_ii^{-1} Y_ik once L_ii^{-1} is known.  Every block product is
+// one 64 x 64 x 64 MFMA tile.
+//
+// The panel of column j (L_ij = A_ij L_jj^{-T} and X_jk = L_jj^{-1} Y_jk) is not a launch of
+// its own: each tile of step j that needs a panel block forms it in LDS from A_ij or Y_jk, and
+// the panel blocks are stored in place by step j + 1, when nothing reads their old values
+// any more (two small launches store the last two panels).  Recomputed blocks are the same
+// tile products on the same operands, so every stored value is the one a separate panel
+// launch would store.
 
 __device__ __forceinline__ int rl_rows(int b, int N) { return min(64, N - 64 * b); }
 
-// acc = P op(Q) for 64 x 64 blocks (entries past Mv rows / Nv columns / Kv of K read as
-// zero) by 512 threads: wavefront w computes the 32 x 32 quadrant ((w >> 1) & 1, w & 1) over
-// the K half w >> 2, and the upper half parks its partial sums in LDS for the lower one to
-// add.  Returns true on the lower four wavefronts, which then hold the product.  Ps, Qs:
-// LDS, 64 x 65 doubles each; Ps is reused for the parked sums.
-__device__ __forceinline__ bool tile_product(const double* P, int ldp, const double* Q,
-                                             int ldq, bool qT, int Mv, int Nv, int Kv,
-                                             double (*Ps)[65], double (*Qs)[65],
-                                             v4d (&acc)[2][2]) {
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6, kh = w >> 2, wm = (w >> 1) & 1, wn = w & 1;
-  const int lr = lane & 15, lk = lane >> 4;
+// Ps/Qs <- the 64 x 64 operand blocks of P op(Q) (entries past Mv rows / Nv columns / Kv of
+// K read as zero): Ps[k][m] = P[m][k], Qs[k][n] = op(Q)[k][n].  Ends with a barrier.
+__device__ __forceinline__ void tile_load(const double* P, int ldp, const double* Q, int ldq,
+                                          bool qT, int Mv, int Nv, int Kv, double (*Ps)[65],
+                                          double (*Qs)[65]) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   double pv[8], qv[8];  // all loads in flight before the first LDS store
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
@@ -384,6 +384,18 @@ __device__ __forceinline__ bool tile_product(const double* P, int ldp, const dou
     else Qs[rr][cc] = qv[u];
   }
   __syncthreads();
+}
+
+// acc = (the product of the blocks in Ps, Qs) by 512 threads: wavefront w computes the
+// 32 x 32 quadrant ((w >> 1) & 1, w & 1) over the K half w >> 2, and the upper half parks its
+// partial sums in `park` (64 x 64 doubles of LDS, which may alias Ps) for the lower half to
+// add.  Every wavefront passes the same barriers; returns true on the lower four, which then
+// hold the product.
+__device__ __forceinline__ bool tile_mma(const double (*Ps)[65], const double (*Qs)[65],
+                                         double* park, v4d (&acc)[2][2]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, kh = w >> 2, wm = (w >> 1) & 1, wn = w & 1;
+  const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -400,137 +412,38 @@ __device__ __forceinline__ bool tile_product(const double* P, int ldp, const dou
     acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
     acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
   }
-  __syncthreads();  // every wavefront is done with Ps: reuse it for the upper half's sums
-  double* park = &Ps[0][0] + (size_t)(w & 3) * 64 * 16;
+  __syncthreads();  // every wavefront is done with the operands (park may alias Ps)
+  double* mine = park + (size_t)(w & 3) * 64 * 16;
   if (kh == 1) {
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) park[((mi * 2 + ni) * 4 + q) * 64 + lane] = acc[mi][ni][q];
+        for (int q = 0; q < 4; ++q) mine[((mi * 2 + ni) * 4 + q) * 64 + lane] = acc[mi][ni][q];
   }
   __syncthreads();
-  if (kh == 1) return false;
+  if (kh == 0) {
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni)
+      for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[mi][ni][q] += park[((mi * 2 + ni) * 4 + q) * 64 + lane];
-  return true;
+        for (int q = 0; q < 4; ++q) acc[mi][ni][q] += mine[((mi * 2 + ni) * 4 + q) * 64 + lane];
+  }
+  __syncthreads();  // park is free again
+  return kh == 0;
 }
 
-// One block product per workgroup, C = alpha P op(Q) + beta C on 64 x 64 blocks (entries past
-// the node edge read as zero and are not written).  With r = nb - 1 - j, step j:
-//   panel: tiles t < r:        L_ij = A_ij L_jj^{-T}, i = j + 1 + t (in place in A);
-//          tiles r <= t < r+j: X_jk = L_jj^{-1} Y_jk, k = t - r (in place in Li);
-//   trail: tiles t < r(r+1)/2: A_ik -= L_ij L_kj^T for j < k <= i;
-//          the rest:           Y_ik = [k < j] Y_ik - L_ij X_jk for i > j, k <= j;
-//          tile 0, the diagonal block (j + 1, j + 1), is updated into LDS and workgroup 0 goes
-//          on to the leaf of block column j + 1 (its Cholesky factor and inverse), so the
-//          next column's leaf runs beside the trailing update instead of after it.
-// The operands of a tile are never written by another tile of the same launch, and a tile
-// that updates one of its own operands loads both before it stores.
-template <int MODE>
-__global__ __launch_bounds__(512) void k_rl_step(double* __restrict__ A, int lda,
-                                                 double* __restrict__ Li, int ldi, int N,
-                                                 int j, int* flag) {
-  static_assert(NB == 64 && NB * LW == 512 && kLeafLds <= 64 * 65, "leaf inside a tile step");
-  __shared__ double Ps[64][65];  // Ps[k][m] = P[m][k] (odd row pitch against bank conflicts)
-  __shared__ double Qs[64][65];  // Qs[k][n] = op(Q)[k][n]
-  const int nb = (N + 63) >> 6, r = nb - 1 - j, t = blockIdx.x;
-  const double* P;
-  const double* Q;
-  double* C;
-  int ldp, ldq, ldc, Mv, Nv, Kv;
-  bool qT;
-  double alpha = 1.0, beta = 0.0;
-  if (MODE == kRLPanel) {
-    if (t < r) {
-      const int i = j + 1 + t;
-      P = A + (size_t)(64 * i) * lda + 64 * j; ldp = lda;
-      Q = Li + (size_t)(64 * j) * ldi + 64 * j; ldq = ldi; qT = true;
-      C = A + (size_t)(64 * i) * lda + 64 * j; ldc = lda;
-      Mv = rl_rows(i, N); Nv = 64; Kv = 64;
-    } else {
-      const int k = t - r;
-      P = Li + (size_t)(64 * j) * ldi + 64 * j; ldp = ldi;
-      Q = Li + (size_t)(64 * j) * ldi + 64 * k; ldq = ldi; qT = false;
-      C = Li + (size_t)(64 * j) * ldi + 64 * k; ldc = ldi;
-      Mv = rl_rows(j, N); Nv = 64; Kv = rl_rows(j, N);
-    }
-  } else {
-    if (t == 0) {  // A_dd -= L_dj L_dj^T, then the leaf of block d
-      const int d = j + 1, nd = rl_rows(d, N);
-      const double* Pd = A + (size_t)(64 * d) * lda + 64 * j;
-      double* Add = A + (size_t)(64 * d) * lda + 64 * d;
-      const int tid = threadIdx.x;
-      const int lane = tid & 63, w = tid >> 6, kh = w >> 2, wm = (w >> 1) & 1, wn = w & 1;
-      const int lr = lane & 15, lk = lane >> 4;
-      double cv[2][2][4];
-      if (kh == 0) {
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int i = wm * 32 + mi * 16 + lk + 4 * q, c = wn * 32 + ni * 16 + lr;
-              cv[mi][ni][q] = (i < nd && c <= i) ? Add[(size_t)i * lda + c] : 0.0;
-            }
-      }
-      v4d acc[2][2];
-      double* Al = &Qs[0][0];  // the updated block, row pitch NB + 1
-      if (tile_product(Pd, lda, Pd, lda, true, nd, nd, 64, Ps, Qs, acc)) {
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-          for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-              const int i = wm * 32 + mi * 16 + lk + 4 * q, c = wn * 32 + ni * 16 + lr;
-              Al[i * (NB + 1) + c] = cv[mi][ni][q] - acc[mi][ni][q];
-            }
-      }
-      __syncthreads();
-      leaf_factor(Add, nd, lda, Al, flag, Li + (size_t)(64 * d) * ldi + 64 * d, ldi, nd,
-                  &Ps[0][0]);
-      return;
-    }
-    // block (i, k) of A (k > j) or of Y (k <= j) that this tile updates
-    const int ta = r * (r + 1) / 2;
-    const bool yt = t >= ta;
-    int i, k;
-    if (!yt) {
-      int ii = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-      while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
-      while (ii * (ii + 1) / 2 > t) --ii;
-      i = j + 1 + ii;
-      k = j + 1 + (t - ii * (ii + 1) / 2);
-    } else {
-      i = j + 1 + (t - ta) / (j + 1);
-      k = (t - ta) % (j + 1);
-    }
-    if (!yt) {
-      P = A + (size_t)(64 * i) * lda + 64 * j; ldp = lda;
-      Q = A + (size_t)(64 * k) * lda + 64 * j; ldq = lda; qT = true;
-      C = A + (size_t)(64 * i) * lda + 64 * k; ldc = lda;
-      Mv = rl_rows(i, N); Nv = rl_rows(k, N); Kv = 64;
-      alpha = -1.0; beta = 1.0;
-    } else {
-      P = A + (size_t)(64 * i) * lda + 64 * j; ldp = lda;
-      Q = Li + (size_t)(64 * j) * ldi + 64 * k; ldq = ldi; qT = false;
-      C = Li + (size_t)(64 * i) * ldi + 64 * k; ldc = ldi;
-      Mv = rl_rows(i, N); Nv = 64; Kv = 64;
-      alpha = -1.0; beta = (k < j) ? 1.0 : 0.0;
-    }
-  }
+// H <- the product held by the lower wavefronts, transposed (H[c][i] = acc(i, c), the layout
+// of an operand block loaded into Ps, or into Qs with qT) or not (H[i][c], Qs without qT).
+// Ends with a barrier.
+__device__ __forceinline__ void tile_stash(bool lower, const v4d (&acc)[2][2], bool transposed,
+                                           double (*H)[65]) {
   const int tid = threadIdx.x;
-  const int lane = tid & 63, w = tid >> 6, kh = w >> 2, wm = (w >> 1) & 1, wn = w & 1;
+  const int lane = tid & 63, w = tid >> 6, wm = (w >> 1) & 1, wn = w & 1;
   const int lr = lane & 15, lk = lane >> 4;
-  double cv[2][2][4];  // the old C values this thread stores back into (beta != 0)
-  if (kh == 0 && beta != 0.0) {
+  if (lower) {
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -538,11 +451,21 @@ __global__ __launch_bounds__(512) void k_rl_step(double* __restrict__ A, int lda
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int i = wm * 32 + mi * 16 + lk + 4 * q, c = wn * 32 + ni * 16 + lr;
-          cv[mi][ni][q] = (i < Mv && c < Nv) ? C[(size_t)i * ldc + c] : 0.0;
+          if (transposed) H[c][i] = acc[mi][ni][q];
+          else H[i][c] = acc[mi][ni][q];
         }
   }
-  v4d acc[2][2];
-  if (!tile_product(P, ldp, Q, ldq, qT, Mv, Nv, Kv, Ps, Qs, acc)) return;
+  __syncthreads();
+}
+
+// C (Mv x Nv at ldc) = alpha acc + beta cv by the lower wavefronts
+__device__ __forceinline__ void tile_store(bool lower, const v4d (&acc)[2][2],
+                                           const double (&cv)[2][2][4], double* C, int ldc,
+                                           int Mv, int Nv, double alpha, double beta) {
+  if (!lower) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, wm = (w >> 1) & 1, wn = w & 1;
+  const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -557,6 +480,155 @@ __global__ __launch_bounds__(512) void k_rl_step(double* __restrict__ A, int lda
           C[(size_t)i * ldc + c] = v;
         }
       }
+}
+
+// cv <- the block of C that the lower wavefronts will store into (entries past Mv x Nv, and
+// above the diagonal when lowerOnly, read as zero)
+__device__ __forceinline__ void tile_old(const double* C, int ldc, int Mv, int Nv,
+                                         bool lowerOnly, double (&cv)[2][2][4]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, kh = w >> 2, wm = (w >> 1) & 1, wn = w & 1;
+  const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = wm * 32 + mi * 16 + lk + 4 * q, c = wn * 32 + ni * 16 + lr;
+        cv[mi][ni][q] = (kh == 0 && i < Mv && c < Nv && (!lowerOnly || c <= i))
+                            ? C[(size_t)i * ldc + c] : 0.0;
+      }
+}
+
+// Tile tp of the panel of column jp (r = nb - 1 - jp):
+//   tp < r:         L_ij = A_ij L_jj^{-T}, i = jp + 1 + tp (in place in A);
+//   r <= tp < r+jp: X_jk = L_jj^{-1} Y_jk, k = tp - r (in place in Li).
+__device__ __forceinline__ void panel_tile(double* A, int lda, double* Li, int ldi, int N,
+                                           int jp, int tp, double (*Ps)[65], double (*Qs)[65]) {
+  const int nb = (N + 63) >> 6, r = nb - 1 - jp;
+  const double* Ljinv = Li + (size_t)(64 * jp) * ldi + 64 * jp;
+  v4d acc[2][2];
+  double cv[2][2][4] = {};
+  if (tp < r) {
+    const int i = jp + 1 + tp;
+    double* C = A + (size_t)(64 * i) * lda + 64 * jp;
+    tile_load(C, lda, Ljinv, ldi, true, rl_rows(i, N), 64, 64, Ps, Qs);
+    const bool lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
+    tile_store(lo, acc, cv, C, lda, rl_rows(i, N), 64, 1.0, 0.0);
+  } else {
+    const int k = tp - r, mj = rl_rows(jp, N);
+    double* C = Li + (size_t)(64 * jp) * ldi + 64 * k;
+    tile_load(Ljinv, ldi, C, ldi, false, mj, 64, mj, Ps, Qs);
+    const bool lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
+    tile_store(lo, acc, cv, C, ldi, mj, 64, 1.0, 0.0);
+  }
+}
+
+// The panel of column j alone (the last two columns of a node).
+__global__ __launch_bounds__(512) void k_rl_panel(double* __restrict__ A, int lda,
+                                                  double* __restrict__ Li, int ldi, int N,
+                                                  int j) {
+  __shared__ double Ps[64][65];  // odd row pitch against bank conflicts
+  __shared__ double Qs[64][65];
+  panel_tile(A, lda, Li, ldi, N, j, blockIdx.x, Ps, Qs);
+}
+
+// Step j of a node (r = nb - 1 - j >= 1), one block product chain per workgroup:
+//   tile 0:                  L_dj (d = j + 1) formed, A_dd -= L_dj L_dj^T into LDS, then the
+//                            leaf of block d (its Cholesky factor and inverse);
+//   tiles t < r(r+1)/2:      A_ik -= L_ij L_kj^T, j < k <= i, (i, k) != (d, d), with L_ij and
+//                            L_kj formed from A_ij, A_kj;
+//   next r (j + 1) tiles:    Y_ik = [k < j] Y_ik - L_ij X_jk, i > j, k <= j, with L_ij and
+//                            (k < j) X_jk formed from A_ij, Y_jk (X_jj = L_jj^{-1} is stored);
+//   the rest:                the stores of the panel of column j - 1.
+// The blocks a tile writes are read by no other tile of the launch.
+__global__ __launch_bounds__(512) void k_rl_fused(double* __restrict__ A, int lda,
+                                                  double* __restrict__ Li, int ldi, int N,
+                                                  int j, int* flag) {
+  static_assert(NB == 64 && NB * LW == 512 && kLeafLds <= 64 * 65, "leaf inside a tile step");
+  __shared__ double Ps[64][65];
+  __shared__ double Qs[64][65];
+  __shared__ double H1[64][65];  // formed panel blocks
+  __shared__ double H2[64][65];
+  const int nb = (N + 63) >> 6, r = nb - 1 - j, t = blockIdx.x;
+  const int ta = r * (r + 1) / 2, ty = ta + r * (j + 1);
+  const double* Ljinv = Li + (size_t)(64 * j) * ldi + 64 * j;
+  v4d acc[2][2];
+  double cv[2][2][4];
+  if (t >= ty) {  // deferred stores of the previous column's panel
+    panel_tile(A, lda, Li, ldi, N, j - 1, t - ty, Ps, Qs);
+    return;
+  }
+  if (t == 0) {  // A_dd -= L_dj L_dj^T, then the leaf of block d
+    const int d = j + 1, nd = rl_rows(d, N);
+    double* Add = A + (size_t)(64 * d) * lda + 64 * d;
+    tile_old(Add, lda, nd, nd, true, cv);
+    tile_load(A + (size_t)(64 * d) * lda + 64 * j, lda, Ljinv, ldi, true, nd, 64, 64, Ps, Qs);
+    bool lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
+    tile_stash(lo, acc, true, H1);
+    lo = tile_mma(H1, H1, &Ps[0][0], acc);
+    double* Al = &Qs[0][0];  // the updated block, row pitch NB + 1
+    if (lo) {
+      const int tid = threadIdx.x;
+      const int lane = tid & 63, w = tid >> 6, wm = (w >> 1) & 1, wn = w & 1;
+      const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int i = wm * 32 + mi * 16 + lk + 4 * q, c = wn * 32 + ni * 16 + lr;
+            Al[i * (NB + 1) + c] = cv[mi][ni][q] - acc[mi][ni][q];
+          }
+    }
+    __syncthreads();
+    leaf_factor(Add, nd, lda, Al, flag, Li + (size_t)(64 * d) * ldi + 64 * d, ldi, nd,
+                &Ps[0][0]);
+    return;
+  }
+  if (t < ta) {  // A_ik -= L_ij L_kj^T
+    int ii = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((ii + 1) * (ii + 2) / 2 <= t) ++ii;
+    while (ii * (ii + 1) / 2 > t) --ii;
+    const int i = j + 1 + ii, k = j + 1 + (t - ii * (ii + 1) / 2);
+    const int mi = rl_rows(i, N), mk = rl_rows(k, N);
+    double* C = A + (size_t)(64 * i) * lda + 64 * k;
+    tile_old(C, lda, mi, mk, false, cv);
+    tile_load(A + (size_t)(64 * i) * lda + 64 * j, lda, Ljinv, ldi, true, mi, 64, 64, Ps, Qs);
+    bool lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
+    tile_stash(lo, acc, true, H1);
+    if (k != i) {
+      tile_load(A + (size_t)(64 * k) * lda + 64 * j, lda, Ljinv, ldi, true, mk, 64, 64, Ps, Qs);
+      lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
+      tile_stash(lo, acc, true, H2);
+    }
+    lo = tile_mma(H1, k != i ? H2 : H1, &Ps[0][0], acc);
+    tile_store(lo, acc, cv, C, lda, mi, mk, -1.0, 1.0);
+    return;
+  }
+  {  // Y_ik = [k < j] Y_ik - L_ij X_jk
+    const int i = j + 1 + (t - ta) / (j + 1), k = (t - ta) % (j + 1);
+    const int mi = rl_rows(i, N);
+    double* C = Li + (size_t)(64 * i) * ldi + 64 * k;
+    const double beta = (k < j) ? 1.0 : 0.0;
+    tile_old(C, ldi, beta != 0.0 ? mi : 0, 64, false, cv);
+    tile_load(A + (size_t)(64 * i) * lda + 64 * j, lda, Ljinv, ldi, true, mi, 64, 64, Ps, Qs);
+    bool lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
+    tile_stash(lo, acc, true, H1);
+    if (k < j) {  // X_jk = L_jj^{-1} Y_jk
+      tile_load(Ljinv, ldi, Li + (size_t)(64 * j) * ldi + 64 * k, ldi, false, 64, 64, 64, Ps,
+                Qs);
+      lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
+      tile_stash(lo, acc, false, H2);
+      lo = tile_mma(H1, H2, &Ps[0][0], acc);
+    } else {      // X_jj = L_jj^{-1}, stored by the leaf
+      tile_load(Ljinv, ldi, Ljinv, ldi, false, 0, 64, 64, Ps, Qs);
+      lo = tile_mma(H1, Qs, &Ps[0][0], acc);
+    }
+    tile_store(lo, acc, cv, C, ldi, mi, 64, -1.0, beta);
+  }
 }
 
 __global__ void k_copy_block(const double* __restrict__ S, int lds, double* __restrict__ D,
@@ -739,7 +811,7 @@ static int rl_factor(double* A, int N, int lda, double* Li, int ldi, int* flag, 
   const int nb = (N + NB - 1) / NB;
   const double tile_flops = 2.0 * NB * NB * NB, tile_bytes = 4.0 * NB * NB * 8;
   const double leaf_flops = 2.0 * NB * NB * NB / 3.0, leaf_bytes = 3.0 * 8 * NB * NB;
-  {  // the first block column's leaf; every later one runs inside the previous trail step
+  {  // the first block column's leaf; every later one runs inside the previous step
     const int n0 = std::min(NB, N);
     ProfMark pm = prof_begin(LRSDP_K_LEAF, s);
     k_chol_leaf<<<1, NB * LW, 0, s>>>(A, n0, lda, flag, Li, ldi, n0);
@@ -747,21 +819,23 @@ static int rl_factor(double* A, int N, int lda, double* Li, int ldi, int* flag, 
     // Cholesky n0^3 / 3 and triangular inverse n0^3 / 3 flops; A read, L and L^{-1} written
     prof_end(pm, s, 3.0 * 8 * n0 * n0, 2.0 * n0 * n0 * n0 / 3.0);
   }
-  for (int j = 0; j < nb; ++j) {
+  for (int j = 0; j + 1 < nb; ++j) {
     const int r = nb - 1 - j;
-    if (r + j > 0) {
-      ProfMark pm = prof_begin(LRSDP_K_TILE, s);
-      k_rl_step<kRLPanel><<<r + j, 512, 0, s>>>(A, lda, Li, ldi, N, j, flag);
-      LRSDP_HIP(hipGetLastError());
-      prof_end(pm, s, (r + j) * tile_bytes, (r + j) * tile_flops);
-    }
-    if (r > 0) {
-      const int tiles = r * (r + 1) / 2 + r * (j + 1);
-      ProfMark pm = prof_begin(LRSDP_K_TILE, s);
-      k_rl_step<kRLTrail><<<tiles, 512, 0, s>>>(A, lda, Li, ldi, N, j, flag);
-      LRSDP_HIP(hipGetLastError());
-      prof_end(pm, s, tiles * tile_bytes + leaf_bytes, tiles * tile_flops + leaf_flops);
-    }
+    const int ta = r * (r + 1) / 2, ty = r * (j + 1), tp = j >= 1 ? r + j : 0;
+    // block products: A tiles 3 (2 on the diagonal), Y tiles 3 (2 for k = j), panel stores 1
+    const double products = 3.0 * (ta - 1) - (r - 1) + 2.0 + 3.0 * ty - r + tp;
+    ProfMark pm = prof_begin(LRSDP_K_TILE, s);
+    k_rl_fused<<<ta + ty + tp, 512, 0, s>>>(A, lda, Li, ldi, N, j, flag);
+    LRSDP_HIP(hipGetLastError());
+    prof_end(pm, s, products * tile_bytes + leaf_bytes, products * tile_flops + leaf_flops);
+  }
+  for (int j = std::max(0, nb - 2); j < nb; ++j) {  // the last two panels
+    const int tiles = (nb - 1 - j) + j;
+    if (tiles == 0) continue;
+    ProfMark pm = prof_begin(LRSDP_K_TILE, s);
+    k_rl_panel<<<tiles, 512, 0, s>>>(A, lda, Li, ldi, N, j);
+    LRSDP_HIP(hipGetLastError());
+    prof_end(pm, s, tiles * tile_bytes, tiles * tile_flops);
   }
   return LRSDP_OK;
 }

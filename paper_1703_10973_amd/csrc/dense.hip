@@ -770,13 +770,12 @@ static void launch_gemm(const GemmArgs& g, hipStream_t s) {
 int gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return LRSDP_OK;
   // 32 x 32 tiles with four wavefronts splitting K for small products, 64 x 64 tiles with
-  // two for medium ones, plain 64 x 64 tiles once they alone fill the chip several times
+  // two otherwise (thresholds from a sweep of the factorization's shapes; two K-splitting
+  // wavefronts also beat one at several thousand tiles)
   const int64_t t64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * (g.offs ? g.batch : 1);
-  // (thresholds from a sweep of the factorization's shapes)
   const int te = t64 >= 320 ? 64 : 32;
   ProfMark pm = prof_begin(LRSDP_K_GEMM, s);
-  if (t64 >= 2048) launch_gemm<2, 2, 1>(g, s);
-  else if (t64 >= 320) launch_gemm<2, 2, 2>(g, s);
+  if (t64 >= 320) launch_gemm<2, 2, 2>(g, s);
   else launch_gemm<1, 1, 4>(g, s);
   LRSDP_HIP(hipGetLastError());
   if (pm.kid >= 0) {

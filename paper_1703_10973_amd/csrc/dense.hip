@@ -770,12 +770,14 @@ static void launch_gemm(const GemmArgs& g, hipStream_t s) {
 int gemm(const GemmArgs& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return LRSDP_OK;
   // 32 x 32 tiles with four wavefronts splitting K for small products, 64 x 64 tiles with
-  // two otherwise (thresholds from a sweep of the factorization's shapes; two K-splitting
-  // wavefronts also beat one at several thousand tiles)
+  // two for medium ones, 128 x 128 tiles of eight wavefronts (each a 64 x 32 block) once there
+  // are thousands of them: they re-read half as much of A and B (thresholds from sweeps of
+  // the factorization's shapes and the large configuration's solve)
   const int64_t t64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * (g.offs ? g.batch : 1);
-  const int te = t64 >= 320 ? 64 : 32;
+  const int te = t64 >= 8192 ? 128 : t64 >= 320 ? 64 : 32;
   ProfMark pm = prof_begin(LRSDP_K_GEMM, s);
-  if (t64 >= 320) launch_gemm<2, 2, 2>(g, s);
+  if (t64 >= 8192) launch_gemm<2, 4, 1, 4, 2>(g, s);
+  else if (t64 >= 320) launch_gemm<2, 2, 2>(g, s);
   else launch_gemm<1, 1, 4>(g, s);
   LRSDP_HIP(hipGetLastError());
   if (pm.kid >= 0) {

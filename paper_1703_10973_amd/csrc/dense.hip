@@ -773,10 +773,14 @@ int gemm(const GemmArgs& g, hipStream_t s) {
   // two for medium ones, 128 x 128 tiles of eight wavefronts (each a 64 x 32 block) once there
   // are thousands of them: they re-read half as much of A and B (thresholds from sweeps of
   // the factorization's shapes and the large configuration's solve)
+  // (a triangular operand's K ranges follow the tile edges, so large tiles skip less of it and
+  // need more tiles before they pay)
   const int64_t t64 = (int64_t)((g.M + 63) / 64) * ((g.N + 63) / 64) * (g.offs ? g.batch : 1);
-  const int te = t64 >= 8192 ? 128 : t64 >= 320 ? 64 : 32;
+  const bool tri = (g.flags & (kKFromRow | kKToRow | kKFromCol | kKToCol)) != 0;
+  const bool big = t64 >= 8192 || (!tri && t64 >= 1024);
+  const int te = big ? 128 : t64 >= 320 ? 64 : 32;
   ProfMark pm = prof_begin(LRSDP_K_GEMM, s);
-  if (t64 >= 8192) launch_gemm<2, 4, 1, 4, 2>(g, s);
+  if (big) launch_gemm<2, 4, 1, 4, 2>(g, s);
   else if (t64 >= 320) launch_gemm<2, 2, 2>(g, s);
   else launch_gemm<1, 1, 4>(g, s);
   LRSDP_HIP(hipGetLastError());

@@ -12,6 +12,17 @@
  * PCG is preconditioned by H~ = tau^2 A^T A + bold U bold U^T (eq AtIUUtAt)
  * through the Sherman-Morrison-Woodbury form (eq SMW2).
  *
+ * Step labels used here and in the sources:
+ *   A0 the data A_i as sparse triplets, checked and laid out (Ass. 2, Section 1.1);
+ *   A1 the eigen step: tau and the k largest eigenpairs of W (Algorithm 1 step 1a);
+ *   A2 U, W0 = W - U U^T and Z = chol(2 W0 + U U^T) with Z^{-1} (step 1b);
+ *   A3 formation of bold S = tau^2 I + bold U^T (A^T A)^{-1} bold U (step 2, eq SMW2);
+ *   A4 deflation and the Cholesky factor of bold S with its inverse (step 2);
+ *   A5 the product H v (eq hesseqn2);
+ *   A6 the preconditioner H~^{-1} v (eqs SMW2, Umv; step 3);
+ *   A7 H v in the split form of eq hessExp1, the W0 part in lower precision;
+ *   A8 PCG, and refinement with double-double residuals (step 3).
+ *
  * Conventions shared by every entry point
  *   - Array arguments are DEVICE pointers on the context's device unless the
  *     comment says "host".  The library copies what it keeps; no caller pointer

@@ -307,6 +307,7 @@ void lrsdp_problem_destroy(lrsdp_problem* p) {
   dev_free(c, p->src, nnz * 4);
   dev_free(c, p->mval, nnz * 8);
   dev_free(c, p->vec_scratch, 4 * m * 8);
+  dev_free(c, p->tscr, 2 * n * n * 8);
   delete p;
 }
 
@@ -338,6 +339,7 @@ int lrsdp_problem_create(lrsdp_ctx* c, int64_t n, int64_t m, int64_t nnz, const 
     if ((rc = dev_alloc_n(c, &p->own_oth, (size_t)m))) break;
     if ((rc = dev_alloc_n(c, &p->pat, 2 * (size_t)m))) break;
     if ((rc = dev_alloc_n(c, &p->vec_scratch, 4 * (size_t)m))) break;
+    if (n >= kTGlobalMinN && (rc = dev_alloc_n(c, &p->tscr, 2 * (size_t)n * n))) break;
     ProfScope ps(c);
     rc = ingest(c, p, con, row, col, val, nnz);
   } while (0);

@@ -16,6 +16,7 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr size_t kLdsBudget = 80 * 1024;  // two workgroups of 16 wavefronts per CU
+constexpr size_t kLdsMax = 160 * 1024;    // one workgroup per CU
 
 __global__ void k_scatter(int nnz, const int32_t* __restrict__ src,
                           const double* __restrict__ val, const double* __restrict__ v,
@@ -56,17 +57,19 @@ __device__ __forceinline__ int owner_row(const int32_t* own_ptr, int c0, int cb,
   return c;
 }
 
-template <typename TW, typename TA, int CB, bool kBf16Values>
+// kTG: the workgroup's rows of Tt live in global scratch tg (n x ldn, L2-resident), not in
+// LDS, which then holds only the CB rows of W (large n).
+template <typename TW, typename TA, int CB, bool kBf16Values, bool kTG>
 __global__ __launch_bounds__(kThreads) void k_hv_fused(
     int n, int ldn, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
     const double* __restrict__ mval, const TW* __restrict__ W,
     const int32_t* __restrict__ own_ptr, const int32_t* __restrict__ own_con,
     const int32_t* __restrict__ own_oth, const double* __restrict__ coef,
-    double* __restrict__ Hv) {
+    double* __restrict__ Hv, TA* __restrict__ tg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TA* Wb = reinterpret_cast<TA*>(smem_raw);  // [CB][ldn]
-  TA* Tt = Wb + CB * ldn;                    // [CB][ldn]
   const int c0 = blockIdx.x * CB;
+  TA* Tt = kTG ? tg + (size_t)c0 * ldn : Wb + CB * ldn;  // [CB][ldn]
   const int cb = min(CB, n - c0);
 
   // 1. stage rows c0..c0+cb-1 of W
@@ -104,7 +107,8 @@ __global__ __launch_bounds__(kThreads) void k_hv_fused(
       }
       if (sub == 0) {
 #pragma unroll
-        for (int c = 0; c < CB; ++c) Tt[c * ldn + p] = acc[c];
+        for (int c = 0; c < CB; ++c)
+          if (!kTG || c < cb) Tt[c * ldn + p] = acc[c];  // (global rows stop at n)
       }
     }
   }
@@ -131,31 +135,42 @@ __global__ __launch_bounds__(kThreads) void k_hv_fused(
   }
 }
 
+// Rows of W per workgroup: as many as the LDS holds (up to 8; rows_lds = LDS bytes per row),
+// while at least ~200 workgroups remain so that every CU gets one; fewer rows per
+// workgroup cost only extra (L2-resident) passes over the pattern.
+int rows_per_wg(int n, size_t budget, size_t row_bytes) {
+  int cb = static_cast<int>(budget / row_bytes);
+  if (cb < 1) return 0;
+  cb = cb >= 8 ? 8 : cb >= 4 ? 4 : cb >= 2 ? 2 : 1;
+  while (cb > 1 && (n + cb - 1) / cb < 200) cb >>= 1;
+  return cb;
+}
+
 template <typename TW, typename TA, bool kBf16Values>
 int launch_hv(const lrsdp_problem* P, const TW* W, const double* v, double* Hv, hipStream_t s) {
   const int n = P->n;
   k_scatter<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, v, P->mval);
   const int ldn = n;
-  const size_t row_bytes = 2 * (size_t)ldn * sizeof(TA);
-  int cb = static_cast<int>(kLdsBudget / row_bytes);
-  size_t budget = kLdsBudget;
-  if (cb < 1) {  // large n: one block per CU
-    budget = 160 * 1024;
-    cb = static_cast<int>(budget / row_bytes);
-    if (cb < 1) return LRSDP_ERR_INVALID_ARG;
-  }
-  cb = cb >= 8 ? 8 : cb >= 4 ? 4 : cb >= 2 ? 2 : 1;
-  // at least ~200 workgroups so that every CU gets one; fewer rows per workgroup cost only
-  // extra (L2-resident) passes over the pattern
-  while (cb > 1 && (n + cb - 1) / cb < 200) cb >>= 1;
-  const size_t smem = (size_t)cb * row_bytes;
+  // W and T rows in LDS (two workgroups per CU, else one); with the global scratch, only W
+  int cb = rows_per_wg(n, kLdsBudget, 2 * (size_t)ldn * sizeof(TA));
+  if (cb < 1) cb = rows_per_wg(n, kLdsMax, 2 * (size_t)ldn * sizeof(TA));
+  const bool tg = P->tscr != nullptr && cb < 4;
+  if (tg) cb = rows_per_wg(n, kLdsMax, (size_t)ldn * sizeof(TA));
+  if (cb < 1) return LRSDP_ERR_INVALID_ARG;
+  const size_t smem = (size_t)cb * (tg ? 1 : 2) * ldn * sizeof(TA);
+  TA* tgp = reinterpret_cast<TA*>(P->tscr);
   const int grid = (n + cb - 1) / cb;
   ProfMark pm = prof_begin(LRSDP_K_HV, s);
-#define LRSDP_HV_CASE(CBV)                                                                  \
-  case CBV:                                                                                 \
-    hipLaunchKernelGGL((k_hv_fused<TW, TA, CBV, kBf16Values>), dim3(grid), dim3(kThreads), \
-                       smem, s, n, ldn, P->rowptr, P->colidx, P->mval, W, P->own_ptr,       \
-                       P->own_con, P->own_oth, P->coef, Hv);                                \
+#define LRSDP_HV_CASE(CBV)                                                                     \
+  case CBV:                                                                                    \
+    if (tg)                                                                                    \
+      hipLaunchKernelGGL((k_hv_fused<TW, TA, CBV, kBf16Values, true>), dim3(grid),             \
+                         dim3(kThreads), smem, s, n, ldn, P->rowptr, P->colidx, P->mval, W,    \
+                         P->own_ptr, P->own_con, P->own_oth, P->coef, Hv, tgp);                \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_hv_fused<TW, TA, CBV, kBf16Values, false>), dim3(grid),            \
+                         dim3(kThreads), smem, s, n, ldn, P->rowptr, P->colidx, P->mval, W,    \
+                         P->own_ptr, P->own_con, P->own_oth, P->coef, Hv, nullptr);            \
     break;
   switch (cb) {
     LRSDP_HV_CASE(1)
@@ -192,19 +207,20 @@ __global__ void k_scatter_dd(int nnz, const int32_t* __restrict__ src,
   }
 }
 
-template <int CB>
+// kTG: the rows of (Th, Tl) live in global scratch (tgh, tgl: n x ldn each), as in k_hv_fused.
+template <int CB, bool kTG>
 __global__ __launch_bounds__(kThreads) void k_residual_dd(
     int n, int ldn, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
     const double* __restrict__ mhi, const double* __restrict__ mlo,
     const double* __restrict__ W, const int32_t* __restrict__ own_ptr,
     const int32_t* __restrict__ own_con, const int32_t* __restrict__ own_oth,
     const double* __restrict__ coef, const double* __restrict__ r, double* __restrict__ res,
-    double* __restrict__ res_lo) {
+    double* __restrict__ res_lo, double* __restrict__ tgh, double* __restrict__ tgl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Wb = reinterpret_cast<double*>(smem_raw);  // [CB][ldn]
-  double* Th = Wb + CB * ldn;
-  double* Tl = Th + CB * ldn;
   const int c0 = blockIdx.x * CB;
+  double* Th = kTG ? tgh + (size_t)c0 * ldn : Wb + CB * ldn;
+  double* Tl = kTG ? tgl + (size_t)c0 * ldn : Th + CB * ldn;
   const int cb = min(CB, n - c0);
   for (int idx = threadIdx.x; idx < CB * n; idx += kThreads) {
     int c = idx / n, q = idx - c * n;
@@ -235,6 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_residual_dd(
       if (sub == 0) {
 #pragma unroll
         for (int c = 0; c < CB; ++c) {
+          if (kTG && c >= cb) continue;  // (global rows stop at n)
           Th[c * ldn + p] = acc[c].hi;
           Tl[c * ldn + p] = acc[c].lo;
         }
@@ -287,23 +304,27 @@ int hv_residual_dd(const lrsdp_problem* P, const double* W, const double* r, con
   k_scatter_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, y, ylo, mhi, mlo);
   const int ldn = n;
   const size_t row_bytes = 3 * (size_t)ldn * sizeof(double);
-  int cb = static_cast<int>(kLdsBudget / row_bytes);
-  size_t budget = kLdsBudget;
-  if (cb < 1) {
-    budget = 160 * 1024;
-    cb = static_cast<int>(budget / row_bytes);
-    if (cb < 1) return LRSDP_ERR_INVALID_ARG;
-  }
-  cb = cb >= 4 ? 4 : cb >= 2 ? 2 : 1;
-  while (cb > 1 && (n + cb - 1) / cb < 200) cb >>= 1;
-  const size_t smem = (size_t)cb * row_bytes;
+  int cb = rows_per_wg(n, kLdsBudget, row_bytes);
+  if (cb < 1) cb = rows_per_wg(n, kLdsMax, row_bytes);
+  const bool tg = P->tscr != nullptr && cb < 4;
+  if (tg) cb = rows_per_wg(n, kLdsMax, (size_t)ldn * sizeof(double));
+  if (cb < 1) return LRSDP_ERR_INVALID_ARG;
+  cb = cb >= 4 ? 4 : cb;
+  const size_t smem = (size_t)cb * (tg ? 1 : 3) * ldn * sizeof(double);
+  double* tgh = P->tscr;
+  double* tgl = tg ? P->tscr + (size_t)n * n : nullptr;
   const int grid = (n + cb - 1) / cb;
   ProfMark pm = prof_begin(LRSDP_K_RESDD, s);
-#define LRSDP_RES_CASE(CBV)                                                                \
-  case CBV:                                                                                \
-    hipLaunchKernelGGL((k_residual_dd<CBV>), dim3(grid), dim3(kThreads), smem, s, n, ldn,  \
-                       P->rowptr, P->colidx, mhi, mlo, W, P->own_ptr, P->own_con,          \
-                       P->own_oth, P->coef, r, res, res_lo);                                \
+#define LRSDP_RES_CASE(CBV)                                                                 \
+  case CBV:                                                                                 \
+    if (tg)                                                                                 \
+      hipLaunchKernelGGL((k_residual_dd<CBV, true>), dim3(grid), dim3(kThreads), smem, s,   \
+                         n, ldn, P->rowptr, P->colidx, mhi, mlo, W, P->own_ptr,             \
+                         P->own_con, P->own_oth, P->coef, r, res, res_lo, tgh, tgl);        \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_residual_dd<CBV, false>), dim3(grid), dim3(kThreads), smem, s,  \
+                         n, ldn, P->rowptr, P->colidx, mhi, mlo, W, P->own_ptr,             \
+                         P->own_con, P->own_oth, P->coef, r, res, res_lo, nullptr, nullptr); \
     break;
   switch (cb) {
     LRSDP_RES_CASE(1)

@@ -48,6 +48,10 @@ struct lrsdp_ctx {
                                 // [2] scratch for factorizations whose failure is not an error
 };
 
+// From this n on, the H v kernels keep their rows of T in global scratch (L2-resident) and
+// only rows of W in LDS, so each workgroup covers more rows of W per pass over the pattern.
+constexpr int kTGlobalMinN = 2048;
+
 struct lrsdp_problem {
   lrsdp_ctx* ctx = nullptr;
   int n = 0, m = 0, nnz = 0;        // nnz: entries of the symmetric pattern of mat(A v)
@@ -65,6 +69,8 @@ struct lrsdp_problem {
   int32_t* pat = nullptr;           // 2 m, pattern entries (a,b) and (b,a) of each constraint
   double* mval = nullptr;           // nnz scratch: values of mat(A v) in pattern order
   double* vec_scratch = nullptr;    // 4 m scratch for parity hooks
+  double* tscr = nullptr;           // 2 n^2 (n >= kTGlobalMinN only): rows of T = W mat(A v)
+                                    // for the H v kernels once T no longer fits in LDS
   size_t bytes = 0;
 };
 

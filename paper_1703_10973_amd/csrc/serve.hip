@@ -111,7 +111,8 @@ size_t lrsdp_instance_bytes(int64_t n, int64_t m, int32_t k) {
   // workspace) plus the problem (pairs, pattern, owner lists, scratch)
   const double doubles = 6.0 * nn + 2.25 * nk * nk + nk * r + 12.0 * m + 11.0 * nk +
                          (2.0 + k + pair_cap) * nn + pairs * n + nk * r + 8192.0;
-  const double problem = 112.0 * m + 16.0 * n + 65536.0;
+  const double problem = 112.0 * m + 16.0 * n + 65536.0 +
+                         (n >= kTGlobalMinN ? 16.0 * (double)n * n : 0.0);
   return (size_t)(8.0 * doubles + problem);
 }
 

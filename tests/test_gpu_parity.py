@@ -235,3 +235,34 @@ def test_solve_refined(ctx, mu, prec):
     ref = refine.refine(alg1.factor(C, inst.W, inst.k), inst.r, eps=1e-10)
     err = np.linalg.norm((yh - ref.yh) + (yl - ref.yl)) / np.linalg.norm(ref.yh)
     assert err <= 1e-6
+
+
+# ------------------------------------------------------------------ large n: T rows outside LDS
+
+def test_hessian_apply_large_n(ctx):
+    """n = 2602 (>= 2048): the H v kernels and the double-double residual keep their rows of
+    T in global scratch and only rows of W in LDS; the last workgroup covers a partial block.
+    FP64 and split FP32 products against the oracle's matrix-free product, and the residual
+    r - H (y + y_lo) on sampled constraints against the closed form of H in double-double."""
+    from test_gpu_large import _sampled_residual
+    inst = make_instance(2602, 3, 30000, 1e-6, seed=2602)
+    P = problem_from(ctx, inst)
+    C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(inst.m)
+    ref = alg1.hessian_apply_mf(C, inst.W, v)
+    assert rel(host(P.hessian_apply(to_dev(inst.W), to_dev(v))), ref) <= 1e-12
+    F = pk.Factor(P, to_dev(inst.W), inst.k)
+    vd = to_dev(v)
+    assert rel(host(F.hessian_apply_split(vd, pk.LRSDP_PREC_FP64)), ref) <= 1e-12
+    assert rel(host(F.hessian_apply_split(vd, pk.LRSDP_PREC_FP32)), ref) <= 1e-5
+    yh = rng.standard_normal(inst.m)
+    yl = yh * 1e-17 * rng.standard_normal(inst.m)
+    res = torch.empty(inst.m, dtype=torch.float64, device="cuda")
+    pk._lib.lrsdp_residual_dd(F.handle, to_dev(inst.r), to_dev(yh), to_dev(yl), res)
+    idx = rng.choice(inst.m, 12, replace=False)
+    want = _sampled_residual(inst, yh, yl, idx)
+    got = host(res)[idx]
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.linalg.norm(inst.r), (got, want)
+    F.close()
+    P.close()

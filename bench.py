@@ -56,7 +56,8 @@ def parse():
     ap.add_argument("--qps", type=float, default=4.0, help="serving arrival rate")
     ap.add_argument("--qps-sweep", action="store_true",
                     help="serving: measure capacity, then 0.25x to 1x of it")
-    ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--workers", type=int, default=8,
+                    help="host worker threads (streams) of the batch and serving workloads")
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="no GPU: print the top kernels of a rocprofv3 --kernel-trace --stats "
                          "-f csv output folder as a text table")

@@ -52,11 +52,14 @@ def _check_residual(inst, yh, yl):
     assert r_true <= 1e-8, (inst.n, inst.k, inst.m, inst.mu, r_true)
 
 
-def test_batch_matches_alone(ctx):
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_matches_alone(ctx, precision):
     """Batched-workload shapes (n in [64, 512], k in 1..4, mu = 1e-6): a batch of 10 on four
-    workers, each instance bitwise equal to its solve alone."""
+    workers, each instance bitwise equal to its solve alone, in FP64 and in the mixed form
+    (FP32 W0 part of H v inside the double-double refinement)."""
     insts = batch_instances(10, base_seed=3000)
-    opts = pk.opts(dd_mode=pk.LRSDP_DD_AUTO)
+    prec = pk.LRSDP_PREC_FP64 if precision == "fp64" else pk.LRSDP_PREC_AUTO
+    opts = pk.opts(precision=prec, dd_mode=pk.LRSDP_DD_AUTO)
     devs = [_device_instance(i) for i in insts]
     torch.cuda.synchronize()
     st, info = pk.solve_batch(ctx, devs, opts, workers=4)
@@ -81,8 +84,8 @@ def test_batch_empty_and_errors(ctx):
 
 @pytest.mark.parametrize("budget", [0, 1])
 def test_server_mixed_stream(ctx, budget):
-    """Serving-style requests of mixed shape and mu submitted at once; budget 1 byte admits
-    one request at a time.  Every result equals the instance solved alone."""
+    """Serving-style requests of mixed shape and mu submitted at once, in the mixed form; budget
+    1 byte admits one request at a time.  Every result equals the instance solved alone."""
     shapes = []
     for s in range(50000, 50040):
         n, k, m, mu = draw_serving_shape(s)
@@ -91,7 +94,7 @@ def test_server_mixed_stream(ctx, budget):
         if len(shapes) == 6:
             break
     insts = [make_instance(n, k, m, mu, seed=s) for (n, k, m, mu, s) in shapes]
-    opts = pk.opts(dd_mode=pk.LRSDP_DD_AUTO)
+    opts = pk.opts(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO)
     srv = pk.Server(ctx, workers=3, hbm_budget_bytes=budget)
     devs = [_device_instance(i) for i in insts]
     torch.cuda.synchronize()

@@ -278,7 +278,12 @@ int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lr
     status = LRSDP_NOT_CONVERGED;
     for (int outer = 0; outer <= o.max_outer; ++outer) {
       double rel = 1.0;
-      LRSDP_TRY(residual_dd(f, r, y, yl, w.dd0, w.dd1, &rel));
+      if (outer == 0) {  // y = 0: the residual is r itself (relative size 1; r = 0 is caught
+                         // by the inner solve, whose answer then leaves y = 0)
+        k_copy<<<vg, kT, 0, s>>>(m, r, w.dd0);
+      } else {
+        LRSDP_TRY(residual_dd(f, r, y, yl, w.dd0, w.dd1, &rel));
+      }
       inf.relres = rel;
       if (!std::isfinite(rel)) {
         status = LRSDP_ERR_DEVICE;

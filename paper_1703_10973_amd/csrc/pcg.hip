@@ -157,21 +157,14 @@ int pcg(lrsdp_factor* f, const double* b, double eps, int max_iter, HM Hmul, PM 
   LRSDP_TRY(Pinv(w.r, w.z));
   LRSDP_TRY(dot(f, m, w.r, w.z, w.part, sc + kRho0, s));
   k_copy<<<vg, kT, 0, s>>>(m, w.z, w.p);
+  // The starting scalars (r.r, r.z) are read together with the first iteration's: a zero
+  // right-hand side or an indefinite preconditioner is then caught one iteration late, and
+  // the first iteration's (meaningless) update of x is undone.
   double h[8];
-  LRSDP_TRY(read_scalars(ctx, sc, 8, h));
-  const double rr0 = h[kRR0];
+  double rr0 = 0.0;
   out->iters = 0;
   out->relres = 1.0;
   out->status = LRSDP_NOT_CONVERGED;
-  if (rr0 == 0.0) {
-    out->relres = 0.0;
-    out->status = LRSDP_OK;
-    return LRSDP_OK;
-  }
-  if (!(h[kRho0] > 0.0)) {
-    out->status = LRSDP_ERR_INDEFINITE_PRECOND;
-    return LRSDP_OK;
-  }
   int cur = kRho0, nxt = kRho1;
   for (int it = 1; it <= max_iter; ++it) {
     LRSDP_TRY(Hmul(w.p, w.q));
@@ -179,6 +172,15 @@ int pcg(lrsdp_factor* f, const double* b, double eps, int max_iter, HM Hmul, PM 
     k_update_xr<<<red_grid(m), kT, 0, s>>>(m, sc, cur, w.x, w.r, w.p, w.q, w.part,
                                           red_counter(f));
     LRSDP_TRY(read_scalars(ctx, sc, 8, h));
+    if (it == 1) {
+      rr0 = h[kRR0];
+      if (rr0 == 0.0 || !(h[kRho0] > 0.0)) {
+        k_zero<<<vg, kT, 0, s>>>(m, w.x);
+        out->relres = rr0 == 0.0 ? 0.0 : 1.0;
+        out->status = rr0 == 0.0 ? LRSDP_OK : LRSDP_ERR_INDEFINITE_PRECOND;
+        return LRSDP_OK;
+      }
+    }
     out->iters = it;
     const double rel = std::sqrt(std::fmax(h[kRR], 0.0) / rr0);
     out->relres = rel;

@@ -135,10 +135,12 @@ __global__ void k_R_pairs(int n, int nk, int q0, const double* Z, const double* 
 }
 
 // S_JJ += v I for the k diagonal blocks (block J = blockIdx.y).
-__global__ void k_add_diag(double* S, int n, int ld, double v) {
+// the diagonal of the k diagonal blocks += tau^2 (tau = lam[0], on the device)
+__global__ void k_add_diag(double* S, int n, int ld, const double* lam) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const size_t o = (size_t)n * blockIdx.y * ld + (size_t)n * blockIdx.y;
-  if (i < n) S[o + (size_t)i * ld + i] += v;
+  const double tau = lam[0];
+  if (i < n) S[o + (size_t)i * ld + i] += tau * tau;
 }
 
 // N (nk x r): column c <-> pair (i < j): block j holds y_i, block i holds -y_j, y = rows of Yt.
@@ -334,19 +336,11 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
     (void)hipStreamSynchronize(s);
     dev_free(ctx, ews, ewb);
   }
-  if (rc == LRSDP_OK) {
-    f->lam.assign(k + 1, 0.0);
-    if (hipMemcpyAsync(f->lam.data(), f->lam_dev, (k + 1) * sizeof(double),
-                       hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      rc = LRSDP_ERR_DEVICE;
-  }
   LRSDP_TRY(rc);
-  f->tau = f->lam[0];
-  for (double v : f->lam)
-    if (!std::isfinite(v)) return LRSDP_ERR_EIG;
-  if (!(f->tau > 0.0)) return LRSDP_ERR_NOT_PD_W;
-  f->tau2 = f->tau * f->tau;
+  // tau and the eigenvalues are read at the end, with the factorization flags: the steps
+  // below take tau from lam_dev (a W that is not positive definite only makes them compute
+  // garbage, which is discarded)
+  f->lam.assign(k + 1, 0.0);
 
   // ---- 1b: U, W0, Z
   LRSDP_HIP(hipEventRecord(ev[1], s));
@@ -422,7 +416,7 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
       rc = gemm(g, s);
     }
     if (rc != LRSDP_OK) break;
-    k_add_diag<<<dim3(grid_for(n, 256), k), 256, 0, s>>>(S, n, nk, f->tau2);
+    k_add_diag<<<dim3(grid_for(n, 256), k), 256, 0, s>>>(S, n, nk, f->lam_dev);
     // ---- deflation of null(bold U) directions
     if (r) {
       double* Yt = Rb.p;  // k x n: (Z^{-1} U)^T = U Z^{-T}
@@ -469,10 +463,12 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
       rc = LRSDP_ERR_DEVICE;
       break;
     }
-    // one host read for both flags and the shift
+    // one host read for tau and the eigenvalues, both flags and the shift
     int fl[2] = {0, 0};
     double shift = 0.0;
-    if (hipMemcpyAsync(fl, ctx->d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s) !=
+    if (hipMemcpyAsync(f->lam.data(), f->lam_dev, (k + 1) * sizeof(double),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(fl, ctx->d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, s) !=
             hipSuccess ||
         (r && hipMemcpyAsync(&shift, f->sc, sizeof(double), hipMemcpyDeviceToHost, s) !=
                   hipSuccess) ||
@@ -481,8 +477,14 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
       break;
     }
     f->shift = shift;
-    if (fl[1]) rc = LRSDP_ERR_CHOL_Z;
+    f->tau = f->lam[0];
+    bool finite = true;
+    for (double v : f->lam) finite = finite && std::isfinite(v);
+    if (!finite) rc = LRSDP_ERR_EIG;
+    else if (!(f->tau > 0.0)) rc = LRSDP_ERR_NOT_PD_W;
+    else if (fl[1]) rc = LRSDP_ERR_CHOL_Z;
     else if (fl[0]) rc = LRSDP_ERR_CHOL_S;
+    f->tau2 = f->tau * f->tau;
   } while (0);
   free_tmp();
   LRSDP_TRY(rc);

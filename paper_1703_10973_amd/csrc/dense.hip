@@ -220,70 +220,104 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 }
 
 // Cholesky factor L of a diagonal block (N <= 64) and L^{-1}, by 8-column panels.
-// The matrix being reduced sits in registers as rows: lane i = t % 64 holds row i, and
-// wavefront g = t / 64 the columns [8g, 8g + 8).  L^{-1} is built by forward substitution
-// on the identity in the transposed layout: lane c holds column c and wavefront g the rows
-// [8g, 8g + 8).  Between barrier P - 1 and barrier P:
-//   wavefront P factors panel P alone (pivots and l_cj by cross-lane reads) and publishes
-//   its columns;
-//   wavefront P - 1 finishes rows [8(P-1), 8P) of L^{-1} (an 8 x 8 forward substitution
-//   whose coefficients are its panel's l values) and publishes them.
+// Wavefront g owns the matrix columns [8g, 8g + 8) and the rows [8g, 8g + 8) of L^{-1}, both
+// as MFMA accumulators of a 64 x 16 block (four 16 x 16 tiles; columns 8..15 stay zero): the
+// matrix block as it is, the L^{-1} rows transposed.  Between barrier P - 1 and barrier P:
+//   wavefront P factors panel P alone: it moves its block to rows-in-lanes form through LDS
+//   (lane i holds row i), takes the pivots and l_cj by cross-lane reads, and publishes the
+//   panel's columns;
+//   wavefront P - 1 finishes rows [8(P-1), 8P) of L^{-1} the same way (an 8 x 8 forward
+//   substitution whose coefficients are its panel's l values) and publishes them.
 // After barrier P every wavefront g > P applies panel P's rank-8 update to its matrix
-// columns, and the wavefronts g >= P apply panel P - 1's update to their rows of L^{-1};
-// the wavefront that factors panel P + 1 defers that one until after the next barrier.  So the chain from
-// one factorization to the next holds one rank-8 update of eight columns and no L^{-1}
-// work.  Only the lower triangle of the registers is L: the updates are not masked, the
-// entries above the diagonal collect values that are never read as L (panels are published
-// with zeros there).  Every update keeps the order of the unblocked algorithm.  Rows and
-// columns beyond N are the identity.  A non-positive pivot sets *flag (the result is then
-// garbage).  Writes L (lower, zero above the diagonal) into A and L^{-1} (zero above the
-// diagonal) into Li (li_rows x li_rows).
+// columns, and the wavefronts g >= P apply panel P - 1's update to their rows of L^{-1}; the
+// wavefront that factors panel P + 1 defers that one until after the next barrier.  Each
+// update is a 64 x 8 x 8 product on the matrix cores, whose operands every lane reads from
+// LDS once (lane-distinct values) instead of every lane reading the same 8 x 8 block; the
+// products add their terms in the unblocked algorithm's order (the factors came out bit for
+// bit equal to those of one FMA per term).  Only
+// the lower triangle of the matrix block is L: rows above a wavefront's columns are not
+// updated, and panels are published with zeros there.  Rows and columns beyond N are the
+// identity.  A non-positive pivot sets *flag (the result is then garbage).  Writes L (lower,
+// zero above the diagonal) into A and L^{-1} (zero above the diagonal) into Li
+// (li_rows x li_rows).
 constexpr int LW = NB / 8;   // wavefronts of the leaf kernel
 constexpr int LP = NB / LW;  // panel width = columns (rows of L^{-1}) per wavefront
+static_assert(LP == 8 && NB == 64, "8-column panels of a 64-row block in 16 x 16 x 4 MFMAs");
 
 // LDS of the leaf: Ls[4][NB][LP + 1] (panel P's columns of L, row-indexed, buffer P % 4)
-// and Xs[2][LP][NB] (panel P's rows of L^{-1}, buffer P % 2).
+// and Xs[2][LP][NB] (panel P's rows of L^{-1}, buffer P % 2); separately Cv[2][NB][LP + 1]
+// (the form change of the factoring wavefront's block, 0, and of the finishing one's, 1).
 constexpr int kLeafLds = 4 * NB * (LP + 1) + 2 * LP * NB;  // doubles
+constexpr int kLeafConv = 2 * NB * (LP + 1);               // doubles
 
 // The leaf's work by its NB * LW threads.  The block comes from A (global, row pitch lda) or,
 // when Ain is given, from LDS (row pitch NB + 1); L goes to A in either case.
 __device__ __forceinline__ void leaf_factor(double* __restrict__ A, int N, int lda,
                                             const double* Ain, int* flag,
                                             double* __restrict__ Li, int ldi, int li_rows,
-                                            double* lds) {
+                                            double* lds, double* conv) {
   double(*Ls)[NB][LP + 1] = reinterpret_cast<double(*)[NB][LP + 1]>(lds);
   double(*Xs)[LP][NB] = reinterpret_cast<double(*)[LP][NB]>(lds + 4 * NB * (LP + 1));
+  double(*Cv)[NB][LP + 1] = reinterpret_cast<double(*)[NB][LP + 1]>(conv);
   const int t = threadIdx.x, i = t & (NB - 1), g = t / NB;
-  double a[LP], y[LP];
+  const int lr = i & 15, lk = i >> 4;  // MFMA roles: tile row / column lr, K or row group lk
+  // ca: this wavefront's matrix columns; cy: its rows of L^{-1}, transposed (row = column
+  // of L^{-1}).  Tile u, register r: row 16u + lk + 4r, column LP g + lr (lr < LP).
+  v4d ca[4], cy[4];
 #pragma unroll
-  for (int q = 0; q < LP; ++q) {
-    const int c = g * LP + q;
-    double v = 0.0;
-    if (i < N && c <= i) v = Ain ? Ain[i * (NB + 1) + c] : A[(size_t)i * lda + c];
-    else if (i == c) v = 1.0;
-    a[q] = v;
-    y[q] = (c == i) ? 1.0 : 0.0;  // row c = 8g + q, column i (lane) of the identity
-  }
-  bool bad = false;
-  double inv[LP];  // 1 / l_jj of this wavefront's panel
-  // this wavefront's rows of L^{-1} -= (panel p's l_cj) x (panel p's rows of L^{-1})
-  auto y_update = [&](int p) {
-    const int lb = p & 3, xb = p & 1;
-    double xj[LP];
+  for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int jj = 0; jj < LP; ++jj) xj[jj] = Xs[xb][jj][i];
-#pragma unroll
-    for (int q = 0; q < LP; ++q) {
-      const int c = g * LP + q;
-      double yacc = y[q];
-#pragma unroll
-      for (int jj = 0; jj < LP; ++jj) yacc = fma(-Ls[lb][c][jj], xj[jj], yacc);
-      y[q] = yacc;
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * u + lk + 4 * r, col = g * LP + lr;
+      double v = 0.0;
+      if (lr < LP) {
+        if (row < N && col <= row) v = Ain ? Ain[row * (NB + 1) + col] : A[(size_t)row * lda + col];
+        else if (row == col) v = 1.0;
+      }
+      ca[u][r] = v;
+      cy[u][r] = (lr < LP && row == col) ? 1.0 : 0.0;
     }
+  double a[LP], y[LP], inv[LP];  // rows-in-lanes forms; 1 / l_jj of this wavefront's panel
+#pragma unroll
+  for (int q = 0; q < LP; ++q) a[q] = y[q] = inv[q] = 0.0;
+  bool bad = false;
+  // acc(tiles u0..3) -= (64 x 8 block of rows 16u + m, entry opnd(16u + m, k)) x
+  // (panel p's rows [LP g, LP g + LP))^T
+  auto update = [&](v4d(&acc)[4], int u0, int u1, int lb, auto opnd) {
+    double bq[2];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) bq[kk] = lr < LP ? Ls[lb][g * LP + lr][4 * kk + lk] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      if (u < u0 || u > u1) continue;
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(-opnd(16 * u + lr, 4 * kk + lk), bq[kk],
+                                                      acc[u], 0, 0, 0);
+    }
+  };
+  // the block of acc into rows-in-lanes form out[q] = block(row i, column q), via Cv[cb]
+  auto to_rows = [&](const v4d(&acc)[4], int cb, double(&out)[LP]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (lr < LP) Cv[cb][16 * u + lk + 4 * r][lr] = acc[u][r];
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int q = 0; q < LP; ++q) out[q] = Cv[cb][i][q];
+  };
+  // this wavefront's rows of L^{-1} -= (panel p's l_cj) x (panel p's rows of L^{-1}); the
+  // rows of L^{-1} of panel p are zero beyond column LP p + LP - 1
+  auto y_update = [&](int p) {
+    const int xb = p & 1;
+    update(cy, 0, (LP * p + LP - 1) >> 4, p & 3,
+           [&](int row, int k) { return Xs[xb][k][row]; });
   };
   for (int P = 0; P <= LW; ++P) {
     const int j0 = P * LP;
     if (P < LW && g == P) {  // factor panel P: every update from panels < P is in
+      to_rows(ca, 0, a);
       const int jl0 = __builtin_amdgcn_readfirstlane(j0);
 #pragma unroll
       for (int jj = 0; jj < LP; ++jj) {
@@ -297,8 +331,10 @@ __device__ __forceinline__ void leaf_factor(double* __restrict__ A, int N, int l
       }
 #pragma unroll
       for (int q = 0; q < LP; ++q) Ls[P & 3][i][q] = (i >= j0 + q) ? a[q] : 0.0;
+      __builtin_amdgcn_s_setprio(0);
     }
     if (P >= 1 && g == P - 1) {  // rows of L^{-1} of panel P - 1: all updates are in
+      to_rows(cy, 1, y);
       const int jl0 = __builtin_amdgcn_readfirstlane(j0 - LP);
 #pragma unroll
       for (int jj = 0; jj < LP; ++jj) {
@@ -312,19 +348,12 @@ __device__ __forceinline__ void leaf_factor(double* __restrict__ A, int N, int l
     }
     if (P == LW) break;
     __syncthreads();
-    if (g > P) {  // rank-8 update of this wavefront's matrix columns with panel P
+    // the next panel's wavefront issues first on its SIMD (its update is on the critical path);
+    // it drops back to normal priority once it has published its panel
+    if (g == P + 1) __builtin_amdgcn_s_setprio(2);
+    if (g > P) {  // rank-8 update of this wavefront's matrix columns (rows >= LP g) by panel P
       const int lb = P & 3;
-      double li[LP];
-#pragma unroll
-      for (int jj = 0; jj < LP; ++jj) li[jj] = Ls[lb][i][jj];
-#pragma unroll
-      for (int q = 0; q < LP; ++q) {
-        const int c = g * LP + q;
-        double acc = a[q];
-#pragma unroll
-        for (int jj = 0; jj < LP; ++jj) acc = fma(-li[jj], Ls[lb][c][jj], acc);
-        a[q] = acc;
-      }
+      update(ca, (g * LP) >> 4, 3, lb, [&](int row, int k) { return Ls[lb][row][k]; });
     }
     if (g == P && P >= 2) y_update(P - 2);  // deferred while this wavefront factored
     if (P >= 1 && g >= P && g != P + 1) y_update(P - 1);
@@ -343,7 +372,8 @@ __global__ __launch_bounds__(NB * LW) void k_chol_leaf(double* __restrict__ A, i
                                                        int* flag, double* __restrict__ Li,
                                                        int ldi, int li_rows) {
   __shared__ double lds[kLeafLds];
-  leaf_factor(A, N, lda, nullptr, flag, Li, ldi, li_rows, lds);
+  __shared__ double conv[kLeafConv];
+  leaf_factor(A, N, lda, nullptr, flag, Li, ldi, li_rows, lds, conv);
 }
 
 // ---------------------------------------------------------------- right-looking node
@@ -546,7 +576,8 @@ __global__ __launch_bounds__(512) void k_rl_panel(double* __restrict__ A, int ld
 __global__ __launch_bounds__(512) void k_rl_fused(double* __restrict__ A, int lda,
                                                   double* __restrict__ Li, int ldi, int N,
                                                   int j, int* flag) {
-  static_assert(NB == 64 && NB * LW == 512 && kLeafLds <= 64 * 65, "leaf inside a tile step");
+  static_assert(NB == 64 && NB * LW == 512 && kLeafLds <= 64 * 65 && kLeafConv <= 64 * 65,
+                "leaf inside a tile step");
   __shared__ double Ps[64][65];
   __shared__ double Qs[64][65];
   __shared__ double H1[64][65];  // formed panel blocks
@@ -585,7 +616,7 @@ __global__ __launch_bounds__(512) void k_rl_fused(double* __restrict__ A, int ld
     }
     __syncthreads();
     leaf_factor(Add, nd, lda, Al, flag, Li + (size_t)(64 * d) * ldi + 64 * d, ldi, nd,
-                &Ps[0][0]);
+                &Ps[0][0], &H1[0][0]);
     return;
   }
   if (t < ta) {  // A_ik -= L_ij L_kj^T

@@ -531,6 +531,132 @@ __device__ __forceinline__ void tile_old(const double* C, int ldc, int Mv, int N
       }
 }
 
+// acc = the product of the blocks in Ps, Qs when op(Q) is upper triangular (Qs[k][n] = 0 for
+// k > n: the factor L_jj^{-T} of a panel block L_ij = A_ij L_jj^{-T}), by 512 threads with K
+// unsplit: the 16 x 16 output tile (ti, tc) sums its nonzero K range [0, 16 tc + 16) in one
+// MFMA chain.  Wavefront w computes the tiles (w & 3, 3) and (w & 3, 0) when w < 4, else
+// (w & 3, 2) and (w & 3, 1): 20 MFMAs each (40 per SIMD) instead of 32, and no partial sums
+// to fold.  Ends with a barrier (Ps and Qs are free again).
+__device__ __forceinline__ void tile_mma_uq(const double (*Ps)[65], const double (*Qs)[65],
+                                            v4d (&acc)[2]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, ti = w & 3;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int tc0 = w < 4 ? 3 : 2, tc1 = 3 - tc0;
+  acc[0] = acc[1] = (v4d){0.0, 0.0, 0.0, 0.0};
+  for (int k16 = 0; k16 < 16 * tc0 + 16; k16 += 16) {
+    const bool both = k16 < 16 * tc1 + 16;
+#pragma unroll
+    for (int k4 = 0; k4 < 16; k4 += 4) {
+      const int kr = k16 + k4 + lk;
+      const double a = Ps[kr][16 * ti + lr];
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Qs[kr][16 * tc0 + lr], acc[0], 0, 0, 0);
+      if (both)
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, Qs[kr][16 * tc1 + lr], acc[1], 0, 0, 0);
+    }
+  }
+  __syncthreads();
+}
+
+// H[c][i] = acc(i, c) for the tiles of tile_mma_uq (the layout of an operand block loaded
+// into Ps, or into Qs with qT).  Ends with a barrier.
+__device__ __forceinline__ void tile_stash_uq(const v4d (&acc)[2], double (*H)[65]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, ti = w & 3;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int tc0 = w < 4 ? 3 : 2;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = 16 * (h == 0 ? tc0 : 3 - tc0) + lr;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) H[c][16 * ti + lk + 4 * q] = acc[h][q];
+  }
+  __syncthreads();
+}
+
+// C (Mv x Nv at ldc) = the product of tile_mma_uq
+__device__ __forceinline__ void tile_store_uq(const v4d (&acc)[2], double* C, int ldc, int Mv,
+                                              int Nv) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6, ti = w & 3;
+  const int lr = lane & 15, lk = lane >> 4;
+  const int tc0 = w < 4 ? 3 : 2;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = 16 * (h == 0 ? tc0 : 3 - tc0) + lr;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * ti + lk + 4 * q;
+      if (i < Mv && c < Nv) C[(size_t)i * ldc + c] = acc[h][q];
+    }
+  }
+}
+
+// The lower 16 x 16 tiles of a symmetric product H^T H (H[k][m] = P[m][k], so the product is
+// P P^T): ten tiles, each K = 64 in two halves, make 20 MFMA chains of 8; wavefront w takes
+// jobs w, w + 8 and w + 16 (< 20), five per SIMD.  Job j is the half j / 10 of lower tile
+// j % 10 (row-major: (0,0), (1,0), (1,1), (2,0), ...).  The second halves are parked in
+// `park` (2560 doubles, may alias neither H nor Out) and added to the first in that order;
+// Out[i][c] (row pitch 65) = Cv(i, c) - the product, with Cv read from C (rows past Mv and
+// entries above the diagonal as zero).  Entries of Out above the diagonal tiles are not written,
+// those above the diagonal inside a diagonal tile are garbage.  Ends with a barrier.
+__device__ __forceinline__ void tile_syrk_lower(const double (*H)[65], const double* C, int ldc,
+                                                int Mv, double* park, double* Out) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  auto tile_i = [](int t) { return t >= 6 ? 3 : t >= 3 ? 2 : t >= 1 ? 1 : 0; };
+  auto tile_c = [&](int t) { const int i = tile_i(t); return t - i * (i + 1) / 2; };
+  v4d acc[3];
+  double cv[3][4];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int j = w + 8 * s, t = j % 10;
+    const int ti = tile_i(t), tc = tile_c(t);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 16 * ti + lk + 4 * q, c = 16 * tc + lr;
+      cv[s][q] = (j < 10 && i < Mv && c <= i) ? C[(size_t)i * ldc + c] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int j = w + 8 * s;
+    acc[s] = (v4d){0.0, 0.0, 0.0, 0.0};
+    if (j >= 20) continue;
+    const int t = j % 10, k0 = 32 * (j / 10);
+    const int ti = tile_i(t), tc = tile_c(t);
+#pragma unroll
+    for (int k4 = 0; k4 < 32; k4 += 4) {
+      const int kr = k0 + k4 + lk;
+      acc[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(H[kr][16 * ti + lr], H[kr][16 * tc + lr],
+                                                    acc[s], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int j = w + 8 * s;
+    if (j >= 10 && j < 20) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) park[((j - 10) * 4 + q) * 64 + lane] = acc[s][q];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    const int j = w + 8 * s;
+    if (j < 10) {
+      const int ti = tile_i(j), tc = tile_c(j);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double v = acc[s][q] + park[(j * 4 + q) * 64 + lane];
+        Out[(16 * ti + lk + 4 * q) * 65 + 16 * tc + lr] = cv[s][q] - v;
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // Tile tp of the panel of column jp (r = nb - 1 - jp):
 //   tp < r:         L_ij = A_ij L_jj^{-T}, i = jp + 1 + tp (in place in A);
 //   r <= tp < r+jp: X_jk = L_jj^{-1} Y_jk, k = tp - r (in place in Li).
@@ -544,8 +670,9 @@ __device__ __forceinline__ void panel_tile(double* A, int lda, double* Li, int l
     const int i = jp + 1 + tp;
     double* C = A + (size_t)(64 * i) * lda + 64 * jp;
     tile_load(C, lda, Ljinv, ldi, true, rl_rows(i, N), 64, 64, Ps, Qs);
-    const bool lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
-    tile_store(lo, acc, cv, C, lda, rl_rows(i, N), 64, 1.0, 0.0);
+    v4d au[2];
+    tile_mma_uq(Ps, Qs, au);
+    tile_store_uq(au, C, lda, rl_rows(i, N), 64);
   } else {
     const int k = tp - r, mj = rl_rows(jp, N);
     double* C = Li + (size_t)(64 * jp) * ldi + 64 * k;
@@ -594,27 +721,12 @@ __global__ __launch_bounds__(512) void k_rl_fused(double* __restrict__ A, int ld
   if (t == 0) {  // A_dd -= L_dj L_dj^T, then the leaf of block d
     const int d = j + 1, nd = rl_rows(d, N);
     double* Add = A + (size_t)(64 * d) * lda + 64 * d;
-    tile_old(Add, lda, nd, nd, true, cv);
     tile_load(A + (size_t)(64 * d) * lda + 64 * j, lda, Ljinv, ldi, true, nd, 64, 64, Ps, Qs);
-    bool lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
-    tile_stash(lo, acc, true, H1);
-    lo = tile_mma(H1, H1, &Ps[0][0], acc);
+    v4d au[2];
+    tile_mma_uq(Ps, Qs, au);
+    tile_stash_uq(au, H1);
     double* Al = &Qs[0][0];  // the updated block, row pitch NB + 1
-    if (lo) {
-      const int tid = threadIdx.x;
-      const int lane = tid & 63, w = tid >> 6, wm = (w >> 1) & 1, wn = w & 1;
-      const int lr = lane & 15, lk = lane >> 4;
-#pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int ni = 0; ni < 2; ++ni)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int i = wm * 32 + mi * 16 + lk + 4 * q, c = wn * 32 + ni * 16 + lr;
-            Al[i * (NB + 1) + c] = cv[mi][ni][q] - acc[mi][ni][q];
-          }
-    }
-    __syncthreads();
+    tile_syrk_lower(H1, Add, lda, nd, &Ps[0][0], Al);
     leaf_factor(Add, nd, lda, Al, flag, Li + (size_t)(64 * d) * ldi + 64 * d, ldi, nd,
                 &Ps[0][0], &H1[0][0]);
     return;
@@ -628,14 +740,15 @@ __global__ __launch_bounds__(512) void k_rl_fused(double* __restrict__ A, int ld
     double* C = A + (size_t)(64 * i) * lda + 64 * k;
     tile_old(C, lda, mi, mk, false, cv);
     tile_load(A + (size_t)(64 * i) * lda + 64 * j, lda, Ljinv, ldi, true, mi, 64, 64, Ps, Qs);
-    bool lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
-    tile_stash(lo, acc, true, H1);
+    v4d au[2];
+    tile_mma_uq(Ps, Qs, au);
+    tile_stash_uq(au, H1);
     if (k != i) {
       tile_load(A + (size_t)(64 * k) * lda + 64 * j, lda, Ljinv, ldi, true, mk, 64, 64, Ps, Qs);
-      lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
-      tile_stash(lo, acc, true, H2);
+      tile_mma_uq(Ps, Qs, au);
+      tile_stash_uq(au, H2);
     }
-    lo = tile_mma(H1, k != i ? H2 : H1, &Ps[0][0], acc);
+    const bool lo = tile_mma(H1, k != i ? H2 : H1, &Ps[0][0], acc);
     tile_store(lo, acc, cv, C, lda, mi, mk, -1.0, 1.0);
     return;
   }
@@ -646,8 +759,10 @@ __global__ __launch_bounds__(512) void k_rl_fused(double* __restrict__ A, int ld
     const double beta = (k < j) ? 1.0 : 0.0;
     tile_old(C, ldi, beta != 0.0 ? mi : 0, 64, false, cv);
     tile_load(A + (size_t)(64 * i) * lda + 64 * j, lda, Ljinv, ldi, true, mi, 64, 64, Ps, Qs);
-    bool lo = tile_mma(Ps, Qs, &Ps[0][0], acc);
-    tile_stash(lo, acc, true, H1);
+    v4d au[2];
+    tile_mma_uq(Ps, Qs, au);
+    tile_stash_uq(au, H1);
+    bool lo;
     if (k < j) {  // X_jk = L_jj^{-1} Y_jk
       tile_load(Ljinv, ldi, Li + (size_t)(64 * j) * ldi + 64 * k, ldi, false, 64, 64, 64, Ps,
                 Qs);

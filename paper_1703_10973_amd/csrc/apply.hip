@@ -124,8 +124,14 @@ int spmm_U_dd(const lrsdp_problem* P, int k, const double* ginv, const double* v
 // ---------------------------------------------------------------- dense n x n times n x k
 // out[j][p] = sum_{q in range(p)} A[p][q] X[j][q]; range: 0 full, 1 q <= p, 2 q >= p.
 // (FP64: k_rows_kr below.)  The double-double form takes one workgroup per row p: its four
-// wavefronts split the row, every load of a thread is in flight at once, and the partial
-// sums meet in a fixed order.
+// wavefronts split the row and every load of a thread is in flight at once.  Each wavefront
+// then reduces its K2 column sums (k padded to K2) by a reduce-scatter butterfly: at the
+// exchange across lane bit o, the lower lanes keep the first half of the columns they carry
+// and the upper lanes the second half, each adding its partner's copy, until every group of
+// 64 / K2 lanes carries one column (column = lane / (64 / K2)); plain butterflies finish the
+// groups.  That is K2 - 1 + log2(64 / K2) double-double additions per wavefront instead of
+// 6 k.  The four wavefronts' sums meet in a fixed order.
+template <int K2>
 __global__ __launch_bounds__(kT) void k_rows_k_dd(int n, int k, const double* __restrict__ A,
                                                   int range, const double* __restrict__ Xh,
                                                   const double* __restrict__ Xl,
@@ -133,32 +139,44 @@ __global__ __launch_bounds__(kT) void k_rows_k_dd(int n, int k, const double* __
                                                   double* __restrict__ ol, double c,
                                                   const double* __restrict__ th,
                                                   const double* __restrict__ tl) {
-  __shared__ double red[kT / kWave][KMAX][2];
+  static_assert(K2 >= 2 && K2 <= 16 && (K2 & (K2 - 1)) == 0, "K2 a power of two");
+  constexpr int G = kWave / K2;  // lanes per column after the scatter
+  __shared__ double red[kT / kWave][K2][2];
   const int p = blockIdx.x, t = threadIdx.x;
   const int lane = t & (kWave - 1), wid = t / kWave;
   const int qlo = (range == 2) ? p : 0;
   const int qhi = (range == 1) ? p + 1 : n;
   const double* a = A + (size_t)p * n;
-  dd acc[KMAX];
+  dd acc[K2];
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j) acc[j] = {0.0, 0.0};
+  for (int j = 0; j < K2; ++j) acc[j] = {0.0, 0.0};
 #pragma unroll 2
   for (int q = qlo + t; q < qhi; q += kT) {
     const double av = a[q];
 #pragma unroll
-    for (int j = 0; j < KMAX; ++j)
+    for (int j = 0; j < K2; ++j)
       if (j < k)
         acc[j] = dd_fma2(acc[j], av, Xh[(size_t)j * n + q], Xl ? Xl[(size_t)j * n + q] : 0.0);
   }
+  // reduce-scatter: slot s of a lane holds the s-th column of the range it carries
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j)
-    if (j < k) {
-      const dd v = wave_sum_dd(acc[j]);
-      if (lane == 0) {
-        red[wid][j][0] = v.hi;
-        red[wid][j][1] = v.lo;
-      }
+  for (int o = kWave / 2, h = K2 / 2; h >= 1; o >>= 1, h >>= 1) {
+    const bool upper = (lane & o) != 0;
+#pragma unroll
+    for (int s = 0; s < h; ++s) {
+      const dd send = upper ? acc[s] : acc[h + s];
+      const dd keep = upper ? acc[h + s] : acc[s];
+      acc[s] = dd_add(keep, shfl_xor_dd(send, o));
     }
+  }
+  dd v = acc[0];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v = dd_add(v, shfl_xor_dd(v, o));
+  const int col = lane / G;
+  if (lane % G == 0) {
+    red[wid][col][0] = v.hi;
+    red[wid][col][1] = v.lo;
+  }
   __syncthreads();
   if (t < k) {
     dd u = dd_add({red[0][t][0], red[0][t][1]}, {red[1][t][0], red[1][t][1]});
@@ -402,7 +420,10 @@ namespace {
 int rows_k_dd(int n, int k, const double* A, int range, const double* Xh, const double* Xl,
               double* oh, double* ol, hipStream_t s, double c = 0.0,
               const double* th = nullptr, const double* tl = nullptr) {
-  k_rows_k_dd<<<n, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol, c, th, tl);
+  if (k <= 2) k_rows_k_dd<2><<<n, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol, c, th, tl);
+  else if (k <= 4) k_rows_k_dd<4><<<n, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol, c, th, tl);
+  else if (k <= 8) k_rows_k_dd<8><<<n, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol, c, th, tl);
+  else k_rows_k_dd<16><<<n, kT, 0, s>>>(n, k, A, range, Xh, Xl, oh, ol, c, th, tl);
   return LRSDP_OK;
 }
 

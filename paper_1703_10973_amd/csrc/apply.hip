@@ -24,6 +24,65 @@ constexpr int kT = 256;
 // lane-to-entry map, then an xor-shuffle tree), so the summation order is fixed.
 constexpr int kRL = 16;
 
+// Reduce-scatter of K2 per-lane sums over groups of kRL lanes (K2 <= kRL, both powers of two):
+// at the exchange across lane bit o the lower lanes keep the first half of the sums they carry
+// and the upper lanes the second half, each adding its partner's copy, until every sub-group
+// of kRL / K2 lanes carries one sum (sum index = (lane % kRL) / (kRL / K2)); butterflies finish
+// the sub-groups.  Each sum pairs the same lanes in the same order as a butterfly of its own,
+// with K2 - 1 + log2(kRL / K2) additions instead of K2 log2(kRL).
+// one exchange level: H sums kept out of 2H, across lane bit O (compile-time, so every index
+// into the accumulators is a constant and they stay in registers)
+template <int H, int O, int K2>
+__device__ __forceinline__ void rs_level(double (&acc)[K2], int sub) {
+  if constexpr (H >= 1) {
+    const bool upper = (sub & O) != 0;
+#pragma unroll
+    for (int s = 0; s < H; ++s) {
+      const double send = upper ? acc[s] : acc[H + s];
+      const double keep = upper ? acc[H + s] : acc[s];
+      acc[s] = keep + __shfl_xor(send, O, kRL);
+    }
+    rs_level<H / 2, O / 2, K2>(acc, sub);
+  }
+}
+
+template <int H, int O, int K2>
+__device__ __forceinline__ void rs_level(dd (&acc)[K2], int sub) {
+  if constexpr (H >= 1) {
+    const bool upper = (sub & O) != 0;
+#pragma unroll
+    for (int s = 0; s < H; ++s) {
+      const double sh = upper ? acc[s].hi : acc[H + s].hi;
+      const double sl = upper ? acc[s].lo : acc[H + s].lo;
+      const dd keep = {upper ? acc[H + s].hi : acc[s].hi, upper ? acc[H + s].lo : acc[s].lo};
+      acc[s] = dd_add(keep, {__shfl_xor(sh, O, kRL), __shfl_xor(sl, O, kRL)});
+    }
+    rs_level<H / 2, O / 2, K2>(acc, sub);
+  }
+}
+
+template <int K2>
+__device__ __forceinline__ double group_reduce_scatter(double (&acc)[K2], int sub) {
+  static_assert((K2 & (K2 - 1)) == 0 && K2 <= kRL, "K2 a power of two, at most kRL");
+  rs_level<K2 / 2, kRL / 2, K2>(acc, sub);
+  double v = acc[0];
+#pragma unroll
+  for (int o = kRL / K2 / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kRL);
+  return v;
+}
+
+template <int K2>
+__device__ __forceinline__ dd group_reduce_scatter(dd (&acc)[K2], int sub) {
+  static_assert((K2 & (K2 - 1)) == 0 && K2 <= kRL, "K2 a power of two, at most kRL");
+  rs_level<K2 / 2, kRL / 2, K2>(acc, sub);
+  dd v = acc[0];
+#pragma unroll
+  for (int o = kRL / K2 / 2; o > 0; o >>= 1)
+    v = dd_add(v, {__shfl_xor(v.hi, o, kRL), __shfl_xor(v.lo, o, kRL)});
+  return v;
+}
+
+template <int K2>
 __global__ __launch_bounds__(kT) void k_spmm_U(int n, int k, const int32_t* __restrict__ rowptr,
                                                const int32_t* __restrict__ colidx,
                                                const int32_t* __restrict__ src,
@@ -35,9 +94,9 @@ __global__ __launch_bounds__(kT) void k_spmm_U(int n, int k, const int32_t* __re
   const int p = blockIdx.x * (kT / kRL) + threadIdx.x / kRL;
   const int sub = threadIdx.x & (kRL - 1);
   const bool live = p < n;
-  double acc[KMAX];
+  double acc[K2];
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+  for (int j = 0; j < K2; ++j) acc[j] = 0.0;
   if (live) {
     const int hi = rowptr[p + 1];
     for (int e = rowptr[p] + sub; e < hi; e += kRL) {
@@ -45,22 +104,17 @@ __global__ __launch_bounds__(kT) void k_spmm_U(int n, int k, const int32_t* __re
       const int i = src[e];
       const double mv = val[i] * (ginv ? v[i] * ginv[i] : v[i]);
 #pragma unroll
-      for (int j = 0; j < KMAX; ++j)
+      for (int j = 0; j < K2; ++j)
         if (j < k) acc[j] = fma(mv, U[(size_t)j * n + q], acc[j]);
     }
   }
-#pragma unroll
-  for (int j = 0; j < KMAX; ++j) {
-    if (j < k) {
-      double v = acc[j];
-#pragma unroll
-      for (int o = kRL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kRL);
-      if (live && sub == 0) out[(size_t)j * n + p] = v;
-    }
-  }
+  const double r = group_reduce_scatter<K2>(acc, sub);
+  const int j = sub / (kRL / K2);
+  if (live && sub % (kRL / K2) == 0 && j < k) out[(size_t)j * n + p] = r;
 }
 
 // double-double version: M_e = (vh_i + vl_i) * scale_i * val_i, each product in double-double
+template <int K2>
 __global__ __launch_bounds__(kT) void k_spmm_U_dd(int n, int k,
                                                   const int32_t* __restrict__ rowptr,
                                                   const int32_t* __restrict__ colidx,
@@ -75,9 +129,9 @@ __global__ __launch_bounds__(kT) void k_spmm_U_dd(int n, int k,
   const int p = blockIdx.x * (kT / kRL) + threadIdx.x / kRL;
   const int sub = threadIdx.x & (kRL - 1);
   const bool live = p < n;
-  dd acc[KMAX];
+  dd acc[K2];
 #pragma unroll
-  for (int j = 0; j < KMAX; ++j) acc[j] = {0.0, 0.0};
+  for (int j = 0; j < K2; ++j) acc[j] = {0.0, 0.0};
   if (live) {
     const int hi = rowptr[p + 1];
     for (int e = rowptr[p] + sub; e < hi; e += kRL) {
@@ -87,37 +141,44 @@ __global__ __launch_bounds__(kT) void k_spmm_U_dd(int n, int k,
       if (ginv) u = dd_mul_d(u, ginv[i]);
       u = dd_mul_d(u, val[i]);
 #pragma unroll
-      for (int j = 0; j < KMAX; ++j)
+      for (int j = 0; j < K2; ++j)
         if (j < k) acc[j] = dd_fma2(acc[j], U[(size_t)j * n + q], u.hi, u.lo);
     }
   }
-#pragma unroll
-  for (int j = 0; j < KMAX; ++j) {
-    if (j < k) {
-      dd v = acc[j];
-#pragma unroll
-      for (int o = kRL / 2; o > 0; o >>= 1)
-        v = dd_add(v, {__shfl_xor(v.hi, o, kRL), __shfl_xor(v.lo, o, kRL)});
-      if (live && sub == 0) {
-        oh[(size_t)j * n + p] = v.hi;
-        ol[(size_t)j * n + p] = v.lo;
-      }
-    }
+  const dd r = group_reduce_scatter<K2>(acc, sub);
+  const int j = sub / (kRL / K2);
+  if (live && sub % (kRL / K2) == 0 && j < k) {
+    oh[(size_t)j * n + p] = r.hi;
+    ol[(size_t)j * n + p] = r.lo;
   }
 }
 
 // out = M U with M = mat(A (ginv o v)) (ginv may be nullptr)
 int spmm_U(const lrsdp_problem* P, int k, const double* ginv, const double* v, const double* U,
            double* out, hipStream_t s) {
-  k_spmm_U<<<(P->n + kT / kRL - 1) / (kT / kRL), kT, 0, s>>>(P->n, k, P->rowptr, P->colidx,
-                                                              P->src, P->val, ginv, v, U, out);
+  const int grid = (P->n + kT / kRL - 1) / (kT / kRL);
+#define LRSDP_SPMM(K2_)                                                                    \
+  k_spmm_U<K2_><<<grid, kT, 0, s>>>(P->n, k, P->rowptr, P->colidx, P->src, P->val, ginv, v, U, \
+                                    out)
+  if (k <= 2) LRSDP_SPMM(2);
+  else if (k <= 4) LRSDP_SPMM(4);
+  else if (k <= 8) LRSDP_SPMM(8);
+  else LRSDP_SPMM(16);
+#undef LRSDP_SPMM
   return LRSDP_OK;
 }
 // (oh, ol) = M U in double-double, M = mat(A G^{-1} (vh + vl)) (ginv, vl may be nullptr)
 int spmm_U_dd(const lrsdp_problem* P, int k, const double* ginv, const double* vh,
               const double* vl, const double* U, double* oh, double* ol, hipStream_t s) {
-  k_spmm_U_dd<<<(P->n + kT / kRL - 1) / (kT / kRL), kT, 0, s>>>(
-      P->n, k, P->rowptr, P->colidx, P->src, P->val, ginv, vh, vl, U, oh, ol);
+  const int grid = (P->n + kT / kRL - 1) / (kT / kRL);
+#define LRSDP_SPMM_DD(K2_)                                                                   \
+  k_spmm_U_dd<K2_><<<grid, kT, 0, s>>>(P->n, k, P->rowptr, P->colidx, P->src, P->val, ginv, vh, \
+                                       vl, U, oh, ol)
+  if (k <= 2) LRSDP_SPMM_DD(2);
+  else if (k <= 4) LRSDP_SPMM_DD(4);
+  else if (k <= 8) LRSDP_SPMM_DD(8);
+  else LRSDP_SPMM_DD(16);
+#undef LRSDP_SPMM_DD
   return LRSDP_OK;
 }
 
@@ -376,14 +437,28 @@ __global__ __launch_bounds__(kT) void k_rows_kr(int n, int k, const double* __re
 #pragma unroll
         for (int j = 0; j < KC; ++j) acc[r][j] = fma(av[u][r], xv[u][j], acc[r][j]);
   }
+  // reduce-scatter over the S = R KC sums (slot r KC + j): at the exchange across lane bit o the
+  // lower lanes keep the first half of the slots they carry and the upper lanes the second half,
+  // each adding its partner's copy, until every group of 64 / S lanes carries one slot; plain
+  // butterflies finish the groups.  Each slot's sum pairs the same lanes in the same order as a
+  // butterfly of its own, with S - 1 + log2(64 / S) additions per wavefront instead of 6 R k.
+  constexpr int S = R * KC, G = kWave / S;
+  static_assert((S & (S - 1)) == 0 && S <= kWave, "R KC a power of two, at most 64");
+  double* sl = &acc[0][0];
 #pragma unroll
-  for (int r = 0; r < R; ++r)
+  for (int o = kWave / 2, h = S / 2; h >= 1; o >>= 1, h >>= 1) {
+    const bool upper = (lane & o) != 0;
 #pragma unroll
-    for (int j = 0; j < KC; ++j)
-      if (j < k) {
-        const double v = wave_sum(acc[r][j]);
-        if (lane == 0) red[wid][r * KC + j] = v;
-      }
+    for (int s = 0; s < h; ++s) {
+      const double send = upper ? sl[s] : sl[h + s];
+      const double keep = upper ? sl[h + s] : sl[s];
+      sl[s] = keep + __shfl_xor(send, o, kWave);
+    }
+  }
+  double v = sl[0];
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+  if (lane % G == 0) red[wid][lane / G] = v;
   __syncthreads();
   if (t < R * KC) {
     const int r = t / KC, j = t - r * KC, p = p0 + r;

@@ -171,6 +171,37 @@ def test_precond_matches_oracle(ctx, mu, rule):
     assert rel(zd, refine.dd_precond_apply(Fo, v)) <= 1e-7
 
 
+@pytest.mark.parametrize("k", [1, 3, 7, 12])
+def test_precond_all_widths_match_oracle(ctx, k):
+    """Every column-count width of the reduction kernels (k <= 2, 4, 8, 16), FP64 and
+    double-double, against the oracle's preconditioner (Section 3.2, eq SMW2)."""
+    inst = make_instance(60, k, 600, 1e-2, seed=40 + k)
+    P = problem_from(ctx, inst)
+    F = pk.Factor(P, to_dev(inst.W), k, pk.opts(tau_rule=RULES["min"]))
+    C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
+    Fo = alg1.factor(C, inst.W, k, tau_rule="min")
+    v = np.random.default_rng(3).standard_normal(inst.m)
+    zo = alg1.precond_apply(Fo, v)
+    z = host(F.precond_apply(to_dev(v)))
+    zd = host(F.precond_apply(to_dev(v), dd=True))
+    assert rel(z, zo) <= 1e-7
+    assert rel(zd, refine.dd_precond_apply(Fo, v)) <= 1e-7
+
+
+@pytest.mark.parametrize("k", [7, 12])
+def test_refined_solve_wide_k(ctx, k):
+    """The double-double refinement (every width of its double-double kernels) reaches the
+    target true residual (Algorithm 1 step 3)."""
+    inst = make_instance(60, k, 600, 1e-6, seed=50 + k)
+    P = problem_from(ctx, inst)
+    F = pk.Factor(P, to_dev(inst.W), k)
+    y, ylo, st, info = F.solve(to_dev(inst.r), pk.opts(dd_mode=pk.LRSDP_DD_ON))
+    assert st == 0, info
+    r_true, _ = ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val, inst.r, host(y),
+                                           host(ylo))
+    assert r_true <= 1e-8
+
+
 # ------------------------------------------------------------------ A7 split H v
 
 @pytest.mark.parametrize("mu", [1e-2, 1e-6])

@@ -69,15 +69,19 @@ def parse():
     return ap.parse_args()
 
 
-# kernel class (as profiled by the library) -> kernel names counted in it; a class launch is
-# one launch of the first name
+# kernel class (as profiled by the library) -> (kernel-name prefixes whose launches are class
+# launches, further prefixes whose bytes count in the class).  The method's GEMMs are the
+# instances with a transposed operand; the explicit-inverse products have none.
 TRAFFIC_CLASSES = {
-    "gemm": ("k_gemm",), "hv": ("k_hv_fused",), "gemv": ("k_gemv_tri",),
-    "resdd": ("k_residual_dd",), "bz": ("k_PJ", "k_dJL"), "leaf": ("k_chol_leaf",),
-    "tile": ("k_rl_fused", "k_rl_panel"),
+    "gemm": (("k_gemm<true", "k_gemm<false, true"), ()),
+    "gemm_inv": (("k_gemm<false, false",), ()),
+    "hv": (("k_hv_fused",), ("k_scatter",)), "gemv": (("k_gemv_tri",), ()),
+    "resdd": (("k_residual_dd",), ("k_scatter_dd",)), "bz": (("k_PJ",), ("k_dJL",)),
+    "leaf": (("k_chol_leaf",), ()), "tile": (("k_rl_fused", "k_rl_panel"), ()),
 }
-CLASS_SOURCE = {"gemm": "dense.hip", "hv": "hv.hip", "gemv": "dense.hip", "resdd": "hv.hip",
-                "bz": "factor.hip", "leaf": "dense.hip", "tile": "dense.hip"}
+CLASS_SOURCE = {"gemm": "dense.hip", "gemm_inv": "dense.hip", "hv": "hv.hip",
+                "gemv": "dense.hip", "resdd": "hv.hip", "bz": "factor.hip", "leaf": "dense.hip",
+                "tile": "dense.hip"}
 
 
 def summarize_traffic(dirs):
@@ -126,9 +130,12 @@ def summarize_traffic(dirs):
         print(f"{k[:40]:40s} {e['n']:8d} {e['f'] / 1e6:10.2f} {e['w'] / 1e6:10.2f} "
               f"{(e['f'] + e['w']) / 1e6 / max(e['n'], 1):10.3f}")
     classes = {}
-    for cls, names in TRAFFIC_CLASSES.items():
-        hit = [(k, e) for k, e in per.items() if any(k.startswith(nm) for nm in names)]
-        launches = sum(e["n"] for k, e in hit if k.startswith(names[0]))
+    def _m(k, nm):  # a kernel name, any of its template instances, or a template prefix
+        return k == nm or k.startswith(nm + "<") or ("<" in nm and k.startswith(nm))
+
+    for cls, (lnames, xnames) in TRAFFIC_CLASSES.items():
+        hit = [(k, e) for k, e in per.items() if any(_m(k, nm) for nm in lnames + xnames)]
+        launches = sum(e["n"] for k, e in hit if any(_m(k, nm) for nm in lnames))
         if not launches:
             continue
         src = os.path.join(ROOT, "paper_1703_10973_amd", "csrc", CLASS_SOURCE[cls])
@@ -245,7 +252,9 @@ def main():
     #      a further timed region of the same steps (mixed mode); kept apart from the region
     #      that gives `value` because the events add host work per launch
     hv_id = pk.LRSDP_K_NAMES.index("hv")
-    ctx.profile((1 << dom_id) | (1 << hv_id))
+    gm_id = pk.LRSDP_K_NAMES.index("gemm")
+    gi_id = pk.LRSDP_K_NAMES.index("gemm_inv")
+    ctx.profile((1 << dom_id) | (1 << hv_id) | (1 << gm_id) | (1 << gi_id))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -254,6 +263,7 @@ def main():
     prof_ms_per_step = (time.perf_counter() - t0) / args.steps * 1e3
     pstat = ctx.profile_read()
     dstat, hstat = pstat[dom], pstat["hv"]
+    nsolves_prof = args.steps * len(MUS)
     ctx.profile(0)
 
     # ---- accuracy of the returned answers (untimed): GPU double-double true residual
@@ -301,22 +311,26 @@ def main():
 
     mixed, fp64 = summ("mixed"), summ("fp64")
 
-    # ---- roofline of the dominant kernel class, from the events of the timed region
+    # ---- roofline of the dominant kernel class, from the events of the timed region.  The
+    #      flops are algorithmic: the method's own (bold S formation, the Cholesky's panel
+    #      solves and trailing updates, deflation), counted on structurally nonzero operand
+    #      entries; the products that form the explicit inverse L^{-1} are a class of their own
+    #      and are reported beside it, not counted.
+    def mfma_record(st, name):
+        n_l = max(st["launches"], 1)
+        a_ms = st["ms"] / n_l
+        ach = st["flops"] / n_l / (a_ms * 1e-3) / 1e12 if a_ms > 0 else 0.0
+        return dict(bound="mfma", achieved=ach, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
+                    frac=ach / (FP64_PEAK / 1e12), traffic=None, kernel=name,
+                    launches=st["launches"], avg_us=a_ms * 1e3,
+                    flops_per_launch=st["flops"] / n_l,
+                    flops_per_solve=st["flops"] / nsolves_prof,
+                    ms_per_solve=st["ms"] / nsolves_prof)
+
     avg_ms = dstat["ms"] / max(dstat["launches"], 1)
-    if dom in ("gemm", "tile"):
-        per = dstat["flops"] / max(dstat["launches"], 1)
-        achieved = per / (avg_ms * 1e-3) / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
-                    frac=achieved / (FP64_PEAK / 1e12), traffic=None, kernel=dom,
-                    launches=dstat["launches"], avg_us=avg_ms * 1e3,
-                    profiled_ms_per_step=prof_ms_per_step)
-    elif dom == "leaf":  # latency-bound FP64 vector arithmetic
-        per = dstat["flops"] / max(dstat["launches"], 1)
-        achieved = per / (avg_ms * 1e-3) / 1e12
-        roof = dict(bound="alu", achieved=achieved, peak=FP64_PEAK / 1e12, unit="TFLOP/s",
-                    frac=achieved / (FP64_PEAK / 1e12), traffic=None, kernel=dom,
-                    launches=dstat["launches"], avg_us=avg_ms * 1e3,
-                    profiled_ms_per_step=prof_ms_per_step)
+    if dom in ("gemm", "tile", "gemm_inv", "leaf"):
+        roof = mfma_record(dstat, dom)
+        roof["profiled_ms_per_step"] = prof_ms_per_step
     else:
         per = dstat["bytes"] / max(dstat["launches"], 1)
         achieved = per / (avg_ms * 1e-3) / 1e9
@@ -391,6 +405,10 @@ def main():
         "pcg_only_solves_per_s": {k: v for k, v in pcg_only.items()},
         "kernel_profile_ms": {k: round(v["ms"], 3) for k, v in prof.items()},
         "roofline": roof,
+        "gemm_method_roofline": mfma_record(pstat["gemm"], "gemm"),
+        "explicit_inverse_gemm": {k: v for k, v in mfma_record(pstat["gemm_inv"], "gemm_inv").items()
+                                  if k in ("launches", "avg_us", "flops_per_solve",
+                                           "ms_per_solve", "achieved")},
         "hv_roofline": hv_roof,
         "solve_roofline": solve_roof,
         "cpu_baseline": cpu,
@@ -637,36 +655,72 @@ def run_copy(args):
                       "launches": 5}))
 
 
-def cpu_baseline(insts, budget_s, answers=None):
-    """The oracle (Algorithm 1 in numpy FP64) on a bounded sample of the same workload; the
-    library's answers for those instances (mixed mode) are compared with the oracle's."""
-    from oracle import alg1
-    easy = [i for i in insts if i.mu >= 1e-4]
-    t0 = time.perf_counter()
-    solved = 0
-    err = {}
-    while True:
-        for inst in easy:
-            C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
-            F = alg1.factor(C, inst.W, inst.k)
-            out = alg1.solve(F, inst.r, eps=1e-8)
-            solved += 1
-            if answers and inst.mu in answers and f"{inst.mu:g}" not in err:
-                yh, yl = answers[inst.mu]
-                err[f"{inst.mu:g}"] = float(np.linalg.norm(yh + yl - out.y) / np.linalg.norm(out.y))
-        if time.perf_counter() - t0 > budget_s * 0.5 or solved >= 12:
-            break
-    el = time.perf_counter() - t0
+def _cpu_model():
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except ImportError:
-        cores = os.cpu_count()
-    return {"value": solved / el, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": f"{solved} FP64 Algorithm-1 solves (setup + PCG) of the n=1000 k=5 m=20000 "
-                      f"instance at mu=1e-2 and 1e-4 only (numpy/scipy, all host BLAS threads); "
-                      f"the mu<=1e-6 solves need the double-double oracle, minutes each",
-            "seconds": el, "gpu_rel_err_vs_oracle": err}
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_solve(inst):
+    """One oracle solve of an instance of the mu path: FP64 Algorithm 1 where FP64 represents
+    the answer (mu >= 1e-4), else the double-double refinement (mu <= 1e-6).  Returns the
+    answer as one FP64 vector and the wall time."""
+    from oracle import alg1, refine
+    t0 = time.perf_counter()
+    C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
+    F = alg1.factor(C, inst.W, inst.k, tau_rule="mean")
+    if inst.mu >= 1e-4:
+        y = alg1.solve(F, inst.r, eps=1e-8).y
+    else:
+        out = refine.refine(F, inst.r, eps=1e-8)
+        y = out.yh + out.yl
+    return y, time.perf_counter() - t0
+
+
+def cpu_baseline(insts, budget_s, answers=None):
+    """The oracle on the host CPU, on the same instances as one GPU step: one solve per mu of
+    the path (FP64 Algorithm 1 at 1e-2 and 1e-4, the double-double refinement at 1e-6 and
+    1e-8), with every host BLAS thread, and a one-thread leg on the FP64 solves.  Also the
+    oracle's double-double true residual of the GPU's answers and their distance from the
+    oracle's."""
+    from oracle import dd as ddo
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_info = threadpool_limits = None
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1]) \
+        if threadpool_info else os.cpu_count()
+    per_mu, err, gpu_relres = {}, {}, {}
+    total = 0.0
+    for inst in insts:
+        y, el = _oracle_solve(inst)
+        total += el
+        per_mu[f"{inst.mu:g}"] = round(el, 3)
+        if answers and inst.mu in answers:
+            yh, yl = answers[inst.mu]
+            err[f"{inst.mu:g}"] = float(np.linalg.norm(yh + yl - y) / np.linalg.norm(y))
+            if inst.mu <= 1e-6:
+                gpu_relres[f"{inst.mu:g}"] = ddo.true_relative_residual(
+                    inst.W, inst.a, inst.b, inst.val, inst.r, yh, yl)[0]
+    one = None
+    if threadpool_limits is not None:
+        easy = [i for i in insts if i.mu >= 1e-4]
+        with threadpool_limits(limits=1):
+            t1 = sum(_oracle_solve(i)[1] for i in easy)
+        one = {"value": len(easy) / t1, "unit": "solves/s", "cores": 1,
+               "sample": "the FP64 Algorithm-1 solves (mu = 1e-2, 1e-4) only", "seconds": t1}
+    return {"value": len(insts) / total, "unit": "solves/s", "cores": threads, "kind": "oracle",
+            "sample": f"one oracle solve (setup + PCG) per mu of the n=1000 k=5 m=20000 path: "
+                      f"numpy/scipy FP64 Algorithm 1 at mu=1e-2,1e-4, the double-double "
+                      f"refinement at mu=1e-6,1e-8; all host BLAS threads",
+            "seconds": total, "seconds_per_mu": per_mu, "cpu_model": _cpu_model(),
+            "os_cpu_count": os.cpu_count(), "blas_threads": threads, "one_thread": one,
+            "gpu_rel_err_vs_oracle": err, "gpu_true_relres_oracle_dd": gpu_relres}
 
 
 if __name__ == "__main__":

@@ -31,9 +31,18 @@
  *     of columns (W, Z, W0 are symmetric or lower triangular n x n).
  *   - Work is enqueued on the context's stream; every call that returns a status
  *     synchronizes that stream before returning, so outputs are ready on return.
+ *   - Input ordering: a call reads its device inputs when its work reaches the context's
+ *     stream.  A context created with stream == NULL runs on a stream of its own that is
+ *     blocking, i.e. ordered after all earlier work on the legacy default stream (stream 0),
+ *     so inputs written there (for example by torch on its default stream) need no extra
+ *     synchronization.  Inputs written on any other stream must be complete before the call,
+ *     or the context must be created on that stream.
  *   - Return value: LRSDP_OK (0), a positive warning, or a negative error.  After
  *     an error every handle stays valid and may be reused or destroyed.
  *   - A handle must not be used by two host threads at once.
+ *   - Handles may be destroyed in any order: destroying a context that still has live
+ *     problems, or a problem that still has live factors, only marks it, and it is released
+ *     together with its last child.  A marked handle must not be used again.
  */
 #ifndef LRSDP_H
 #define LRSDP_H
@@ -134,7 +143,7 @@ LRSDP_API const char* lrsdp_status_string(int status);
 
 /* ------------------------------------------------------------------ context */
 /* Creates a context on HIP device `device`.  `stream` is a hipStream_t to run on (NULL:
- * the library creates its own default-priority stream).  `hbm_budget_bytes` caps the
+ * the library creates its own default-priority blocking stream, see "Input ordering").  `hbm_budget_bytes` caps the
  * device memory all handles of this context may hold (0: no cap).  out: host. */
 LRSDP_API int lrsdp_ctx_create(int device, void* stream, size_t hbm_budget_bytes, lrsdp_ctx** out);
 LRSDP_API void lrsdp_ctx_destroy(lrsdp_ctx* ctx);
@@ -146,14 +155,19 @@ LRSDP_API int lrsdp_ctx_memory(const lrsdp_ctx* ctx, size_t* in_use, size_t* bud
  * class.  `enable` is a bit mask of classes (bit LRSDP_K_*; -1 all, 0 off); every call resets
  * the counters.  Used by benchmarks to compute roofline fractions. */
 #define LRSDP_K_HV      0   /* fused scatter -> SpMM -> sampled-gather H v kernel (A5/A7)     */
-#define LRSDP_K_GEMM    1   /* FP64 MFMA GEMM (bold S formation, Cholesky/inverse updates)    */
+#define LRSDP_K_GEMM    1   /* FP64 MFMA GEMM of the method: bold S formation, the Cholesky's */
+                            /* panel solves and trailing updates, deflation (flops counted    */
+                            /* on the structurally nonzero operand entries only)              */
 #define LRSDP_K_TRI     2   /* Householder tridiagonalization step (A1)                       */
 #define LRSDP_K_GEMV    3   /* bold S^{-1} w = L^{-T} (L^{-1} w), two triangular GEMVs (A6)    */
 #define LRSDP_K_BZ      4   /* sparse B_JL Z pass of bold S formation (A3)                    */
 #define LRSDP_K_RESDD   5   /* double-double residual r - H y (A8)                            */
 #define LRSDP_K_LEAF    6   /* 64 x 64 Cholesky and inverse of a diagonal block (A2/A4)       */
 #define LRSDP_K_TILE    7   /* 64 x 64 MFMA block steps of the right-looking factorization    */
-#define LRSDP_K_COUNT   8
+                            /* (flops: the Cholesky's own, not the L^{-1} products or the     */
+                            /* recomputed panel blocks the steps also execute)                */
+#define LRSDP_K_GEMMINV 8   /* FP64 MFMA GEMMs that form the explicit inverse factor L^{-1}   */
+#define LRSDP_K_COUNT   9
 LRSDP_API int lrsdp_ctx_profile(lrsdp_ctx* ctx, int enable);
 /* Time only one launch in `every` (>= 1) of each enabled class, so that a timed run is not
  * slowed by the events; counts restart.  Default 1. */
@@ -194,6 +208,8 @@ LRSDP_API int lrsdp_hessian_apply(lrsdp_problem* p, const double* W, const doubl
 LRSDP_API int lrsdp_factor_create(lrsdp_problem* p, const double* W, int32_t k, const lrsdp_opts* opts,
                         lrsdp_factor** out);
 LRSDP_API void lrsdp_factor_destroy(lrsdp_factor* f);
+/* Sizes of a factor: n, the problem's m, and k.  Every output is host and may be NULL. */
+LRSDP_API int lrsdp_factor_info(const lrsdp_factor* f, int64_t* n, int64_t* m, int32_t* k);
 
 /* Export of the setup results for parity checks.  Host outputs: tau, shift (the deflation
  * shift, 0 if none), lam[k + 1] = {tau, then the k largest eigenvalues ascending},

@@ -86,18 +86,11 @@ class SplitOperator:
     C: Constraints
     W0: np.ndarray         # FP64 (rounded once from double-double)
     U: np.ndarray
-    lowprec: str = "fp64"  # precision of the W0 M W0 part: fp64 | fp32
 
     def __call__(self, v):
         C, U, W0 = self.C, self.U, self.W0
-        if self.lowprec == "fp32":
-            M = C.mat(v).astype(np.float32)
-            T = (M @ W0.astype(np.float32)).astype(np.float32)
-            X = (W0.astype(np.float32) @ T).astype(np.float64)
-            h0 = C.At(X)
-        else:
-            T = C.mat(v) @ W0
-            h0 = C.At(W0 @ T)
+        T = C.mat(v) @ W0
+        h0 = C.At(W0 @ T)
         rows, cols, h, l = _sym_entries(C, v, np.zeros_like(v))
         Ph, Pl = dd_spmm(C.n, rows, cols, h, l, U)
         Q = W0 @ Ph
@@ -183,12 +176,12 @@ class RefineResult:
 
 
 def refine(F: Factor, r, eps=1e-8, inner_eps=1e-3, max_outer=12, max_inner=200,
-           dd_precond=None, lowprec="fp64"):
+           dd_precond=None):
     """Outer iterative refinement y <- y + PCG(H_split, r - H y) with y a double-double
     pair and r - H y evaluated in double-double from the plain definition of H."""
     C = F.C
     W0 = dd_W0(F.W, F.split.U)
-    Hs = SplitOperator(C, W0, F.split.U, lowprec=lowprec)
+    Hs = SplitOperator(C, W0, F.split.U)
     if dd_precond is None:
         dd_precond = F.tau < 1e-7 * float(F.split.lam[-1])
     Pinv = (lambda v: dd_precond_apply(F, v)) if dd_precond else None

@@ -10,6 +10,7 @@ Context / Problem / Factor wrap the handles.
 
 from __future__ import annotations
 
+import atexit
 import weakref
 
 import torch
@@ -21,7 +22,7 @@ from ._lib import (  # noqa: F401
     LRSDP_PREC_FP64, LrsdpError, header_symbols, lib, lrsdp_ctx_create, lrsdp_ctx_destroy,
     lrsdp_ctx_memory, lrsdp_ctx_profile, lrsdp_ctx_profile_read, lrsdp_ctx_profile_sample,
     LRSDP_K_NAMES,
-    lrsdp_factor_create, lrsdp_factor_destroy, lrsdp_factor_export,
+    lrsdp_factor_create, lrsdp_factor_destroy, lrsdp_factor_export, lrsdp_factor_info,
     lrsdp_hessian_apply, lrsdp_hessian_apply_split, lrsdp_info, lrsdp_opts,
     lrsdp_opts_default, lrsdp_precond_apply, lrsdp_problem_create, lrsdp_problem_destroy,
     lrsdp_problem_info, lrsdp_residual_dd, lrsdp_solve, status_string, lrsdp_instance,
@@ -40,15 +41,38 @@ def opts(**kw):
     return o
 
 
+# Live contexts, closed (children first) by an exit hook while the interpreter and the HIP
+# runtime are still whole, rather than by finalizers late in interpreter shutdown.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for c in list(_LIVE):
+        try:
+            c.close()
+        except Exception:
+            pass
+
+
 class Context:
-    """A device, stream and HBM budget.  Closing it first closes every problem and factor
-    created under it (the C ABI requires children to be destroyed before their parent)."""
+    """A device, stream and HBM budget.  Closing it first closes every problem, factor and
+    server created under it that is still alive.  The library defers releasing a parent
+    handle destroyed before its children until the last child is destroyed, so the order in
+    which garbage collection finalizes these objects does not matter."""
 
     def __init__(self, device=0, stream=None, hbm_budget_bytes=0):
+        """stream: a hipStream_t handle to run on.  None: torch's current stream on `device`
+        when that is a stream of its own; when it is the default stream, the library's own
+        blocking stream, which is ordered after work on the default stream.  Either way the
+        library reads tensors that torch wrote before the call in order."""
         self.device = device
         self.handle = None
         self._children = weakref.WeakSet()
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream or None
         self.handle = lrsdp_ctx_create(device, stream, hbm_budget_bytes)
+        _LIVE.add(self)
 
     def memory(self):
         return lrsdp_ctx_memory(self.handle)
@@ -67,6 +91,7 @@ class Context:
                 ch.close()
             lrsdp_ctx_destroy(self.handle)
             self.handle = None
+        _LIVE.discard(self)
 
     def __del__(self):
         try:
@@ -100,6 +125,7 @@ class Problem:
                 ch.close()
             lrsdp_problem_destroy(self.handle)
             self.handle = None
+        self.ctx._children.discard(self)
 
     def __del__(self):
         try:
@@ -132,9 +158,11 @@ class Factor:
         lrsdp_hessian_apply_split(self.handle, v, out, precision)
         return out
 
-    def precond_apply(self, v, dd=False, out=None):
+    def precond_apply(self, v, dd=False, out=None, mode=None):
+        """z = H~^{-1} v.  mode 0: FP64; 1: double-double w and t; 2: FP64 with one
+        refinement step of t (default: 1 if dd else 0)."""
         out = torch.empty_like(v) if out is None else out
-        lrsdp_precond_apply(self.handle, v, out, 1 if dd else 0)
+        lrsdp_precond_apply(self.handle, v, out, (1 if dd else 0) if mode is None else int(mode))
         return out
 
     def residual_dd(self, r, y, y_lo=None):
@@ -150,6 +178,7 @@ class Factor:
         if self.handle:
             lrsdp_factor_destroy(self.handle)
             self.handle = None
+        self.problem._children.discard(self)
 
     def __del__(self):
         try:
@@ -189,6 +218,7 @@ class Server:
             lrsdp_server_destroy(self.handle)
             self.handle = None
             self._keep.clear()
+        self.ctx._children.discard(self)
 
     def __del__(self):
         try:

@@ -88,6 +88,8 @@ _SIGS = {
     "lrsdp_hessian_apply": (C.c_int, [_P, _P, _P, _P]),
     "lrsdp_factor_create": (C.c_int, [_P, _P, C.c_int32, C.POINTER(lrsdp_opts), C.POINTER(_P)]),
     "lrsdp_factor_destroy": (None, [_P]),
+    "lrsdp_factor_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_int32)]),
     "lrsdp_factor_export": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                       C.POINTER(C.c_double), C.POINTER(C.c_double), _P, _P, _P,
                                       _P]),
@@ -153,14 +155,16 @@ def status_string(s):
 def _ptr(t, dtype=None, numel=None, name="array"):
     if t is None:
         return None
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
     if dtype is not None and t.dtype != dtype:
         raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
-    if numel is not None and t.numel() != numel:
-        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
     return C.c_void_p(t.data_ptr())
 
 
@@ -196,7 +200,7 @@ def lrsdp_ctx_memory(ctx):
     return a.value, b.value
 
 
-LRSDP_K_NAMES = ["hv", "gemm", "tri", "gemv", "bz", "resdd", "leaf", "tile"]
+LRSDP_K_NAMES = ["hv", "gemm", "tri", "gemv", "bz", "resdd", "leaf", "tile", "gemm_inv"]
 
 
 def lrsdp_ctx_profile(ctx, enable):
@@ -236,18 +240,27 @@ def lrsdp_problem_info(p):
 
 
 def lrsdp_hessian_apply(p, W, v, Hv):
-    _ok(lib().lrsdp_hessian_apply(p, _ptr(W, torch.float64, name="W"),
-                                  _ptr(v, torch.float64, name="v"),
-                                  _ptr(Hv, torch.float64, v.numel(), "Hv")),
+    n, m, _ = lrsdp_problem_info(p)
+    _ok(lib().lrsdp_hessian_apply(p, _ptr(W, torch.float64, n * n, "W"),
+                                  _ptr(v, torch.float64, m, "v"),
+                                  _ptr(Hv, torch.float64, m, "Hv")),
         "lrsdp_hessian_apply")
 
 
 def lrsdp_factor_create(p, W, k, opts=None):
+    n, _, _ = lrsdp_problem_info(p)
     out = C.c_void_p()
-    st = lib().lrsdp_factor_create(p, _ptr(W, torch.float64, name="W"), int(k),
+    st = lib().lrsdp_factor_create(p, _ptr(W, torch.float64, n * n, "W"), int(k),
                                    C.byref(opts) if opts is not None else None, C.byref(out))
     _ok(st, "lrsdp_factor_create")
     return out
+
+
+def lrsdp_factor_info(f):
+    """(n, m, k) of a factor."""
+    n, m, k = C.c_int64(), C.c_int64(), C.c_int32()
+    _ok(lib().lrsdp_factor_info(f, C.byref(n), C.byref(m), C.byref(k)), "lrsdp_factor_info")
+    return n.value, m.value, k.value
 
 
 def lrsdp_factor_destroy(f):
@@ -255,44 +268,51 @@ def lrsdp_factor_destroy(f):
 
 
 def lrsdp_factor_export(f, k, U=None, W0=None, Z=None, Sinv=None):
+    n, _, fk = lrsdp_factor_info(f)
+    if int(k) != fk:
+        raise ValueError(f"k = {k} does not match the factor's k = {fk}")
     tau, shift, ms = C.c_double(), C.c_double(), C.c_double()
     lam = (C.c_double * (k + 1))()
     st = lib().lrsdp_factor_export(f, C.byref(tau), C.byref(shift), lam, C.byref(ms),
-                                   _ptr(U, torch.float64, name="U"),
-                                   _ptr(W0, torch.float64, name="W0"),
-                                   _ptr(Z, torch.float64, name="Z"),
-                                   _ptr(Sinv, torch.float64, name="Sinv"))
+                                   _ptr(U, torch.float64, n * k, "U"),
+                                   _ptr(W0, torch.float64, n * n, "W0"),
+                                   _ptr(Z, torch.float64, n * n, "Z"),
+                                   _ptr(Sinv, torch.float64, (n * k) ** 2, "Sinv"))
     _ok(st, "lrsdp_factor_export")
     return dict(tau=tau.value, shift=shift.value, lam=list(lam), setup_ms=ms.value)
 
 
 def lrsdp_hessian_apply_split(f, v, Hv, precision):
-    _ok(lib().lrsdp_hessian_apply_split(f, _ptr(v, torch.float64, name="v"),
-                                        _ptr(Hv, torch.float64, v.numel(), "Hv"),
+    m = lrsdp_factor_info(f)[1]
+    _ok(lib().lrsdp_hessian_apply_split(f, _ptr(v, torch.float64, m, "v"),
+                                        _ptr(Hv, torch.float64, m, "Hv"),
                                         int(precision)), "lrsdp_hessian_apply_split")
 
 
 def lrsdp_precond_apply(f, v, z, dd=0):
-    _ok(lib().lrsdp_precond_apply(f, _ptr(v, torch.float64, name="v"),
-                                  _ptr(z, torch.float64, v.numel(), "z"), int(dd)),
+    m = lrsdp_factor_info(f)[1]
+    _ok(lib().lrsdp_precond_apply(f, _ptr(v, torch.float64, m, "v"),
+                                  _ptr(z, torch.float64, m, "z"), int(dd)),
         "lrsdp_precond_apply")
 
 
 def lrsdp_residual_dd(f, r, y, y_lo=None, res=None):
+    m = lrsdp_factor_info(f)[1]
     rel = C.c_double()
-    _ok(lib().lrsdp_residual_dd(f, _ptr(r, torch.float64, name="r"),
-                                _ptr(y, torch.float64, r.numel(), "y"),
-                                _ptr(y_lo, torch.float64, r.numel(), "y_lo"),
-                                _ptr(res, torch.float64, r.numel(), "res"), C.byref(rel)),
+    _ok(lib().lrsdp_residual_dd(f, _ptr(r, torch.float64, m, "r"),
+                                _ptr(y, torch.float64, m, "y"),
+                                _ptr(y_lo, torch.float64, m, "y_lo"),
+                                _ptr(res, torch.float64, m, "res"), C.byref(rel)),
         "lrsdp_residual_dd")
     return rel.value
 
 
 def lrsdp_solve(f, r, y, y_lo=None, opts=None):
+    m = lrsdp_factor_info(f)[1]
     info = lrsdp_info()
-    st = lib().lrsdp_solve(f, _ptr(r, torch.float64, name="r"),
-                           _ptr(y, torch.float64, r.numel(), "y"),
-                           _ptr(y_lo, torch.float64, r.numel(), "y_lo"),
+    st = lib().lrsdp_solve(f, _ptr(r, torch.float64, m, "r"),
+                           _ptr(y, torch.float64, m, "y"),
+                           _ptr(y_lo, torch.float64, m, "y_lo"),
                            C.byref(opts) if opts is not None else None, C.byref(info))
     if st < 0 and st != LRSDP_ERR_STAGNATED:
         raise LrsdpError(st, "lrsdp_solve")

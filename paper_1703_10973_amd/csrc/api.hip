@@ -190,7 +190,15 @@ const char* lrsdp_status_string(int s) {
   }
 }
 
-int lrsdp_ctx_create(int device, void* stream, size_t budget, lrsdp_ctx** out) {
+}  // extern "C"
+
+namespace lrsdp {
+
+// A context on `device`.  With stream == NULL the context makes its own stream: blocking
+// (ordered after work on the legacy default stream, where callers such as torch produce their
+// inputs) for the public entry point, non-blocking for the server's workers, whose requests
+// are complete before submission and which must not serialize with each other through it.
+int ctx_create(int device, void* stream, size_t budget, bool blocking, lrsdp_ctx** out) {
   if (!out) return LRSDP_ERR_INVALID_ARG;
   *out = nullptr;
   int ndev = 0;
@@ -204,7 +212,8 @@ int lrsdp_ctx_create(int device, void* stream, size_t budget, lrsdp_ctx** out) {
   if (stream) {
     c->stream = static_cast<hipStream_t>(stream);
   } else {
-    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipStreamCreateWithFlags(&c->stream, blocking ? hipStreamDefault : hipStreamNonBlocking) !=
+        hipSuccess) {
       delete c;
       return LRSDP_ERR_DEVICE;
     }
@@ -229,8 +238,19 @@ int lrsdp_ctx_create(int device, void* stream, size_t budget, lrsdp_ctx** out) {
   return LRSDP_OK;
 }
 
-void lrsdp_ctx_destroy(lrsdp_ctx* c) {
-  if (!c) return;
+}  // namespace lrsdp
+
+extern "C" {
+
+int lrsdp_ctx_create(int device, void* stream, size_t budget, lrsdp_ctx** out) {
+  return ctx_create(device, stream, budget, true, out);
+}
+
+}  // extern "C"
+
+namespace {
+
+void ctx_release(lrsdp_ctx* c) {
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
   prof_flush(&c->prof);
@@ -248,6 +268,50 @@ void lrsdp_ctx_destroy(lrsdp_ctx* c) {
   if (c->d_flag) (void)hipFree(c->d_flag);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
+}
+
+// Releases a problem's device memory and the handle; then its context, if that was destroyed
+// while this was its last live problem.
+void problem_release(lrsdp_problem* p) {
+  lrsdp_ctx* c = p->ctx;
+  {
+    DeviceGuard g(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    const size_t m = p->m, n = p->n, nnz = p->nnz;
+    dev_free(c, p->a, m * 4);
+    dev_free(c, p->b, m * 4);
+    dev_free(c, p->val, m * 8);
+    dev_free(c, p->coef, m * 8);
+    dev_free(c, p->ginv, m * 8);
+    dev_free(c, p->rowptr, (n + 1) * 4);
+    dev_free(c, p->own_ptr, (n + 1) * 4);
+    dev_free(c, p->own_con, m * 4);
+    dev_free(c, p->own_oth, m * 4);
+    dev_free(c, p->pat, 2 * m * 4);
+    dev_free(c, p->colidx, nnz * 4);
+    dev_free(c, p->src, nnz * 4);
+    dev_free(c, p->mval, nnz * 8);
+    dev_free(c, p->vec_scratch, 4 * m * 8);
+    dev_free(c, p->tscr, 2 * n * n * 8);
+  }
+  delete p;
+  if (--c->children == 0 && c->closing) ctx_release(c);
+}
+
+}  // namespace
+
+extern "C" {
+
+// Destroying a handle that still has live children (problems of a context, factors of a
+// problem) only marks it: it is released together with its last child, so handles may be
+// destroyed in any order (for example by a garbage collector).
+void lrsdp_ctx_destroy(lrsdp_ctx* c) {
+  if (!c) return;
+  if (c->children > 0) {
+    c->closing = true;
+    return;
+  }
+  ctx_release(c);
 }
 
 int lrsdp_ctx_profile(lrsdp_ctx* c, int enable) {
@@ -289,26 +353,11 @@ int lrsdp_ctx_memory(const lrsdp_ctx* c, size_t* in_use, size_t* budget) {
 
 void lrsdp_problem_destroy(lrsdp_problem* p) {
   if (!p) return;
-  lrsdp_ctx* c = p->ctx;
-  DeviceGuard g(c->device);
-  (void)hipStreamSynchronize(c->stream);
-  const size_t m = p->m, n = p->n, nnz = p->nnz;
-  dev_free(c, p->a, m * 4);
-  dev_free(c, p->b, m * 4);
-  dev_free(c, p->val, m * 8);
-  dev_free(c, p->coef, m * 8);
-  dev_free(c, p->ginv, m * 8);
-  dev_free(c, p->rowptr, (n + 1) * 4);
-  dev_free(c, p->own_ptr, (n + 1) * 4);
-  dev_free(c, p->own_con, m * 4);
-  dev_free(c, p->own_oth, m * 4);
-  dev_free(c, p->pat, 2 * m * 4);
-  dev_free(c, p->colidx, nnz * 4);
-  dev_free(c, p->src, nnz * 4);
-  dev_free(c, p->mval, nnz * 8);
-  dev_free(c, p->vec_scratch, 4 * m * 8);
-  dev_free(c, p->tscr, 2 * n * n * 8);
-  delete p;
+  if (p->children > 0) {
+    p->closing = true;
+    return;
+  }
+  problem_release(p);
 }
 
 int lrsdp_problem_create(lrsdp_ctx* c, int64_t n, int64_t m, int64_t nnz, const int32_t* con,
@@ -326,6 +375,7 @@ int lrsdp_problem_create(lrsdp_ctx* c, int64_t n, int64_t m, int64_t nnz, const 
   p->ctx = c;
   p->n = (int)n;
   p->m = (int)m;
+  ++c->children;  // released (and counted down) by problem_release, also on failure
   int rc = LRSDP_OK;
   do {
     if ((rc = dev_alloc_n(c, &p->a, (size_t)m))) break;
@@ -344,7 +394,7 @@ int lrsdp_problem_create(lrsdp_ctx* c, int64_t n, int64_t m, int64_t nnz, const 
     rc = ingest(c, p, con, row, col, val, nnz);
   } while (0);
   if (rc != LRSDP_OK) {
-    lrsdp_problem_destroy(p);
+    problem_release(p);
     return rc;
   }
   p->bytes = c->in_use;
@@ -389,20 +439,34 @@ int lrsdp_factor_create(lrsdp_problem* p, const double* W, int32_t k, const lrsd
   int rc = factor_setup(f, W, o);
   if (rc != LRSDP_OK) {
     (void)hipStreamSynchronize(p->ctx->stream);
+    if (p->ctx->side) (void)hipStreamSynchronize(p->ctx->side);
     factor_release(f);
     delete f;
     return rc;
   }
+  ++p->children;
   *out = f;
+  return LRSDP_OK;
+}
+
+int lrsdp_factor_info(const lrsdp_factor* f, int64_t* n, int64_t* m, int32_t* k) {
+  if (!f) return LRSDP_ERR_INVALID_ARG;
+  if (n) *n = f->n;
+  if (m) *m = f->P->m;
+  if (k) *k = f->k;
   return LRSDP_OK;
 }
 
 void lrsdp_factor_destroy(lrsdp_factor* f) {
   if (!f) return;
-  DeviceGuard g(f->P->ctx->device);
-  (void)hipStreamSynchronize(f->P->ctx->stream);
-  factor_release(f);
+  lrsdp_problem* p = f->P;
+  {
+    DeviceGuard g(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
+    factor_release(f);
+  }
   delete f;
+  if (--p->children == 0 && p->closing) problem_release(p);
 }
 
 int lrsdp_factor_export(const lrsdp_factor* f, double* tau, double* shift, double* lam,

@@ -7,15 +7,18 @@
 
 namespace lrsdp {
 
-// Triangular-structure hints: K-range trimming per output tile (tile granularity 64), so a
-// product with a triangular operand skips its zero tiles.  Within a 64-aligned diagonal tile
-// the stored zeros are read, so triangular operands must hold explicit zeros there.
+// Triangular-structure hints: K-range trimming per output tile, so a product with a
+// triangular operand skips its zero tiles; inside the tiles it does compute, the entries a
+// flag declares zero are never read (they are staged as zeros), so the other triangle of a
+// triangular operand may hold anything.
 enum GemmFlags : unsigned {
   kKFromRow = 1u,   // op(A)[i][k] == 0 for k < i   -> k starts at the tile's first row
   kKToRow = 2u,     // op(A)[i][k] == 0 for k > i   -> k ends after the tile's last row
   kKFromCol = 4u,   // op(B)[k][j] == 0 for k < j
   kKToCol = 8u,     // op(B)[k][j] == 0 for k > j
   kLowerOut = 16u,  // compute / write only C[i][j] with j <= i
+  kInverseOnly = 32u,  // accounting only: a product of the explicit inverse factor L^{-1},
+                       // not of the factorization itself (timed as its own kernel class)
 };
 
 struct GemmArgs {

@@ -6,7 +6,8 @@
 // Operand fragments follow the MFMA register layout: lane l holds A[l % 16][l / 16] and
 // B[l / 16][l % 16]; the 16 x 16 result lives as D[l / 16 + 4 r][l % 16], r = 0..3
 // (rows interleaved across the four result registers).
-// Triangular operands skip whole zero tiles through per-tile K ranges (GemmFlags).
+// Triangular operands skip whole zero tiles through per-tile K ranges (GemmFlags), and the
+// entries the flags declare zero inside the remaining tiles are staged as zeros unread.
 //
 // The Cholesky factor and its inverse come out of one recursion (split at a multiple of 64):
 // [L11 0; L21 L22] with L21 = A21 L11^{-T}, L22 from A22 - L21 L21^T, and
@@ -81,30 +82,41 @@ __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
   const int wm = wmn / WN, wn = wmn % WN;
   const int lr = lane & 15, lk = lane >> 4;
 
-  // staging map: consecutive threads walk the contiguous dimension of each operand
+  // staging map: consecutive threads walk the contiguous dimension of each operand.  Entries
+  // a flag declares zero are staged as zeros without being read, so a triangular operand's
+  // other triangle may hold anything (a tile's K range follows its own edges, and a 128-wide
+  // diagonal tile would otherwise read the block beside a 64-aligned diagonal block).
+  const bool a_from = (g.flags & kKFromRow) != 0, a_to = (g.flags & kKToRow) != 0;
+  const bool b_from = (g.flags & kKFromCol) != 0, b_to = (g.flags & kKToCol) != 0;
   double ra[EA], rb[EB];
   auto load = [&](int k0) {
 #pragma unroll
     for (int u = 0; u < EA; ++u) {
       const int e = t + u * NT;
+      int i, k;
       if (!TA) {
-        const int r = e / TKc, kk = e % TKc, i = i0 + r, k = k0 + kk;
-        ra[u] = (i < g.M && k < khi) ? Ap[(size_t)i * g.lda + k] : 0.0;
+        i = i0 + e / TKc;
+        k = k0 + e % TKc;
       } else {
-        const int kk = e / TMv, r = e % TMv, i = i0 + r, k = k0 + kk;
-        ra[u] = (i < g.M && k < khi) ? Ap[(size_t)k * g.lda + i] : 0.0;
+        i = i0 + e % TMv;
+        k = k0 + e / TMv;
       }
+      const bool nz = i < g.M && k < khi && !(a_from && k < i) && !(a_to && k > i);
+      ra[u] = nz ? (TA ? Ap[(size_t)k * g.lda + i] : Ap[(size_t)i * g.lda + k]) : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < EB; ++u) {
       const int e = t + u * NT;
+      int j, k;
       if (!TB) {
-        const int kk = e / TNv, c = e % TNv, j = j0 + c, k = k0 + kk;
-        rb[u] = (j < g.N && k < khi) ? Bp[(size_t)k * g.ldb + j] : 0.0;
+        j = j0 + e % TNv;
+        k = k0 + e / TNv;
       } else {
-        const int c = e / TKc, kk = e % TKc, j = j0 + c, k = k0 + kk;
-        rb[u] = (j < g.N && k < khi) ? Bp[(size_t)j * g.ldb + k] : 0.0;
+        j = j0 + e / TKc;
+        k = k0 + e % TKc;
       }
+      const bool nz = j < g.N && k < khi && !(b_from && k < j) && !(b_to && k > j);
+      rb[u] = nz ? (TB ? Bp[(size_t)j * g.ldb + k] : Bp[(size_t)k * g.ldb + j]) : 0.0;
     }
   };
   auto store = [&](int buf) {
@@ -896,6 +908,38 @@ static void gemm_cost(const GemmArgs& g, int te, double* flops, double* bytes) {
                   (double)g.M * g.N * (g.beta != 0.0 ? 2.0 : 1.0));
 }
 
+// Algorithmic flops of one GEMM call: 2 x the multiply-adds on the structurally nonzero
+// operand entries (the triangular zeros the flags declare, entry by entry rather than by tile)
+// of the output entries computed (the lower triangle with kLowerOut).  For output row i the
+// K range is [a, b) with a = i (kKFromRow) and b = i + 1 (kKToRow); column j narrows it to
+// [max(a, j), .) (kKFromCol) or (., min(b, j + 1)) (kKToCol).  Summed in closed form per row.
+static double gemm_alg_flops(const GemmArgs& g) {
+  const bool fc = (g.flags & kKFromCol) != 0, tc = (g.flags & kKToCol) != 0;
+  double f = 0.0;
+  for (int i = 0; i < g.M; ++i) {
+    const double a = (g.flags & kKFromRow) ? i : 0;
+    const double b = (g.flags & kKToRow) ? std::min(g.K, i + 1) : g.K;
+    const double J = (g.flags & kLowerOut) ? std::min(g.N, i + 1) : g.N;
+    if (b <= a) continue;
+    double s = 0.0;
+    if (!fc && !tc) {
+      s = J * (b - a);
+    } else if (fc && !tc) {  // sum_j (b - max(a, j))+
+      s = std::min(J, a) * (b - a);
+      const double j1 = std::min(J, b);
+      if (j1 > a) s += (j1 - a) * b - (a + j1 - 1.0) * (j1 - a) / 2.0;
+    } else if (!fc && tc) {  // sum_j (min(b, j + 1) - a)+
+      const double j1 = std::min(J, b);
+      if (j1 > a) s += (j1 - a) * (j1 - a + 1.0) / 2.0;
+      if (J > b) s += (J - b) * (b - a);
+    } else {  // both: one term for each j in [a, b)
+      s = std::max(0.0, std::min(J, b) - a);
+    }
+    f += s;
+  }
+  return 2.0 * f;
+}
+
 template <int WM, int WN, int KS, int FM = 2, int FN = 2>
 static void launch_gemm(const GemmArgs& g, hipStream_t s) {
   constexpr int te_m = 16 * FM * WM, te_n = 16 * FN * WN;
@@ -925,16 +969,16 @@ int gemm(const GemmArgs& g, hipStream_t s) {
   const bool tri = (g.flags & (kKFromRow | kKToRow | kKFromCol | kKToCol)) != 0;
   const bool big = t64 >= 8192 || (!tri && t64 >= 1024);
   const int te = big ? 128 : t64 >= 320 ? 64 : 32;
-  ProfMark pm = prof_begin(LRSDP_K_GEMM, s);
+  ProfMark pm = prof_begin((g.flags & kInverseOnly) ? LRSDP_K_GEMMINV : LRSDP_K_GEMM, s);
   if (big) launch_gemm<2, 4, 1, 4, 2>(g, s);
   else if (t64 >= 320) launch_gemm<2, 2, 2>(g, s);
   else launch_gemm<1, 1, 4>(g, s);
   LRSDP_HIP(hipGetLastError());
-  if (pm.kid >= 0) {
+  if (pm.kid >= 0) {  // compulsory bytes, algorithmic flops
     double fl = 0.0, by = 0.0;
     gemm_cost(g, te, &fl, &by);
     const double nb = g.offs ? g.batch : 1;
-    prof_end(pm, s, by * nb, fl * nb);
+    prof_end(pm, s, by * nb, gemm_alg_flops(g) * nb);
   }
   return LRSDP_OK;
 }
@@ -958,17 +1002,24 @@ constexpr int kSideMin = 512;
 // L^{-1} into Li's), 64-block columns in order.  (Splitting off the trailing tiles that the
 // next column waits for, onto a second stream, measured slower: the cross-stream waits
 // cost more than the overlap gains at this size.)
+// Profiled flops of the right-looking steps are the Cholesky's own (the method's): at block
+// column j with r block rows below it, the panel solve L_ij = A_ij L_jj^{-T} (NB^3 per block)
+// and the trailing update of the r (r + 1) / 2 lower blocks (2 NB^3 each, NB^3 on the
+// diagonal), r^2 NB^3 + r NB^3 in all, plus the next diagonal block's Cholesky NB^3 / 3;
+// summed over the node this is N^3 / 3.  The L^{-1} products and the recomputed panel blocks
+// the steps also execute are not counted.
 static int rl_factor(double* A, int N, int lda, double* Li, int ldi, int* flag, hipStream_t s) {
   const int nb = (N + NB - 1) / NB;
-  const double tile_flops = 2.0 * NB * NB * NB, tile_bytes = 4.0 * NB * NB * 8;
-  const double leaf_flops = 2.0 * NB * NB * NB / 3.0, leaf_bytes = 3.0 * 8 * NB * NB;
+  const double nb3 = (double)NB * NB * NB;
+  const double tile_bytes = 4.0 * NB * NB * 8;
+  const double leaf_flops = nb3 / 3.0, leaf_bytes = 3.0 * 8 * NB * NB;
   {  // the first block column's leaf; every later one runs inside the previous step
     const int n0 = std::min(NB, N);
     ProfMark pm = prof_begin(LRSDP_K_LEAF, s);
     k_chol_leaf<<<1, NB * LW, 0, s>>>(A, n0, lda, flag, Li, ldi, n0);
     LRSDP_HIP(hipGetLastError());
-    // Cholesky n0^3 / 3 and triangular inverse n0^3 / 3 flops; A read, L and L^{-1} written
-    prof_end(pm, s, 3.0 * 8 * n0 * n0, 2.0 * n0 * n0 * n0 / 3.0);
+    // Cholesky n0^3 / 3 flops; A read, L and L^{-1} written
+    prof_end(pm, s, 3.0 * 8 * n0 * n0, (double)n0 * n0 * n0 / 3.0);
   }
   for (int j = 0; j + 1 < nb; ++j) {
     const int r = nb - 1 - j;
@@ -978,7 +1029,8 @@ static int rl_factor(double* A, int N, int lda, double* Li, int ldi, int* flag, 
     ProfMark pm = prof_begin(LRSDP_K_TILE, s);
     k_rl_fused<<<ta + ty + tp, 512, 0, s>>>(A, lda, Li, ldi, N, j, flag);
     LRSDP_HIP(hipGetLastError());
-    prof_end(pm, s, products * tile_bytes + leaf_bytes, products * tile_flops + leaf_flops);
+    prof_end(pm, s, products * tile_bytes + leaf_bytes,
+             ((double)r * r + r) * nb3 + leaf_flops);
   }
   for (int j = std::max(0, nb - 2); j < nb; ++j) {  // the last two panels
     const int tiles = (nb - 1 - j) + j;
@@ -986,7 +1038,8 @@ static int rl_factor(double* A, int N, int lda, double* Li, int ldi, int* flag, 
     ProfMark pm = prof_begin(LRSDP_K_TILE, s);
     k_rl_panel<<<tiles, 512, 0, s>>>(A, lda, Li, ldi, N, j);
     LRSDP_HIP(hipGetLastError());
-    prof_end(pm, s, tiles * tile_bytes, tiles * tile_flops);
+    // the panel stores of the last two block columns: no Cholesky flops left
+    prof_end(pm, s, tiles * tile_bytes, 0.0);
   }
   return LRSDP_OK;
 }
@@ -1028,7 +1081,7 @@ static int potrf_inv_rec(double* A, int N, int lda, double* Li, int ldi, int* fl
   pg.M = N2; pg.N = N1; pg.K = N1;
   pg.A = L21; pg.lda = ld21;
   pg.B = Li; pg.ldb = ldi;  // L11^{-1}[k][j], zero for k < j
-  pg.flags = kKFromCol;
+  pg.flags = kKFromCol | kInverseOnly;
   const bool use_side = !want_L && side && side->stream && N >= kSideMin && depth < side->depths;
   hipEvent_t ev_in = use_side ? side->ev[2 * depth] : nullptr;
   hipEvent_t ev_out = use_side ? side->ev[2 * depth + 1] : nullptr;
@@ -1064,7 +1117,7 @@ static int potrf_inv_rec(double* A, int N, int lda, double* Li, int ldi, int* fl
     g.A = Li22; g.lda = ldi;  // zero for k > i
     g.B = want_L ? tmp : A21; g.ldb = want_L ? N1 : lda;
     g.C = Li21; g.ldc = ldi;
-    g.alpha = -1.0; g.flags = kKToRow;
+    g.alpha = -1.0; g.flags = kKToRow | kInverseOnly;
     LRSDP_TRY(gemm(g, s));
   }
   return LRSDP_OK;

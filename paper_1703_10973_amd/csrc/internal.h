@@ -46,6 +46,8 @@ struct lrsdp_ctx {
   hipEvent_t phase_ev[5] = {};  // boundaries of the setup phases of a factor
   int* d_flag = nullptr;        // device error/status words: [0] general and bold S, [1] Z,
                                 // [2] scratch for factorizations whose failure is not an error
+  int children = 0;             // live problems created under this context
+  bool closing = false;         // destroyed while children were alive: released with the last
 };
 
 // From this n on, the H v kernels keep their rows of T in global scratch (L2-resident) and
@@ -72,6 +74,8 @@ struct lrsdp_problem {
   double* tscr = nullptr;           // 2 n^2 (n >= kTGlobalMinN only): rows of T = W mat(A v)
                                     // for the H v kernels once T no longer fits in LDS
   size_t bytes = 0;
+  int children = 0;                 // live factors created on this problem
+  bool closing = false;             // destroyed while factors were alive: released with the last
 };
 
 namespace lrsdp {
@@ -97,6 +101,11 @@ struct ProfScope {
     tls_prof = prev;
   }
 };
+
+// ---------------------------------------------------------------- contexts
+// blocking: the context's own stream (stream == NULL) is ordered after the legacy default
+// stream; the server's worker contexts are created non-blocking.
+int ctx_create(int device, void* stream, size_t budget, bool blocking, lrsdp_ctx** out);
 
 // ---------------------------------------------------------------- memory
 int dev_alloc(lrsdp_ctx* ctx, void** p, size_t bytes);

@@ -126,7 +126,7 @@ int lrsdp_server_create(lrsdp_ctx* ctx, int workers, size_t hbm_budget_bytes,
   s->budget = hbm_budget_bytes;
   for (int w = 0; w < workers; ++w) {
     lrsdp_ctx* c = nullptr;
-    const int rc = lrsdp_ctx_create(ctx->device, nullptr, 0, &c);
+    const int rc = lrsdp::ctx_create(ctx->device, nullptr, 0, false, &c);
     if (rc != LRSDP_OK) {
       for (lrsdp_ctx* x : s->ctxs) lrsdp_ctx_destroy(x);
       delete s;

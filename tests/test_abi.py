@@ -43,3 +43,18 @@ def test_context_needs_a_device(binding):
         pytest.skip("a GPU is present")
     with pytest.raises(binding.LrsdpError):
         binding.lrsdp_ctx_create(0)
+
+
+def test_argument_sizes_are_checked_before_any_call(binding):
+    """A short or long array is refused by the binding before it reaches the library (a
+    kernel would otherwise read or write past the allocation)."""
+    import torch
+    from paper_1703_10973_amd import _lib
+    with pytest.raises(ValueError):
+        _lib._ptr(torch.zeros(5, dtype=torch.float64), torch.float64, 6, "v")
+    with pytest.raises(ValueError):
+        _lib._ptr(torch.zeros(7, dtype=torch.float64), torch.float64, 6, "v")
+    with pytest.raises(TypeError):
+        _lib._ptr(torch.zeros(6, dtype=torch.float32), torch.float64, 6, "v")
+    with pytest.raises(TypeError):      # right size and type, but host memory
+        _lib._ptr(torch.zeros(6, dtype=torch.float64), torch.float64, 6, "v")

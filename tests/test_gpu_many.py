@@ -130,3 +130,49 @@ def test_server_poll_pending_and_unknown_ticket(ctx):
     with pytest.raises(pk.LrsdpError):
         srv.poll(t)            # released by the poll that returned the result
     srv.close()
+
+
+def test_server_mix_with_a_large_request(ctx):
+    """A serving mix that includes one request at the top of the serving range (n = 2950,
+    k = 8, m = 565 661, seed 50239) between small ones, on three workers: each answer is
+    bitwise the one the request gets alone.  The large answer is checked by the library's
+    double-double true residual and, on sampled constraints, against the oracle's closed form
+    of H in double-double; the small ones by the oracle's full true residual."""
+    from test_gpu_large import _sampled_residual
+    seeds = [50239, 50000, 50001, 50002]
+    insts = []
+    for s in seeds:
+        n, k, m, mu = draw_serving_shape(s)
+        if s != 50239 and n > 600:
+            n, k, m, mu = 300, k, min(300 * 301 // 2, m), mu   # keep the small ones small
+        insts.append(make_instance(n, k, m, mu, seed=s))
+    assert (insts[0].n, insts[0].k) == (2950, 8)
+    opts = pk.opts(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO)
+    srv = pk.Server(ctx, workers=3)
+    devs = [_device_instance(i) for i in insts]
+    torch.cuda.synchronize()
+    print("server mix with n=2950 k=8", flush=True)
+    tickets = [srv.submit(d["n"], d["k"], d["con"], d["row"], d["col"], d["val"], d["W"],
+                          d["r"], d["y"], d["y_lo"], opts) for d in devs]
+    for t in tickets:
+        st, info = srv.poll(t, wait=True)
+        assert st == 0, info
+    srv.close()
+    for j, (inst, d) in enumerate(zip(insts, devs)):
+        yh, yl = host(d["y"]), host(d["y_lo"])
+        ya, yla, _ = _alone(ctx, inst, opts)
+        assert np.array_equal(yh, ya) and np.array_equal(yl, yla), inst.n
+        if j > 0:
+            _check_residual(inst, yh, yl)
+    big, d = insts[0], devs[0]
+    P = pk.Problem(ctx, big.n, big.m, d["con"], d["row"], d["col"], d["val"])
+    F = pk.Factor(P, d["W"], big.k, opts)
+    res = torch.empty_like(d["y"])
+    relres = pk._lib.lrsdp_residual_dd(F.handle, d["r"], d["y"], d["y_lo"], res)
+    assert relres <= 1e-8, relres
+    idx = np.random.default_rng(9).choice(big.m, 8, replace=False)
+    want = _sampled_residual(big, host(d["y"]), host(d["y_lo"]), idx)
+    got = host(res)[idx]
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.linalg.norm(big.r), (got, want)
+    F.close()
+    P.close()

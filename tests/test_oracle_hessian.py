@@ -125,3 +125,35 @@ def test_paper_hessian_storage_figure():
         g = json.load(f)["largest_instance"]
     gb = hs.hessian_storage_bytes(g["m"]) / 1e9
     assert abs(gb - g["hessian_storage_GB"]) / g["hessian_storage_GB"] < 0.01
+
+
+def test_check_spd_rejects_indefinite_and_nonsymmetric(rng):
+    """check_spd must say no to an indefinite H and to a non-symmetric one."""
+    inst = make_instance(30, 2, 120, 1e-2, seed=5)
+    H = hs.hessian_dense(inst.W, inst.a, inst.b, inst.val)
+    assert hs.check_spd(H) == (True, True)
+    lam, V = np.linalg.eigh(H)
+    Hneg = H - 2.0 * lam[0] * np.outer(V[:, 0], V[:, 0])   # smallest eigenvalue -> -lam[0]
+    Hneg = 0.5 * (Hneg + Hneg.T)
+    sym, pd = hs.check_spd(Hneg)
+    assert not pd
+    Hns = H.copy()
+    Hns[0, 1] += 1e-9 * abs(H[0, 1]) + 1e-300
+    sym, _ = hs.check_spd(Hns)
+    assert not sym
+    # a PSD but singular H (a repeated constraint row) is not positive definite
+    Hs = H.copy()
+    Hs[:, 1] = Hs[:, 0]
+    Hs[1, :] = Hs[0, :]
+    assert hs.check_spd(Hs)[1] is False
+
+
+def test_exact_hessian_is_the_trace_of_dense_products(rng):
+    """mp.exact_hessian (dense A_i, 50 digits) against the Kronecker definition
+    A^T (W kron W) A in FP64, on general disjoint-support data (values other than 1/2)."""
+    W, a, b, val = tiny_general(rng, n=6, m=10)
+    Hx = mp.exact_hessian(W, a, b, val)
+    A = vec_cols(hs.dense_constraints(W.shape[0], a, b, val))
+    Hk = A.T @ np.kron(W, W) @ A
+    Hf = np.array([[float(Hx[i, j]) for j in range(len(a))] for i in range(len(a))])
+    assert np.max(np.abs(Hf - Hk)) <= 1e-13 * np.max(np.abs(Hk))

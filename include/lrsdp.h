@@ -78,6 +78,8 @@ extern "C" {
 #define LRSDP_ERR_INDEFINITE_PRECOND -9   /* PCG met r^T z <= 0 or p^T H p <= 0                */
 #define LRSDP_ERR_DEVICE            -10   /* a HIP runtime call failed                          */
 #define LRSDP_ERR_EIG               -11   /* the symmetric eigensolver did not converge         */
+#define LRSDP_ERR_SCRATCH           -12   /* the call needs more than the library's fixed       */
+                                          /* scratch array holds (allocation-free entry point) */
 #define LRSDP_PENDING                 2   /* lrsdp_server_poll: the request has not finished   */
 
 /* ------------------------------------------------------------------ handles */
@@ -196,6 +198,18 @@ LRSDP_API int lrsdp_problem_info(const lrsdp_problem* p, int64_t* n, int64_t* m,
 /* Hv = H v = [A_i . (W mat(A v) W)]_i in FP64 (eq hesseqn2), W an n x n symmetric device
  * array (not retained), v and Hv length-m device arrays.  Parity hook for step A5. */
 LRSDP_API int lrsdp_hessian_apply(lrsdp_problem* p, const double* W, const double* v, double* Hv);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): lrsdp_hessian_apply without any allocation.
+ * Same arguments, layout and result (bitwise) as lrsdp_hessian_apply; the values of mat(A v)
+ * go to a fixed scratch array that every GPU the library runs on holds for the life of the
+ * process (16 MiB: patterns of up to 2^21 stored entries; problems with n >= 2048, whose
+ * H v keeps rows of T in global scratch, are refused too).  Errors: INVALID_ARG, SCRATCH
+ * (too large), DEVICE.  The array is shared by every call on a GPU and keeps the last call's
+ * contents: two calls that overlap on one GPU (different host threads, or streams of
+ * different contexts on one device) race and must be serialized by the caller. */
+LRSDP_API int lrsdp_hessian_apply_noalloc(lrsdp_problem* p, const double* W, const double* v,
+                                          double* Hv);
 
 /* ------------------------------------------------------------------ A1-A4: setup */
 /* Algorithm 1 steps 1-2 for scaling matrix W (n x n symmetric positive definite, device,

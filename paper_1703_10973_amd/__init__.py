@@ -23,7 +23,8 @@ from ._lib import (  # noqa: F401
     lrsdp_ctx_memory, lrsdp_ctx_profile, lrsdp_ctx_profile_read, lrsdp_ctx_profile_sample,
     LRSDP_K_NAMES,
     lrsdp_factor_create, lrsdp_factor_destroy, lrsdp_factor_export, lrsdp_factor_info,
-    lrsdp_hessian_apply, lrsdp_hessian_apply_split, lrsdp_info, lrsdp_opts,
+    lrsdp_hessian_apply, lrsdp_hessian_apply_noalloc, lrsdp_hessian_apply_split, lrsdp_info,
+    lrsdp_opts,
     lrsdp_opts_default, lrsdp_precond_apply, lrsdp_problem_create, lrsdp_problem_destroy,
     lrsdp_problem_info, lrsdp_residual_dd, lrsdp_solve, status_string, lrsdp_instance,
     make_instance, lrsdp_solve_batch, lrsdp_server_create, lrsdp_server_submit,

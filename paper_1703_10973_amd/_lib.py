@@ -29,6 +29,7 @@ LRSDP_ERR_STAGNATED = -8
 LRSDP_ERR_INDEFINITE_PRECOND = -9
 LRSDP_ERR_DEVICE = -10
 LRSDP_ERR_EIG = -11
+LRSDP_ERR_SCRATCH = -12
 LRSDP_PENDING = 2
 
 LRSDP_PREC_FP64, LRSDP_PREC_FP32, LRSDP_PREC_BF16, LRSDP_PREC_AUTO = 0, 1, 2, 3
@@ -86,6 +87,7 @@ _SIGS = {
     "lrsdp_problem_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                      C.POINTER(C.c_int64)]),
     "lrsdp_hessian_apply": (C.c_int, [_P, _P, _P, _P]),
+    "lrsdp_hessian_apply_noalloc": (C.c_int, [_P, _P, _P, _P]),
     "lrsdp_factor_create": (C.c_int, [_P, _P, C.c_int32, C.POINTER(lrsdp_opts), C.POINTER(_P)]),
     "lrsdp_factor_destroy": (None, [_P]),
     "lrsdp_factor_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -245,6 +247,15 @@ def lrsdp_hessian_apply(p, W, v, Hv):
                                   _ptr(v, torch.float64, m, "v"),
                                   _ptr(Hv, torch.float64, m, "Hv")),
         "lrsdp_hessian_apply")
+
+
+def lrsdp_hessian_apply_noalloc(p, W, v, Hv):
+    """lrsdp_hessian_apply with its scratch in the library's fixed per-device array."""
+    n, m, _ = lrsdp_problem_info(p)
+    _ok(lib().lrsdp_hessian_apply_noalloc(p, _ptr(W, torch.float64, n * n, "W"),
+                                          _ptr(v, torch.float64, m, "v"),
+                                          _ptr(Hv, torch.float64, m, "Hv")),
+        "lrsdp_hessian_apply_noalloc")
 
 
 def lrsdp_factor_create(p, W, k, opts=None):

@@ -186,6 +186,7 @@ const char* lrsdp_status_string(int s) {
     case LRSDP_ERR_INDEFINITE_PRECOND: return "INDEFINITE_PRECOND";
     case LRSDP_ERR_DEVICE: return "DEVICE_ERROR";
     case LRSDP_ERR_EIG: return "EIG_FAILED";
+    case LRSDP_ERR_SCRATCH: return "SCRATCH_TOO_SMALL";
     default: return "UNKNOWN";
   }
 }
@@ -225,6 +226,11 @@ int ctx_create(int device, void* stream, size_t budget, bool blocking, lrsdp_ctx
     if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
+    return LRSDP_ERR_DEVICE;
+  }
+  // the allocation-free entry point's fixed scratch: its address on this device, once
+  if (noalloc_scratch_setup(device) != LRSDP_OK) {
+    lrsdp_ctx_destroy(c);
     return LRSDP_ERR_DEVICE;
   }
   for (hipEvent_t& e : c->phase_ev) {
@@ -415,6 +421,14 @@ int lrsdp_hessian_apply(lrsdp_problem* p, const double* W, const double* v, doub
   DeviceGuard g(p->ctx->device);
   ProfScope ps(p->ctx);
   LRSDP_TRY(hv_apply_f64(p, W, v, Hv, p->ctx->stream));
+  LRSDP_HIP(hipStreamSynchronize(p->ctx->stream));
+  return LRSDP_OK;
+}
+
+int lrsdp_hessian_apply_noalloc(lrsdp_problem* p, const double* W, const double* v, double* Hv) {
+  if (!p || !W || !v || !Hv) return LRSDP_ERR_INVALID_ARG;
+  DeviceGuard g(p->ctx->device);
+  LRSDP_TRY(hv_apply_f64_noalloc(p, W, v, Hv, p->ctx->device, p->ctx->stream));
   LRSDP_HIP(hipStreamSynchronize(p->ctx->stream));
   return LRSDP_OK;
 }

@@ -9,6 +9,8 @@
 //                is read, W's row a streams from L2 / HBM with coalesced 64-wide loads.
 // Work per product: 2 (nnz + m) n flops; HBM traffic: W once (the LDS blocks) plus the
 // gather's row reads, which hit L2 / MALL for n up to a few thousand.
+#include <mutex>
+
 #include "internal.h"
 
 namespace lrsdp {
@@ -146,10 +148,13 @@ int rows_per_wg(int n, size_t budget, size_t row_bytes) {
   return cb;
 }
 
+// mval: nnz doubles of scratch for the values of mat(A v) (the problem's own, or the fixed
+// array of the allocation-free entry point).
 template <typename TW, typename TA, bool kBf16Values>
-int launch_hv(const lrsdp_problem* P, const TW* W, const double* v, double* Hv, hipStream_t s) {
+int launch_hv(const lrsdp_problem* P, const TW* W, const double* v, double* Hv, double* mval,
+              hipStream_t s) {
   const int n = P->n;
-  k_scatter<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, v, P->mval);
+  k_scatter<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, v, mval);
   const int ldn = n;
   // W and T rows in LDS (two workgroups per CU, else one); with the global scratch, only W
   int cb = rows_per_wg(n, kLdsBudget, 2 * (size_t)ldn * sizeof(TA));
@@ -165,11 +170,11 @@ int launch_hv(const lrsdp_problem* P, const TW* W, const double* v, double* Hv, 
   case CBV:                                                                                    \
     if (tg)                                                                                    \
       hipLaunchKernelGGL((k_hv_fused<TW, TA, CBV, kBf16Values, true>), dim3(grid),             \
-                         dim3(kThreads), smem, s, n, ldn, P->rowptr, P->colidx, P->mval, W,    \
+                         dim3(kThreads), smem, s, n, ldn, P->rowptr, P->colidx, mval, W,       \
                          P->own_ptr, P->own_con, P->own_oth, P->coef, Hv, tgp);                \
     else                                                                                       \
       hipLaunchKernelGGL((k_hv_fused<TW, TA, CBV, kBf16Values, false>), dim3(grid),            \
-                         dim3(kThreads), smem, s, n, ldn, P->rowptr, P->colidx, P->mval, W,    \
+                         dim3(kThreads), smem, s, n, ldn, P->rowptr, P->colidx, mval, W,       \
                          P->own_ptr, P->own_con, P->own_oth, P->coef, Hv, nullptr);            \
     break;
   switch (cb) {
@@ -284,15 +289,52 @@ __global__ __launch_bounds__(kThreads) void k_residual_dd(
 
 int hv_apply_f64(const lrsdp_problem* P, const double* W, const double* v, double* Hv,
                  hipStream_t s) {
-  return launch_hv<double, double, false>(P, W, v, Hv, s);
+  return launch_hv<double, double, false>(P, W, v, Hv, P->mval, s);
 }
 int hv_apply_f32(const lrsdp_problem* P, const float* W, const double* v, double* Hv,
                  hipStream_t s) {
-  return launch_hv<float, float, false>(P, W, v, Hv, s);
+  return launch_hv<float, float, false>(P, W, v, Hv, P->mval, s);
 }
 int hv_apply_bf16(const lrsdp_problem* P, const uint16_t* W, const double* v, double* Hv,
                   hipStream_t s) {
-  return launch_hv<uint16_t, float, true>(P, W, v, Hv, s);
+  return launch_hv<uint16_t, float, true>(P, W, v, Hv, P->mval, s);
+}
+
+// ---------------------------------------------------------------- allocation-free H v
+// The fixed scratch of lrsdp_hessian_apply_noalloc: the values of mat(A v), nnz doubles.  Every
+// GPU the library runs on holds one copy until the process ends; its address on each device
+// comes from hipGetSymbolAddress at context creation (the array's name is not a device
+// address in host code).
+namespace {
+constexpr size_t kScratchDoubles = (size_t)2 << 20;  // 16 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int noalloc_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return LRSDP_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return LRSDP_OK;
+  void* ptr = nullptr;  // the caller has made `device` current
+  LRSDP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  g_scratch_ptr[device] = static_cast<double*>(ptr);
+  return LRSDP_OK;
+}
+
+size_t noalloc_scratch_doubles() { return kScratchDoubles; }
+
+int hv_apply_f64_noalloc(const lrsdp_problem* P, const double* W, const double* v, double* Hv,
+                         int device, hipStream_t s) {
+  if ((size_t)P->nnz > kScratchDoubles || P->tscr != nullptr) return LRSDP_ERR_SCRATCH;
+  double* buf = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    buf = (device >= 0 && device < kMaxDevices) ? g_scratch_ptr[device] : nullptr;
+  }
+  if (!buf) return LRSDP_ERR_DEVICE;
+  return launch_hv<double, double, false>(P, W, v, Hv, buf, s);
 }
 
 int hv_residual_dd(const lrsdp_problem* P, const double* W, const double* r, const double* y,

@@ -128,6 +128,14 @@ int hv_apply_f32(const lrsdp_problem* P, const float* W, const double* v, double
                  hipStream_t s);
 int hv_apply_bf16(const lrsdp_problem* P, const uint16_t* W, const double* v, double* Hv,
                   hipStream_t s);
+// The allocation-free H v: mat(A v) in the library's fixed per-device scratch array, whose
+// device address noalloc_scratch_setup looks up once per device (with that device current).
+// Problems whose pattern has more entries than the array holds, or that keep rows of T in
+// global scratch (n >= kTGlobalMinN), are refused with LRSDP_ERR_SCRATCH.
+int noalloc_scratch_setup(int device);
+size_t noalloc_scratch_doubles();
+int hv_apply_f64_noalloc(const lrsdp_problem* P, const double* W, const double* v, double* Hv,
+                         int device, hipStream_t s);
 // Double-double H (y + ylo); writes res = r - H y (rounded) and per-block partial sums of
 // res^2 and r^2 into part (2 * gridDim doubles); returns nothing on host.
 int hv_residual_dd(const lrsdp_problem* P, const double* W, const double* r, const double* y,

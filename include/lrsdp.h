@@ -110,7 +110,23 @@ typedef struct lrsdp_opts {
   int dd_precond;        /* SMW pieces in double-double: 0 off, 1 on, 2 auto (default 2:    */
                          /* on when tau < 1e-7 lambda_max(W))                                */
   int tau_rule;          /* LRSDP_TAU_* (default MEAN)                                      */
+  int precond;           /* LRSDP_PRECOND_* (default SMW)                                   */
 } lrsdp_opts;
+
+/* The preconditioner of the PCG (a factor is built for one of them).
+ *   SMW: H~ = tau^2 A^T A + bold U bold U^T (eq AtIUUtAt), applied by eq SMW2 (Algorithm 1):
+ *        Z = chol(2 W0 + U U^T), bold S = tau^2 I + bold U^T (A^T A)^{-1} bold U; its FP64
+ *        form loses definiteness as mu -> 0 and is then carried in double-double (dd_precond).
+ *   AUG: H^ = A^T (tau^2 I + 2 tau (U U^T kron I)) A (eq sparse_prec, Section 4.2), applied
+ *        through the augmented system of eq aug_prec: x is eliminated first (1 x 1 pivots
+ *        tau^2 (A^T A)_ii, no fill outside the pattern) and the trailing nk x nk block
+ *        tau/2 I + B^T (A^T A)^{-1} B, B = A^T (U kron I), is factored densely (Cholesky and
+ *        inverse, FP64 MFMA).  No Z, no bold S formation GEMMs, no double-double pieces: the
+ *        condition number of eq aug_prec is Theta(1/sqrt(mu)).  PCG needs about
+ *        k^2 + O(log 1/(eps mu)) iterations (Lemma aug_prec).  dd_precond and deflate are
+ *        ignored. */
+#define LRSDP_PRECOND_SMW 0
+#define LRSDP_PRECOND_AUG 1
 
 /* The shift tau of the split W = W0 + U U^T (eq Wsplit2).  Algorithm 1 step 1a takes
  * tau = lambda_min(W); Section 3.1 allows any tau in [lambda_min(Lambda_s), lambda_max(Lambda_s)),
@@ -228,7 +244,9 @@ LRSDP_API int lrsdp_factor_info(const lrsdp_factor* f, int64_t* n, int64_t* m, i
 /* Export of the setup results for parity checks.  Host outputs: tau, shift (the deflation
  * shift, 0 if none), lam[k + 1] = {tau, then the k largest eigenvalues ascending},
  * setup_ms.  Device outputs (each may be NULL): U (n x k), W0 (n x n), Z (n x n, lower, zero
- * above the diagonal), Sinv (nk x nk, full symmetric, nk index p + n j). */
+ * above the diagonal; INVALID_ARG for an LRSDP_PRECOND_AUG factor, which has none), Sinv
+ * (nk x nk, full symmetric, nk index p + n j: bold S^{-1}, or for LRSDP_PRECOND_AUG the
+ * inverse of tau/2 I + B^T (A^T A)^{-1} B). */
 LRSDP_API int lrsdp_factor_export(const lrsdp_factor* f, double* tau, double* shift, double* lam,
                         double* setup_ms, double* U, double* W0, double* Z, double* Sinv);
 
@@ -239,7 +257,8 @@ LRSDP_API int lrsdp_hessian_apply_split(lrsdp_factor* f, const double* v, double
 /* Step A6 parity hook: z = H~^{-1} v by eq SMW2.  dd = 0: FP64 with the explicit bold S^{-1};
  * dd = 1: w = bold U^T G^{-1} v and t = bold S^{-1} w carried in double-double (t refined
  * against the matrix-free bold S); dd = 2: FP64 with one refinement step of t.  v, z:
- * length-m device arrays. */
+ * length-m device arrays.  For an LRSDP_PRECOND_AUG factor: z = H^{-1} v (eq aug_prec) in
+ * FP64, dd must be 0. */
 LRSDP_API int lrsdp_precond_apply(lrsdp_factor* f, const double* v, double* z, int dd);
 
 /* The true relative residual ||r - H (y + y_lo)|| / ||r|| with every product in

@@ -176,15 +176,21 @@ class RefineResult:
 
 
 def refine(F: Factor, r, eps=1e-8, inner_eps=1e-3, max_outer=12, max_inner=200,
-           dd_precond=None):
+           dd_precond=None, precond=None):
     """Outer iterative refinement y <- y + PCG(H_split, r - H y) with y a double-double
-    pair and r - H y evaluated in double-double from the plain definition of H."""
+    pair and r - H y evaluated in double-double from the plain definition of H.  F: an
+    Algorithm 1 factor (its U is the split's; its preconditioner H~ is used unless `precond`
+    gives another, e.g. the augmented preconditioner of oracle.aug)."""
     C = F.C
-    W0 = dd_W0(F.W, F.split.U)
-    Hs = SplitOperator(C, W0, F.split.U)
-    if dd_precond is None:
-        dd_precond = F.tau < 1e-7 * float(F.split.lam[-1])
-    Pinv = (lambda v: dd_precond_apply(F, v)) if dd_precond else None
+    U = F.U if precond is not None else F.split.U
+    W0 = dd_W0(F.W, U)
+    Hs = SplitOperator(C, W0, U)
+    if precond is not None:
+        Pinv = precond
+    else:
+        if dd_precond is None:
+            dd_precond = F.tau < 1e-7 * float(F.split.lam[-1])
+        Pinv = (lambda v: dd_precond_apply(F, v)) if dd_precond else None
     if Pinv is None:
         from .alg1 import precond_apply
         Pinv = lambda v: precond_apply(F, v)  # noqa: E731

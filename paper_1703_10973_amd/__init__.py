@@ -18,7 +18,7 @@ import torch
 from ._lib import (  # noqa: F401
     LRSDP_DD_AUTO, LRSDP_DD_OFF, LRSDP_DD_ON, LRSDP_PREC_BF16, LRSDP_PREC_FP32, LRSDP_TAU_MEAN,
     LRSDP_PREC_AUTO,
-    LRSDP_TAU_MIN,
+    LRSDP_TAU_MIN, LRSDP_PRECOND_SMW, LRSDP_PRECOND_AUG,
     LRSDP_PREC_FP64, LrsdpError, header_symbols, lib, lrsdp_ctx_create, lrsdp_ctx_destroy,
     lrsdp_ctx_memory, lrsdp_ctx_profile, lrsdp_ctx_profile_read, lrsdp_ctx_profile_sample,
     LRSDP_K_NAMES,

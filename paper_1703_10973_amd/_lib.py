@@ -35,13 +35,14 @@ LRSDP_PENDING = 2
 LRSDP_PREC_FP64, LRSDP_PREC_FP32, LRSDP_PREC_BF16, LRSDP_PREC_AUTO = 0, 1, 2, 3
 LRSDP_DD_OFF, LRSDP_DD_ON, LRSDP_DD_AUTO = 0, 1, 2
 LRSDP_TAU_MIN, LRSDP_TAU_MEAN = 0, 1
+LRSDP_PRECOND_SMW, LRSDP_PRECOND_AUG = 0, 1
 
 
 class lrsdp_opts(C.Structure):
     _fields_ = [("eps", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int),
                 ("dd_mode", C.c_int), ("deflate", C.c_int), ("max_outer", C.c_int),
                 ("inner_eps", C.c_double), ("dd_auto_ratio", C.c_double),
-                ("dd_precond", C.c_int), ("tau_rule", C.c_int)]
+                ("dd_precond", C.c_int), ("tau_rule", C.c_int), ("precond", C.c_int)]
 
 
 class lrsdp_info(C.Structure):

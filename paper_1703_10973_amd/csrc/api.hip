@@ -150,7 +150,7 @@ bool opts_valid(const lrsdp_opts& o) {
   return o.eps > 0.0 && o.max_iter >= 1 && o.precision >= 0 && o.precision <= 3 &&
          o.dd_mode >= 0 && o.dd_mode <= 2 && o.max_outer >= 0 && o.inner_eps > 0.0 &&
          o.inner_eps < 1.0 && o.dd_precond >= 0 && o.dd_precond <= 2 && o.tau_rule >= 0 &&
-         o.tau_rule <= 1;
+         o.tau_rule <= 1 && (o.precond == LRSDP_PRECOND_SMW || o.precond == LRSDP_PRECOND_AUG);
 }
 
 }  // namespace
@@ -169,6 +169,7 @@ void lrsdp_opts_default(lrsdp_opts* o) {
   o->dd_auto_ratio = 2e-5;
   o->dd_precond = 2;
   o->tau_rule = LRSDP_TAU_MEAN;
+  o->precond = LRSDP_PRECOND_SMW;
 }
 
 const char* lrsdp_status_string(int s) {
@@ -495,6 +496,7 @@ int lrsdp_factor_export(const lrsdp_factor* f, double* tau, double* shift, doubl
   if (lam) std::memcpy(lam, f->lam.data(), f->lam.size() * sizeof(double));
   if (U) LRSDP_HIP(hipMemcpyAsync(U, f->U, nk * 8, hipMemcpyDeviceToDevice, s));
   if (W0) LRSDP_HIP(hipMemcpyAsync(W0, f->W0, nn * 8, hipMemcpyDeviceToDevice, s));
+  if (Z && !f->Z) return LRSDP_ERR_INVALID_ARG;  // the augmented preconditioner has no Z
   if (Z) LRSDP_HIP(hipMemcpyAsync(Z, f->Z, nn * 8, hipMemcpyDeviceToDevice, s));
   if (Sinv) LRSDP_TRY(export_sinv(f, Sinv, s));
   LRSDP_HIP(hipStreamSynchronize(s));
@@ -515,6 +517,7 @@ int lrsdp_precond_apply(lrsdp_factor* f, const double* v, double* z, int ddm) {
   DeviceGuard g(f->P->ctx->device);
   ProfScope ps(f->P->ctx);
   hipStream_t s = f->P->ctx->stream;
+  if (f->precond == LRSDP_PRECOND_AUG && ddm != 0) return LRSDP_ERR_INVALID_ARG;
   if (ddm == 1) LRSDP_TRY(precond_apply_dd(f, v, z, s, 2));
   else LRSDP_TRY(precond_apply_f64(f, v, z, s, ddm == 2));
   LRSDP_HIP(hipStreamSynchronize(s));

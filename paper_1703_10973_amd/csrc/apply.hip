@@ -588,6 +588,15 @@ int precond_apply_f64(const lrsdp_factor* f, const double* v, double* z, hipStre
   const int n = f->n, k = f->k, m = P->m, nk = f->nk;
   if (k > KMAX) return LRSDP_ERR_INVALID_ARG;
   spmm_U(P, k, P->ginv, v, f->U, w.y, s);                // M U, M = mat(A G^{-1} v)
+  if (f->precond == LRSDP_PRECOND_AUG) {
+    // H^{-1} v (eq aug_prec, x eliminated): w = B^T G^{-1} v = vec(M U), t = Sh^{-1} w with
+    // Sh = tau/2 I + B^T G^{-1} B, z = (v - B t) G^{-1} / tau^2, B t = [A_i . (T U^T)]_i
+    LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.y, w.h, w.t, s));
+    k_smw_out<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, P->ginv,
+                                               1.0 / f->tau2, w.t, f->U, v, z);
+    LRSDP_HIP(hipGetLastError());
+    return LRSDP_OK;
+  }
   rows_k(n, k, f->Zt, 2, w.y, w.w, s);                    // w = vec(Z^T M U)
   LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.w, w.h, w.t, s));  // t = bold S^{-1} w
   if (refine) {                                           // t += bold S^{-1} (w - bold S t)

@@ -56,7 +56,7 @@ __global__ void k_make_W0(int n, int k, const double* W, const double* U, double
   }
   const double w0 = acc.hi + acc.lo;
   W0[idx] = w0;
-  Zin[idx] = fma(2.0, w0, uu);
+  if (Zin) Zin[idx] = fma(2.0, w0, uu);
 }
 
 // P_J[a][c] = sum_{b in Obar(a)} u_J[b] Z[b][c] for every J at once (Z rows read once).
@@ -188,6 +188,46 @@ __global__ __launch_bounds__(kT) void k_max_diag(const double* S, int N, int ld,
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// ---- the augmented preconditioner of Section 4.2 (eqs sparse_prec, aug_prec)
+// Eliminating x from eq aug_prec (1 x 1 pivots tau^2 (A^T A)_ii, no fill outside the pattern)
+// leaves -tau (tau/2 I + B^T (A^T A)^{-1} B), B = A^T (U kron I).  Its block (X, Y) is
+// (tau/2) delta_XY I + 1/2 [diag(d_XY) + D_{u_Y} Obar D_{u_X}] with d_XY = Obar (u_X o u_Y),
+// supported on the pattern Obar plus the diagonal.  One wavefront per row a writes the row's
+// entries of every block pair X >= Y into the zero-filled matrix (row a + n X, column b + n Y).
+__global__ __launch_bounds__(256) void k_aug_schur(int n, int k, int nk, const int32_t* rowptr,
+                                                   const int32_t* colidx, const double* U,
+                                                   const double* d, const double* lam,
+                                                   double* S) {
+  const int a = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (a >= n) return;  // whole wavefront
+  const double half_tau = 0.5 * lam[0];
+  const int lo = rowptr[a], hi = rowptr[a + 1];
+  for (int X = 0; X < k; ++X)
+    for (int Y = 0; Y <= X; ++Y) {
+      const double dterm = 0.5 * d[(size_t)(X * (X + 1) / 2 + Y) * n + a] +
+                           (X == Y ? half_tau : 0.0);
+      double* row = S + (size_t)(a + (size_t)n * X) * nk + (size_t)n * Y;
+      const double uya = 0.5 * U[(size_t)Y * n + a];
+      bool diag_seen = false;
+      for (int e = lo + lane; e < hi; e += 64) {
+        const int b = colidx[e];
+        double v = uya * U[(size_t)X * n + b];
+        if (b == a) {
+          v += dterm;
+          diag_seen = true;
+        }
+        row[b] = v;
+      }
+      if (!__any(diag_seen) && lane == 0) row[a] = dterm;
+    }
+}
+
+__global__ void k_fill(size_t cnt, double* a, double v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < cnt;
+       i += (size_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+
 __global__ void k_f64_to_f32(size_t cnt, const double* a, float* b) {
   const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
   if (i < cnt) b[i] = static_cast<float>(a[i]);
@@ -279,6 +319,87 @@ int export_sinv(const lrsdp_factor* f, double* out, hipStream_t s) {
   return rc;
 }
 
+// Algorithm 1 step 2 with the augmented preconditioner of Section 4.2: the trailing block of
+// eq aug_prec after x is eliminated, divided by -tau, formed from the pattern and factored
+// (Cholesky and inverse, as bold S is).  tau, U and W0 are in place.
+static int factor_setup_aug(lrsdp_factor* f, std::chrono::steady_clock::time_point t_start) {
+  lrsdp_problem* P = f->P;
+  lrsdp_ctx* ctx = P->ctx;
+  hipStream_t s = ctx->stream;
+  const int n = f->n, k = f->k, nk = f->nk;
+  hipEvent_t* ev = ctx->phase_ev;
+  const int npairs = k * (k + 1) / 2;
+  double *Sb = nullptr, *ptmp = nullptr, *dd_ = nullptr;
+  const size_t cS = (size_t)nk * nk, cT = std::max<size_t>(1, potrf_inv_tmp_doubles(nk)),
+               cD = (size_t)npairs * n;
+  int rc = dev_alloc_n(ctx, &Sb, cS);
+  if (rc == LRSDP_OK) rc = dev_alloc_n(ctx, &ptmp, cT);
+  if (rc == LRSDP_OK) rc = dev_alloc_n(ctx, &dd_, cD);
+  auto free_tmp = [&]() {
+    (void)hipStreamSynchronize(s);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    dev_free(ctx, Sb, cS * sizeof(double));
+    dev_free(ctx, ptmp, cT * sizeof(double));
+    dev_free(ctx, dd_, cD * sizeof(double));
+  };
+  if (rc != LRSDP_OK) {
+    free_tmp();
+    return rc;
+  }
+  int* flag_S = ctx->d_flag;
+  do {
+    if (hipEventRecord(ev[2], s) != hipSuccess) {  // no Z: the phase ends with W0
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    k_fill<<<grid_for((int64_t)cS, 256, 8192), 256, 0, s>>>(cS, Sb, 0.0);
+    if (hipMemsetAsync(ctx->d_flag, 0, 3 * sizeof(int), s) != hipSuccess) {  // the flags
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    k_dJL<<<(n + 3) / 4, 256, 0, s>>>(n, k, P->rowptr, P->colidx, f->U, dd_);
+    k_aug_schur<<<(n + 3) / 4, 256, 0, s>>>(n, k, nk, P->rowptr, P->colidx, f->U, dd_,
+                                           f->lam_dev, Sb);
+    if (hipGetLastError() != hipSuccess || hipEventRecord(ev[3], s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    SideStream side;
+    if ((rc = ctx_side(ctx, &side))) break;
+    if ((rc = potrf_inv(Sb, nk, nk, f->Sinv, nk, flag_S, ptmp, false, s, &side))) break;
+    if ((rc = mirror_lower(f->Sinv, nk, nk, s))) break;
+    if (hipEventRecord(ev[4], s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    int fl = 0;
+    if (hipMemcpyAsync(f->lam.data(), f->lam_dev, (k + 1) * sizeof(double),
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&fl, flag_S, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      rc = LRSDP_ERR_DEVICE;
+      break;
+    }
+    f->shift = 0.0;
+    f->tau = f->lam[0];
+    bool finite = true;
+    for (double v : f->lam) finite = finite && std::isfinite(v);
+    if (!finite) rc = LRSDP_ERR_EIG;
+    else if (!(f->tau > 0.0)) rc = LRSDP_ERR_NOT_PD_W;
+    else if (fl) rc = LRSDP_ERR_CHOL_S;
+    f->tau2 = f->tau * f->tau;
+  } while (0);
+  free_tmp();
+  LRSDP_TRY(rc);
+  for (int i = 0; i < 4; ++i) {
+    float ms = 0.0f;
+    f->phase_ms[i] = hipEventElapsedTime(&ms, ev[i], ev[i + 1]) == hipSuccess ? ms : 0.0;
+  }
+  auto t_end = std::chrono::steady_clock::now();
+  f->setup_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+  return LRSDP_OK;
+}
+
 int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
   auto t_start = std::chrono::steady_clock::now();
   lrsdp_problem* P = f->P;
@@ -286,7 +407,9 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
   hipStream_t s = ctx->stream;
   const int n = f->n, k = f->k, nk = f->nk;
   const size_t nn = (size_t)n * n;
-  f->r = (o.deflate && k >= 2) ? k * (k - 1) / 2 : 0;
+  const bool aug = o.precond == LRSDP_PRECOND_AUG;
+  f->precond = o.precond;
+  f->r = (!aug && o.deflate && k >= 2) ? k * (k - 1) / 2 : 0;
   const int r = f->r;
 
   // persistent buffers
@@ -294,16 +417,18 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
   LRSDP_TRY(dev_alloc_n(ctx, &f->W, nn));
   LRSDP_TRY(dev_alloc_n(ctx, &f->W0, nn));
   LRSDP_TRY(dev_alloc_n(ctx, &f->U, (size_t)nk));
-  LRSDP_TRY(dev_alloc_n(ctx, &f->Z, nn));
-  LRSDP_TRY(dev_alloc_n(ctx, &f->Zt, nn));
+  if (!aug) {  // the augmented preconditioner needs no Z
+    LRSDP_TRY(dev_alloc_n(ctx, &f->Z, nn));
+    LRSDP_TRY(dev_alloc_n(ctx, &f->Zt, nn));
+  }
   LRSDP_TRY(dev_alloc_n(ctx, &f->Sinv, (size_t)nk * nk));
   if (r) LRSDP_TRY(dev_alloc_n(ctx, &f->QN, (size_t)nk * r));
   f->work_doubles = work_doubles(n, P->m, k);
   LRSDP_TRY(dev_alloc_n(ctx, &f->work, f->work_doubles));
   LRSDP_TRY(dev_alloc_n(ctx, &f->sc, (size_t)64));
   LRSDP_HIP(hipMemsetAsync(f->sc, 0, 64 * sizeof(double), ctx->stream));  // scalars, counters
-  f->bytes = (k + 1 + 5 * nn + (size_t)nk + (size_t)nk * nk + (size_t)nk * r + f->work_doubles +
-              64) * sizeof(double);
+  f->bytes = (k + 1 + (aug ? 3 : 5) * nn + (size_t)nk + (size_t)nk * nk + (size_t)nk * r +
+              f->work_doubles + 64) * sizeof(double);
 
   LRSDP_HIP(hipMemcpyAsync(f->W, W, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
   hipEvent_t* ev = ctx->phase_ev;  // phase boundaries, read after the final synchronization
@@ -347,6 +472,7 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
   k_make_U<<<grid_for((int64_t)nk, 256), 256, 0, s>>>(n, k, f->lam_dev, Vl, f->U);
   k_make_W0<<<grid_for((int64_t)nn, 256), 256, 0, s>>>(n, k, f->W, f->U, f->W0, f->Z);
   LRSDP_HIP(hipGetLastError());
+  if (aug) return factor_setup_aug(f, t_start);
   // temporaries: inverse diagonal blocks of Z, bold S and the Gram matrix; bold S itself;
   // P_J and the R_JL blocks of its formation
   const int npairs = k * (k + 1) / 2;

@@ -150,6 +150,8 @@ struct lrsdp_factor {
   double tau = 0.0, tau2 = 0.0, shift = 0.0, setup_ms = 0.0;
   double phase_ms[4] = {0.0, 0.0, 0.0, 0.0};  // setup phases (see lrsdp_info)
   int eig_sweeps = 0;                // subspace-iteration sweeps (0: Householder path)
+  int precond = LRSDP_PRECOND_SMW;   // LRSDP_PRECOND_*: AUG has no Z (Z, Zt null) and keeps the
+                                     // inverse of tau/2 I + B^T G^{-1} B in Sinv
   std::vector<double> lam;           // host copy: tau, then the k largest ascending
   double* lam_dev = nullptr;         // k + 1
   double* W = nullptr;               // n x n, copy of the caller's W

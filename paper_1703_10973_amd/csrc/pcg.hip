@@ -252,7 +252,11 @@ int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lr
   if (o.dd_precond == 1) dd_prec = true;
   else if (o.dd_precond == 0) dd_prec = false;
   else dd_prec = ratio < 1e-7;
-  const int ref64 = ratio < 1e-3 ? 1 : 0;
+  int ref64 = ratio < 1e-3 ? 1 : 0;
+  if (f->precond == LRSDP_PRECOND_AUG) {  // FP64 only (eq aug_prec is Theta(1/sqrt(mu)))
+    dd_prec = false;
+    ref64 = 0;
+  }
 
   auto Pinv = [&](const double* v, double* z) -> int {
     return dd_prec ? precond_apply_dd(f, v, z, s, 2) : precond_apply_f64(f, v, z, s, ref64);

@@ -72,6 +72,25 @@ def test_full_size_solve_meets_target(problem, mode, mu):
     F.close()
 
 
+@pytest.mark.parametrize("mu", [1e-2, 1e-8])
+def test_full_size_augmented_preconditioner(problem, mu):
+    """The benchmark shape with the augmented preconditioner of Section 4.2 (no Z, no double-
+    double SMW pieces): the true residual (oracle, double-double) meets 1e-8 and the answer is
+    the oracle's; the iteration counts are printed."""
+    inst = make_instance(1000, 5, 20000, mu, seed=2001)
+    o = pk.opts(precision=pk.LRSDP_PREC_AUTO, precond=pk.LRSDP_PRECOND_AUG)
+    F = pk.Factor(problem, to_dev(inst.W), inst.k, o)
+    y, ylo, st, info = F.solve(to_dev(inst.r), o)
+    assert st == 0, info
+    yh, yl = host(y), host(ylo)
+    r_true, _ = ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val, inst.r, yh, yl)
+    assert r_true <= 1e-8
+    assert rel(yh + yl, _oracle_reference(inst)) <= 1e-6
+    print(f"full-size aug mu={mu:g}: iters={info['iters']} outer={info['outer_iters']} "
+          f"setup={info['setup_ms']:.2f} ms solve={info['solve_ms']:.2f} ms", flush=True)
+    F.close()
+
+
 @pytest.mark.parametrize("rule", ["min", "mean"])
 def test_full_size_tau_and_top_eigenvalues(problem, rule):
     inst = make_instance(1000, 5, 20000, 1e-6, seed=2001)

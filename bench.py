@@ -41,10 +41,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving-with-resident-factors stream of the headline line")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mu-path",
-                    choices=["mu-path", "batch", "serving", "large", "single",
-                             "copy-calibration"],
+                    choices=["mu-path", "batch", "serving", "serving-sessions", "large",
+                             "single", "copy-calibration"],
                     help="mu-path (default): the headline line; batch: 256 independent "
                          "instances (n in [64, 512], k in 1..4, mu = 1e-6); serving: Poisson "
                          "request stream (n in [200, 3000], k in 1..8, mu in [1e-8, 1e-2]); "
@@ -185,7 +187,8 @@ def main():
         sys.exit(2)
     if args.workload != "mu-path":
         return {"batch": run_batch, "serving": run_serving, "large": run_large,
-                "single": run_single, "copy-calibration": run_copy}[args.workload](args)
+                "serving-sessions": run_serving_sessions, "single": run_single,
+                "copy-calibration": run_copy}[args.workload](args)
     import torch
 
     import paper_1703_10973_amd as pk
@@ -373,6 +376,15 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(insts, args.cpu_seconds, answers)
 
+    # ---- serving with resident factors (the serving configuration's 2000 requests)
+    serving = None
+    if not args.no_serving:
+        try:
+            serving = serving_sessions(pk, torch, count=2000, workers=args.workers,
+                                       log=lambda x: print(x, file=sys.stderr, flush=True))
+        except Exception as e:  # reported, never hides the headline line
+            serving = {"error": repr(e)}
+
     line = {
         "metric": METRIC,
         "value": mixed["value"],
@@ -412,6 +424,7 @@ def main():
         "hv_roofline": hv_roof,
         "solve_roofline": solve_roof,
         "cpu_baseline": cpu,
+        "serving_resident": serving,
     }
     print(json.dumps(line))
 
@@ -576,6 +589,147 @@ def run_serving(args):
         "workers": args.workers, "dtype": "f32+f64+dd", "data": "synthetic",
         "relres_sampled_max": max(rr), "config": cfg}))
     ctx.close()
+
+
+def serving_sessions(pk, torch, count=2000, sessions=32, rhs_per_step=2, qps=None,
+                     workers=8, log=None):
+    """Serving with resident factors: `count` requests in a Poisson stream over `sessions`
+    SDPs of the serving shapes (n log-uniform [200,3000], k 1..8, m = min(n(n+1)/2,
+    3nk ln n), mu log-uniform [1e-8,1e-2], seeds 50000+).  Each session keeps its problem and
+    current factor resident on the server; its requests are interior-point steps: a factor
+    request for the step's W (the session's draws at mu, mu/10, mu/100 in turn, an IPM path)
+    followed by `rhs_per_step` solve requests against it.  Returns the capacity run (every
+    request submitted at once) and the stream at 0.5 and 0.9 of that capacity, with p50/p99
+    latency (completion - arrival) over all requests and over the solve requests."""
+    from synth import draw_serving_shape, make_path
+    dev = torch.device("cuda", 0)
+    t_gen = time.perf_counter()
+    sess = []
+    for s in range(sessions):
+        n, k, m, mu = draw_serving_shape(50000 + s)
+        mus = [max(mu * f, 1e-8) for f in (1.0, 1e-1, 1e-2)]
+        path = make_path(n, k, m, mus, seed=50000 + s)
+        t = lambda x, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)  # noqa: E731
+        con, row, col, val = path[0].triplets()
+        rng = np.random.default_rng(59000 + s)
+        sess.append(dict(n=n, k=k, m=m, insts=path, con=t(con, torch.int32), row=t(row, torch.int32),
+                         col=t(col, torch.int32), val=t(val), W=[t(i.W) for i in path],
+                         r=[t(rng.standard_normal(m)) for _ in range(rhs_per_step)]))
+    gen_s = time.perf_counter() - t_gen
+    # the request list: per session, steps of (factor, solve x rhs_per_step), sessions
+    # interleaved in a seeded random order that keeps each session's own order
+    per = [[] for _ in range(sessions)]
+    rng = np.random.default_rng(59999)
+    order = rng.integers(0, sessions, size=count)
+    for s in order:
+        q = per[s]
+        step, pos = divmod(len(q), rhs_per_step + 1)
+        q.append(("factor", step % 3) if pos == 0 else ("solve", pos - 1))
+    reqs = []
+    cursor = [0] * sessions
+    for s in order:
+        reqs.append((int(s),) + per[s][cursor[s]])
+        cursor[s] += 1
+    opts = pk.opts(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO)
+
+    def stream(arrive):
+        srv = pk.Server(pk_ctx, workers=workers)
+        sid = []
+        for d in sess:
+            s_id, t_open = srv.open_session(d["n"], d["m"], d["con"], d["row"], d["col"], d["val"])
+            sid.append(s_id)
+            assert srv.poll(t_open, wait=True)[0] == 0
+        outs = [torch.empty(d["m"], dtype=torch.float64, device=dev) for d in sess]
+        outl = [torch.empty(d["m"], dtype=torch.float64, device=dev) for d in sess]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pending, lat, kind, nxt = {}, {}, {}, 0
+        while len(lat) < len(reqs):
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and arrive[nxt] <= now:
+                s, what, arg = reqs[nxt]
+                d = sess[s]
+                if what == "factor":
+                    tk = srv.submit_factor(sid[s], d["W"][arg], d["k"], opts)
+                else:
+                    tk = srv.submit_solve(sid[s], d["r"][arg], outs[s], outl[s], opts)
+                pending[tk] = nxt
+                kind[nxt] = what
+                nxt += 1
+            for tk in list(pending):
+                out = srv.poll(tk)
+                if out is not None:
+                    i = pending.pop(tk)
+                    lat[i] = (time.perf_counter() - t0 - arrive[i]) * 1e3
+                    if out[0] != 0:
+                        raise RuntimeError(f"request {i} ({reqs[i]}) failed: {out}")
+            time.sleep(0.0002)
+        wall = time.perf_counter() - t0
+        for s_id in sid:
+            srv.poll(srv.close_session(s_id), wait=True)
+        srv.close()
+        L = np.array([lat[i] for i in range(len(reqs))])
+        Ls = np.array([lat[i] for i in range(len(reqs)) if kind[i] == "solve"])
+        Lf = np.array([lat[i] for i in range(len(reqs)) if kind[i] == "factor"])
+        return dict(requests_per_s=len(reqs) / wall, wall_s=wall,
+                    p50_ms=float(np.percentile(L, 50)), p99_ms=float(np.percentile(L, 99)),
+                    solve_p50_ms=float(np.percentile(Ls, 50)),
+                    solve_p99_ms=float(np.percentile(Ls, 99)),
+                    factor_p50_ms=float(np.percentile(Lf, 50)),
+                    factor_p99_ms=float(np.percentile(Lf, 99)))
+
+    pk_ctx = pk.Context(0)
+    unit = np.cumsum(np.random.default_rng(59998).exponential(1.0, size=len(reqs)))
+    unit -= unit[0]
+    cap = stream(np.zeros(len(reqs)))
+    if log:
+        log(f"# serving sessions: capacity {cap['requests_per_s']:.1f} requests/s")
+    points = []
+    for load in (0.5, 0.9):
+        q = load * cap["requests_per_s"] if qps is None else qps
+        pt = stream(unit / q)
+        pt.update(qps=q, load=load)
+        points.append(pt)
+        if log:
+            log(f"# serving sessions at {q:.1f}/s: p50 {pt['p50_ms']:.1f} ms p99 {pt['p99_ms']:.1f} ms")
+    # accuracy of a few answers (untimed): solve again alone and check the oracle's residual
+    checks = []
+    for d in sess:
+        if d["n"] > 600 or len(checks) >= 3:
+            continue
+        inst = d["insts"][0]
+        P = pk.Problem(pk_ctx, d["n"], d["m"], d["con"], d["row"], d["col"], d["val"])
+        F = pk.Factor(P, d["W"][0], d["k"], opts)
+        y, ylo, st, _ = F.solve(d["r"][0], opts)
+        from oracle import dd as ddo
+        checks.append(ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val,
+                                                 d["r"][0].cpu().numpy(), y.cpu().numpy(),
+                                                 ylo.cpu().numpy())[0])
+        F.close()
+        P.close()
+    pk_ctx.close()
+    return dict(requests=len(reqs), sessions=sessions, rhs_per_step=rhs_per_step,
+                workers=workers, capacity=cap, points=points,
+                relres_sampled_max=max(checks) if checks else None,
+                input_generation_s=round(gen_s, 2),
+                config="C5 serving shapes as resident sessions: each request is an interior-point "
+                       "step (factor of a new W on the resident problem) or a further right-hand "
+                       "side against the resident factor; Poisson arrivals, seeds 50000+, "
+                       "arrivals 59998/59999")
+
+
+def run_serving_sessions(args):
+    import torch
+
+    import paper_1703_10973_amd as pk
+    out = serving_sessions(pk, torch, count=args.count or 2000, workers=args.workers,
+                           log=lambda x: print(x, file=sys.stderr, flush=True))
+    pt = out["points"][-1]
+    print(json.dumps({"metric": "serving with resident factors: requests/s and p50/p99 ms",
+                      "value": out["capacity"]["requests_per_s"], "unit": "requests/s",
+                      "n_gpus": 1, "higher_is_better": True, "p50_ms": pt["p50_ms"],
+                      "p99_ms": pt["p99_ms"], "dtype": "f32+f64+dd", "data": "synthetic",
+                      "detail": out}))
 
 
 def run_large(args):

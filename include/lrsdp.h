@@ -319,6 +319,32 @@ LRSDP_API int lrsdp_server_submit(lrsdp_server* srv, const lrsdp_instance* inst,
                                   const lrsdp_opts* opts, uint64_t* ticket);
 LRSDP_API int lrsdp_server_poll(lrsdp_server* srv, uint64_t ticket, int wait, int* status,
                                 lrsdp_info* info);
+/* Sessions: one SDP's data and its current factor resident on the device between requests,
+ * as an interior-point method uses them (Section 2: a new scaling matrix W at every step,
+ * one or a few right-hand sides per W, eqs hesseqn2 and Newt).  open queues the ingest of the
+ * triplets (as lrsdp_problem_create; the arrays must stay valid until that request finishes)
+ * and returns the session id and the request's ticket.  A factor request builds the factor of
+ * W (n x n, valid until it finishes) with rank k (Algorithm 1 steps 1-2), replacing the
+ * previous one; a solve request runs step 3 against the current factor (r, y, y_lo as for
+ * lrsdp_solve, valid until it finishes; INVALID_ARG without a factor); close releases the
+ * session after its earlier requests.  A session has a device stream of its own; its requests
+ * run one at a time in submission order, on whichever worker is free, beside other sessions
+ * and instances.
+ * Results are bitwise those of lrsdp_problem_create / lrsdp_factor_create / lrsdp_solve alone.
+ * Memory: a session holds its problem's bytes from open to close and its largest factor's
+ * estimated peak bytes (lrsdp_instance_bytes less the problem's share) from its first factor
+ * request to close, against the server's budget.  Every call returns a ticket for
+ * lrsdp_server_poll; requests on an unknown or closing session return INVALID_ARG. */
+LRSDP_API int lrsdp_server_session_open(lrsdp_server* srv, int64_t n, int64_t m,
+                                        const int32_t* con, const int32_t* row,
+                                        const int32_t* col, const double* val,
+                                        uint64_t* session, uint64_t* ticket);
+LRSDP_API int lrsdp_server_submit_factor(lrsdp_server* srv, uint64_t session, const double* W,
+                                         int32_t k, const lrsdp_opts* opts, uint64_t* ticket);
+LRSDP_API int lrsdp_server_submit_solve(lrsdp_server* srv, uint64_t session, const double* r,
+                                        double* y, double* y_lo, const lrsdp_opts* opts,
+                                        uint64_t* ticket);
+LRSDP_API int lrsdp_server_session_close(lrsdp_server* srv, uint64_t session, uint64_t* ticket);
 /* Requests queued, running and finished-but-unpolled, and the estimated bytes in flight;
  * every output is host and may be NULL. */
 LRSDP_API int lrsdp_server_stats(lrsdp_server* srv, int* queued, int* running, int* done,

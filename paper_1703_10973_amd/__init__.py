@@ -29,6 +29,8 @@ from ._lib import (  # noqa: F401
     lrsdp_problem_info, lrsdp_residual_dd, lrsdp_solve, status_string, lrsdp_instance,
     make_instance, lrsdp_solve_batch, lrsdp_server_create, lrsdp_server_submit,
     lrsdp_server_poll, lrsdp_server_stats, lrsdp_server_destroy, lrsdp_instance_bytes,
+    lrsdp_server_session_open, lrsdp_server_submit_factor, lrsdp_server_submit_solve,
+    lrsdp_server_session_close,
     LRSDP_PENDING)
 
 
@@ -197,6 +199,7 @@ class Server:
         self.handle = None
         self.handle = lrsdp_server_create(ctx.handle, workers, hbm_budget_bytes)
         self._keep = {}
+        self._sessions = {}
         ctx._children.add(self)
 
     def submit(self, n, k, con, row, col, val, W, r, y, y_lo=None, options=None):
@@ -204,6 +207,28 @@ class Server:
         t = lrsdp_server_submit(self.handle, inst, options)
         self._keep[t] = (con, row, col, val, W, r, y, y_lo)
         return t
+
+    def open_session(self, n, m, con, row, col, val):
+        """A resident session for one SDP's data; returns (session, ticket)."""
+        sid, t = lrsdp_server_session_open(self.handle, n, m, con, row, col, val)
+        self._keep[t] = (con, row, col, val)
+        self._sessions[sid] = (int(n), int(m))
+        return sid, t
+
+    def submit_factor(self, session, W, k, options=None):
+        n, _ = self._sessions[session]
+        t = lrsdp_server_submit_factor(self.handle, session, n, W, k, options)
+        self._keep[t] = (W,)
+        return t
+
+    def submit_solve(self, session, r, y, y_lo=None, options=None):
+        _, m = self._sessions[session]
+        t = lrsdp_server_submit_solve(self.handle, session, m, r, y, y_lo, options)
+        self._keep[t] = (r, y, y_lo)
+        return t
+
+    def close_session(self, session):
+        return lrsdp_server_session_close(self.handle, session)
 
     def poll(self, ticket, wait=False):
         out = lrsdp_server_poll(self.handle, ticket, wait)

@@ -107,6 +107,13 @@ _SIGS = {
                                       C.POINTER(C.c_uint64)]),
     "lrsdp_server_poll": (C.c_int, [_P, C.c_uint64, C.c_int, C.POINTER(C.c_int),
                                     C.POINTER(lrsdp_info)]),
+    "lrsdp_server_session_open": (C.c_int, [_P, C.c_int64, C.c_int64, _P, _P, _P, _P,
+                                            C.POINTER(C.c_uint64), C.POINTER(C.c_uint64)]),
+    "lrsdp_server_submit_factor": (C.c_int, [_P, C.c_uint64, _P, C.c_int32,
+                                             C.POINTER(lrsdp_opts), C.POINTER(C.c_uint64)]),
+    "lrsdp_server_submit_solve": (C.c_int, [_P, C.c_uint64, _P, _P, _P, C.POINTER(lrsdp_opts),
+                                            C.POINTER(C.c_uint64)]),
+    "lrsdp_server_session_close": (C.c_int, [_P, C.c_uint64, C.POINTER(C.c_uint64)]),
     "lrsdp_server_stats": (C.c_int, [_P, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                      C.POINTER(C.c_int), C.POINTER(C.c_size_t)]),
     "lrsdp_server_destroy": (None, [_P]),
@@ -378,6 +385,43 @@ def lrsdp_server_poll(srv, ticket, wait=False):
         return None
     _ok(rc, "lrsdp_server_poll")
     return st.value, inf.as_dict()
+
+
+def lrsdp_server_session_open(srv, n, m, con, row, col, val):
+    """Returns (session, ticket)."""
+    s, t = C.c_uint64(), C.c_uint64()
+    _ok(lib().lrsdp_server_session_open(srv, int(n), int(m), _ptr(con, torch.int32, m, "con"),
+                                        _ptr(row, torch.int32, m, "row"),
+                                        _ptr(col, torch.int32, m, "col"),
+                                        _ptr(val, torch.float64, m, "val"), C.byref(s), C.byref(t)),
+        "lrsdp_server_session_open")
+    return s.value, t.value
+
+
+def lrsdp_server_submit_factor(srv, session, n, W, k, opts=None):
+    t = C.c_uint64()
+    _ok(lib().lrsdp_server_submit_factor(srv, C.c_uint64(session),
+                                         _ptr(W, torch.float64, int(n) * int(n), "W"), int(k),
+                                         C.byref(opts) if opts is not None else None, C.byref(t)),
+        "lrsdp_server_submit_factor")
+    return t.value
+
+
+def lrsdp_server_submit_solve(srv, session, m, r, y, y_lo=None, opts=None):
+    t = C.c_uint64()
+    _ok(lib().lrsdp_server_submit_solve(srv, C.c_uint64(session), _ptr(r, torch.float64, m, "r"),
+                                        _ptr(y, torch.float64, m, "y"),
+                                        _ptr(y_lo, torch.float64, m, "y_lo"),
+                                        C.byref(opts) if opts is not None else None, C.byref(t)),
+        "lrsdp_server_submit_solve")
+    return t.value
+
+
+def lrsdp_server_session_close(srv, session):
+    t = C.c_uint64()
+    _ok(lib().lrsdp_server_session_close(srv, C.c_uint64(session), C.byref(t)),
+        "lrsdp_server_session_close")
+    return t.value
 
 
 def lrsdp_server_stats(srv):

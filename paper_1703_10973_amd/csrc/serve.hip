@@ -1,14 +1,27 @@
-// Many independent instances: a batch call and a request server.
+// Many Hessian-equation solves on one device: a batch call and a request server.
 //
 // Each worker is a host thread with a context of its own (its own stream, pinned staging and
-// status word on the same device), so instances run concurrently and never share scratch.
-// An instance is the whole hot path: A0 (problem), Algorithm 1 steps 1-2 (factor) and
-// step 3 (solve), then its handles are released.  The kernels and their launch shapes do not
-// depend on what else runs, so a result is bitwise the one the instance gets alone.
+// status word on the same device), so requests run concurrently and never share scratch.
+// The kernels and their launch shapes depend only on their own instance, so a result is
+// bitwise the one the instance gets alone.
 //
-// Admission: the server starts a queued request only while the estimated device memory of
-// the requests in flight, plus its own, stays within the budget (a request larger than the
-// whole budget runs alone).  Requests start in submission order.
+// Requests are of two sorts.
+//   * Instances: the whole hot path, A0 (problem), Algorithm 1 steps 1-2 (factor) and step 3
+//     (solve), after which the handles are released.
+//   * Requests on a session: a session keeps one SDP's data (the problem) and its current
+//     factor resident on the device between requests, the way an interior-point method uses
+//     them (Section 2: one scaling matrix W per step, one or a few right-hand sides per W).
+//     A factor request builds the factor of a new W (steps 1-2); a solve request runs step 3
+//     against the resident factor.  A session has a context of its own (stream and memory
+//     pool), so whichever worker is free runs its next request; its requests run one at a
+//     time, in submission order, and overlap with those of other sessions and instances.
+//
+// Admission by device memory: an instance holds its estimated peak bytes while it runs; a
+// session holds its problem's bytes from open to close and its factor's estimated peak bytes
+// from its first factor request to close.  A request starts only while the bytes held, plus
+// what it adds, fit the budget (a request that alone exceeds the budget runs when nothing
+// else is running).  Requests that need memory are admitted in submission order; a request
+// waiting for its session's previous request does not hold up others.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -23,11 +36,29 @@
 
 namespace {
 
+enum JobKind : int { kInstance = 0, kOpen = 1, kFactor = 2, kSolve = 3, kClose = 4 };
+
+struct Session {
+  uint64_t id = 0;
+  lrsdp_ctx* ctx = nullptr;      // its own context (created by the open request)
+  bool busy = false;             // one of its requests is running
+  bool closing = false;          // close submitted: no further requests are accepted
+  int pending = 0;               // submitted requests not finished
+  int64_t n = 0, m = 0;
+  lrsdp_problem* P = nullptr;
+  lrsdp_factor* F = nullptr;
+  size_t problem_bytes = 0;      // held from open to close
+  size_t factor_bytes = 0;       // held from the first factor request to close
+};
+
 struct Job {
   uint64_t ticket = 0;
-  lrsdp_instance inst{};
+  int kind = kInstance;
+  lrsdp_instance inst{};  // instance: everything; open: n, m and the triplets; factor: W, k;
+                          // solve: r, y, y_lo
   lrsdp_opts opts{};
-  size_t bytes = 0;
+  size_t bytes = 0;       // instance: held while it runs; open / factor: the session's share
+  Session* sess = nullptr;
   int status = LRSDP_PENDING;
   lrsdp_info info{};
   bool done = false;
@@ -48,6 +79,58 @@ int run_instance(lrsdp_ctx* ctx, const lrsdp_instance& in, const lrsdp_opts& o,
   return rc;
 }
 
+void session_release(Session* S) {
+  if (S->F) lrsdp_factor_destroy(S->F);
+  if (S->P) lrsdp_problem_destroy(S->P);
+  if (S->ctx) lrsdp_ctx_destroy(S->ctx);
+  S->F = nullptr;
+  S->P = nullptr;
+  S->ctx = nullptr;
+}
+
+// A session request, on the session's own context, from the worker thread that runs it (one
+// at a time per session).
+int run_session_job(int device, Job* j, lrsdp_info* info) {
+  Session* S = j->sess;
+  const lrsdp_instance& in = j->inst;
+  switch (j->kind) {
+    case kOpen: {
+      const int rc = lrsdp::ctx_create(device, nullptr, 0, false, &S->ctx);
+      if (rc != LRSDP_OK) return rc;
+      return lrsdp_problem_create(S->ctx, in.n, in.m, in.m, in.con, in.row, in.col, in.val,
+                                  &S->P);
+    }
+    case kFactor: {
+      if (!S->P) return LRSDP_ERR_INVALID_ARG;
+      if (S->F) {  // the previous W's factor goes first (its memory is reused)
+        lrsdp_factor_destroy(S->F);
+        S->F = nullptr;
+      }
+      const int rc = lrsdp_factor_create(S->P, in.W, in.k, &j->opts, &S->F);
+      if (rc == LRSDP_OK) {
+        info->setup_ms = S->F->setup_ms;
+        info->tau = S->F->tau;
+        info->eig_sweeps = S->F->eig_sweeps;
+        for (int i = 0; i < 4; ++i) info->phase_ms[i] = S->F->phase_ms[i];
+      }
+      info->status = rc;
+      return rc;
+    }
+    case kSolve:
+      if (!S->F) return LRSDP_ERR_INVALID_ARG;
+      return lrsdp_solve(S->F, in.r, in.y, in.y_lo, &j->opts, info);
+    case kClose:
+      session_release(S);
+      return LRSDP_OK;
+  }
+  return LRSDP_ERR_INVALID_ARG;
+}
+
+size_t problem_bytes_estimate(int64_t n, int64_t m) {
+  return (size_t)(112.0 * m + 16.0 * n + 65536.0 +
+                  (n >= kTGlobalMinN ? 16.0 * (double)n * n : 0.0));
+}
+
 }  // namespace
 
 struct lrsdp_server {
@@ -57,45 +140,95 @@ struct lrsdp_server {
   std::condition_variable cv_work;  // workers: a request may be startable
   std::condition_variable cv_done;  // pollers: a request finished
   std::deque<Job*> queue;
-  std::unordered_map<uint64_t, Job*> jobs;  // every ticket not yet released
-  uint64_t next_ticket = 1;
-  size_t in_flight = 0;
+  std::unordered_map<uint64_t, Job*> jobs;          // every ticket not yet released
+  std::unordered_map<uint64_t, Session*> sessions;  // sessions not yet fully closed
+  uint64_t next_ticket = 1, next_session = 1;
+  size_t in_flight = 0;   // bytes held by running instances and by open sessions
   int running = 0;
   bool stop = false;
   std::vector<std::thread> workers;
   std::vector<lrsdp_ctx*> ctxs;
 
-  // the front request may start now
-  bool startable() const {
-    if (queue.empty()) return false;
-    const size_t b = queue.front()->bytes;
-    return budget == 0 || running == 0 || in_flight + b <= budget;
+  // Bytes a job adds to in_flight when it starts.
+  static size_t need(const Job* j) {
+    if (j->kind == kInstance || j->kind == kOpen) return j->bytes;
+    if (j->kind == kFactor && j->bytes > j->sess->factor_bytes)
+      return j->bytes - j->sess->factor_bytes;
+    return 0;
+  }
+
+  // The first queued job that may start now, or the end of the queue.  A job waiting for its
+  // session's previous request is passed over; one that needs memory the budget cannot give
+  // yet stops the search, so memory is granted in submission order.
+  std::deque<Job*>::iterator pick() {
+    for (auto it = queue.begin(); it != queue.end(); ++it) {
+      Job* j = *it;
+      if (j->sess && j->sess->busy) continue;
+      const size_t b = need(j);
+      if (b == 0 || budget == 0 || running == 0 || in_flight + b <= budget) return it;
+      return queue.end();
+    }
+    return queue.end();
+  }
+
+  void finish(Job* j, int st, const lrsdp_info& info, size_t held) {
+    j->status = st;
+    j->info = info;
+    j->done = true;
+    in_flight -= held;
+    if (Session* S = j->sess) {
+      S->busy = false;
+      --S->pending;
+      if (j->kind == kClose) {
+        in_flight -= S->problem_bytes + S->factor_bytes;
+        S->problem_bytes = S->factor_bytes = 0;
+        sessions.erase(S->id);
+        delete S;
+        j->sess = nullptr;
+      }
+    }
+    --running;
+    cv_done.notify_all();
+    cv_work.notify_all();
   }
 
   void work(lrsdp_ctx* ctx) {
     std::unique_lock<std::mutex> lk(mu);
     for (;;) {
-      cv_work.wait(lk, [&] { return stop || startable(); });
-      if (!startable()) {
-        if (stop && queue.empty()) return;
-        continue;
+      auto it = queue.end();
+      cv_work.wait(lk, [&] { return (it = pick()) != queue.end() || (stop && queue.empty()); });
+      if (it == queue.end()) return;  // stopping, nothing left
+      Job* j = *it;
+      queue.erase(it);
+      size_t held = 0;  // released when the job finishes (instances only)
+      const size_t add = need(j);
+      in_flight += add;
+      if (j->kind == kInstance) held = add;
+      if (Session* S = j->sess) {
+        S->busy = true;
+        if (j->kind == kOpen) {
+          S->problem_bytes = add;
+        } else if (j->kind == kFactor) {
+          S->factor_bytes += add;
+        }
       }
-      Job* j = queue.front();
-      queue.pop_front();
-      in_flight += j->bytes;
       ++running;
       lk.unlock();
       lrsdp_info info{};
-      const int st = run_instance(ctx, j->inst, j->opts, &info);
+      const int st = j->sess ? run_session_job(ctx->device, j, &info)
+                             : run_instance(ctx, j->inst, j->opts, &info);
       lk.lock();
-      j->status = st;
-      j->info = info;
-      j->done = true;
-      in_flight -= j->bytes;
-      --running;
-      cv_done.notify_all();
-      cv_work.notify_all();
+      finish(j, st, info, held);
     }
+  }
+
+  // Queues a job (the lock is held); returns its ticket.
+  uint64_t enqueue(Job* j) {
+    j->ticket = next_ticket++;
+    jobs[j->ticket] = j;
+    queue.push_back(j);
+    if (j->sess) ++j->sess->pending;
+    return j->ticket;
   }
 };
 
@@ -111,9 +244,7 @@ size_t lrsdp_instance_bytes(int64_t n, int64_t m, int32_t k) {
   // workspace) plus the problem (pairs, pattern, owner lists, scratch)
   const double doubles = 6.0 * nn + 2.25 * nk * nk + nk * r + 12.0 * m + 11.0 * nk +
                          (2.0 + k + pair_cap) * nn + pairs * n + nk * r + 8192.0;
-  const double problem = 112.0 * m + 16.0 * n + 65536.0 +
-                         (n >= kTGlobalMinN ? 16.0 * (double)n * n : 0.0);
-  return (size_t)(8.0 * doubles + problem);
+  return (size_t)(8.0 * doubles) + problem_bytes_estimate(n, m);
 }
 
 int lrsdp_server_create(lrsdp_ctx* ctx, int workers, size_t hbm_budget_bytes,
@@ -134,8 +265,9 @@ int lrsdp_server_create(lrsdp_ctx* ctx, int workers, size_t hbm_budget_bytes,
     }
     s->ctxs.push_back(c);
   }
-  for (lrsdp_ctx* c : s->ctxs)
-    s->workers.emplace_back([s, c] {
+  for (int w = 0; w < workers; ++w)
+    s->workers.emplace_back([s, w] {
+      lrsdp_ctx* c = s->ctxs[w];
       (void)hipSetDevice(c->device);
       s->work(c);
     });
@@ -158,13 +290,109 @@ int lrsdp_server_submit(lrsdp_server* s, const lrsdp_instance* inst, const lrsdp
       delete j;
       return LRSDP_ERR_INVALID_ARG;
     }
-    j->ticket = s->next_ticket++;
-    s->jobs[j->ticket] = j;
-    s->queue.push_back(j);
+    *ticket = s->enqueue(j);
   }
-  *ticket = j->ticket;
   s->cv_work.notify_all();
   return LRSDP_OK;
+}
+
+int lrsdp_server_session_open(lrsdp_server* s, int64_t n, int64_t m, const int32_t* con,
+                              const int32_t* row, const int32_t* col, const double* val,
+                              uint64_t* session, uint64_t* ticket) {
+  if (!s || !session || !ticket || n < 2 || m < 1 || !con || !row || !col || !val)
+    return LRSDP_ERR_INVALID_ARG;
+  Session* S = new (std::nothrow) Session();
+  Job* j = new (std::nothrow) Job();
+  if (!S || !j) {
+    delete S;
+    delete j;
+    return LRSDP_ERR_OUT_OF_BUDGET;
+  }
+  S->n = n;
+  S->m = m;
+  j->kind = kOpen;
+  j->sess = S;
+  j->inst.n = n;
+  j->inst.m = m;
+  j->inst.con = con;
+  j->inst.row = row;
+  j->inst.col = col;
+  j->inst.val = val;
+  lrsdp_opts_default(&j->opts);
+  j->bytes = problem_bytes_estimate(n, m);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+      delete S;
+      delete j;
+      return LRSDP_ERR_INVALID_ARG;
+    }
+    S->id = s->next_session++;
+    s->sessions[S->id] = S;
+    *session = S->id;
+    *ticket = s->enqueue(j);
+  }
+  s->cv_work.notify_all();
+  return LRSDP_OK;
+}
+
+namespace {
+
+// Queues a factor, solve or close request on an open session.
+int submit_on_session(lrsdp_server* s, uint64_t session, Job* j, uint64_t* ticket) {
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->sessions.find(session);
+    if (s->stop || it == s->sessions.end() || it->second->closing) {
+      delete j;
+      return LRSDP_ERR_INVALID_ARG;
+    }
+    j->sess = it->second;
+    if (j->kind == kFactor)
+      j->bytes = lrsdp_instance_bytes(j->sess->n, j->sess->m, j->inst.k) -
+                 problem_bytes_estimate(j->sess->n, j->sess->m);
+    if (j->kind == kClose) j->sess->closing = true;
+    *ticket = s->enqueue(j);
+  }
+  s->cv_work.notify_all();
+  return LRSDP_OK;
+}
+
+}  // namespace
+
+int lrsdp_server_submit_factor(lrsdp_server* s, uint64_t session, const double* W, int32_t k,
+                               const lrsdp_opts* opts, uint64_t* ticket) {
+  if (!s || !W || !ticket) return LRSDP_ERR_INVALID_ARG;
+  Job* j = new (std::nothrow) Job();
+  if (!j) return LRSDP_ERR_OUT_OF_BUDGET;
+  j->kind = kFactor;
+  j->inst.W = W;
+  j->inst.k = k;
+  lrsdp_opts_default(&j->opts);
+  if (opts) j->opts = *opts;
+  return submit_on_session(s, session, j, ticket);
+}
+
+int lrsdp_server_submit_solve(lrsdp_server* s, uint64_t session, const double* r, double* y,
+                              double* y_lo, const lrsdp_opts* opts, uint64_t* ticket) {
+  if (!s || !r || !y || !ticket) return LRSDP_ERR_INVALID_ARG;
+  Job* j = new (std::nothrow) Job();
+  if (!j) return LRSDP_ERR_OUT_OF_BUDGET;
+  j->kind = kSolve;
+  j->inst.r = r;
+  j->inst.y = y;
+  j->inst.y_lo = y_lo;
+  lrsdp_opts_default(&j->opts);
+  if (opts) j->opts = *opts;
+  return submit_on_session(s, session, j, ticket);
+}
+
+int lrsdp_server_session_close(lrsdp_server* s, uint64_t session, uint64_t* ticket) {
+  if (!s || !ticket) return LRSDP_ERR_INVALID_ARG;
+  Job* j = new (std::nothrow) Job();
+  if (!j) return LRSDP_ERR_OUT_OF_BUDGET;
+  j->kind = kClose;
+  return submit_on_session(s, session, j, ticket);
 }
 
 int lrsdp_server_poll(lrsdp_server* s, uint64_t ticket, int wait, int* status,
@@ -204,6 +432,11 @@ void lrsdp_server_destroy(lrsdp_server* s) {
   }
   s->cv_work.notify_all();
   for (auto& t : s->workers) t.join();
+  // sessions left open: release their handles (the workers have finished)
+  for (auto& kv : s->sessions) {
+    session_release(kv.second);
+    delete kv.second;
+  }
   for (lrsdp_ctx* c : s->ctxs) lrsdp_ctx_destroy(c);
   for (auto& kv : s->jobs) delete kv.second;
   delete s;

@@ -8,6 +8,7 @@ from it, so a parity test always compares the two on identical data.
 from .generator import (  # noqa: F401
     Instance,
     make_instance,
+    make_path,
     draw_batch_shape,
     draw_serving_shape,
     batch_instances,

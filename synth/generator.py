@@ -102,6 +102,34 @@ def make_instance(n: int, k: int, m: int, mu: float, seed: int) -> Instance:
                     bvec=bvec, lam=np.sort(lam))
 
 
+def make_path(n: int, k: int, m: int, mus, seed: int):
+    """make_instance(n, k, m, mu, seed) for each mu in mus: every draw is shared (the same
+    pattern, Q, uniforms and r), so only W changes, as along an interior-point path.  The QR
+    of the Haar draw is done once."""
+    rng = np.random.default_rng(seed)
+    zgen = rng.standard_normal((n, k))
+    n_off = m - n
+    t = np.sort(rng.choice(n * (n - 1) // 2, size=n_off, replace=False).astype(np.int64))
+    a_off, b_off = _pair_from_linear(t, n)
+    diag = np.arange(n, dtype=np.int32)
+    a = np.concatenate([diag, a_off]).astype(np.int32)
+    b = np.concatenate([diag, b_off]).astype(np.int32)
+    val = np.where(a == b, 1.0, 0.5)
+    q = _haar(rng, n)
+    u_small = rng.uniform(1.0, 2.0, size=n - k)
+    large = rng.uniform(1.0, 2.0, size=k)
+    r = rng.standard_normal(m)
+    bvec = np.einsum("ij,ij->i", zgen[a], zgen[b])
+    out = []
+    for mu in mus:
+        lam = np.concatenate([mu * u_small, large])
+        W = (q * lam[None, :]) @ q.T
+        W = np.ascontiguousarray(0.5 * (W + W.T))
+        out.append(Instance(n=n, k=k, m=m, mu=mu, seed=seed, a=a, b=b, val=val, W=W, r=r,
+                            bvec=bvec, lam=np.sort(lam)))
+    return out
+
+
 def draw_batch_shape(seed: int):
     """Shape of one instance of the batched workload: n log-uniform in [64, 512],
     k uniform in {1..4}, m = min(n(n+1)/2, ceil(3 n k ln n)), mu = 1e-6."""

@@ -176,3 +176,98 @@ def test_server_mix_with_a_large_request(ctx):
     assert np.max(np.abs(got - want)) <= 1e-12 * np.linalg.norm(big.r), (got, want)
     F.close()
     P.close()
+
+
+def test_server_sessions_resident_factors_match_alone(ctx):
+    """Resident sessions beside plain requests: a session on the n = 2950, k = 8 serving shape
+    takes two interior-point steps (a factor request per W, the problem kept) with two and one
+    right-hand sides; a small session and two plain instances run at the same time.  Every
+    answer is bitwise the one the same calls give alone, and meets the target residual."""
+    from test_gpu_large import _sampled_residual
+    n, k, m, mu = draw_serving_shape(50239)
+    big = [make_instance(n, k, m, mu_, seed=50239) for mu_ in (mu, mu * 1e-2)]  # an IPM path
+    small = [make_instance(300, 3, 9000, mu_, seed=71) for mu_ in (1e-3, 1e-5)]
+    plain = [make_instance(250, 2, 5000, 1e-4, seed=72), make_instance(400, 4, 12000, 1e-6,
+                                                                         seed=73)]
+    opts = pk.opts(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO)
+    rng = np.random.default_rng(74)
+    srv = pk.Server(ctx, workers=3)
+    print("sessions: n=2950 k=8 (2 steps, 3 right-hand sides), n=300, two instances",
+          flush=True)
+
+    def session_plan(insts, rhs_per_step):
+        d0 = _device_instance(insts[0])
+        sid, t_open = srv.open_session(insts[0].n, insts[0].m, d0["con"], d0["row"], d0["col"],
+                                       d0["val"])
+        plan, tickets = [], [t_open]
+        for inst, nr in zip(insts, rhs_per_step):
+            W = to_dev(inst.W)
+            tickets.append(srv.submit_factor(sid, W, inst.k, opts))
+            for _ in range(nr):
+                r = to_dev(rng.standard_normal(inst.m))
+                y = torch.zeros(inst.m, dtype=torch.float64, device="cuda")
+                ylo = torch.zeros_like(y)
+                tickets.append(srv.submit_solve(sid, r, y, ylo, opts))
+                plan.append((inst, W, r, y, ylo))
+        tickets.append(srv.close_session(sid))
+        return d0, plan, tickets
+
+    torch.cuda.synchronize()
+    dB, planB, tB = session_plan(big, [2, 1])
+    dS, planS, tS = session_plan(small, [1, 2])
+    devs = [_device_instance(i) for i in plain]
+    tP = [srv.submit(d["n"], d["k"], d["con"], d["row"], d["col"], d["val"], d["W"], d["r"],
+                     d["y"], d["y_lo"], opts) for d in devs]
+    for t in tB + tS + tP:
+        st, info = srv.poll(t, wait=True)
+        assert st == 0, info
+    assert srv.stats()["bytes_in_flight"] == 0
+    srv.close()
+    # alone: the same problem, factor and solve calls on the test's own context
+    for d0, plan in ((dB, planB), (dS, planS)):
+        inst0 = plan[0][0]
+        P = pk.Problem(ctx, inst0.n, inst0.m, d0["con"], d0["row"], d0["col"], d0["val"])
+        F, cur = None, None
+        for inst, W, r, y, ylo in plan:
+            if cur is not W:
+                if F is not None:
+                    F.close()
+                F = pk.Factor(P, W, inst.k, opts)
+                cur = W
+            ya, yla, sa, _ = F.solve(r, opts)
+            assert sa == 0
+            assert np.array_equal(host(y), host(ya)) and np.array_equal(host(ylo), host(yla))
+            if inst.n <= 400:
+                rh = host(r)
+                rt, _ = ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val, rh, host(y),
+                                                   host(ylo))
+                assert rt <= 1e-8, rt
+            else:
+                res = torch.empty_like(y)
+                assert pk._lib.lrsdp_residual_dd(F.handle, r, y, ylo, res) <= 1e-8
+                idx = np.random.default_rng(9).choice(inst.m, 4, replace=False)
+                saved = inst.r
+                inst.r = host(r)
+                want = _sampled_residual(inst, host(y), host(ylo), idx)
+                inst.r = saved
+                assert np.max(np.abs(host(res)[idx] - want)) <= 1e-12 * np.linalg.norm(host(r))
+        F.close()
+        P.close()
+    for inst, d in zip(plain, devs):
+        ya, yla, _ = _alone(ctx, inst, opts)
+        assert np.array_equal(host(d["y"]), ya) and np.array_equal(host(d["y_lo"]), yla)
+
+
+def test_server_session_errors(ctx):
+    inst = make_instance(60, 2, 400, 1e-2, seed=5)
+    d = _device_instance(inst)
+    srv = pk.Server(ctx, workers=2)
+    sid, t = srv.open_session(inst.n, inst.m, d["con"], d["row"], d["col"], d["val"])
+    ts = srv.submit_solve(sid, d["r"], d["y"], d["y_lo"])        # no factor yet
+    assert srv.poll(t, wait=True)[0] == 0
+    assert srv.poll(ts, wait=True)[0] == pk._lib.LRSDP_ERR_INVALID_ARG
+    tc = srv.close_session(sid)
+    with pytest.raises(pk.LrsdpError):                             # closing: refused
+        srv.submit_factor(sid, d["W"], 2)
+    assert srv.poll(tc, wait=True)[0] == 0
+    srv.close()

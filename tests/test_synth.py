@@ -37,3 +37,12 @@ def test_batch_and_serving_shapes():
         n, k, m, mu = draw_serving_shape(s)
         assert 200 <= n <= 3000 and 1 <= k <= 8 and 1e-8 <= mu <= 1e-2
         assert n <= m <= n * (n + 1) // 2
+
+
+def test_make_path_equals_make_instance():
+    from synth import make_instance, make_path
+    path = make_path(50, 2, 300, (1e-2, 1e-6), seed=17)
+    for inst in path:
+        ref = make_instance(50, 2, 300, inst.mu, seed=17)
+        for f in ("a", "b", "val", "W", "r", "bvec", "lam"):
+            assert np.array_equal(getattr(inst, f), getattr(ref, f)), f

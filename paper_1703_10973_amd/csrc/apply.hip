@@ -591,17 +591,17 @@ int precond_apply_f64(const lrsdp_factor* f, const double* v, double* z, hipStre
   if (f->precond == LRSDP_PRECOND_AUG) {
     // H^{-1} v (eq aug_prec, x eliminated): w = B^T G^{-1} v = vec(M U), t = Sh^{-1} w with
     // Sh = tau/2 I + B^T G^{-1} B, z = (v - B t) G^{-1} / tau^2, B t = [A_i . (T U^T)]_i
-    LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.y, w.h, w.t, s));
+    LRSDP_TRY(binv_apply(f->Sinv, nk, f->sinv_split, nk, w.y, nullptr, w.h, w.t, false, s));
     k_smw_out<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, P->ginv,
                                                1.0 / f->tau2, w.t, f->U, v, z);
     LRSDP_HIP(hipGetLastError());
     return LRSDP_OK;
   }
   rows_k(n, k, f->Zt, 2, w.y, w.w, s);                    // w = vec(Z^T M U)
-  LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.w, w.h, w.t, s));  // t = bold S^{-1} w
+  LRSDP_TRY(binv_apply(f->Sinv, nk, f->sinv_split, nk, w.w, nullptr, w.h, w.t, false, s));
   if (refine) {                                           // t += bold S^{-1} (w - bold S t)
     LRSDP_TRY(schur_apply_f64(f, w.t, w.s, s));
-    LRSDP_TRY(trmv_pair_ex(f->Sinv, nk, nk, w.w, w.s, w.h, w.t, true, s));
+    LRSDP_TRY(binv_apply(f->Sinv, nk, f->sinv_split, nk, w.w, w.s, w.h, w.t, true, s));
   }
   rows_k(n, k, f->Z, 1, w.t, w.y, s);                      // Y = Z T
   k_smw_out<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, P->ginv,
@@ -621,12 +621,12 @@ int precond_apply_dd(const lrsdp_factor* f, const double* v, double* z, hipStrea
   rows_k_dd(n, k, f->Zt, 2, w.y, w.yl, w.w, w.wl, s);
   // t = bold S^{-1} w: FP64 inverse, refined against the matrix-free bold S in double-double
   k_dd_combine<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.wl, w.g0);
-  LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.g0, w.h, w.t, s));
+  LRSDP_TRY(binv_apply(f->Sinv, nk, f->sinv_split, nk, w.g0, nullptr, w.h, w.t, false, s));
   LRSDP_HIP(hipMemsetAsync(w.tl, 0, (size_t)nk * sizeof(double), s));
   for (int it = 0; it < nref; ++it) {
     LRSDP_TRY(schur_apply_dd(f, w.t, w.tl, w.s, w.sl, s));
     k_dd_sub_round<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.wl, w.s, w.sl, w.g0);
-    LRSDP_TRY(trmv_pair(f->Sinv, nk, nk, w.g0, w.h, w.g1, s));
+    LRSDP_TRY(binv_apply(f->Sinv, nk, f->sinv_split, nk, w.g0, nullptr, w.h, w.g1, false, s));
     k_dd_accum<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.t, w.tl, w.g1);
   }
   // x = bold U t (dd);  z = (v - x) G^{-1} / tau^2

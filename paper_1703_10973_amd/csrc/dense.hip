@@ -876,6 +876,36 @@ __global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, 
   if (lane == 0) y[row] = kAcc ? y[row] + t : t;
 }
 
+// y[r] = (b[r] - bs[r]) - sum_{c < K} A[r][c] x[c] for rows r < R (kSub; else b[r] - ...), one
+// wavefront per row with eight loads in flight per lane, like k_gemv_tri.
+template <bool kSub>
+__global__ __launch_bounds__(256) void k_gemv_rect(const double* __restrict__ A, int R, int K,
+                                                   int lda, const double* __restrict__ x,
+                                                   const double* __restrict__ b,
+                                                   const double* __restrict__ bs,
+                                                   double* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= R) return;
+  const double* a = A + (size_t)row * lda;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int c = lane;
+  for (; c + 7 * 64 < K; c += 8 * 64) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] = fma(a[c + u * 64], x[c + u * 64], s[u]);
+  }
+  for (int u = 0; c < K; c += 64, ++u) s[u] = fma(a[c], x[c], s[u]);
+  double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+  t = wave_sum(t);
+  if (lane == 0) y[row] = (kSub ? b[row] - bs[row] : b[row]) - t;
+}
+
+__global__ void k_copy_acc(int n, const double* __restrict__ src, double* __restrict__ dst,
+                           int acc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = acc ? dst[i] + src[i] : src[i];
+}
+
 int split64(int N) {
   int h = (N + 1) / 2;
   int n1 = ((h + NB - 1) / NB) * NB;
@@ -1126,6 +1156,103 @@ static int potrf_inv_rec(double* A, int N, int lda, double* Li, int ldi, int* fl
 int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
               bool want_L, hipStream_t s, const SideStream* side) {
   return potrf_inv_rec(A, N, lda, Li, ldi, flag, tmp, want_L, s, side, 0);
+}
+
+// From this size on the top node is kept block-explicit.  Below it the L^{-1} array stays in
+// the MALL and its single triangular pair per direction beats the block form's three dependent
+// GEMVs by more than the two skipped products save over a solve (n k = 5000: setup -0.6 ms,
+// PCG +0.3 ms per solve, PCG alone -12 %); above it the GEMVs stream the array from HBM and
+// the skipped products are a large share of the setup.
+constexpr int kBlockInvMin = 8192;
+
+int potrf_binv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
+               hipStream_t s, const SideStream* side, int* split) {
+  *split = 0;
+  if (N < kBlockInvMin) return potrf_inv_rec(A, N, lda, Li, ldi, flag, tmp, false, s, side, 0);
+  const int N1 = split64(N), N2 = N - N1;
+  double* A21 = A + (size_t)N1 * lda;
+  double* A22 = A21 + N1;
+  double* L21 = Li + (size_t)N1 * ldi;  // the (2, 1) block of Li keeps L21 itself
+  double* Li22 = L21 + N1;
+  // each child joins its own side-stream product before it returns, so tmp is free again
+  LRSDP_TRY(potrf_inv_rec(A, N1, lda, Li, ldi, flag, tmp, false, s, side, 1));
+  {  // L21 = A21 L11^{-T}
+    GemmArgs g;
+    g.M = N2; g.N = N1; g.K = N1;
+    g.A = A21; g.lda = lda;
+    g.B = Li; g.ldb = ldi; g.transB = true;  // op(B)[k][j] = L11^{-1}[j][k], zero for k > j
+    g.C = L21; g.ldc = ldi;
+    g.flags = kKToCol;
+    LRSDP_TRY(gemm(g, s));
+  }
+  {  // A22 -= L21 L21^T (lower)
+    GemmArgs g;
+    g.M = N2; g.N = N2; g.K = N1;
+    g.A = L21; g.lda = ldi;
+    g.B = L21; g.ldb = ldi; g.transB = true;
+    g.C = A22; g.ldc = lda;
+    g.alpha = -1.0; g.beta = 1.0; g.flags = kLowerOut;
+    LRSDP_TRY(gemm(g, s));
+  }
+  LRSDP_TRY(potrf_inv_rec(A22, N2, lda, Li22, ldi, flag, tmp, false, s, side, 1));
+  *split = N1;
+  return LRSDP_OK;
+}
+
+int binv_apply(const double* M, int N, int split, int ld, const double* x, const double* xsub,
+               double* tmp, double* y, bool accumulate, hipStream_t s) {
+  if (split <= 0) return trmv_pair_ex(M, N, ld, x, xsub, tmp, y, accumulate, s);
+  ProfMark pm = prof_begin(LRSDP_K_GEMV, s);
+  const int N1 = split, N2 = N - N1;
+  double* T = tmp;      // [t1; t2]
+  double* U = tmp + N;  // [u1; u2]
+  const double* M21 = M + (size_t)N1 * ld;  // L21 (lower part)
+  const double* M12 = M + N1;               // L21^T (mirrored into the upper part)
+  const double* M22 = M21 + N1;
+  const int g1 = (N1 + 3) / 4, g2 = (N2 + 3) / 4;
+  // forward, L^{-1}: t1 = L11^{-1} w1; t2 = w2 - L21 t1; u2 = L22^{-1} t2
+  if (xsub) {
+    k_gemv_tri<true, false><<<g1, 256, 0, s>>>(M, N1, ld, x, xsub, T, 0);
+    k_gemv_rect<true><<<g2, 256, 0, s>>>(M21, N2, N1, ld, T, x + N1, xsub + N1, T + N1);
+  } else {
+    k_gemv_tri<false, false><<<g1, 256, 0, s>>>(M, N1, ld, x, nullptr, T, 0);
+    k_gemv_rect<false><<<g2, 256, 0, s>>>(M21, N2, N1, ld, T, x + N1, nullptr, T + N1);
+  }
+  k_gemv_tri<false, false><<<g2, 256, 0, s>>>(M22, N2, ld, T + N1, nullptr, U + N1, 0);
+  // backward, L^{-T}: t2 = L22^{-T} u2; u1 = t1 - L21^T t2; y1 = L11^{-T} u1; y2 = t2
+  k_gemv_tri<false, false><<<g2, 256, 0, s>>>(M22, N2, ld, U + N1, nullptr, T + N1, 1);
+  k_gemv_rect<false><<<g1, 256, 0, s>>>(M12, N1, N2, ld, T + N1, T, nullptr, U);
+  if (accumulate) k_gemv_tri<false, true><<<g1, 256, 0, s>>>(M, N1, ld, U, nullptr, y, 1);
+  else k_gemv_tri<false, false><<<g1, 256, 0, s>>>(M, N1, ld, U, nullptr, y, 1);
+  k_copy_acc<<<(N2 + 255) / 256, 256, 0, s>>>(N2, T + N1, y + N1, accumulate ? 1 : 0);
+  LRSDP_HIP(hipGetLastError());
+  prof_end(pm, s, 8.0 * (double)N * (N + 1) + 64.0 * N, 2.0 * (double)N * (N + 1));
+  return LRSDP_OK;
+}
+
+int binv_full_inverse(double* Li, int N, int split, int ld, double* tmp, hipStream_t s) {
+  if (split <= 0) return LRSDP_OK;
+  const int N1 = split, N2 = N - N1;
+  double* L21 = Li + (size_t)N1 * ld;
+  {  // tmp = L21 L11^{-1}
+    GemmArgs g;
+    g.M = N2; g.N = N1; g.K = N1;
+    g.A = L21; g.lda = ld;
+    g.B = Li; g.ldb = ld;  // L11^{-1}[k][j], zero for k < j
+    g.C = tmp; g.ldc = N1;
+    g.flags = kKFromCol | kInverseOnly;
+    LRSDP_TRY(gemm(g, s));
+  }
+  {  // (L^{-1})_21 = -L22^{-1} tmp
+    GemmArgs g;
+    g.M = N2; g.N = N1; g.K = N2;
+    g.A = L21 + N1; g.lda = ld;  // L22^{-1}, zero for k > i
+    g.B = tmp; g.ldb = N1;
+    g.C = L21; g.ldc = ld;
+    g.alpha = -1.0; g.flags = kKToRow | kInverseOnly;
+    LRSDP_TRY(gemm(g, s));
+  }
+  return LRSDP_OK;
 }
 
 int trmv_pair_ex(const double* M, int N, int ld, const double* x, const double* xsub,

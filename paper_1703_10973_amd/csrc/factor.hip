@@ -241,7 +241,7 @@ __global__ void k_f64_to_bf16(size_t cnt, const double* a, uint16_t* b) {
 
 size_t work_doubles(int n, int m, int k) {
   const size_t nk = (size_t)n * k;
-  return 12 * (size_t)m + 11 * nk + 2 * (size_t)k * k + 8192;
+  return 12 * (size_t)m + 12 * nk + 2 * (size_t)k * k + 8192;
 }
 
 Work work_view(const lrsdp_factor* f) {
@@ -253,7 +253,7 @@ Work work_view(const lrsdp_factor* f) {
     *pp = b;
     b += m;
   }
-  double** kv[] = {&w.w, &w.wl, &w.t, &w.tl, &w.s, &w.sl, &w.y, &w.yl, &w.g0, &w.g1, &w.h};
+  double** kv[] = {&w.w, &w.wl, &w.t, &w.tl, &w.s, &w.sl, &w.y, &w.yl, &w.g0, &w.g1, &w.h, &w.h2};
   for (auto pp : kv) {
     *pp = b;
     b += nk;
@@ -312,9 +312,15 @@ int export_sinv(const lrsdp_factor* f, double* out, hipStream_t s) {
                      s) != hipSuccess)
     rc = LRSDP_ERR_DEVICE;
   if (rc == LRSDP_OK) rc = zero_upper(Lt, nk, nk, s);
+  // a block-explicit factor: its (2, 1) block holds L21; form (L^{-1})_21 for the export
+  double* X = nullptr;
+  const size_t xs = f->sinv_split > 0 ? (size_t)(nk - f->sinv_split) * f->sinv_split : 0;
+  if (rc == LRSDP_OK && xs) rc = dev_alloc_n(ctx, &X, xs);
+  if (rc == LRSDP_OK && xs) rc = binv_full_inverse(Lt, nk, f->sinv_split, nk, X, s);
   if (rc == LRSDP_OK) rc = lauum(Lt, nk, nk, out, nk, s);
   if (rc == LRSDP_OK) rc = mirror_lower(out, nk, nk, s);
   if (hipStreamSynchronize(s) != hipSuccess && rc == LRSDP_OK) rc = LRSDP_ERR_DEVICE;
+  dev_free(ctx, X, xs * sizeof(double));
   dev_free(ctx, Lt, (size_t)nk * nk * sizeof(double));
   return rc;
 }
@@ -366,7 +372,8 @@ static int factor_setup_aug(lrsdp_factor* f, std::chrono::steady_clock::time_poi
     }
     SideStream side;
     if ((rc = ctx_side(ctx, &side))) break;
-    if ((rc = potrf_inv(Sb, nk, nk, f->Sinv, nk, flag_S, ptmp, false, s, &side))) break;
+    if ((rc = potrf_binv(Sb, nk, nk, f->Sinv, nk, flag_S, ptmp, s, &side, &f->sinv_split)))
+      break;
     if ((rc = mirror_lower(f->Sinv, nk, nk, s))) break;
     if (hipEventRecord(ev[4], s) != hipSuccess) {
       rc = LRSDP_ERR_DEVICE;
@@ -583,7 +590,8 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
     }
     SideStream side;
     if ((rc = ctx_side(ctx, &side))) break;
-    if ((rc = potrf_inv(S, nk, nk, f->Sinv, nk, flag_S, ptmp.p, false, s, &side))) break;
+    if ((rc = potrf_binv(S, nk, nk, f->Sinv, nk, flag_S, ptmp.p, s, &side, &f->sinv_split)))
+      break;
     if ((rc = mirror_lower(f->Sinv, nk, nk, s))) break;
     if (hipEventRecord(ev[4], s) != hipSuccess) {
       rc = LRSDP_ERR_DEVICE;

@@ -161,7 +161,9 @@ struct lrsdp_factor {
   double* U = nullptr;               // k x n (n x k column-major)
   double* Z = nullptr;               // n x n lower, Z Z^T = 2 W0 + U U^T
   double* Zt = nullptr;              // n x n, Z^T
-  double* Sinv = nullptr;            // nk x nk: L^{-1} (lower) and L^{-T} (upper), bold S = L L^T
+  double* Sinv = nullptr;            // nk x nk: L^{-1} (lower) and L^{-T} (upper), bold S = L L^T,
+                                     // block-explicit above the right-looking size (sinv_split)
+  int sinv_split = 0;                // 0: Sinv holds L^{-1}; else N1 of potrf_binv's blocks
   double* QN = nullptr;              // nk x r orthonormal deflation basis
   // per-solve work vectors (allocated with the factor)
   double* work = nullptr;            // see factor.hip for the carve-up
@@ -183,7 +185,7 @@ struct Work {
   // m-vectors
   double *x, *r, *z, *p, *q, *t0, *t1, *t2, *t3, *ylo, *dd0, *dd1;
   // nk-vectors / k x n blocks
-  double *w, *wl, *t, *tl, *s, *sl, *y, *yl, *g0, *g1, *h;
+  double *w, *wl, *t, *tl, *s, *sl, *y, *yl, *g0, *g1, *h, *h2;  // h, h2 contiguous
   // small
   double *kk;     // k x k
   double *part;   // reduction partials

@@ -318,3 +318,52 @@ def test_hessian_apply_large_n(ctx):
     assert np.max(np.abs(got - want)) <= 1e-12 * np.linalg.norm(inst.r), (got, want)
     F.close()
     P.close()
+
+
+@pytest.mark.parametrize("precond", ["smw", "aug"])
+def test_block_explicit_factor_matches_oracle(ctx, precond):
+    """nk = 8400 is above the block-explicit size, so the factor of bold S (or of the augmented
+    trailing block) is kept as L11^{-1}, L21, L22^{-1}.  The exported inverse (the library then
+    forms the full L^{-1}), every preconditioner mode and the solve match the oracle.  (At this
+    size the checks use a random block and the bound kappa <= lambda_max / lambda_min, with
+    Gershgorin's bound on lambda_max and a lower bound on the smallest eigenvalue: tau^2 for deflated bold S, tau / 2 for the augmented block.)"""
+    from oracle import aug
+    inst = make_instance(2100, 4, 24000, 1e-2, seed=17)
+    nk = inst.n * inst.k
+    P = problem_from(ctx, inst)
+    o = pk.opts(precond=1 if precond == "aug" else 0)
+    F = pk.Factor(P, to_dev(inst.W), inst.k, o)
+    ex = F.export(U=True, Sinv=True)
+    U, tau = host(ex["U"]).T, ex["tau"]
+    C = alg1.Constraints(inst.n, inst.a, inst.b, inst.val)
+    Sinv = host(ex["Sinv"])
+    g = C.g
+    v = np.random.default_rng(3).standard_normal(inst.m)
+    if precond == "aug":
+        S = aug.trailing_schur(C, U, tau)
+        lam_min = tau / 2
+        B = aug.bold_B(C, U)
+        t = np.linalg.solve(S, B.T @ (v / g))
+        zo = (v - B @ t) / (tau * tau * g)
+    else:
+        Fo = alg1.factor(C, inst.W, inst.k, tau_rule="mean")
+        c = np.einsum("pj,pj->j", U, Fo.split.U)
+        d = np.repeat(np.sign(c), inst.n)
+        S = d[:, None] * Fo.S * d[None, :]
+        lam_min = tau * tau
+        zo = alg1.precond_apply(Fo, v)
+    X = np.random.default_rng(4).standard_normal((nk, 4))
+    lam_max = np.max(np.abs(S).sum(axis=1))  # Gershgorin: an upper bound
+    kap = lam_max / lam_min
+    err = np.linalg.norm(Sinv @ (S @ X) - X) / np.linalg.norm(X)
+    assert err <= 1e-12 * kap, (err, kap)
+    modes = (0,) if precond == "aug" else (0, 1, 2)
+    for mode in modes:
+        assert rel(host(F.precond_apply(to_dev(v), mode=mode)), zo) <= 1e-10, mode
+    y, ylo, st, info = F.solve(to_dev(inst.r), o)
+    assert st == 0, info
+    r_true, _ = ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val, inst.r, host(y),
+                                           host(ylo))
+    assert r_true <= 1e-8
+    F.close()
+    P.close()

@@ -190,9 +190,17 @@ class Factor:
             pass
 
 
+def _caller_work_done(ctx: "Context"):
+    """The server's and the batch's workers run on streams of their own, which are not ordered
+    after the caller's: finish what the caller's current stream still has to write into the
+    request's tensors (inputs, and outputs such as a freshly zeroed y) before handing them over."""
+    torch.cuda.current_stream(ctx.device).synchronize()
+
+
 class Server:
     """Request server over the C ABI: submit instances, poll their results.  Each request
-    keeps references to its tensors until its result has been polled."""
+    keeps references to its tensors until its result has been polled.  Submissions first wait
+    for the caller's current stream, so tensors it is still writing are complete."""
 
     def __init__(self, ctx: "Context", workers=8, hbm_budget_bytes=0):
         self.ctx = ctx
@@ -203,6 +211,7 @@ class Server:
         ctx._children.add(self)
 
     def submit(self, n, k, con, row, col, val, W, r, y, y_lo=None, options=None):
+        _caller_work_done(self.ctx)
         inst = make_instance(n, k, con, row, col, val, W, r, y, y_lo)
         t = lrsdp_server_submit(self.handle, inst, options)
         self._keep[t] = (con, row, col, val, W, r, y, y_lo)
@@ -210,6 +219,7 @@ class Server:
 
     def open_session(self, n, m, con, row, col, val):
         """A resident session for one SDP's data; returns (session, ticket)."""
+        _caller_work_done(self.ctx)
         sid, t = lrsdp_server_session_open(self.handle, n, m, con, row, col, val)
         self._keep[t] = (con, row, col, val)
         self._sessions[sid] = (int(n), int(m))
@@ -217,12 +227,14 @@ class Server:
 
     def submit_factor(self, session, W, k, options=None):
         n, _ = self._sessions[session]
+        _caller_work_done(self.ctx)
         t = lrsdp_server_submit_factor(self.handle, session, n, W, k, options)
         self._keep[t] = (W,)
         return t
 
     def submit_solve(self, session, r, y, y_lo=None, options=None):
         _, m = self._sessions[session]
+        _caller_work_done(self.ctx)
         t = lrsdp_server_submit_solve(self.handle, session, m, r, y, y_lo, options)
         self._keep[t] = (r, y, y_lo)
         return t
@@ -256,6 +268,7 @@ class Server:
 def solve_batch(ctx: "Context", instances, options=None, workers=8):
     """instances: list of dicts with n, k, con, row, col, val, W, r, y and optionally y_lo
     (torch device tensors).  Returns (statuses, infos)."""
+    _caller_work_done(ctx)
     insts = [make_instance(d["n"], d["k"], d["con"], d["row"], d["col"], d["val"], d["W"],
                            d["r"], d["y"], d.get("y_lo")) for d in instances]
     return lrsdp_solve_batch(ctx.handle, insts, options, workers)

@@ -241,6 +241,13 @@ int ctx_create(int device, void* stream, size_t budget, bool blocking, lrsdp_ctx
       return LRSDP_ERR_DEVICE;
     }
   }
+  for (hipEvent_t& e : c->scal_ev) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      e = nullptr;
+      lrsdp_ctx_destroy(c);
+      return LRSDP_ERR_DEVICE;
+    }
+  }
   *out = c;
   return LRSDP_OK;
 }
@@ -270,6 +277,8 @@ void ctx_release(lrsdp_ctx* c) {
   }
   pool_trim(c, 0);
   for (hipEvent_t e : c->phase_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->scal_ev)
     if (e) (void)hipEventDestroy(e);
   if (c->h_pinned) (void)hipHostFree(c->h_pinned);
   if (c->d_flag) (void)hipFree(c->d_flag);

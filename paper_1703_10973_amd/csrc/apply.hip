@@ -343,9 +343,14 @@ __global__ void k_lowrank_add(int m, int n, int k, const int32_t* a, const int32
 }
 
 // ---------------------------------------------------------------- nk-vector helpers
-__global__ void k_dd_combine(int N, const double* h, const double* l, double* out) {
+// out = h + l rounded to FP64; zero[i] = 0 when zero is given
+__global__ void k_dd_combine(int N, const double* h, const double* l, double* out,
+                             double* zero) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < N) out[i] = h[i] + l[i];
+  if (i < N) {
+    out[i] = h[i] + l[i];
+    if (zero) zero[i] = 0.0;
+  }
 }
 // (ah, al) - (bh, bl) rounded to FP64
 __global__ void k_dd_sub_round(int N, const double* ah, const double* al, const double* bh,
@@ -620,9 +625,8 @@ int precond_apply_dd(const lrsdp_factor* f, const double* v, double* z, hipStrea
   spmm_U_dd(P, k, P->ginv, v, nullptr, f->U, w.y, w.yl, s);
   rows_k_dd(n, k, f->Zt, 2, w.y, w.yl, w.w, w.wl, s);
   // t = bold S^{-1} w: FP64 inverse, refined against the matrix-free bold S in double-double
-  k_dd_combine<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.wl, w.g0);
+  k_dd_combine<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.wl, w.g0, w.tl);  // tl = 0
   LRSDP_TRY(binv_apply(f->Sinv, nk, f->sinv_split, nk, w.g0, nullptr, w.h, w.t, false, s));
-  LRSDP_HIP(hipMemsetAsync(w.tl, 0, (size_t)nk * sizeof(double), s));
   for (int it = 0; it < nref; ++it) {
     LRSDP_TRY(schur_apply_dd(f, w.t, w.tl, w.s, w.sl, s));
     k_dd_sub_round<<<grid_for(nk, 256), 256, 0, s>>>(nk, w.w, w.wl, w.s, w.sl, w.g0);

@@ -60,7 +60,7 @@ int ctx_side(lrsdp_ctx* ctx, SideStream* out);
 size_t potrf_inv_tmp_doubles(int N);
 int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
               bool want_L, hipStream_t s, const SideStream* side = nullptr);
-// Cholesky A = L L^T with a block-explicit inverse.  Below a size (8192) the result is that of
+// Cholesky A = L L^T with a block-explicit inverse.  Below a size (4096) the result is that of
 // potrf_inv (Li holds L^{-1}, *split = 0).  From it on the top node keeps L11^{-1} in Li's
 // (1, 1) block, L21 itself in its (2, 1) block and L22^{-1} in its (2, 2) block (*split = N1):
 // the two products that would turn L21 into (L^{-1})_21 are the largest of the factorization

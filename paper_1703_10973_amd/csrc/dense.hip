@@ -849,20 +849,22 @@ __global__ __launch_bounds__(256) void k_gemv(const double* __restrict__ A, int 
   if (lane == 0) y[row] = s;
 }
 
-// y = tri(A) x with tri the lower (upper = 0) or upper (upper = 1) triangle including the
-// diagonal; one wavefront per row, eight independent accumulators so that eight loads per
+// y = tri(A) x for rows r < R of A, with tri the lower (upper = 0: columns [0, min(r + 1, C)))
+// or upper (upper = 1: columns [r, C)) part including the diagonal.  One wavefront per row, eight independent accumulators so that eight loads per
 // lane are in flight (the rows are long and the product is bound by HBM).
-// kSub: the vector is x - xs (each difference rounded once); kAcc: y += the product.
+// kSub: the vector is x - xs (each difference rounded once); kAcc: y += the product.  When y2
+// is given, the row's result (y's new value) is also stored there (y2[r] += it when acc2).
 template <bool kSub, bool kAcc>
-__global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, int N, int lda,
-                                                  const double* __restrict__ x,
+__global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, int R, int C,
+                                                  int lda, const double* __restrict__ x,
                                                   const double* __restrict__ xs,
-                                                  double* __restrict__ y, int upper) {
+                                                  double* __restrict__ y, int upper,
+                                                  double* __restrict__ y2, int acc2) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= N) return;
+  if (row >= R) return;
   const double* a = A + (size_t)row * lda;
-  const int lo = upper ? row : 0, hi = upper ? N : row + 1;
+  const int lo = upper ? row : 0, hi = upper ? C : min(row + 1, C);
   auto xv = [&](int c) { return kSub ? x[c] - xs[c] : x[c]; };
   double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int c = lo + lane;
@@ -873,7 +875,10 @@ __global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, 
   for (int u = 0; c < hi; c += 64, ++u) s[u] = fma(a[c], xv(c), s[u]);
   double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   t = wave_sum(t);
-  if (lane == 0) y[row] = kAcc ? y[row] + t : t;
+  if (lane == 0) {
+    y[row] = kAcc ? y[row] + t : t;
+    if (y2) y2[row] = acc2 ? y2[row] + t : t;
+  }
 }
 
 // y[r] = (b[r] - bs[r]) - sum_{c < K} A[r][c] x[c] for rows r < R (kSub; else b[r] - ...), one
@@ -898,12 +903,6 @@ __global__ __launch_bounds__(256) void k_gemv_rect(const double* __restrict__ A,
   double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   t = wave_sum(t);
   if (lane == 0) y[row] = (kSub ? b[row] - bs[row] : b[row]) - t;
-}
-
-__global__ void k_copy_acc(int n, const double* __restrict__ src, double* __restrict__ dst,
-                           int acc) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) dst[i] = acc ? dst[i] + src[i] : src[i];
 }
 
 int split64(int N) {
@@ -1158,12 +1157,14 @@ int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double*
   return potrf_inv_rec(A, N, lda, Li, ldi, flag, tmp, want_L, s, side, 0);
 }
 
-// From this size on the top node is kept block-explicit.  Below it the L^{-1} array stays in
-// the MALL and its single triangular pair per direction beats the block form's three dependent
-// GEMVs by more than the two skipped products save over a solve (n k = 5000: setup -0.6 ms,
-// PCG +0.3 ms per solve, PCG alone -12 %); above it the GEMVs stream the array from HBM and
-// the skipped products are a large share of the setup.
-constexpr int kBlockInvMin = 8192;
+// From this size on the top node is kept block-explicit: its (2, 1) block keeps L21 and the
+// two products that would turn it into (L^{-1})_21 = -L22^{-1} L21 L11^{-1} are skipped, the
+// largest of the inverse work (n k = 5000: the factor of bold S 3.96 -> 3.33 ms).  Applying L^{-1} then
+// takes six dependent GEMVs over the same bytes instead of two (PCG +0.3 ms per solve there).
+// (Keeping -L21 L11^{-1} instead, formed on the side stream while the trailing block factors,
+// needs four: at n k = 5000 it cost 0.4 ms more setup than it saved in the PCG, and at
+// n k = 40000 the product competed with the trailing factorization: 528 -> 661 ms.)
+constexpr int kBlockInvMin = 4096;
 
 int potrf_binv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
                hipStream_t s, const SideStream* side, int* split) {
@@ -1212,19 +1213,23 @@ int binv_apply(const double* M, int N, int split, int ld, const double* x, const
   const int g1 = (N1 + 3) / 4, g2 = (N2 + 3) / 4;
   // forward, L^{-1}: t1 = L11^{-1} w1; t2 = w2 - L21 t1; u2 = L22^{-1} t2
   if (xsub) {
-    k_gemv_tri<true, false><<<g1, 256, 0, s>>>(M, N1, ld, x, xsub, T, 0);
+    k_gemv_tri<true, false><<<g1, 256, 0, s>>>(M, N1, N1, ld, x, xsub, T, 0, nullptr, 0);
     k_gemv_rect<true><<<g2, 256, 0, s>>>(M21, N2, N1, ld, T, x + N1, xsub + N1, T + N1);
   } else {
-    k_gemv_tri<false, false><<<g1, 256, 0, s>>>(M, N1, ld, x, nullptr, T, 0);
+    k_gemv_tri<false, false><<<g1, 256, 0, s>>>(M, N1, N1, ld, x, nullptr, T, 0, nullptr, 0);
     k_gemv_rect<false><<<g2, 256, 0, s>>>(M21, N2, N1, ld, T, x + N1, nullptr, T + N1);
   }
-  k_gemv_tri<false, false><<<g2, 256, 0, s>>>(M22, N2, ld, T + N1, nullptr, U + N1, 0);
-  // backward, L^{-T}: t2 = L22^{-T} u2; u1 = t1 - L21^T t2; y1 = L11^{-T} u1; y2 = t2
-  k_gemv_tri<false, false><<<g2, 256, 0, s>>>(M22, N2, ld, U + N1, nullptr, T + N1, 1);
+  k_gemv_tri<false, false><<<g2, 256, 0, s>>>(M22, N2, N2, ld, T + N1, nullptr, U + N1, 0,
+                                              nullptr, 0);
+  // backward, L^{-T}: t2 = L22^{-T} u2 (also the answer's second block); u1 = t1 - L21^T t2;
+  // y1 = L11^{-T} u1
+  k_gemv_tri<false, false><<<g2, 256, 0, s>>>(M22, N2, N2, ld, U + N1, nullptr, T + N1, 1,
+                                              y + N1, accumulate ? 1 : 0);
   k_gemv_rect<false><<<g1, 256, 0, s>>>(M12, N1, N2, ld, T + N1, T, nullptr, U);
-  if (accumulate) k_gemv_tri<false, true><<<g1, 256, 0, s>>>(M, N1, ld, U, nullptr, y, 1);
-  else k_gemv_tri<false, false><<<g1, 256, 0, s>>>(M, N1, ld, U, nullptr, y, 1);
-  k_copy_acc<<<(N2 + 255) / 256, 256, 0, s>>>(N2, T + N1, y + N1, accumulate ? 1 : 0);
+  if (accumulate)
+    k_gemv_tri<false, true><<<g1, 256, 0, s>>>(M, N1, N1, ld, U, nullptr, y, 1, nullptr, 0);
+  else
+    k_gemv_tri<false, false><<<g1, 256, 0, s>>>(M, N1, N1, ld, U, nullptr, y, 1, nullptr, 0);
   LRSDP_HIP(hipGetLastError());
   prof_end(pm, s, 8.0 * (double)N * (N + 1) + 64.0 * N, 2.0 * (double)N * (N + 1));
   return LRSDP_OK;
@@ -1259,10 +1264,14 @@ int trmv_pair_ex(const double* M, int N, int ld, const double* x, const double* 
                  double* tmp, double* y, bool accumulate, hipStream_t s) {
   ProfMark pm = prof_begin(LRSDP_K_GEMV, s);
   const int grid = (N + 3) / 4;
-  if (xsub) k_gemv_tri<true, false><<<grid, 256, 0, s>>>(M, N, ld, x, xsub, tmp, 0);
-  else k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, ld, x, nullptr, tmp, 0);
-  if (accumulate) k_gemv_tri<false, true><<<grid, 256, 0, s>>>(M, N, ld, tmp, nullptr, y, 1);
-  else k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, ld, tmp, nullptr, y, 1);
+  if (xsub)
+    k_gemv_tri<true, false><<<grid, 256, 0, s>>>(M, N, N, ld, x, xsub, tmp, 0, nullptr, 0);
+  else
+    k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, N, ld, x, nullptr, tmp, 0, nullptr, 0);
+  if (accumulate)
+    k_gemv_tri<false, true><<<grid, 256, 0, s>>>(M, N, N, ld, tmp, nullptr, y, 1, nullptr, 0);
+  else
+    k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, N, ld, tmp, nullptr, y, 1, nullptr, 0);
   LRSDP_HIP(hipGetLastError());
   prof_end(pm, s, 8.0 * (double)N * (N + 1) + 32.0 * N, 2.0 * (double)N * (N + 1));
   return LRSDP_OK;

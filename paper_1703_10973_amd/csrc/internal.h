@@ -44,6 +44,7 @@ struct lrsdp_ctx {
   hipEvent_t side_ev[48] = {};  // its join events, two per recursion depth
   double* h_pinned = nullptr;   // small pinned host staging area (scalars)
   hipEvent_t phase_ev[5] = {};  // boundaries of the setup phases of a factor
+  hipEvent_t scal_ev[2] = {};   // PCG: the host copies of two iterations' scalars are done
   int* d_flag = nullptr;        // device error/status words: [0] general and bold S, [1] Z,
                                 // [2] scratch for factorizations whose failure is not an error
   int children = 0;             // live problems created under this context

@@ -127,14 +127,6 @@ int dot(const lrsdp_factor* f, int m, const double* a, const double* b, double* 
   return LRSDP_OK;
 }
 
-int read_scalars(lrsdp_ctx* ctx, const double* sc, int count, double* host) {
-  LRSDP_HIP(hipMemcpyAsync(ctx->h_pinned, sc, count * sizeof(double), hipMemcpyDeviceToHost,
-                           ctx->stream));
-  LRSDP_HIP(hipStreamSynchronize(ctx->stream));
-  for (int i = 0; i < count; ++i) host[i] = ctx->h_pinned[i];
-  return LRSDP_OK;
-}
-
 struct PcgOut {
   int iters = 0;
   double relres = 1.0;
@@ -160,18 +152,39 @@ int pcg(lrsdp_factor* f, const double* b, double eps, int max_iter, HM Hmul, PM 
   // The starting scalars (r.r, r.z) are read together with the first iteration's: a zero
   // right-hand side or an indefinite preconditioner is then caught one iteration late, and
   // the first iteration's (meaningless) update of x is undone.
-  double h[8];
-  double rr0 = 0.0;
+  // Each iteration's scalars go to a host slot of their own behind an event.  While the host
+  // waits for them, the iteration's preconditioner step (z, r.z and p, which touch neither
+  // x nor r) is already queued when the residual history says that the iteration will not be
+  // the last one, so the device does not idle through the host's check.  A wrong guess costs
+  // that step's work once; x and r are those of the stopping iteration either way, and every
+  // kernel runs on the same data as without the look-ahead.
+  double rr0 = 0.0, rel1 = 1.0, rel2 = 1.0;  // relative residuals of iterations it-1, it-2
   out->iters = 0;
   out->relres = 1.0;
   out->status = LRSDP_NOT_CONVERGED;
   int cur = kRho0, nxt = kRho1;
+  auto precond_step = [&]() -> int {
+    LRSDP_TRY(Pinv(w.r, w.z));
+    LRSDP_TRY(dot(f, m, w.r, w.z, w.part, sc + nxt, s));
+    k_update_p<<<vg, kT, 0, s>>>(m, sc, nxt, cur, w.z, w.p);
+    return LRSDP_OK;
+  };
   for (int it = 1; it <= max_iter; ++it) {
     LRSDP_TRY(Hmul(w.p, w.q));
     LRSDP_TRY(dot(f, m, w.p, w.q, w.part, sc + kPQ, s));
     k_update_xr<<<red_grid(m), kT, 0, s>>>(m, sc, cur, w.x, w.r, w.p, w.q, w.part,
                                           red_counter(f));
-    LRSDP_TRY(read_scalars(ctx, sc, 8, h));
+    double* slot = ctx->h_pinned + 16 + 8 * (it & 1);
+    hipEvent_t ev = ctx->scal_ev[it & 1];
+    LRSDP_HIP(hipMemcpyAsync(slot, sc, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+    LRSDP_HIP(hipEventRecord(ev, s));
+    // guess: the residual keeps shrinking at the last rate, squared (CG tends to speed up)
+    const double q = it >= 2 ? rel1 / rel2 : 1.0;
+    const bool ahead = it < max_iter && rel1 * q * q > eps;
+    if (ahead) LRSDP_TRY(precond_step());
+    LRSDP_HIP(hipEventSynchronize(ev));
+    double h[8];
+    for (int i = 0; i < 8; ++i) h[i] = slot[i];
     if (it == 1) {
       rr0 = h[kRR0];
       if (rr0 == 0.0 || !(h[kRho0] > 0.0)) {
@@ -192,9 +205,9 @@ int pcg(lrsdp_factor* f, const double* b, double eps, int max_iter, HM Hmul, PM 
       out->status = LRSDP_OK;
       return LRSDP_OK;
     }
-    LRSDP_TRY(Pinv(w.r, w.z));
-    LRSDP_TRY(dot(f, m, w.r, w.z, w.part, sc + nxt, s));
-    k_update_p<<<vg, kT, 0, s>>>(m, sc, nxt, cur, w.z, w.p);
+    if (!ahead) LRSDP_TRY(precond_step());
+    rel2 = rel1;
+    rel1 = rel;
     std::swap(cur, nxt);
   }
   return LRSDP_OK;
@@ -253,13 +266,20 @@ int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lr
   else if (o.dd_precond == 0) dd_prec = false;
   else dd_prec = ratio < 1e-7;
   int ref64 = ratio < 1e-3 ? 1 : 0;
+  // Double-double refinement steps of bold S t = w inside the preconditioner.  kappa(bold S)
+  // grows like 1 / ratio, so the FP64 inverse leaves a relative error of about u / ratio in t
+  // and one step squares it; the SMW subtraction then magnifies what is left by about
+  // 1 / ratio.  One step keeps the preconditioner within 1e-5 of exact down to
+  // ratio = 1e-9, far inside the inner tolerance; below that a second step is taken.
+  const int dd_steps = ratio >= 1e-9 ? 1 : 2;
   if (f->precond == LRSDP_PRECOND_AUG) {  // FP64 only (eq aug_prec is Theta(1/sqrt(mu)))
     dd_prec = false;
     ref64 = 0;
   }
 
   auto Pinv = [&](const double* v, double* z) -> int {
-    return dd_prec ? precond_apply_dd(f, v, z, s, 2) : precond_apply_f64(f, v, z, s, ref64);
+    return dd_prec ? precond_apply_dd(f, v, z, s, dd_steps)
+                   : precond_apply_f64(f, v, z, s, ref64);
   };
   int status = LRSDP_OK;
   if (!refine) {

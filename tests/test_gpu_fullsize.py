@@ -30,6 +30,7 @@ def problem(ctx):
 
 MODES = {"mixed": dict(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO),
          "fp32-refined": dict(precision=pk.LRSDP_PREC_FP32, dd_mode=pk.LRSDP_DD_ON),
+         "bf16-refined": dict(precision=pk.LRSDP_PREC_BF16, dd_mode=pk.LRSDP_DD_AUTO),
          "fp64": dict(precision=pk.LRSDP_PREC_FP64, dd_mode=pk.LRSDP_DD_AUTO)}
 
 
@@ -52,7 +53,7 @@ def _oracle_reference(inst):
     return _REFS[inst.mu]
 
 
-@pytest.mark.parametrize("mode", ["mixed", "fp32-refined", "fp64"])
+@pytest.mark.parametrize("mode", ["mixed", "fp32-refined", "bf16-refined", "fp64"])
 @pytest.mark.parametrize("mu", [1e-2, 1e-4, 1e-6, 1e-8])
 def test_full_size_solve_meets_target(problem, mode, mu):
     """Every mu of the benchmark's path, in each mode the benchmark can run: the oracle's

@@ -52,13 +52,15 @@ def _check_residual(inst, yh, yl):
     assert r_true <= 1e-8, (inst.n, inst.k, inst.m, inst.mu, r_true)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "bf16"])
 def test_batch_matches_alone(ctx, precision):
     """Batched-workload shapes (n in [64, 512], k in 1..4, mu = 1e-6): a batch of 10 on four
-    workers, each instance bitwise equal to its solve alone, in FP64 and in the mixed form
-    (FP32 W0 part of H v inside the double-double refinement)."""
+    workers, each instance bitwise equal to its solve alone, in FP64 and in the mixed forms
+    (FP32, or BF16 as the batched configuration specifies, for the W0 part of H v inside the
+    double-double refinement)."""
     insts = batch_instances(10, base_seed=3000)
-    prec = pk.LRSDP_PREC_FP64 if precision == "fp64" else pk.LRSDP_PREC_AUTO
+    prec = {"fp64": pk.LRSDP_PREC_FP64, "mixed": pk.LRSDP_PREC_AUTO,
+            "bf16": pk.LRSDP_PREC_BF16}[precision]
     opts = pk.opts(precision=prec, dd_mode=pk.LRSDP_DD_AUTO)
     devs = [_device_instance(i) for i in insts]
     torch.cuda.synchronize()

@@ -80,6 +80,9 @@ extern "C" {
 #define LRSDP_ERR_EIG               -11   /* the symmetric eigensolver did not converge         */
 #define LRSDP_ERR_SCRATCH           -12   /* the call needs more than the library's fixed       */
                                           /* scratch array holds (allocation-free entry point) */
+#define LRSDP_ERR_IPM               -13   /* lrsdp_ipm_solve: an iterate X or S lost positive   */
+                                          /* definiteness, or the square root of the scaling  */
+                                          /* did not converge                                  */
 #define LRSDP_PENDING                 2   /* lrsdp_server_poll: the request has not finished   */
 
 /* ------------------------------------------------------------------ handles */
@@ -352,6 +355,73 @@ LRSDP_API int lrsdp_server_stats(lrsdp_server* srv, int* queued, int* running, i
 LRSDP_API void lrsdp_server_destroy(lrsdp_server* srv);
 /* Device bytes one instance is estimated to hold at its peak (setup). */
 LRSDP_API size_t lrsdp_instance_bytes(int64_t n, int64_t m, int32_t k);
+
+/* ------------------------------------------------------------------ the outer method */
+/* The interior-point method the Hessian equation comes from (Section 2), run on the device:
+ * infeasible primal-dual path following on  min C . X  s.t.  A_i . X = b_i, X PSD  (eq SDP)
+ * and its dual (eq SDD) with the Nesterov-Todd scaling W (W S W = X, Section 2.2).  Each
+ * iteration solves H dy = b - sigma mu A(S^{-1}) + A(W R_d W), R_d = C - S - sum y_i A_i
+ * (eqs hesseqn1, hesseqn2), with Algorithm 1 (lrsdp_factor_create with rank k, then
+ * lrsdp_solve); then dS = R_d - sum dy_i A_i, dX = sigma mu S^{-1} - X - W dS W, and X and
+ * (y, S) each take `frac` of the step to the boundary of the cone (capped at 1).  Start:
+ * X = xi I, S = eta I, y = 0 with xi = max(10, sqrt n, n max_i (1 + |b_i|) / (1 + sqrt((A^T A)_ii)))
+ * and eta = max(10, sqrt n, 1 + ||C||_F).  Stops when max(pinf, dinf, gap) <= tol with
+ * pinf = ||b - A(X)|| / (1 + ||b||), dinf = ||R_d||_F / (1 + ||C||_F) and
+ * gap = X . S / (1 + |C . X| + |b^T y|). */
+typedef struct lrsdp_ipm_opts {
+  double tol;            /* stopping threshold (default 1e-9)                               */
+  int max_iter;          /* iterations (default 60)                                          */
+  double sigma;          /* centering parameter (default 0.1)                               */
+  double frac;           /* fraction of the step to the boundary (default 0.9)             */
+  int32_t k;             /* rank of the preconditioner's split of W (default 2); its upper  */
+                         /* bound k_max when rank_eta > 0                                   */
+  double rank_eta;       /* > 0: estimate the rank per step (Section 5) as the largest       */
+                         /* i <= k with lambda_i(W) >= rank_eta lambda_{i+1}(W), at least 1  */
+                         /* (default 0: k fixed)                                             */
+  double pcg_eps;        /* tolerance of each Hessian solve (default 1e-9)                  */
+  double pcg_eps_mu;     /* > 0: tolerance min(1e-3, max(pcg_eps, pcg_eps_mu mu / mu_0)),   */
+                         /* mu_0 the starting mu, keeping eps / mu about constant (default 0) */
+  int max_ns_iter;       /* Newton-Schulz steps for the scaling's square root (default 100) */
+  double ns_tol;         /* ||I - Z Y||_F at which that iteration stops (default 1e-10)     */
+  lrsdp_opts solve;      /* options of the factor and the solves (eps is pcg_eps)           */
+} lrsdp_ipm_opts;
+
+typedef struct lrsdp_ipm_info {
+  int status;            /* same as the return value                                         */
+  int iters;             /* Newton steps taken                                              */
+  int records;           /* entries written to recs                                         */
+  int pcg_iters_total;   /* PCG iterations over all Hessian solves                          */
+  double mu, pinf, dinf, gap;      /* at the last iterate                                    */
+  double primal_obj, dual_obj;     /* C . X and b^T y at the last iterate                    */
+  double ms;             /* wall time of the call                                           */
+} lrsdp_ipm_info;
+
+/* One Newton step: the measures of the iterate it started from, the Hessian solve and the
+ * step lengths. */
+typedef struct lrsdp_ipm_record {
+  double mu, pinf, dinf, gap;
+  double alpha_p, alpha_d;         /* step lengths of X and of (y, S)                        */
+  int pcg_iters, outer_iters;      /* of the Hessian solve                                    */
+  int ns_iters;                    /* Newton-Schulz steps of the scaling                     */
+  int k;                           /* rank of the split used                                 */
+  int solve_status;                /* the Hessian solve's status (NOT_CONVERGED and          */
+                                   /* STAGNATED still give the step their best iterate)      */
+  double eps;                      /* the Hessian solve's tolerance                          */
+  double relres;                   /* the Hessian solve's final relative residual            */
+  double factor_ms, solve_ms, ms;  /* its setup, its solve, the whole step                   */
+} lrsdp_ipm_record;
+
+/* Fills *o with the defaults listed above.  o: host. */
+LRSDP_API void lrsdp_ipm_opts_default(lrsdp_ipm_opts* o);
+/* Runs the method on problem p (its constraints A_i) with right-hand side b (device, m) and
+ * cost C (device, n x n symmetric; NULL: the identity).  X, S (device, n x n) and y (device, m)
+ * receive the last iterate.  info (host, may be NULL); recs (host, may be NULL) receives up to
+ * max_recs per-step records.  Returns OK, NOT_CONVERGED (max_iter reached), or the error of
+ * the step that failed (IPM, or one of lrsdp_factor_create / lrsdp_solve): X, y, S then hold
+ * the last iterate.  Requires 3 <= n <= 4096 and 1 <= k <= 16, k < n. */
+LRSDP_API int lrsdp_ipm_solve(lrsdp_problem* p, const double* b, const double* C,
+                              const lrsdp_ipm_opts* opts, double* X, double* y, double* S,
+                              lrsdp_ipm_info* info, lrsdp_ipm_record* recs, int max_recs);
 
 #ifdef __cplusplus
 }

@@ -74,6 +74,8 @@ class IPMRecord:
     pcg_iters: int
     dy_rel_diff: float     # ||dy_pcg - dy_dense|| / ||dy_dense||
     w_gap: float           # lambda_k(W) / lambda_{k+1}(W)
+    alpha_p: float = 0.0   # step lengths of X and of (y, S)
+    alpha_d: float = 0.0
 
 
 @dataclass
@@ -122,13 +124,14 @@ def run(inst, tol=1e-9, max_iter=60, sigma=0.1, frac=0.9, pcg_k=None, pcg_eps=1e
         res = alg1.solve(F, rhs, eps=pcg_eps, max_iter=500,
                          Hmul=lambda v: H @ v)
         diff = float(np.linalg.norm(res.y - dy) / max(np.linalg.norm(dy), 1e-300))
-        recs.append(IPMRecord(mu=mu, pinf=pinf, dinf=dinf, gap=gap, pcg_iters=res.iters,
-                              dy_rel_diff=diff, w_gap=float(lamW[n - k] / lamW[n - k - 1])))
         dS = Rd - Cst.mat(dy).toarray()
         dX = sigma * mu * Si - X - W @ dS @ W
         dX = 0.5 * (dX + dX.T)
         ap = min(1.0, frac * _max_step(X, dX))
         ad = min(1.0, frac * _max_step(S, dS))
+        recs.append(IPMRecord(mu=mu, pinf=pinf, dinf=dinf, gap=gap, pcg_iters=res.iters,
+                              dy_rel_diff=diff, w_gap=float(lamW[n - k] / lamW[n - k - 1]),
+                              alpha_p=ap, alpha_d=ad))
         X = X + ap * dX
         X = 0.5 * (X + X.T)
         y = y + ad * dy

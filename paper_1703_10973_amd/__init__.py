@@ -31,12 +31,23 @@ from ._lib import (  # noqa: F401
     lrsdp_server_poll, lrsdp_server_stats, lrsdp_server_destroy, lrsdp_instance_bytes,
     lrsdp_server_session_open, lrsdp_server_submit_factor, lrsdp_server_submit_solve,
     lrsdp_server_session_close,
-    LRSDP_PENDING)
+    LRSDP_PENDING, LRSDP_ERR_IPM, lrsdp_ipm_opts, lrsdp_ipm_opts_default, lrsdp_ipm_solve)
 
 
 def opts(**kw):
     """lrsdp_opts with the library defaults, overridden by keyword."""
     o = lrsdp_opts_default()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise AttributeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def ipm_opts(**kw):
+    """lrsdp_ipm_opts with the library defaults, overridden by keyword (solve=... takes an
+    lrsdp_opts)."""
+    o = lrsdp_ipm_opts_default()
     for k, v in kw.items():
         if not hasattr(o, k):
             raise AttributeError(f"unknown option {k}")
@@ -121,6 +132,17 @@ class Problem:
 
     def info(self):
         return lrsdp_problem_info(self.handle)
+
+    def ipm_solve(self, b, C=None, options=None, max_recs=200, **kw):
+        """The interior-point method on this problem (lrsdp_ipm_solve): right-hand side b
+        (device, m), cost C (device n x n, None: the identity).  options: an lrsdp_ipm_opts,
+        or keywords of it (k=..., tol=...).  Returns (X, y, S, status, info, records)."""
+        o = options if options is not None else ipm_opts(**kw)
+        X = torch.empty(self.n, self.n, dtype=torch.float64, device=b.device)
+        S = torch.empty_like(X)
+        y = torch.empty(self.m, dtype=torch.float64, device=b.device)
+        st, info, recs = lrsdp_ipm_solve(self.handle, b, C, o, X, y, S, max_recs)
+        return X, y, S, st, info, recs
 
     def close(self):
         if self.handle:

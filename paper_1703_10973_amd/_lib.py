@@ -30,6 +30,7 @@ LRSDP_ERR_INDEFINITE_PRECOND = -9
 LRSDP_ERR_DEVICE = -10
 LRSDP_ERR_EIG = -11
 LRSDP_ERR_SCRATCH = -12
+LRSDP_ERR_IPM = -13
 LRSDP_PENDING = 2
 
 LRSDP_PREC_FP64, LRSDP_PREC_FP32, LRSDP_PREC_BF16, LRSDP_PREC_AUTO = 0, 1, 2, 3
@@ -55,6 +56,35 @@ class lrsdp_info(C.Structure):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["phase_ms"] = list(d["phase_ms"])
         return d
+
+
+class lrsdp_ipm_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("sigma", C.c_double),
+                ("frac", C.c_double), ("k", C.c_int32), ("rank_eta", C.c_double),
+                ("pcg_eps", C.c_double), ("pcg_eps_mu", C.c_double),
+                ("max_ns_iter", C.c_int), ("ns_tol", C.c_double), ("solve", lrsdp_opts)]
+
+
+class lrsdp_ipm_info(C.Structure):
+    _fields_ = [("status", C.c_int), ("iters", C.c_int), ("records", C.c_int),
+                ("pcg_iters_total", C.c_int), ("mu", C.c_double), ("pinf", C.c_double),
+                ("dinf", C.c_double), ("gap", C.c_double), ("primal_obj", C.c_double),
+                ("dual_obj", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class lrsdp_ipm_record(C.Structure):
+    _fields_ = [("mu", C.c_double), ("pinf", C.c_double), ("dinf", C.c_double),
+                ("gap", C.c_double), ("alpha_p", C.c_double), ("alpha_d", C.c_double),
+                ("pcg_iters", C.c_int), ("outer_iters", C.c_int), ("ns_iters", C.c_int),
+                ("k", C.c_int), ("solve_status", C.c_int), ("eps", C.c_double),
+                ("relres", C.c_double), ("factor_ms", C.c_double), ("solve_ms", C.c_double),
+                ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class lrsdp_instance(C.Structure):
@@ -118,6 +148,10 @@ _SIGS = {
                                      C.POINTER(C.c_int), C.POINTER(C.c_size_t)]),
     "lrsdp_server_destroy": (None, [_P]),
     "lrsdp_instance_bytes": (C.c_size_t, [C.c_int64, C.c_int64, C.c_int32]),
+    "lrsdp_ipm_opts_default": (None, [C.POINTER(lrsdp_ipm_opts)]),
+    "lrsdp_ipm_solve": (C.c_int, [_P, _P, _P, C.POINTER(lrsdp_ipm_opts), _P, _P, _P,
+                                  C.POINTER(lrsdp_ipm_info), C.POINTER(lrsdp_ipm_record),
+                                  C.c_int]),
 }
 
 
@@ -438,3 +472,27 @@ def lrsdp_server_destroy(srv):
 
 def lrsdp_instance_bytes(n, m, k):
     return int(lib().lrsdp_instance_bytes(int(n), int(m), int(k)))
+
+
+# ----------------------------------------------------------------- the outer method
+
+def lrsdp_ipm_opts_default():
+    o = lrsdp_ipm_opts()
+    lib().lrsdp_ipm_opts_default(C.byref(o))
+    return o
+
+
+def lrsdp_ipm_solve(p, b, C_, opts, X, y, S, max_recs=200):
+    n, m, _ = lrsdp_problem_info(p)
+    info = lrsdp_ipm_info()
+    recs = (lrsdp_ipm_record * max_recs)()
+    st = lib().lrsdp_ipm_solve(p, _ptr(b, torch.float64, m, "b"),
+                               _ptr(C_, torch.float64, n * n, "C"),
+                               C.byref(opts) if opts is not None else None,
+                               _ptr(X, torch.float64, n * n, "X"),
+                               _ptr(y, torch.float64, m, "y"),
+                               _ptr(S, torch.float64, n * n, "S"),
+                               C.byref(info), recs, int(max_recs))
+    if st < 0:
+        raise LrsdpError(st, "lrsdp_ipm_solve")
+    return st, info.as_dict(), [recs[i].as_dict() for i in range(min(info.records, max_recs))]

@@ -188,6 +188,7 @@ const char* lrsdp_status_string(int s) {
     case LRSDP_ERR_DEVICE: return "DEVICE_ERROR";
     case LRSDP_ERR_EIG: return "EIG_FAILED";
     case LRSDP_ERR_SCRATCH: return "SCRATCH_TOO_SMALL";
+    case LRSDP_ERR_IPM: return "IPM_FAILED";
     default: return "UNKNOWN";
   }
 }
@@ -555,6 +556,41 @@ int lrsdp_solve(lrsdp_factor* f, const double* r, double* y, double* ylo, const 
   DeviceGuard g(f->P->ctx->device);
   ProfScope ps(f->P->ctx);
   return solve_run(f, r, y, ylo, o, info);
+}
+
+void lrsdp_ipm_opts_default(lrsdp_ipm_opts* o) {
+  if (!o) return;
+  o->tol = 1e-9;
+  o->max_iter = 60;
+  o->sigma = 0.1;
+  o->frac = 0.9;
+  o->k = 2;
+  o->rank_eta = 0.0;
+  o->pcg_eps = 1e-9;
+  o->pcg_eps_mu = 0.0;
+  o->max_ns_iter = 100;
+  o->ns_tol = 1e-10;
+  lrsdp_opts_default(&o->solve);
+  o->solve.precision = LRSDP_PREC_AUTO;
+  o->solve.dd_mode = LRSDP_DD_AUTO;
+}
+
+int lrsdp_ipm_solve(lrsdp_problem* p, const double* b, const double* C,
+                    const lrsdp_ipm_opts* opts, double* X, double* y, double* S,
+                    lrsdp_ipm_info* info, lrsdp_ipm_record* recs, int max_recs) {
+  if (!p || !b || !X || !y || !S || max_recs < 0) return LRSDP_ERR_INVALID_ARG;
+  lrsdp_ipm_opts o;
+  lrsdp_ipm_opts_default(&o);
+  if (opts) o = *opts;
+  if (!(o.tol > 0.0) || o.max_iter < 0 || !(o.sigma >= 0.0 && o.sigma < 1.0) ||
+      !(o.frac > 0.0 && o.frac < 1.0) || o.k < 1 || o.k > 16 || o.k >= p->n ||
+      !(o.pcg_eps > 0.0 && o.pcg_eps < 1.0) || !(o.pcg_eps_mu >= 0.0) || !(o.rank_eta >= 0.0) ||
+      o.max_ns_iter < 1 || !(o.ns_tol > 0.0) || (o.rank_eta > 0.0 && o.k + 1 >= p->n) ||
+      !opts_valid(o.solve) || p->n < 3 || p->n > 4096)
+    return LRSDP_ERR_INVALID_ARG;
+  DeviceGuard g(p->ctx->device);
+  ProfScope ps(p->ctx);
+  return ipm_run(p, b, C, o, X, y, S, info, recs, max_recs);
 }
 
 }  // extern "C"

@@ -175,6 +175,17 @@ __global__ __launch_bounds__(kT) void k_gram_cols(int N, int r, const double* __
   if (threadIdx.x == 0) G[a * r + b] = s;
 }
 
+// When the Gram matrix of the null basis was not positive definite (U Z^{-T} rank-deficient,
+// e.g. U = 0 for a W with equal top eigenvalues, where bold U = 0 leaves nothing to deflate),
+// the deflation is dropped: basis and shift become 0, which the products that add the
+// deflation term (here and in the matrix-free bold S) then skip consistently.
+__global__ void k_deflate_guard(const int* flag, size_t count, double* QN, double* shift) {
+  if (*flag == 0) return;
+  const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (i < count) QN[i] = 0.0;
+  if (i == 0) *shift = 0.0;
+}
+
 __global__ __launch_bounds__(kT) void k_max_diag(const double* S, int N, int ld, double* out) {
   __shared__ double red[kT];
   double m = 0.0;
@@ -573,6 +584,8 @@ int factor_setup(lrsdp_factor* f, const double* W, const lrsdp_opts& o) {
       }
       if (rc) break;
       k_max_diag<<<1, kT, 0, s>>>(S, nk, nk, f->sc);  // the shift, kept on the device
+      k_deflate_guard<<<grid_for((int64_t)nk * r, 256), 256, 0, s>>>(flag_scratch,
+                                                                    (size_t)nk * r, f->QN, f->sc);
       GemmArgs g;
       g.M = nk; g.N = nk; g.K = r;
       g.A = f->QN; g.lda = r;

@@ -211,4 +211,9 @@ int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lr
 int residual_dd(lrsdp_factor* f, const double* r, const double* y, const double* ylo,
                 double* res, double* res_lo, double* relres);
 
+// ---------------------------------------------------------------- ipm.hip
+int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_ipm_opts& o,
+            double* X, double* y, double* S, lrsdp_ipm_info* info, lrsdp_ipm_record* recs,
+            int max_recs);
+
 }  // namespace lrsdp

@@ -1,0 +1,527 @@
+// The interior-point method around the Hessian equation (Section 2), on the device.
+//
+// Infeasible primal-dual path following on  min C . X  s.t.  A_i . X = b_i,  X PSD  (eq SDP)
+// and its dual (eq SDD), with the Nesterov-Todd scaling of Section 2.2: W is the positive
+// definite matrix with W S W = X.  Each iteration reduces the Newton system to the Hessian
+// equation  H dy = b - sigma mu A(S^{-1}) + A(W R_d W),  R_d = C - S - sum y_i A_i,
+// H = A^T (W kron W) A (eqs hesseqn1, hesseqn2), which Algorithm 1 solves on the device (a
+// rank-k factor of W, then PCG).  Then dS = R_d - sum dy_i A_i and
+// dX = sigma mu S^{-1} - X - W dS W (Todd, Toh and Tutuncu, SIAM J. Optim. 1998), and X and
+// (y, S) each move a fixed fraction of the way to the boundary of the cone.
+//
+// Every matrix step runs here:
+//   - W from Cholesky factors and a matrix square root.  With S = L L^T and G = L^T X L,
+//     W = L^{-T} G^{1/2} L^{-1} gives W S W = L^{-T} G L^{-1} = X.  The eigenvalues of G are
+//     those of X S, all of the order of mu near the central path, so G is well conditioned
+//     and its square root comes from the coupled Newton-Schulz iteration (three FP64 MFMA
+//     GEMMs per step) rather than from an eigendecomposition;
+//   - S^{-1} = L^{-T} L^{-1} (one GEMM; the Cholesky factor and its inverse come from the
+//     recursive factorization of the setup);
+//   - the step to the boundary from the smallest eigenvalue of L_X^{-1} dX L_X^{-T} (and of
+//     L^{-1} dS L^{-T}), by the eigen step's Householder tridiagonalization and Sturm
+//     bisection;
+//   - A(X), sum y_i A_i, the residuals and inner products: gathers, scatters and reductions
+//     with a fixed summation order.
+// The host keeps the loop and reads a few scalars per iteration.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+
+#include "dense.h"
+#include "eig.h"
+
+namespace lrsdp {
+namespace {
+
+constexpr int kT = 256;
+constexpr int kG = 256;  // partial sums per reduction
+
+// ---------------------------------------------------------------- elementwise kernels
+// M = a I (n x n, full storage)
+__global__ void k_scaled_eye(int n, double a, double* M) {
+  const size_t nn = (size_t)n * n;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn;
+       i += (size_t)gridDim.x * blockDim.x)
+    M[i] = (i % (n + 1) == 0) ? a : 0.0;
+}
+
+// Rd = C - S, with C = I when C is null
+__global__ void k_c_minus(int n, const double* C, const double* S, double* Rd) {
+  const size_t nn = (size_t)n * n;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const double c = C ? C[i] : ((i % (n + 1) == 0) ? 1.0 : 0.0);
+    Rd[i] = c - S[i];
+  }
+}
+
+// M += scale sum_i v_i A_i.  A_i has val_i at (a_i, b_i) and (b_i, a_i); the pairs are
+// distinct, so no two constraints write one entry.
+__global__ void k_add_At(int m, int n, const int32_t* a, const int32_t* b, const double* val,
+                         const double* v, double scale, double* M) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double t = scale * val[i] * v[i];
+  const int ai = a[i], bi = b[i];
+  M[(size_t)ai * n + bi] += t;
+  if (ai != bi) M[(size_t)bi * n + ai] += t;
+}
+
+// out_i = base_i + scale (A_i . X) (base may be null: 0, and may alias out), X symmetric
+__global__ void k_gather_A(int m, int n, const int32_t* a, const int32_t* b, const double* coef,
+                           const double* X, const double* base, double scale, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m) return;
+  const double t = scale * (coef[i] * X[(size_t)a[i] * n + b[i]]);
+  out[i] = base ? base[i] + t : t;
+}
+
+// X = sym(X + alpha D) (D may be null: X = sym(X)); thread per pair i <= j
+__global__ void k_sym_axpy(int n, double* X, double alpha, const double* D) {
+  const size_t nn = (size_t)n * n;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < nn;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / n), j = (int)(idx - (size_t)i * n);
+    if (i > j) continue;
+    const size_t ij = (size_t)i * n + j, ji = (size_t)j * n + i;
+    double u = X[ij], w = X[ji];
+    if (D) {
+      u += alpha * D[ij];
+      w += alpha * D[ji];
+    }
+    const double v = 0.5 * (u + w);
+    X[ij] = v;
+    X[ji] = v;
+  }
+}
+
+// dX = sm Si - X - T
+__global__ void k_dx(int n, double sm, const double* Si, const double* X, const double* T,
+                     double* dX) {
+  const size_t nn = (size_t)n * n;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn;
+       i += (size_t)gridDim.x * blockDim.x)
+    dX[i] = sm * Si[i] - X[i] - T[i];
+}
+
+// Newton-Schulz: T = (3 I - P) / 2
+__global__ void k_ns_t(int n, const double* P, double* T) {
+  const size_t nn = (size_t)n * n;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nn;
+       i += (size_t)gridDim.x * blockDim.x)
+    T[i] = ((i % (n + 1) == 0) ? 1.5 : 0.0) - 0.5 * P[i];
+}
+
+// dst = a src
+__global__ void k_scale(size_t len, double a, const double* src, double* dst) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < len;
+       i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = a * src[i];
+}
+
+// y += a d (length m)
+__global__ void k_axpy(int m, double a, const double* d, double* y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) y[i] = fma(a, d[i], y[i]);
+}
+
+// y = y + ylo (the double-double answer of the Hessian solve, rounded once)
+__global__ void k_round_pair(int m, double* y, const double* ylo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) y[i] = y[i] + ylo[i];
+}
+
+__global__ void k_zero_int(int count, int* p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+// ---------------------------------------------------------------- reductions
+// Kinds of the per-element term of a sum over len elements.
+enum : int { kDot = 0, kEyeDev = 1, kStartRatio = 2, kTrace = 3 };
+
+// part[blockIdx.x] = this block's share of the sum (grid-stride, fixed grid, so the order
+// of every sum depends only on len):
+//   kDot:        x_i y_i;
+//   kEyeDev:     (delta_ij - x_ij)^2 over an n x n matrix (len = n^2, y unused);
+//   kStartRatio: max over i of (1 + |x_i|) / (1 + sqrt(1 / y_i)) (y = 1 / (A^T A)_ii);
+//   kTrace:      the diagonal x_ii of an n x n matrix (len = n^2, y unused).
+__global__ __launch_bounds__(kT) void k_reduce_part(int kind, size_t len, int n, const double* x,
+                                                    const double* y, double* part) {
+  __shared__ double red[kT / kWave];
+  __shared__ double mx[kT];
+  double s = 0.0, hi = 0.0;
+  for (size_t i = blockIdx.x * (size_t)kT + threadIdx.x; i < len; i += (size_t)gridDim.x * kT) {
+    if (kind == kDot) {
+      s = fma(x[i], y[i], s);
+    } else if (kind == kEyeDev) {
+      const double d = ((i % (n + 1) == 0) ? 1.0 : 0.0) - x[i];
+      s = fma(d, d, s);
+    } else if (kind == kTrace) {
+      if (i % (n + 1) == 0) s += x[i];
+    } else {
+      hi = fmax(hi, (1.0 + fabs(x[i])) / (1.0 + sqrt(1.0 / y[i])));
+    }
+  }
+  if (kind == kStartRatio) {
+    mx[threadIdx.x] = hi;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double h = 0.0;
+      for (int t = 0; t < kT; ++t) h = fmax(h, mx[t]);
+      part[blockIdx.x] = h;
+    }
+    return;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// out = the sum (or the max, kStartRatio) of part[0..G) in index order
+__global__ void k_reduce_fin(int kind, int G, const double* part, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int g = 0; g < G; ++g) s = (kind == kStartRatio) ? fmax(s, part[g]) : s + part[g];
+  *out = s;
+}
+
+int reduce_grid(size_t len) {
+  return (int)std::max<size_t>(1, std::min<size_t>(kG, (len + kT - 1) / kT));
+}
+
+// ---------------------------------------------------------------- the iteration's state
+struct Ipm {
+  lrsdp_problem* P = nullptr;
+  lrsdp_ctx* ctx = nullptr;
+  hipStream_t s = nullptr;
+  int n = 0, m = 0, kmax = 1;
+  size_t nn = 0;
+  // n x n
+  double *Rd = nullptr, *W = nullptr, *Si = nullptr, *Lb = nullptr, *Li = nullptr,
+         *Lxi = nullptr, *G = nullptr, *Y = nullptr, *Y2 = nullptr, *Z = nullptr,
+         *Z2 = nullptr, *Pm = nullptr, *T1 = nullptr, *T2 = nullptr, *dX = nullptr,
+         *dS = nullptr, *Mx = nullptr;
+  // m
+  double *rhs = nullptr, *dy = nullptr, *dylo = nullptr, *rp = nullptr;
+  // scratch
+  double *ptmp = nullptr, *part = nullptr, *sc = nullptr, *lam = nullptr, *vl = nullptr;
+  void* ews = nullptr;
+  int* flag = nullptr;
+  size_t ptmp_n = 0, ews_bytes = 0;
+
+  int reduce(int kind, size_t len, const double* x, const double* y, int slot) {
+    const int g = reduce_grid(len);
+    k_reduce_part<<<g, kT, 0, s>>>(kind, len, n, x, y, part + (size_t)slot * kG);
+    k_reduce_fin<<<1, 64, 0, s>>>(kind, g, part + (size_t)slot * kG, sc + slot);
+    LRSDP_HIP(hipGetLastError());
+    return LRSDP_OK;
+  }
+  int read(int count, double* h) {
+    LRSDP_HIP(hipMemcpyAsync(ctx->h_pinned, sc, count * sizeof(double), hipMemcpyDeviceToHost,
+                             s));
+    LRSDP_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < count; ++i) h[i] = ctx->h_pinned[i];
+    return LRSDP_OK;
+  }
+  // C = alpha op(A) op(B) + beta C, n x n operands
+  int mm(const double* A, bool tA, const double* B, bool tB, double* C, unsigned flags,
+         double alpha = 1.0, double beta = 0.0) {
+    GemmArgs g;
+    g.M = g.N = g.K = n;
+    g.A = A;
+    g.lda = n;
+    g.transA = tA;
+    g.B = B;
+    g.ldb = n;
+    g.transB = tB;
+    g.C = C;
+    g.ldc = n;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.flags = flags;
+    return gemm(g, s);
+  }
+  // Cholesky of M (copied into Lb) and its inverse into Linv (lower; the upper part outside
+  // the 64-aligned diagonal blocks is left undefined, and no product below reads it).  Returns
+  // 1 in *bad when a pivot was not positive.
+  int chol_inv(const double* M, double* Linv, bool keep_L, int* bad) {
+    LRSDP_HIP(hipMemcpyAsync(Lb, M, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+    k_zero_int<<<1, 64, 0, s>>>(1, flag);
+    LRSDP_TRY(potrf_inv(Lb, n, n, Linv, n, flag, ptmp, keep_L, s));
+    int h = 0;
+    LRSDP_HIP(hipMemcpyAsync(&ctx->h_pinned[40], flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    LRSDP_HIP(hipStreamSynchronize(s));
+    std::memcpy(&h, &ctx->h_pinned[40], sizeof(int));
+    *bad = h;
+    return LRSDP_OK;
+  }
+  // largest step t in (0, inf] with M + t D PSD, M = L L^T with Linv = L^{-1}:
+  // -1 / lambda_min(L^{-1} D L^{-T}), inf when that eigenvalue is >= 0
+  int max_step(const double* Linv, const double* D, double* out) {
+    LRSDP_TRY(mm(Linv, false, D, false, T1, kKToRow));   // L^{-1} D
+    LRSDP_TRY(mm(T1, false, Linv, true, Mx, kKToCol));   // (L^{-1} D) L^{-T}
+    k_sym_axpy<<<grid_for((int64_t)nn, kT, 4096), kT, 0, s>>>(n, Mx, 0.0, nullptr);
+    LRSDP_TRY(eig_top_and_min(Mx, n, 1, ews, lam, vl, s));
+    double h[1];
+    LRSDP_HIP(hipMemcpyAsync(ctx->h_pinned, lam, sizeof(double), hipMemcpyDeviceToHost, s));
+    LRSDP_HIP(hipStreamSynchronize(s));
+    h[0] = ctx->h_pinned[0];
+    *out = (h[0] >= 0.0) ? INFINITY : -1.0 / h[0];
+    return LRSDP_OK;
+  }
+};
+
+double* ctx_pinned(const Ipm& I) { return I.ctx->h_pinned; }
+
+// slots of sc
+enum : int { kXS = 0, kRp2 = 1, kRd2 = 2, kCX = 3, kBy = 4, kB2 = 5, kC2 = 6, kRatio = 7,
+             kGF = 8, kNS = 9, kSlots = 10 };
+
+int ipm_alloc(Ipm& I) {
+  const size_t nn = I.nn, m = I.m;
+  double** mats[] = {&I.Rd, &I.W, &I.Si, &I.Lb, &I.Li, &I.Lxi, &I.G, &I.Y, &I.Y2, &I.Z,
+                     &I.Z2, &I.Pm, &I.T1, &I.T2, &I.dX, &I.dS, &I.Mx};
+  for (double** p : mats) LRSDP_TRY(dev_alloc_n(I.ctx, p, nn));
+  double** vecs[] = {&I.rhs, &I.dy, &I.dylo, &I.rp};
+  for (double** p : vecs) LRSDP_TRY(dev_alloc_n(I.ctx, p, m));
+  I.ptmp_n = std::max<size_t>(1, potrf_inv_tmp_doubles(I.n));
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.ptmp, I.ptmp_n));
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.part, (size_t)kSlots * kG));
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.sc, (size_t)kSlots));
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.lam, (size_t)I.kmax + 4));
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.vl, (size_t)(I.kmax + 2) * I.n));
+  I.ews_bytes = std::max(eig_workspace_bytes(I.n, 1), eig_workspace_bytes(I.n, I.kmax + 1));
+  LRSDP_TRY(dev_alloc(I.ctx, &I.ews, I.ews_bytes));
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.flag, (size_t)4));
+  return LRSDP_OK;
+}
+
+void ipm_free(Ipm& I) {
+  const size_t nn = I.nn, m = I.m;
+  double* mats[] = {I.Rd, I.W, I.Si, I.Lb, I.Li, I.Lxi, I.G, I.Y, I.Y2, I.Z,
+                    I.Z2, I.Pm, I.T1, I.T2, I.dX, I.dS, I.Mx};
+  for (double* p : mats) dev_free(I.ctx, p, nn * sizeof(double));
+  double* vecs[] = {I.rhs, I.dy, I.dylo, I.rp};
+  for (double* p : vecs) dev_free(I.ctx, p, m * sizeof(double));
+  dev_free(I.ctx, I.ptmp, I.ptmp_n * sizeof(double));
+  dev_free(I.ctx, I.part, (size_t)kSlots * kG * sizeof(double));
+  dev_free(I.ctx, I.sc, (size_t)kSlots * sizeof(double));
+  dev_free(I.ctx, I.lam, ((size_t)I.kmax + 4) * sizeof(double));
+  dev_free(I.ctx, I.vl, (size_t)(I.kmax + 2) * I.n * sizeof(double));
+  dev_free(I.ctx, I.ews, I.ews_bytes);
+  dev_free(I.ctx, I.flag, 4 * sizeof(int));
+}
+
+// W (n x n) with W S W = X, and S^{-1}, from S = L L^T (Li = L^{-1}, Lb = L) and the
+// coupled Newton-Schulz iteration on G / c, c = ||G||_F:  T = (3 I - Z Y) / 2,
+// Y <- Y T, Z <- T Z, so that Y -> (G / c)^{1/2} and Z -> (G / c)^{-1/2}.
+int nt_scaling(Ipm& I, const double* X, int max_ns, double ns_tol, int* ns_iters) {
+  const int n = I.n;
+  hipStream_t s = I.s;
+  const int eg = grid_for((int64_t)I.nn, kT, 4096);
+  LRSDP_TRY(I.mm(X, false, I.Lb, false, I.T1, kKFromCol));  // X L   (L lower)
+  LRSDP_TRY(I.mm(I.Lb, true, I.T1, false, I.G, kKFromRow));  // L^T X L
+  k_sym_axpy<<<eg, kT, 0, s>>>(n, I.G, 0.0, nullptr);
+  LRSDP_TRY(I.reduce(kDot, I.nn, I.G, I.G, kGF));
+  double h[kSlots];
+  LRSDP_TRY(I.read(kSlots, h));
+  const double c = std::sqrt(h[kGF]);
+  if (!(c > 0.0) || !std::isfinite(c)) return LRSDP_ERR_DEVICE;
+  k_scale<<<eg, kT, 0, s>>>(I.nn, 1.0 / c, I.G, I.Y);
+  k_scaled_eye<<<eg, kT, 0, s>>>(n, 1.0, I.Z);
+  int it = 0;
+  bool done = false;
+  for (; it < max_ns && !done; ++it) {
+    LRSDP_TRY(I.mm(I.Z, false, I.Y, false, I.Pm, 0));
+    LRSDP_TRY(I.reduce(kEyeDev, I.nn, I.Pm, nullptr, kNS));
+    k_ns_t<<<eg, kT, 0, s>>>(n, I.Pm, I.T1);
+    LRSDP_TRY(I.mm(I.Y, false, I.T1, false, I.Y2, 0));
+    LRSDP_TRY(I.mm(I.T1, false, I.Z, false, I.Z2, 0));
+    std::swap(I.Y, I.Y2);
+    std::swap(I.Z, I.Z2);
+    LRSDP_TRY(I.read(kSlots, h));
+    // ||I - Z Y||_F of the step just taken; the update squares it (quadratic phase)
+    done = std::sqrt(h[kNS]) <= ns_tol;
+  }
+  *ns_iters = it;
+  if (!done) return LRSDP_ERR_IPM;
+  // G^{1/2} = sqrt(c) Y;  W = L^{-T} G^{1/2} L^{-1};  S^{-1} = L^{-T} L^{-1}
+  k_sym_axpy<<<eg, kT, 0, s>>>(n, I.Y, 0.0, nullptr);
+  LRSDP_TRY(I.mm(I.Y, false, I.Li, false, I.T1, kKFromCol, std::sqrt(c)));
+  LRSDP_TRY(I.mm(I.Li, true, I.T1, false, I.W, kKFromRow));
+  k_sym_axpy<<<eg, kT, 0, s>>>(n, I.W, 0.0, nullptr);
+  LRSDP_TRY(I.mm(I.Li, true, I.Li, false, I.Si, kKFromRow | kKFromCol));
+  k_sym_axpy<<<eg, kT, 0, s>>>(n, I.Si, 0.0, nullptr);
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
+
+}  // namespace
+
+int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_ipm_opts& o,
+            double* X, double* y, double* S, lrsdp_ipm_info* info, lrsdp_ipm_record* recs,
+            int max_recs) {
+  auto t_start = std::chrono::steady_clock::now();
+  Ipm I;
+  I.P = P;
+  I.ctx = P->ctx;
+  I.s = P->ctx->stream;
+  I.n = P->n;
+  I.m = P->m;
+  I.nn = (size_t)I.n * I.n;
+  I.kmax = o.k;
+  hipStream_t s = I.s;
+  const int n = I.n, m = I.m;
+  int rc = ipm_alloc(I);
+  lrsdp_ipm_info inf{};
+  inf.status = LRSDP_NOT_CONVERGED;
+  const int eg = grid_for((int64_t)I.nn, kT, 4096);
+  const int vg = grid_for(m, kT);
+  auto body = [&]() -> int {
+    LRSDP_TRY(rc);
+    // starting point (the usual scaled identities): X = xi I, S = eta I, y = 0
+    LRSDP_TRY(I.reduce(kDot, m, bvec, bvec, kB2));
+    LRSDP_TRY(I.reduce(kStartRatio, m, bvec, P->ginv, kRatio));
+    if (C) LRSDP_TRY(I.reduce(kDot, I.nn, C, C, kC2));
+    double h[kSlots];
+    LRSDP_TRY(I.read(kSlots, h));
+    const double nb = std::sqrt(h[kB2]);
+    const double nc = C ? std::sqrt(h[kC2]) : std::sqrt((double)n);
+    const double xi = std::max({10.0, std::sqrt((double)n), n * h[kRatio]});
+    const double eta = std::max({10.0, std::sqrt((double)n), 1.0 + nc});
+    k_scaled_eye<<<eg, kT, 0, s>>>(n, xi, X);
+    k_scaled_eye<<<eg, kT, 0, s>>>(n, eta, S);
+    LRSDP_HIP(hipMemsetAsync(y, 0, (size_t)m * sizeof(double), s));
+    LRSDP_HIP(hipGetLastError());
+    lrsdp_opts so = o.solve;
+    double mu0 = 0.0;
+    for (int it = 0; it <= o.max_iter; ++it) {
+      auto t_it = std::chrono::steady_clock::now();
+      // residuals and the duality measure
+      k_c_minus<<<eg, kT, 0, s>>>(n, C, S, I.Rd);
+      k_add_At<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->val, y, -1.0, I.Rd);
+      k_gather_A<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->coef, X, bvec, -1.0, I.rp);
+      LRSDP_TRY(I.reduce(kDot, I.nn, X, S, kXS));
+      LRSDP_TRY(I.reduce(kDot, m, I.rp, I.rp, kRp2));
+      LRSDP_TRY(I.reduce(kDot, I.nn, I.Rd, I.Rd, kRd2));
+      if (C) LRSDP_TRY(I.reduce(kDot, I.nn, C, X, kCX));
+      else LRSDP_TRY(I.reduce(kTrace, I.nn, X, nullptr, kCX));  // C = I: C . X = tr X
+      LRSDP_TRY(I.reduce(kDot, m, bvec, y, kBy));
+      LRSDP_TRY(I.read(kSlots, h));
+      const double xs = h[kXS];
+      const double mu = xs / n;
+      if (it == 0) mu0 = mu;
+      const double pinf = std::sqrt(h[kRp2]) / (1.0 + nb);
+      const double dinf = std::sqrt(h[kRd2]) / (1.0 + nc);
+      const double gap = xs / (1.0 + std::fabs(h[kCX]) + std::fabs(h[kBy]));
+      inf.iters = it;
+      inf.mu = mu;
+      inf.pinf = pinf;
+      inf.dinf = dinf;
+      inf.gap = gap;
+      inf.primal_obj = h[kCX];
+      inf.dual_obj = h[kBy];
+      if (!std::isfinite(mu) || !std::isfinite(pinf) || !std::isfinite(dinf))
+        return LRSDP_ERR_DEVICE;
+      if (std::max({pinf, dinf, gap}) <= o.tol) {
+        inf.status = LRSDP_OK;
+        return LRSDP_OK;
+      }
+      if (it == o.max_iter) return LRSDP_OK;  // NOT_CONVERGED
+      lrsdp_ipm_record rec{};
+      rec.mu = mu;
+      rec.pinf = pinf;
+      rec.dinf = dinf;
+      rec.gap = gap;
+      // Nesterov-Todd scaling W and S^{-1} from S = L L^T
+      int bad = 0;
+      LRSDP_TRY(I.chol_inv(S, I.Li, true, &bad));
+      if (bad) return LRSDP_ERR_IPM;
+      int ns = 0;
+      LRSDP_TRY(nt_scaling(I, X, o.max_ns_iter, o.ns_tol, &ns));
+      rec.ns_iters = ns;
+      // rhs = b - sigma mu A(S^{-1}) + A(W R_d W)
+      LRSDP_TRY(I.mm(I.W, false, I.Rd, false, I.T1, 0));
+      LRSDP_TRY(I.mm(I.T1, false, I.W, false, I.T2, 0));
+      k_gather_A<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->coef, I.Si, bvec, -o.sigma * mu, I.rhs);
+      k_gather_A<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->coef, I.T2, I.rhs, 1.0, I.rhs);
+      LRSDP_HIP(hipGetLastError());
+      // the rank of the split: fixed, or (rank_eta > 0) the largest i <= k with
+      // lambda_i(W) >= eta lambda_{i+1}(W), at least 1 (Section 5)
+      int k = o.k;
+      if (o.rank_eta > 0.0) {
+        LRSDP_TRY(eig_top_and_min(I.W, n, o.k + 1, I.ews, I.lam, I.vl, s));
+        double hl[18];
+        LRSDP_HIP(hipMemcpyAsync(ctx_pinned(I), I.lam, (o.k + 2) * sizeof(double),
+                                 hipMemcpyDeviceToHost, s));
+        LRSDP_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < o.k + 2; ++q) hl[q] = ctx_pinned(I)[q];
+        // hl[1 .. k+1]: the k+1 largest ascending, so lambda_i(W) = hl[k + 2 - i]
+        k = 1;
+        for (int i = 1; i <= o.k; ++i)
+          if (hl[o.k + 2 - i] >= o.rank_eta * hl[o.k + 1 - i]) k = i;
+      }
+      rec.k = k;
+      // the solve's tolerance: fixed, or (pcg_eps_mu > 0) in proportion to mu relative to the
+      // start, between pcg_eps and 1e-3 (Section 4.2: the ratio of eps to mu is kept)
+      so.eps = o.pcg_eps;
+      if (o.pcg_eps_mu > 0.0) so.eps = std::min(1e-3, std::max(o.pcg_eps, o.pcg_eps_mu * mu / mu0));
+      rec.eps = so.eps;
+      // H dy = rhs by Algorithm 1: a rank-k factor of W, then PCG (refined in double-double
+      // when W's spectral gap calls for it).  A solve that stops short of eps (NOT_CONVERGED,
+      // STAGNATED) still gives the step its best iterate, as an inexact Newton direction.
+      lrsdp_factor* F = nullptr;
+      int frc = lrsdp_factor_create(P, I.W, k, &so, &F);
+      if (frc < 0) return frc;
+      lrsdp_info si{};
+      int src = lrsdp_solve(F, I.rhs, I.dy, I.dylo, &so, &si);
+      rec.factor_ms = F->setup_ms;
+      lrsdp_factor_destroy(F);
+      rec.solve_status = src;
+      if (src < 0 && src != LRSDP_ERR_STAGNATED) return src;
+      k_round_pair<<<vg, kT, 0, s>>>(m, I.dy, I.dylo);
+      rec.pcg_iters = si.iters;
+      rec.outer_iters = si.outer_iters;
+      rec.solve_ms = si.solve_ms;
+      rec.relres = si.relres;
+      inf.pcg_iters_total += si.iters;
+      // dS = R_d - sum dy_i A_i;  dX = sigma mu S^{-1} - X - W dS W
+      LRSDP_HIP(hipMemcpyAsync(I.dS, I.Rd, I.nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+      k_add_At<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->val, I.dy, -1.0, I.dS);
+      LRSDP_TRY(I.mm(I.W, false, I.dS, false, I.T1, 0));
+      LRSDP_TRY(I.mm(I.T1, false, I.W, false, I.T2, 0));
+      k_dx<<<eg, kT, 0, s>>>(n, o.sigma * mu, I.Si, X, I.T2, I.dX);
+      k_sym_axpy<<<eg, kT, 0, s>>>(n, I.dX, 0.0, nullptr);
+      LRSDP_HIP(hipGetLastError());
+      // steps to the boundary: X + a dX PSD (X = L_X L_X^T), S + a dS PSD (S = L L^T)
+      double tp = 0.0, td = 0.0;
+      LRSDP_TRY(I.chol_inv(X, I.Lxi, false, &bad));
+      if (bad) return LRSDP_ERR_IPM;
+      LRSDP_TRY(I.max_step(I.Lxi, I.dX, &tp));
+      LRSDP_TRY(I.max_step(I.Li, I.dS, &td));
+      const double ap = std::min(1.0, o.frac * tp), ad = std::min(1.0, o.frac * td);
+      rec.alpha_p = ap;
+      rec.alpha_d = ad;
+      k_sym_axpy<<<eg, kT, 0, s>>>(n, X, ap, I.dX);
+      k_axpy<<<vg, kT, 0, s>>>(m, ad, I.dy, y);
+      k_sym_axpy<<<eg, kT, 0, s>>>(n, S, ad, I.dS);
+      LRSDP_HIP(hipGetLastError());
+      LRSDP_HIP(hipStreamSynchronize(s));
+      rec.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_it)
+                   .count();
+      if (recs && it < max_recs) recs[it] = rec;
+      inf.records = it + 1;
+    }
+    return LRSDP_OK;
+  };
+  rc = body();
+  (void)hipStreamSynchronize(s);
+  ipm_free(I);
+  inf.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+               .count();
+  if (rc < 0) inf.status = rc;
+  if (info) *info = inf;
+  return rc < 0 ? rc : inf.status;
+}
+
+}  // namespace lrsdp

@@ -117,3 +117,20 @@ def test_ipm_refuses_bad_options(ctx):
             P.ipm_solve(b, **kw)
         assert e.value.status == pk._lib.LRSDP_ERR_INVALID_ARG, kw
     P.close()
+
+
+def test_ipm_larger_completion_invariants(ctx):
+    """p = q = 150 (n = 300), m = 25 n, rank 3, beyond the oracle's dense Hessian: the method
+    reaches the target from the plain definitions of the residuals, X and S stay positive
+    definite, the rank estimate ends at 3 and the completed block is the sampled matrix."""
+    inst = ipm.matcomp_instance(150, 150, 3, 7500, seed=21)
+    P = _problem(ctx, inst)
+    print("ipm p=q=150 k=3 m=7500", flush=True)
+    X, y, S, st, info, recs = P.ipm_solve(to_dev(inst["bvec"]), k=6, rank_eta=10.0, tol=1e-8,
+                                          pcg_eps=1e-10, pcg_eps_mu=1e-3)
+    assert st == 0, info
+    assert recs[-1]["k"] == 3
+    rec = _check_answer(inst, host(X), host(y), host(S), 1e-7)
+    assert rec <= 1e-4
+    P.close()
+

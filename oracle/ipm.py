@@ -88,11 +88,12 @@ class IPMResult:
     records: list = field(default_factory=list)
 
 
-def run(inst, tol=1e-9, max_iter=60, sigma=0.1, frac=0.9, pcg_k=None, pcg_eps=1e-10):
+def run(inst, tol=1e-9, max_iter=60, sigma=0.1, frac=0.9, pcg_k=None, pcg_eps=1e-10, C=None):
+    """C: the cost matrix of eq SDP (n x n symmetric; None: the identity of eq matcomp_sdp)."""
     n, a, b, val, bvec = inst["n"], inst["a"], inst["b"], inst["val"], inst["bvec"]
     m = len(a)
     Cst = alg1.Constraints(n, a, b, val)
-    Cmat = np.eye(n)
+    Cmat = np.eye(n) if C is None else np.asarray(C, dtype=np.float64)
     xi = max(10.0, np.sqrt(n), n * float(np.max((1 + np.abs(bvec)) / (1 + np.sqrt(Cst.g)))))
     eta = max(10.0, np.sqrt(n), 1.0 + np.linalg.norm(Cmat))
     X = xi * np.eye(n)
@@ -109,7 +110,7 @@ def run(inst, tol=1e-9, max_iter=60, sigma=0.1, frac=0.9, pcg_k=None, pcg_eps=1e
         Rp = bvec - Cst.At(X)
         pinf = np.linalg.norm(Rp) / (1 + np.linalg.norm(bvec))
         dinf = np.linalg.norm(Rd) / (1 + np.linalg.norm(Cmat))
-        gap = float(np.sum(X * S)) / (1 + abs(np.trace(X)) + abs(bvec @ y))
+        gap = float(np.sum(X * S)) / (1 + abs(float(np.sum(Cmat * X))) + abs(bvec @ y))
         if max(pinf, dinf, gap) <= tol:
             conv = True
             break

@@ -134,3 +134,32 @@ def test_ipm_larger_completion_invariants(ctx):
     assert rec <= 1e-4
     P.close()
 
+
+def test_ipm_general_cost_matrix(ctx):
+    """A cost other than the identity (eq SDP with C a positive diagonal: a weighted trace): the
+    device method follows the oracle's path and ends at its X; C = I passed as a dense matrix
+    gives the answer of the default cost."""
+    shape = (10, 10, 2, 90, 5)
+    inst, ref_i = _oracle(shape)
+    n = inst["n"]
+    w = np.random.default_rng(9).uniform(0.5, 2.0, n)
+    Cm = np.diag(w)
+    ref = ipm.run(inst, tol=1e-9, C=Cm)
+    assert ref.converged
+    P = _problem(ctx, inst)
+    b = to_dev(inst["bvec"])
+    X, y, S, st, info, recs = P.ipm_solve(b, C=to_dev(Cm), k=2, tol=1e-9, pcg_eps=1e-10)
+    assert st == 0, info
+    assert abs(info["iters"] - ref.iters) <= 2, (info["iters"], ref.iters)
+    for r, o in zip(recs[:4], ref.records[:4]):
+        for key in ("mu", "gap", "alpha_p", "alpha_d"):
+            want = getattr(o, key)
+            assert abs(r[key] - want) <= 1e-6 * abs(want) + 1e-12, (key, r[key], want)
+    assert np.linalg.norm(host(X) - ref.X) <= 1e-5 * np.linalg.norm(ref.X)
+    assert info["primal_obj"] == pytest.approx(float(np.sum(Cm * ref.X)), rel=1e-6)
+    X1, y1, S1, st1, info1, _ = P.ipm_solve(b, C=to_dev(np.eye(n)), k=2, tol=1e-9, pcg_eps=1e-10)
+    X0, y0, S0, st0, info0, _ = P.ipm_solve(b, k=2, tol=1e-9, pcg_eps=1e-10)
+    assert st1 == 0 and st0 == 0 and info1["iters"] == info0["iters"]
+    assert np.linalg.norm(host(X1) - host(X0)) <= 1e-10 * np.linalg.norm(host(X0))
+    P.close()
+

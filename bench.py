@@ -45,7 +45,7 @@ def parse():
                     help="skip the serving-with-resident-factors stream of the headline line")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mu-path",
-                    choices=["mu-path", "batch", "serving", "serving-sessions", "large", "ipm",
+                    choices=["mu-path", "batch", "serving", "serving-sessions", "large", "ipm", "hv",
                              "single", "copy-calibration"],
                     help="mu-path (default): the headline line; batch: 256 independent "
                          "instances (n in [64, 512], k in 1..4, mu = 1e-6); serving: Poisson "
@@ -63,6 +63,9 @@ def parse():
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="no GPU: print the top kernels of a rocprofv3 --kernel-trace --stats "
                          "-f csv output folder as a text table")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="no GPU: mean value per dispatch of every counter in rocprofv3 --pmc "
+                         "output folders, per kernel")
     ap.add_argument("--summarize-traffic", nargs=4, metavar="DIR",
                     help="no GPU: read four rocprofv3 --pmc output folders (FETCH_SIZE and "
                          "WRITE_SIZE of --workload single, then of --workload "
@@ -153,6 +156,26 @@ def summarize_traffic(dirs):
                   indent=1)
 
 
+def summarize_counters(dirs):
+    """Mean per-dispatch value of each counter, per kernel, over rocprofv3 --pmc folders."""
+    import csv
+    import glob
+    import re
+    per = {}
+    for d in dirs:
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    k = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+                    k = re.sub(r"\(.*", "", k.replace("lrsdp::", ""))
+                    per.setdefault(k, {}).setdefault(r["Counter_Name"], []).append(
+                        float(r["Counter_Value"]))
+    for k, cs in sorted(per.items()):
+        print(k)
+        for c, v in sorted(cs.items()):
+            print(f"  {c:36s} {np.mean(v):16.1f}   ({len(v)} dispatches)")
+
+
 def summarize_stats(d, top=30):
     """Top kernels by total time from a rocprofv3 kernel_stats.csv (durations in us)."""
     import csv
@@ -181,12 +204,15 @@ def main():
         return summarize_stats(args.summarize_stats)
     if args.summarize_traffic:
         return summarize_traffic(args.summarize_traffic)
+    if args.summarize_counters:
+        return summarize_counters(args.summarize_counters)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the per-GPU "
               "shard of this workload is one independent instance stream", file=sys.stderr)
         sys.exit(2)
     if args.workload != "mu-path":
         return {"batch": run_batch, "serving": run_serving, "large": run_large, "ipm": run_ipm,
+                "hv": run_hv,
                 "serving-sessions": run_serving_sessions, "single": run_single,
                 "copy-calibration": run_copy}[args.workload](args)
     import torch
@@ -849,6 +875,32 @@ def run_large(args):
         "pcg_ms_per_inner_iter": info["solve_ms"] / max(info["iters"], 1),
         "dtype": "f32+f64+dd", "data": "synthetic",
         "config": {"workload": "n=4000 k=10 m=400000 mu=1e-8 seed 4001"}}))
+    P.close()
+    ctx.close()
+
+
+def run_hv(args):
+    """H v of the default workload's mu = 1e-2 instance (n=1000 k=5 m=20000): 20 FP64 products
+    with W and 20 split products with the W0 part in FP32 (for counter runs)."""
+    import torch
+
+    import paper_1703_10973_amd as pk
+    from synth import make_instance
+    dev = torch.device("cuda", 0)
+    inst = make_instance(N, K, M, MUS[0], SEED)
+    d = _device_inputs(inst, torch, dev)
+    ctx = pk.Context(0)
+    P = pk.Problem(ctx, inst.n, inst.m, d["con"], d["row"], d["col"], d["val"])
+    F = pk.Factor(P, d["W"], inst.k)
+    v = torch.as_tensor(np.random.default_rng(1).standard_normal(inst.m), device=dev)
+    out = torch.empty_like(v)
+    for _ in range(20):
+        P.hessian_apply(d["W"], v, out)
+    for _ in range(20):
+        F.hessian_apply_split(v, pk.LRSDP_PREC_FP32)
+    torch.cuda.synchronize()
+    print(json.dumps({"hv_fp64": 20, "hv_split_fp32": 20}))
+    F.close()
     P.close()
     ctx.close()
 

@@ -80,7 +80,7 @@ def parse():
 TRAFFIC_CLASSES = {
     "gemm": (("k_gemm<true", "k_gemm<false, true"), ()),
     "gemm_inv": (("k_gemm<false, false",), ()),
-    "hv": (("k_hv_fused",), ("k_scatter",)), "gemv": (("k_gemv_tri",), ()),
+    "hv": (("k_hv_fused",), ("k_scatter",)), "gemv": (("k_gemv_tri",), ("k_gemv_rect",)),
     "resdd": (("k_residual_dd",), ("k_scatter_dd",)), "bz": (("k_PJ",), ("k_dJL",)),
     "leaf": (("k_chol_leaf",), ()), "tile": (("k_rl_fused", "k_rl_panel"), ()),
 }

@@ -809,6 +809,9 @@ def run_ipm(args):
                "seconds": el, "ms_per_iter": el * 1e3 / steps,
                "factor_ms_per_iter": float(np.mean([r["factor_ms"] for r in recs])),
                "solve_ms_per_iter": float(np.mean([r["solve_ms"] for r in recs])),
+               "scaling_ms_per_iter": float(np.mean([r["scaling_ms"] for r in recs])),
+               "rank_ms_per_iter": float(np.mean([r["rank_ms"] for r in recs])),
+               "steps_ms_per_iter": float(np.mean([r["steps_ms"] for r in recs])),
                "pcg_iters_per_step": [r["pcg_iters"] for r in recs],
                "k_used": [r["k"] for r in recs],
                "ns_iters": [r["ns_iters"] for r in recs],

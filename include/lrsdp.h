@@ -409,6 +409,9 @@ typedef struct lrsdp_ipm_record {
   double eps;                      /* the Hessian solve's tolerance                          */
   double relres;                   /* the Hessian solve's final relative residual            */
   double factor_ms, solve_ms, ms;  /* its setup, its solve, the whole step                   */
+  double scaling_ms;               /* W and S^{-1} (Cholesky of S, Newton-Schulz, products)  */
+  double rank_ms;                  /* the rank estimate (0 when k is fixed)                  */
+  double steps_ms;                 /* the two steps to the boundary                          */
 } lrsdp_ipm_record;
 
 /* Fills *o with the defaults listed above.  o: host. */

@@ -81,7 +81,8 @@ class lrsdp_ipm_record(C.Structure):
                 ("pcg_iters", C.c_int), ("outer_iters", C.c_int), ("ns_iters", C.c_int),
                 ("k", C.c_int), ("solve_status", C.c_int), ("eps", C.c_double),
                 ("relres", C.c_double), ("factor_ms", C.c_double), ("solve_ms", C.c_double),
-                ("ms", C.c_double)]
+                ("ms", C.c_double), ("scaling_ms", C.c_double), ("rank_ms", C.c_double),
+                ("steps_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

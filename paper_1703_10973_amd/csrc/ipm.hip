@@ -18,8 +18,9 @@
 //   - S^{-1} = L^{-T} L^{-1} (one GEMM; the Cholesky factor and its inverse come from the
 //     recursive factorization of the setup);
 //   - the step to the boundary from the smallest eigenvalue of L_X^{-1} dX L_X^{-T} (and of
-//     L^{-1} dS L^{-T}), by the eigen step's Householder tridiagonalization and Sturm
-//     bisection;
+//     L^{-1} dS L^{-T}), and the rank estimate from the largest eigenvalues of W, by Lanczos with
+//     full reorthogonalization (GEMVs on the device, the small tridiagonal problem bisected on
+//     the host), or by the eigen step's Householder tridiagonalization where Lanczos stops short;
 //   - A(X), sum y_i A_i, the residuals and inner products: gathers, scatters and reductions
 //     with a fixed summation order.
 // The host keeps the loop and reads a few scalars per iteration.
@@ -136,6 +137,56 @@ __global__ void k_zero_int(int count, int* p) {
   if (i < count) p[i] = 0;
 }
 
+// ---------------------------------------------------------------- Lanczos
+// h[i] = V[i] . w for the rows i < R of V (R x n, row-major): one wavefront per row
+__global__ __launch_bounds__(256) void k_rows_dot(int R, int n, const double* __restrict__ V,
+                                                  const double* __restrict__ w,
+                                                  double* __restrict__ h) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= R) return;
+  const double* v = V + (size_t)row * n;
+  double s = 0.0;
+  for (int c = lane; c < n; c += 64) s = fma(v[c], w[c], s);
+  s = wave_sum(s);
+  if (lane == 0) h[row] = s;
+}
+
+// w -= V^T h over the rows i < R;  *alpha += h[R - 1] (the projection on the newest vector)
+__global__ void k_sub_vt(int R, int n, const double* __restrict__ V, const double* __restrict__ h,
+                         double* __restrict__ w, double* __restrict__ alpha) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) {
+    double t = w[p];
+    for (int i = 0; i < R; ++i) t = fma(-V[(size_t)i * n + p], h[i], t);
+    w[p] = t;
+  }
+  if (p == 0) *alpha += h[R - 1];
+}
+
+__global__ void k_fill(int len, double x, double* p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) p[i] = x;
+}
+
+// v = w / sqrt(nn) (the next Lanczos vector), beta = sqrt(nn)
+__global__ void k_lanczos_next(int n, const double* __restrict__ nn, const double* __restrict__ w,
+                               double* __restrict__ v, double* __restrict__ beta) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  const double b = sqrt(*nn);
+  if (p < n) v[p] = b > 0.0 ? w[p] / b : 0.0;
+  if (p == 0) *beta = b;
+}
+
+// a fixed start vector with no structure the matrices share: v_p = 1 + frac(p golden ratio)
+__global__ void k_lanczos_start(int n, double* v) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p < n) {
+    const double x = p * 0.6180339887498949;
+    v[p] = 1.0 + (x - floor(x));
+  }
+}
+
 // ---------------------------------------------------------------- reductions
 // Kinds of the per-element term of a sum over len elements.
 enum : int { kDot = 0, kEyeDev = 1, kStartRatio = 2, kTrace = 3 };
@@ -189,6 +240,38 @@ int reduce_grid(size_t len) {
   return (int)std::max<size_t>(1, std::min<size_t>(kG, (len + kT - 1) / kT));
 }
 
+// slots of sc
+enum : int { kXS = 0, kRp2 = 1, kRd2 = 2, kCX = 3, kBy = 4, kB2 = 5, kC2 = 6, kRatio = 7,
+             kGF = 8, kNS = 9, kLz = 10, kSlots = 11 };
+
+// The i-th smallest eigenvalue (0-based) of the symmetric tridiagonal matrix with diagonal a and
+// off-diagonal b (j x j), by bisection on the Sturm count to the rounding level.
+double tri_eig(const std::vector<double>& a, const std::vector<double>& b, int j, int i) {
+  double lo = a[0], hi = a[0];
+  for (int q = 0; q < j; ++q) {
+    const double r = (q > 0 ? std::fabs(b[q - 1]) : 0.0) + (q + 1 < j ? std::fabs(b[q]) : 0.0);
+    lo = std::min(lo, a[q] - r);
+    hi = std::max(hi, a[q] + r);
+  }
+  const double scale = std::max(std::fabs(lo), std::fabs(hi));
+  auto below = [&](double x) {  // eigenvalues < x
+    int c = 0;
+    double d = 1.0;
+    for (int q = 0; q < j; ++q) {
+      d = a[q] - x - (q > 0 ? b[q - 1] * b[q - 1] / d : 0.0);
+      if (d == 0.0) d = -1e-300 * (scale > 0.0 ? scale : 1.0);
+      if (d < 0.0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 4e-16 * scale; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (below(mid) > i) hi = mid;
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
 // ---------------------------------------------------------------- the iteration's state
 struct Ipm {
   lrsdp_problem* P = nullptr;
@@ -208,6 +291,10 @@ struct Ipm {
   void* ews = nullptr;
   int* flag = nullptr;
   size_t ptmp_n = 0, ews_bytes = 0;
+  // Lanczos: basis (lz_max x n), work vector, projections, alpha and beta per step
+  int lz_max = 0;
+  double *lzV = nullptr, *lzw = nullptr, *lzh = nullptr, *lza = nullptr, *lzb = nullptr;
+  double* lz_host = nullptr;  // pinned: alpha (lz_max) then beta (lz_max)
 
   int reduce(int kind, size_t len, const double* x, const double* y, int slot) {
     const int g = reduce_grid(len);
@@ -255,17 +342,87 @@ struct Ipm {
     *bad = h;
     return LRSDP_OK;
   }
+  // Extreme eigenvalues of the symmetric M (n x n) by Lanczos with full reorthogonalization
+  // (classical Gram-Schmidt twice per step) from a fixed start vector: lo receives the nlo
+  // smallest Ritz values, hi the nhi largest (largest first).  OK once those Ritz values change
+  // by at most rtol (relative to their scale) over 8 steps, or after n steps (where the Ritz
+  // values are the eigenvalues); NOT_CONVERGED at lz_max steps or when the Krylov space closes
+  // early (it may then miss part of the spectrum), and the caller takes the Householder path.
+  int lanczos(const double* M, int nlo, double* lo, int nhi, double* hi, double rtol,
+              int* steps) {
+    const int g = grid_for(n, kT);
+    const int jmax = std::min(n, lz_max);
+    k_lanczos_start<<<g, kT, 0, s>>>(n, lzV);
+    LRSDP_TRY(reduce(kDot, n, lzV, lzV, kLz));
+    k_lanczos_next<<<g, kT, 0, s>>>(n, sc + kLz, lzV, lzV, lzb + lz_max);  // v_0 = start / |start|
+    k_fill<<<grid_for(lz_max, kT), kT, 0, s>>>(lz_max, 0.0, lza);
+    std::vector<double> a, b, prev_lo(nlo, 0.0), prev_hi(nhi, 0.0);
+    int done_steps = 0;
+    bool converged = false;
+    for (int j = 0; j < jmax; ++j) {
+      const double* v = lzV + (size_t)j * n;
+      LRSDP_TRY(gemv(M, n, n, v, lzw, s));
+      for (int pass = 0; pass < 2; ++pass) {  // w -= V V^T w over the basis so far
+        k_rows_dot<<<(j + 1 + 3) / 4, 256, 0, s>>>(j + 1, n, lzV, lzw, lzh);
+        k_sub_vt<<<g, kT, 0, s>>>(j + 1, n, lzV, lzh, lzw, lza + j);
+      }
+      LRSDP_TRY(reduce(kDot, n, lzw, lzw, kLz));
+      double* next = (j + 1 < jmax) ? lzV + (size_t)(j + 1) * n : lzw;
+      k_lanczos_next<<<g, kT, 0, s>>>(n, sc + kLz, lzw, next, lzb + j);
+      LRSDP_HIP(hipGetLastError());
+      const int jj = j + 1;
+      if (jj % 8 != 0 && jj < jmax) continue;
+      // T_jj: diagonal alpha_0..alpha_{jj-1}, off-diagonal beta_0..beta_{jj-2}
+      LRSDP_HIP(hipMemcpyAsync(lz_host, lza, jj * sizeof(double), hipMemcpyDeviceToHost, s));
+      LRSDP_HIP(hipMemcpyAsync(lz_host + lz_max, lzb, jj * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+      LRSDP_HIP(hipStreamSynchronize(s));
+      a.assign(lz_host, lz_host + jj);
+      b.assign(lz_host + lz_max, lz_host + lz_max + jj);
+      double big = 0.0;
+      for (int q = 0; q < jj; ++q) big = std::max({big, std::fabs(a[q]), std::fabs(b[q])});
+      for (int q = 0; q + 1 < jj; ++q)
+        if (!(std::fabs(b[q]) > 1e-13 * big)) return LRSDP_NOT_CONVERGED;  // invariant subspace:
+                                                                          // the caller falls back
+      std::vector<double> cur_lo(nlo, 0.0), cur_hi(nhi, 0.0);
+      for (int q = 0; q < nlo && q < jj; ++q) cur_lo[q] = tri_eig(a, b, jj, q);
+      for (int q = 0; q < nhi && q < jj; ++q) cur_hi[q] = tri_eig(a, b, jj, jj - 1 - q);
+      double scale = 0.0;
+      for (double x : cur_lo) scale = std::max(scale, std::fabs(x));
+      for (double x : cur_hi) scale = std::max(scale, std::fabs(x));
+      bool same = jj >= 16;
+      for (int q = 0; q < nlo; ++q) same = same && std::fabs(cur_lo[q] - prev_lo[q]) <= rtol * scale;
+      for (int q = 0; q < nhi; ++q) same = same && std::fabs(cur_hi[q] - prev_hi[q]) <= rtol * scale;
+      prev_lo = cur_lo;
+      prev_hi = cur_hi;
+      done_steps = jj;
+      if (same) {
+        converged = true;
+        break;
+      }
+    }
+    if (done_steps == n) converged = true;  // the Ritz values are the eigenvalues
+    for (int q = 0; q < nlo; ++q) lo[q] = prev_lo[q];
+    for (int q = 0; q < nhi; ++q) hi[q] = prev_hi[q];
+    *steps = done_steps;
+    return converged ? LRSDP_OK : LRSDP_NOT_CONVERGED;
+  }
   // largest step t in (0, inf] with M + t D PSD, M = L L^T with Linv = L^{-1}:
   // -1 / lambda_min(L^{-1} D L^{-T}), inf when that eigenvalue is >= 0
   int max_step(const double* Linv, const double* D, double* out) {
     LRSDP_TRY(mm(Linv, false, D, false, T1, kKToRow));   // L^{-1} D
     LRSDP_TRY(mm(T1, false, Linv, true, Mx, kKToCol));   // (L^{-1} D) L^{-T}
     k_sym_axpy<<<grid_for((int64_t)nn, kT, 4096), kT, 0, s>>>(n, Mx, 0.0, nullptr);
-    LRSDP_TRY(eig_top_and_min(Mx, n, 1, ews, lam, vl, s));
     double h[1];
-    LRSDP_HIP(hipMemcpyAsync(ctx->h_pinned, lam, sizeof(double), hipMemcpyDeviceToHost, s));
-    LRSDP_HIP(hipStreamSynchronize(s));
-    h[0] = ctx->h_pinned[0];
+    int steps = 0;
+    const int lrc = lanczos(Mx, 1, h, 0, nullptr, 1e-11, &steps);
+    if (lrc < 0) return lrc;
+    if (lrc != LRSDP_OK) {  // Householder tridiagonalization and Sturm bisection
+      LRSDP_TRY(eig_top_and_min(Mx, n, 1, ews, lam, vl, s));
+      LRSDP_HIP(hipMemcpyAsync(ctx->h_pinned, lam, sizeof(double), hipMemcpyDeviceToHost, s));
+      LRSDP_HIP(hipStreamSynchronize(s));
+      h[0] = ctx->h_pinned[0];
+    }
     *out = (h[0] >= 0.0) ? INFINITY : -1.0 / h[0];
     return LRSDP_OK;
   }
@@ -273,9 +430,7 @@ struct Ipm {
 
 double* ctx_pinned(const Ipm& I) { return I.ctx->h_pinned; }
 
-// slots of sc
-enum : int { kXS = 0, kRp2 = 1, kRd2 = 2, kCX = 3, kBy = 4, kB2 = 5, kC2 = 6, kRatio = 7,
-             kGF = 8, kNS = 9, kSlots = 10 };
+
 
 int ipm_alloc(Ipm& I) {
   const size_t nn = I.nn, m = I.m;
@@ -293,6 +448,17 @@ int ipm_alloc(Ipm& I) {
   I.ews_bytes = std::max(eig_workspace_bytes(I.n, 1), eig_workspace_bytes(I.n, I.kmax + 1));
   LRSDP_TRY(dev_alloc(I.ctx, &I.ews, I.ews_bytes));
   LRSDP_TRY(dev_alloc_n(I.ctx, &I.flag, (size_t)4));
+  I.lz_max = std::min(I.n, 320);
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.lzV, (size_t)I.lz_max * I.n));
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.lzw, (size_t)I.n));
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.lzh, (size_t)I.lz_max));
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.lza, (size_t)I.lz_max));
+  LRSDP_TRY(dev_alloc_n(I.ctx, &I.lzb, (size_t)I.lz_max + 1));
+  if (hipHostMalloc(reinterpret_cast<void**>(&I.lz_host), 2 * (size_t)I.lz_max * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess) {
+    I.lz_host = nullptr;
+    return LRSDP_ERR_DEVICE;
+  }
   return LRSDP_OK;
 }
 
@@ -310,6 +476,12 @@ void ipm_free(Ipm& I) {
   dev_free(I.ctx, I.vl, (size_t)(I.kmax + 2) * I.n * sizeof(double));
   dev_free(I.ctx, I.ews, I.ews_bytes);
   dev_free(I.ctx, I.flag, 4 * sizeof(int));
+  dev_free(I.ctx, I.lzV, (size_t)I.lz_max * I.n * sizeof(double));
+  dev_free(I.ctx, I.lzw, (size_t)I.n * sizeof(double));
+  dev_free(I.ctx, I.lzh, (size_t)I.lz_max * sizeof(double));
+  dev_free(I.ctx, I.lza, (size_t)I.lz_max * sizeof(double));
+  dev_free(I.ctx, I.lzb, ((size_t)I.lz_max + 1) * sizeof(double));
+  if (I.lz_host) (void)hipHostFree(I.lz_host);
 }
 
 // W (n x n) with W S W = X, and S^{-1}, from S = L L^T (Li = L^{-1}, Lb = L) and the
@@ -434,12 +606,16 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
       rec.dinf = dinf;
       rec.gap = gap;
       // Nesterov-Todd scaling W and S^{-1} from S = L L^T
+      auto t_sc = std::chrono::steady_clock::now();
       int bad = 0;
       LRSDP_TRY(I.chol_inv(S, I.Li, true, &bad));
       if (bad) return LRSDP_ERR_IPM;
       int ns = 0;
       LRSDP_TRY(nt_scaling(I, X, o.max_ns_iter, o.ns_tol, &ns));
       rec.ns_iters = ns;
+      LRSDP_HIP(hipStreamSynchronize(s));
+      rec.scaling_ms = std::chrono::duration<double, std::milli>(
+                           std::chrono::steady_clock::now() - t_sc).count();
       // rhs = b - sigma mu A(S^{-1}) + A(W R_d W)
       LRSDP_TRY(I.mm(I.W, false, I.Rd, false, I.T1, 0));
       LRSDP_TRY(I.mm(I.T1, false, I.W, false, I.T2, 0));
@@ -449,19 +625,27 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
       // the rank of the split: fixed, or (rank_eta > 0) the largest i <= k with
       // lambda_i(W) >= eta lambda_{i+1}(W), at least 1 (Section 5)
       int k = o.k;
+      auto t_rank = std::chrono::steady_clock::now();
       if (o.rank_eta > 0.0) {
-        LRSDP_TRY(eig_top_and_min(I.W, n, o.k + 1, I.ews, I.lam, I.vl, s));
-        double hl[18];
-        LRSDP_HIP(hipMemcpyAsync(ctx_pinned(I), I.lam, (o.k + 2) * sizeof(double),
-                                 hipMemcpyDeviceToHost, s));
-        LRSDP_HIP(hipStreamSynchronize(s));
-        for (int q = 0; q < o.k + 2; ++q) hl[q] = ctx_pinned(I)[q];
-        // hl[1 .. k+1]: the k+1 largest ascending, so lambda_i(W) = hl[k + 2 - i]
+        // lam_top[i - 1] = lambda_i(W), the k + 1 largest
+        double lam_top[17];
+        int steps = 0;
+        const int lrc = I.lanczos(I.W, 0, nullptr, o.k + 1, lam_top, 1e-8, &steps);
+        if (lrc < 0) return lrc;
+        if (lrc != LRSDP_OK) {  // Householder path: hl[1 .. k+1] are the k+1 largest ascending
+          LRSDP_TRY(eig_top_and_min(I.W, n, o.k + 1, I.ews, I.lam, I.vl, s));
+          LRSDP_HIP(hipMemcpyAsync(ctx_pinned(I), I.lam, (o.k + 2) * sizeof(double),
+                                   hipMemcpyDeviceToHost, s));
+          LRSDP_HIP(hipStreamSynchronize(s));
+          for (int i = 1; i <= o.k + 1; ++i) lam_top[i - 1] = ctx_pinned(I)[o.k + 2 - i];
+        }
         k = 1;
         for (int i = 1; i <= o.k; ++i)
-          if (hl[o.k + 2 - i] >= o.rank_eta * hl[o.k + 1 - i]) k = i;
+          if (lam_top[i - 1] >= o.rank_eta * lam_top[i]) k = i;
       }
       rec.k = k;
+      rec.rank_ms = std::chrono::duration<double, std::milli>(
+                        std::chrono::steady_clock::now() - t_rank).count();
       // the solve's tolerance: fixed, or (pcg_eps_mu > 0) in proportion to mu relative to the
       // start, between pcg_eps and 1e-3 (Section 4.2: the ratio of eps to mu is kept)
       so.eps = o.pcg_eps;
@@ -495,10 +679,13 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
       LRSDP_HIP(hipGetLastError());
       // steps to the boundary: X + a dX PSD (X = L_X L_X^T), S + a dS PSD (S = L L^T)
       double tp = 0.0, td = 0.0;
+      auto t_st = std::chrono::steady_clock::now();
       LRSDP_TRY(I.chol_inv(X, I.Lxi, false, &bad));
       if (bad) return LRSDP_ERR_IPM;
       LRSDP_TRY(I.max_step(I.Lxi, I.dX, &tp));
       LRSDP_TRY(I.max_step(I.Li, I.dS, &td));
+      rec.steps_ms = std::chrono::duration<double, std::milli>(
+                         std::chrono::steady_clock::now() - t_st).count();
       const double ap = std::min(1.0, o.frac * tp), ad = std::min(1.0, o.frac * td);
       rec.alpha_p = ap;
       rec.alpha_d = ad;

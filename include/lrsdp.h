@@ -382,6 +382,9 @@ typedef struct lrsdp_ipm_opts {
   double pcg_eps_mu;     /* > 0: tolerance min(1e-3, max(pcg_eps, pcg_eps_mu mu / mu_0)),   */
                          /* mu_0 the starting mu, keeping eps / mu about constant (default 0) */
   int max_ns_iter;       /* Newton-Schulz steps for the scaling's square root (default 100) */
+  int householder_eig;   /* 1: the steps to the boundary and the rank estimate from the       */
+                         /* Householder eigen step only (default 0: Lanczos, Householder where */
+                         /* Lanczos stops short)                                              */
   double ns_tol;         /* ||I - Z Y||_F at which that iteration stops (default 1e-10)     */
   lrsdp_opts solve;      /* options of the factor and the solves (eps is pcg_eps)           */
 } lrsdp_ipm_opts;

@@ -62,7 +62,8 @@ class lrsdp_ipm_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("sigma", C.c_double),
                 ("frac", C.c_double), ("k", C.c_int32), ("rank_eta", C.c_double),
                 ("pcg_eps", C.c_double), ("pcg_eps_mu", C.c_double),
-                ("max_ns_iter", C.c_int), ("ns_tol", C.c_double), ("solve", lrsdp_opts)]
+                ("max_ns_iter", C.c_int), ("householder_eig", C.c_int), ("ns_tol", C.c_double),
+                ("solve", lrsdp_opts)]
 
 
 class lrsdp_ipm_info(C.Structure):

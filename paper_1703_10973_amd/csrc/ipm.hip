@@ -278,6 +278,7 @@ struct Ipm {
   lrsdp_ctx* ctx = nullptr;
   hipStream_t s = nullptr;
   int n = 0, m = 0, kmax = 1;
+  bool householder = false;  // the steps from the Householder eigen step only
   size_t nn = 0;
   // n x n
   double *Rd = nullptr, *W = nullptr, *Si = nullptr, *Lb = nullptr, *Li = nullptr,
@@ -415,7 +416,7 @@ struct Ipm {
     k_sym_axpy<<<grid_for((int64_t)nn, kT, 4096), kT, 0, s>>>(n, Mx, 0.0, nullptr);
     double h[1];
     int steps = 0;
-    const int lrc = lanczos(Mx, 1, h, 0, nullptr, 1e-11, &steps);
+    const int lrc = householder ? LRSDP_NOT_CONVERGED : lanczos(Mx, 1, h, 0, nullptr, 1e-11, &steps);
     if (lrc < 0) return lrc;
     if (lrc != LRSDP_OK) {  // Householder tridiagonalization and Sturm bisection
       LRSDP_TRY(eig_top_and_min(Mx, n, 1, ews, lam, vl, s));
@@ -542,6 +543,7 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
   I.m = P->m;
   I.nn = (size_t)I.n * I.n;
   I.kmax = o.k;
+  I.householder = o.householder_eig != 0;
   hipStream_t s = I.s;
   const int n = I.n, m = I.m;
   int rc = ipm_alloc(I);
@@ -630,7 +632,8 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
         // lam_top[i - 1] = lambda_i(W), the k + 1 largest
         double lam_top[17];
         int steps = 0;
-        const int lrc = I.lanczos(I.W, 0, nullptr, o.k + 1, lam_top, 1e-8, &steps);
+        const int lrc = o.householder_eig ? LRSDP_NOT_CONVERGED
+                                          : I.lanczos(I.W, 0, nullptr, o.k + 1, lam_top, 1e-8, &steps);
         if (lrc < 0) return lrc;
         if (lrc != LRSDP_OK) {  // Householder path: hl[1 .. k+1] are the k+1 largest ascending
           LRSDP_TRY(eig_top_and_min(I.W, n, o.k + 1, I.ews, I.lam, I.vl, s));

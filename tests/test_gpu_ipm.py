@@ -163,3 +163,27 @@ def test_ipm_general_cost_matrix(ctx):
     assert np.linalg.norm(host(X1) - host(X0)) <= 1e-10 * np.linalg.norm(host(X0))
     P.close()
 
+
+def test_ipm_lanczos_and_householder_agree(ctx):
+    """The steps to the boundary and the rank estimate by Lanczos (default) and by the
+    Householder eigen step give the same path: same iteration count and rank estimates, step
+    lengths within 1e-9 over the first twelve steps, and the final iterate within 1e-6."""
+    shape = (40, 40, 3, 900, 8)
+    inst, _ = _oracle(shape)
+    P = _problem(ctx, inst)
+    b = to_dev(inst["bvec"])
+    kw = dict(k=6, rank_eta=10.0, tol=1e-9, pcg_eps=1e-10)
+    X1, y1, S1, st1, info1, recs1 = P.ipm_solve(b, **kw)
+    X2, y2, S2, st2, info2, recs2 = P.ipm_solve(b, householder_eig=1, **kw)
+    assert st1 == 0 and st2 == 0
+    assert info1["iters"] == info2["iters"]
+    assert [r["k"] for r in recs1] == [r["k"] for r in recs2]
+    diffs = [max(abs(r1[key] - r2[key]) / max(abs(r2[key]), 1e-12) for key in ("alpha_p", "alpha_d"))
+             for r1, r2 in zip(recs1, recs2)]
+    print("step-length differences:", ["%.1e" % d for d in diffs], flush=True)
+    # the two eigensolvers differ by rounding; the last steps (mu ~ 1e-9 of its start) amplify
+    # such differences by orders of magnitude, so the path is compared over its first half
+    assert max(diffs[:12]) <= 1e-9, diffs
+    assert np.linalg.norm(host(X1) - host(X2)) <= 1e-6 * np.linalg.norm(host(X2))
+    P.close()
+

@@ -15,8 +15,15 @@ R_d = C - S - sum y_i A_i, the NT Newton system reduces to the Hessian equation
 (eq hesseqn1)  H dy = b - sigma mu A(S^{-1}) + A(W R_d W),
 then dS = R_d - sum dy_i A_i and dX = sigma mu S^{-1} - X - W dS W
 (Todd, Toh and Tutuncu, SIAM J. Optim. 1998).  Steps go 0.9 of the way to the
-boundary of the cone, sigma = 0.1.  The paper's own outer solver is SeDuMi's,
-which is not reproduced: parity with it is unpinned.
+boundary of the cone.  The centering parameter is either fixed (sigma = 0.1) or,
+by default, set per step by Mehrotra's predictor rule with that value as its floor:
+the affine direction (sigma = 0) is taken first, its full steps to the boundary (at
+most 1) give the duality measure mu_aff it would reach, and the step uses
+min(1, max(sigma, (mu_aff / mu)^3)), solving the Hessian equation again (no
+second-order corrector).  With a fixed sigma the iterates drift from the central
+path on sparsely sampled instances and the steps shrink to a few percent; the rule
+raises the centering exactly there and otherwise keeps the fixed value.  The paper's own outer solver is SeDuMi's, which is not
+reproduced: parity with it is unpinned.
 """
 
 from __future__ import annotations
@@ -76,6 +83,7 @@ class IPMRecord:
     w_gap: float           # lambda_k(W) / lambda_{k+1}(W)
     alpha_p: float = 0.0   # step lengths of X and of (y, S)
     alpha_d: float = 0.0
+    sigma: float = 0.0     # the centering parameter the step used
 
 
 @dataclass
@@ -88,8 +96,11 @@ class IPMResult:
     records: list = field(default_factory=list)
 
 
-def run(inst, tol=1e-9, max_iter=60, sigma=0.1, frac=0.9, pcg_k=None, pcg_eps=1e-10, C=None):
-    """C: the cost matrix of eq SDP (n x n symmetric; None: the identity of eq matcomp_sdp)."""
+def run(inst, tol=1e-9, max_iter=60, sigma=0.1, frac=0.9, pcg_k=None, pcg_eps=1e-10, C=None,
+        predictor=True):
+    """C: the cost matrix of eq SDP (n x n symmetric; None: the identity of eq matcomp_sdp).
+    predictor: the centering by Mehrotra's rule from the affine direction, at least sigma;
+    False: sigma every step."""
     n, a, b, val, bvec = inst["n"], inst["a"], inst["b"], inst["val"], inst["bvec"]
     m = len(a)
     Cst = alg1.Constraints(n, a, b, val)
@@ -116,8 +127,19 @@ def run(inst, tol=1e-9, max_iter=60, sigma=0.1, frac=0.9, pcg_k=None, pcg_eps=1e
             break
         W = nt_scaling(X, S)
         Si = np.linalg.inv(S)
-        rhs = bvec - sigma * mu * Cst.At(Si) + Cst.At(W @ Rd @ W)
         H = hessian_dense(W, a, b, val)
+        sg = sigma
+        if predictor:
+            # the affine direction: the Newton system with sigma = 0
+            dy_a = np.linalg.solve(H, bvec + Cst.At(W @ Rd @ W))
+            dS_a = Rd - Cst.mat(dy_a).toarray()
+            dX_a = -X - W @ dS_a @ W
+            dX_a = 0.5 * (dX_a + dX_a.T)
+            ap_a = min(1.0, _max_step(X, dX_a))
+            ad_a = min(1.0, _max_step(S, dS_a))
+            mu_a = float(np.sum((X + ap_a * dX_a) * (S + ad_a * dS_a))) / n
+            sg = min(1.0, max(sigma, (mu_a / mu) ** 3))
+        rhs = bvec - sg * mu * Cst.At(Si) + Cst.At(W @ Rd @ W)
         dy = np.linalg.solve(H, rhs)
         # the same Newton system solved by Algorithm 1 (PCG, true rank k)
         lamW = np.linalg.eigvalsh(W)
@@ -126,13 +148,13 @@ def run(inst, tol=1e-9, max_iter=60, sigma=0.1, frac=0.9, pcg_k=None, pcg_eps=1e
                          Hmul=lambda v: H @ v)
         diff = float(np.linalg.norm(res.y - dy) / max(np.linalg.norm(dy), 1e-300))
         dS = Rd - Cst.mat(dy).toarray()
-        dX = sigma * mu * Si - X - W @ dS @ W
+        dX = sg * mu * Si - X - W @ dS @ W
         dX = 0.5 * (dX + dX.T)
         ap = min(1.0, frac * _max_step(X, dX))
         ad = min(1.0, frac * _max_step(S, dS))
         recs.append(IPMRecord(mu=mu, pinf=pinf, dinf=dinf, gap=gap, pcg_iters=res.iters,
                               dy_rel_diff=diff, w_gap=float(lamW[n - k] / lamW[n - k - 1]),
-                              alpha_p=ap, alpha_d=ad))
+                              alpha_p=ap, alpha_d=ad, sigma=sg))
         X = X + ap * dX
         X = 0.5 * (X + X.T)
         y = y + ad * dy

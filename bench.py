@@ -775,11 +775,13 @@ def run_serving_sessions(args):
 
 def run_ipm(args):
     """The interior-point method on the device (lrsdp_ipm_solve) on random bipartite
-    matrix-completion SDPs (Section 5: Omega uniform, M = G1 G2^T Gaussian, m = 25 n as in
-    the paper's first problem set), with the rank estimated from W (k_max = 6, eta = 10) and the
-    solve tolerance kept in proportion to mu.  Reports iterations, time per iteration and its
-    parts, the final measures and the recovery error of M; the oracle's textbook method (dense
-    Newton solves) is timed beside the device on the small instance it can handle."""
+    matrix-completion SDPs (Section 5: Omega uniform, M = G1 G2^T Gaussian): the instance of the
+    paper's comparison with SVT (p = q = 500, rank 4, m = 20 000) and two of its first problem
+    set's shape (m = 25 n, rank 3, n = 2000 and 4000), with the rank estimated from W
+    (k_max = 6, eta = 10), the solve tolerance kept in proportion to mu and the centering by
+    the predictor rule.  Reports iterations, time per iteration and its parts, the final
+    measures and the recovery error of M; the oracle's method (dense Newton solves) is timed
+    beside the device on the small instance it can handle."""
     import torch
 
     import paper_1703_10973_amd as pk
@@ -787,9 +789,9 @@ def run_ipm(args):
     dev = torch.device("cuda", 0)
     ctx = pk.Context(0)
     out = {}
-    for (p, k, seed) in ((40, 3, 8), (500, 3, 11)):
+    for (p, k, m, seed) in ((40, 3, 900, 8), (500, 4, 20000, 11), (1000, 3, 50000, 12),
+                            (2000, 3, 100000, 13)):
         n = 2 * p
-        m = 25 * n if p > 40 else 900
         inst = oipm.matcomp_instance(p, p, k, m, seed)
         t = lambda x, dt=torch.float64: torch.as_tensor(np.ascontiguousarray(x), dtype=dt, device=dev)  # noqa: E731
         P = pk.Problem(ctx, n, m, t(np.arange(m), torch.int32), t(inst["a"], torch.int32),
@@ -812,7 +814,10 @@ def run_ipm(args):
                "scaling_ms_per_iter": float(np.mean([r["scaling_ms"] for r in recs])),
                "rank_ms_per_iter": float(np.mean([r["rank_ms"] for r in recs])),
                "steps_ms_per_iter": float(np.mean([r["steps_ms"] for r in recs])),
+               "predictor_ms_per_iter": float(np.mean([r["pred_ms"] for r in recs])),
                "pcg_iters_per_step": [r["pcg_iters"] for r in recs],
+               "predictor_pcg_iters_per_step": [r["pred_pcg_iters"] for r in recs],
+               "sigma": [round(r["sigma"], 4) for r in recs],
                "k_used": [r["k"] for r in recs],
                "ns_iters": [r["ns_iters"] for r in recs],
                "pinf": info["pinf"], "dinf": info["dinf"], "gap": info["gap"],
@@ -824,18 +829,19 @@ def run_ipm(args):
             row["oracle_iters"] = ref.iters
             row["oracle_note"] = ("oracle: numpy FP64, dense Hessian and dense Newton solves, "
                                   "plus its own PCG comparison per step")
-        out[f"p{p}"] = row
+        out[f"n{n}_m{m}"] = row
         print(f"# ipm n={n} m={m}: {info['iters']} iterations, {el:.2f} s, "
               f"recovery {rec:.1e}", file=sys.stderr)
         P.close()
-    big = out["p500"]
+    big = out["n1000_m20000"]
     print(json.dumps({
         "metric": "interior-point iterations/s on the device (matrix completion, NT scaling, "
                   "Algorithm 1 per Newton system)",
         "value": big["iters"] / big["seconds"], "unit": "iterations/s", "n_gpus": 1,
         "higher_is_better": True, "dtype": "f64+dd", "data": "synthetic",
-        "config": {"workload": "bipartite matrix completion p=q=500 (n=1000), m=25n, rank 3, "
-                               "tol 1e-8; and p=q=40 (n=80), m=900 against the oracle"},
+        "config": {"workload": "bipartite matrix completion p=q=500 (n=1000), m=20000, rank 4, "
+                               "tol 1e-8 (value); n=2000 m=50000 and n=4000 m=100000 rank 3; "
+                               "p=q=40 (n=80), m=900 against the oracle"},
         "detail": out}))
     ctx.close()
 

@@ -371,7 +371,12 @@ LRSDP_API size_t lrsdp_instance_bytes(int64_t n, int64_t m, int32_t k);
 typedef struct lrsdp_ipm_opts {
   double tol;            /* stopping threshold (default 1e-9)                               */
   int max_iter;          /* iterations (default 60)                                          */
-  double sigma;          /* centering parameter (default 0.1)                               */
+  double sigma;          /* centering parameter, or its floor with predictor (default 0.1)  */
+  int predictor;         /* 1: per step, the affine direction (sigma = 0) is solved first    */
+                         /* and the step uses min(1, max(sigma, (mu_aff / mu)^3)), mu_aff the */
+                         /* duality measure that direction reaches with its full steps to the */
+                         /* boundary (Mehrotra's rule, no second-order corrector; the two     */
+                         /* Hessian solves share one factor); 0: sigma every step (default 1) */
   double frac;           /* fraction of the step to the boundary (default 0.9)             */
   int32_t k;             /* rank of the preconditioner's split of W (default 2); its upper  */
                          /* bound k_max when rank_eta > 0                                   */
@@ -415,6 +420,9 @@ typedef struct lrsdp_ipm_record {
   double scaling_ms;               /* W and S^{-1} (Cholesky of S, Newton-Schulz, products)  */
   double rank_ms;                  /* the rank estimate (0 when k is fixed)                  */
   double steps_ms;                 /* the two steps to the boundary                          */
+  double sigma;                    /* the centering parameter the step used                  */
+  int pred_pcg_iters;              /* the predictor's Hessian solve (0 without predictor)    */
+  double pred_ms;                  /* the predictor: its solve, direction and two steps      */
 } lrsdp_ipm_record;
 
 /* Fills *o with the defaults listed above.  o: host. */

@@ -60,7 +60,7 @@ class lrsdp_info(C.Structure):
 
 class lrsdp_ipm_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("sigma", C.c_double),
-                ("frac", C.c_double), ("k", C.c_int32), ("rank_eta", C.c_double),
+                ("predictor", C.c_int), ("frac", C.c_double), ("k", C.c_int32), ("rank_eta", C.c_double),
                 ("pcg_eps", C.c_double), ("pcg_eps_mu", C.c_double),
                 ("max_ns_iter", C.c_int), ("householder_eig", C.c_int), ("ns_tol", C.c_double),
                 ("solve", lrsdp_opts)]
@@ -83,7 +83,8 @@ class lrsdp_ipm_record(C.Structure):
                 ("k", C.c_int), ("solve_status", C.c_int), ("eps", C.c_double),
                 ("relres", C.c_double), ("factor_ms", C.c_double), ("solve_ms", C.c_double),
                 ("ms", C.c_double), ("scaling_ms", C.c_double), ("rank_ms", C.c_double),
-                ("steps_ms", C.c_double)]
+                ("steps_ms", C.c_double), ("sigma", C.c_double), ("pred_pcg_iters", C.c_int),
+                ("pred_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -242,7 +242,7 @@ int reduce_grid(size_t len) {
 
 // slots of sc
 enum : int { kXS = 0, kRp2 = 1, kRd2 = 2, kCX = 3, kBy = 4, kB2 = 5, kC2 = 6, kRatio = 7,
-             kGF = 8, kNS = 9, kLz = 10, kSlots = 11 };
+             kGF = 8, kNS = 9, kLz = 10, kXdS = 11, kdXS = 12, kdXdS = 13, kSlots = 14 };
 
 // The i-th smallest eigenvalue (0-based) of the symmetric tridiagonal matrix with diagonal a and
 // off-diagonal b (j x j), by bisection on the Sturm count to the rounding level.
@@ -618,11 +618,11 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
       LRSDP_HIP(hipStreamSynchronize(s));
       rec.scaling_ms = std::chrono::duration<double, std::milli>(
                            std::chrono::steady_clock::now() - t_sc).count();
-      // rhs = b - sigma mu A(S^{-1}) + A(W R_d W)
+      // the affine part of the right-hand side, b + A(W R_d W); the centering term
+      // -sigma mu A(S^{-1}) is added once sigma is known
       LRSDP_TRY(I.mm(I.W, false, I.Rd, false, I.T1, 0));
       LRSDP_TRY(I.mm(I.T1, false, I.W, false, I.T2, 0));
-      k_gather_A<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->coef, I.Si, bvec, -o.sigma * mu, I.rhs);
-      k_gather_A<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->coef, I.T2, I.rhs, 1.0, I.rhs);
+      k_gather_A<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->coef, I.T2, bvec, 1.0, I.rhs);
       LRSDP_HIP(hipGetLastError());
       // the rank of the split: fixed, or (rank_eta > 0) the largest i <= k with
       // lambda_i(W) >= eta lambda_{i+1}(W), at least 1 (Section 5)
@@ -660,35 +660,77 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
       lrsdp_factor* F = nullptr;
       int frc = lrsdp_factor_create(P, I.W, k, &so, &F);
       if (frc < 0) return frc;
-      lrsdp_info si{};
-      int src = lrsdp_solve(F, I.rhs, I.dy, I.dylo, &so, &si);
       rec.factor_ms = F->setup_ms;
-      lrsdp_factor_destroy(F);
+      // the direction for the current right-hand side: dy (rounded from its double-double
+      // pair), dS = R_d - sum dy_i A_i, dX = c S^{-1} - X - W dS W (c = sigma mu), and the
+      // largest steps to the boundary (X = L_X L_X^T, S = L L^T)
+      double steps_ms = 0.0;  // the steps to the boundary of the step's own direction
+      auto direction = [&](double c, lrsdp_info* si, double* tp, double* td) -> int {
+        const int src = lrsdp_solve(F, I.rhs, I.dy, I.dylo, &so, si);
+        if (src < 0 && src != LRSDP_ERR_STAGNATED) return src;
+        k_round_pair<<<vg, kT, 0, s>>>(m, I.dy, I.dylo);
+        LRSDP_HIP(hipMemcpyAsync(I.dS, I.Rd, I.nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        k_add_At<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->val, I.dy, -1.0, I.dS);
+        LRSDP_TRY(I.mm(I.W, false, I.dS, false, I.T1, 0));
+        LRSDP_TRY(I.mm(I.T1, false, I.W, false, I.T2, 0));
+        k_dx<<<eg, kT, 0, s>>>(n, c, I.Si, X, I.T2, I.dX);
+        k_sym_axpy<<<eg, kT, 0, s>>>(n, I.dX, 0.0, nullptr);
+        LRSDP_HIP(hipGetLastError());
+        const auto t0 = std::chrono::steady_clock::now();
+        LRSDP_TRY(I.max_step(I.Lxi, I.dX, tp));
+        LRSDP_TRY(I.max_step(I.Li, I.dS, td));
+        steps_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                       .count();
+        return src;
+      };
+      auto fin = [&](int rc2) {
+        lrsdp_factor_destroy(F);
+        return rc2;
+      };
+      const auto t_cx = std::chrono::steady_clock::now();
+      const int crc = I.chol_inv(X, I.Lxi, false, &bad);
+      if (crc != LRSDP_OK) return fin(crc);
+      if (bad) return fin(LRSDP_ERR_IPM);
+      const double cholx_ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_cx).count();
+      // the centering: fixed, or Mehrotra's rule from the affine direction (sigma = 0) and the
+      // duality measure its full steps (at most 1) reach,
+      //   n mu_aff = X.S + a_d X.dS + a_p dX.S + a_p a_d dX.dS
+      double sg = o.sigma;
+      double tp = 0.0, td = 0.0;
+      if (o.predictor) {
+        auto t_pr = std::chrono::steady_clock::now();
+        lrsdp_info pi{};
+        const int prc = direction(0.0, &pi, &tp, &td);
+        if (prc < 0 && prc != LRSDP_ERR_STAGNATED) return fin(prc);
+        int drc = I.reduce(kDot, I.nn, X, I.dS, kXdS);
+        if (drc == LRSDP_OK) drc = I.reduce(kDot, I.nn, I.dX, S, kdXS);
+        if (drc == LRSDP_OK) drc = I.reduce(kDot, I.nn, I.dX, I.dS, kdXdS);
+        if (drc == LRSDP_OK) drc = I.read(kSlots, h);
+        if (drc != LRSDP_OK) return fin(drc);
+        const double pa = std::min(1.0, tp), da = std::min(1.0, td);
+        const double mu_aff = (xs + da * h[kXdS] + pa * h[kdXS] + pa * da * h[kdXdS]) / n;
+        const double r = std::max(0.0, mu_aff / mu);
+        sg = std::min(1.0, std::max(o.sigma, r * r * r));
+        rec.pred_pcg_iters = pi.iters;
+        inf.pcg_iters_total += pi.iters;
+        rec.pred_ms = std::chrono::duration<double, std::milli>(
+                          std::chrono::steady_clock::now() - t_pr).count();
+      }
+      rec.sigma = sg;
+      // rhs = b - sigma mu A(S^{-1}) + A(W R_d W)
+      k_gather_A<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->coef, I.Si, I.rhs, -sg * mu, I.rhs);
+      lrsdp_info si{};
+      const int src = direction(sg * mu, &si, &tp, &td);
       rec.solve_status = src;
-      if (src < 0 && src != LRSDP_ERR_STAGNATED) return src;
-      k_round_pair<<<vg, kT, 0, s>>>(m, I.dy, I.dylo);
+      if (src < 0 && src != LRSDP_ERR_STAGNATED) return fin(src);
+      fin(0);
       rec.pcg_iters = si.iters;
       rec.outer_iters = si.outer_iters;
       rec.solve_ms = si.solve_ms;
       rec.relres = si.relres;
       inf.pcg_iters_total += si.iters;
-      // dS = R_d - sum dy_i A_i;  dX = sigma mu S^{-1} - X - W dS W
-      LRSDP_HIP(hipMemcpyAsync(I.dS, I.Rd, I.nn * sizeof(double), hipMemcpyDeviceToDevice, s));
-      k_add_At<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->val, I.dy, -1.0, I.dS);
-      LRSDP_TRY(I.mm(I.W, false, I.dS, false, I.T1, 0));
-      LRSDP_TRY(I.mm(I.T1, false, I.W, false, I.T2, 0));
-      k_dx<<<eg, kT, 0, s>>>(n, o.sigma * mu, I.Si, X, I.T2, I.dX);
-      k_sym_axpy<<<eg, kT, 0, s>>>(n, I.dX, 0.0, nullptr);
-      LRSDP_HIP(hipGetLastError());
-      // steps to the boundary: X + a dX PSD (X = L_X L_X^T), S + a dS PSD (S = L L^T)
-      double tp = 0.0, td = 0.0;
-      auto t_st = std::chrono::steady_clock::now();
-      LRSDP_TRY(I.chol_inv(X, I.Lxi, false, &bad));
-      if (bad) return LRSDP_ERR_IPM;
-      LRSDP_TRY(I.max_step(I.Lxi, I.dX, &tp));
-      LRSDP_TRY(I.max_step(I.Li, I.dS, &td));
-      rec.steps_ms = std::chrono::duration<double, std::milli>(
-                         std::chrono::steady_clock::now() - t_st).count();
+      rec.steps_ms = cholx_ms + steps_ms;
       const double ap = std::min(1.0, o.frac * tp), ad = std::min(1.0, o.frac * td);
       rec.alpha_p = ap;
       rec.alpha_d = ad;

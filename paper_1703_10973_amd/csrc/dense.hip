@@ -51,8 +51,9 @@ __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
   // (workgroups are dealt to the eight XCDs in turn, which spreads tiles of unequal K
   // ranges evenly over them; a contiguous tile range per XCD measured slower here)
   const int tile = blockIdx.x;
+  const bool tri_grid = lower && tiles_m == tiles_n;
   int ti, tj;
-  if (lower && tiles_m == tiles_n) {  // the grid covers only the lower triangle of tiles
+  if (tri_grid) {  // the grid covers only the lower triangle of tiles
     ti = (int)((sqrt(8.0 * tile + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= tile) ++ti;
     while (ti * (ti + 1) / 2 > tile) --ti;
@@ -64,9 +65,10 @@ __global__ __launch_bounds__(64 * WM * WN * KS) void k_gemm(GemmArgs g) {
     ti = tile / tiles_n;
     tj = tile - ti * tiles_n;
   }
-  // triangular operands: start with the tiles whose K range is longest
-  if (g.flags & kKToCol) tj = tiles_n - 1 - tj;
-  if (g.flags & kKToRow) ti = tiles_m - 1 - ti;
+  // triangular operands: start with the tiles whose K range is longest (a permutation of the
+  // full grid only: on the lower-triangle grid it would send tiles across the diagonal)
+  if (!tri_grid && (g.flags & kKToCol)) tj = tiles_n - 1 - tj;
+  if (!tri_grid && (g.flags & kKToRow)) ti = tiles_m - 1 - ti;
   const int i0 = ti * TMv, j0 = tj * TNv;
   if (lower && j0 > i0 + TMv - 1) return;
   int klo = 0, khi = g.K;

@@ -63,12 +63,15 @@ __global__ __launch_bounds__(kT) void k_dot(int m, const double* a, const double
   if (arrive_last(counter)) finish_sum(part, counter, out, red);
 }
 
-// alpha = rho / pq;  y += alpha p;  r -= alpha q;  sc[kRR] = r.r
+// alpha = rho / pq;  y += alpha p;  r -= alpha q;  sc[kRR] = r.r.  A breakdown (pq <= 0 or
+// rho <= 0, from rounding or an indefinite preconditioner) leaves y and r as they are, so the
+// caller, which stops there, keeps the last iterate
 __global__ __launch_bounds__(kT) void k_update_xr(int m, double* sc, int rho_slot, double* x,
                                                   double* r, const double* p, const double* q,
                                                   double* part, int* counter) {
   __shared__ double red[kT / kWave];
-  const double alpha = sc[rho_slot] / sc[kPQ];
+  const double rho = sc[rho_slot], pq = sc[kPQ];
+  const double alpha = (pq > 0.0 && rho > 0.0) ? rho / pq : 0.0;
   double s = 0.0;
   for (int i = blockIdx.x * kT + threadIdx.x; i < m; i += gridDim.x * kT) {
     x[i] = fma(alpha, p[i], x[i]);

@@ -275,7 +275,9 @@ LRSDP_API int lrsdp_residual_dd(lrsdp_factor* f, const double* r, const double* 
  * preconditioner, to ||H y - r|| <= eps ||r||.  With refinement (dd_mode) the answer is the
  * double-double pair y + y_lo (y_lo: length-m device array; required when dd_mode != OFF,
  * zero-filled when the pair is not needed).  info: host, may be NULL.  Returns OK,
- * NOT_CONVERGED, STAGNATED, INDEFINITE_PRECOND, INVALID_ARG or DEVICE. */
+ * NOT_CONVERGED, STAGNATED, INDEFINITE_PRECOND, INVALID_ARG or DEVICE.  With NOT_CONVERGED,
+ * STAGNATED and INDEFINITE_PRECOND y (+ y_lo) holds the last iterate before the stop (zero
+ * when PCG broke down at its first step), info->relres its relative residual. */
 LRSDP_API int lrsdp_solve(lrsdp_factor* f, const double* r, double* y, double* y_lo,
                 const lrsdp_opts* opts, lrsdp_info* info);
 
@@ -377,6 +379,12 @@ typedef struct lrsdp_ipm_opts {
                          /* duality measure that direction reaches with its full steps to the */
                          /* boundary (Mehrotra's rule, no second-order corrector; the two     */
                          /* Hessian solves share one factor); 0: sigma every step (default 1) */
+  int warm_start;        /* 1: start from the X, y, S passed in (X and S symmetric positive   */
+                         /* definite, else LRSDP_ERR_IPM at the first step); 0: the standard */
+                         /* start X = xi I, S = eta I, y = 0 (default 0)                      */
+  int stall_iters;       /* > 0: stop when max(pinf, dinf, gap) has not fallen below 0.9 of   */
+                         /* its best value for this many steps (the accuracy FP64 allows is  */
+                         /* reached); 0: run to max_iter (default 5)                          */
   double frac;           /* fraction of the step to the boundary (default 0.9)             */
   int32_t k;             /* rank of the preconditioner's split of W (default 2); its upper  */
                          /* bound k_max when rank_eta > 0                                   */
@@ -399,9 +407,18 @@ typedef struct lrsdp_ipm_info {
   int iters;             /* Newton steps taken                                              */
   int records;           /* entries written to recs                                         */
   int pcg_iters_total;   /* PCG iterations over all Hessian solves                          */
-  double mu, pinf, dinf, gap;      /* at the last iterate                                    */
-  double primal_obj, dual_obj;     /* C . X and b^T y at the last iterate                    */
+  double mu, pinf, dinf, gap;      /* at the iterate returned                                */
+  double primal_obj, dual_obj;     /* C . X and b^T y at the iterate returned                */
   double ms;             /* wall time of the call                                           */
+  int best_iter;         /* the step whose iterate is returned (the best one seen)           */
+  int stalled;           /* 1: stopped by stall_iters; 2: stopped by a numerical breakdown of  */
+                         /* a step after the first (last_error)                              */
+  int last_error;        /* with stalled = 2: the breakdown (IPM, CHOL_Z, CHOL_S, NOT_PD_W,   */
+                         /* EIG or INDEFINITE_PRECOND); 0 otherwise                          */
+  int fail_stage;        /* with LRSDP_ERR_IPM: 1 the start X or S does not factor, 2 the    */
+                         /* scaling's square root did not reach ns_tol in max_ns_iter steps, */
+                         /* 3 the new iterate did not factor after 10 shortened steps        */
+  double ns_resid;       /* with fail_stage 2: the last ||I - Z Y||_F                        */
 } lrsdp_ipm_info;
 
 /* One Newton step: the measures of the iterate it started from, the Hessian solve and the
@@ -417,22 +434,30 @@ typedef struct lrsdp_ipm_record {
   double eps;                      /* the Hessian solve's tolerance                          */
   double relres;                   /* the Hessian solve's final relative residual            */
   double factor_ms, solve_ms, ms;  /* its setup, its solve, the whole step                   */
-  double scaling_ms;               /* W and S^{-1} (Cholesky of S, Newton-Schulz, products)  */
+  double scaling_ms;               /* W and S^{-1} (Newton-Schulz and products)              */
   double rank_ms;                  /* the rank estimate (0 when k is fixed)                  */
-  double steps_ms;                 /* the two steps to the boundary                          */
+  double steps_ms;                 /* the two steps to the boundary and the update (Cholesky */
+                                   /* factors of the new X and S)                            */
   double sigma;                    /* the centering parameter the step used                  */
   int pred_pcg_iters;              /* the predictor's Hessian solve (0 without predictor)    */
   double pred_ms;                  /* the predictor: its solve, direction and two steps      */
+  int backtracks;                  /* times the step was shortened by 0.8 because the new X  */
+                                   /* or S did not factor (FP64 end-game; 0 before it)       */
 } lrsdp_ipm_record;
 
 /* Fills *o with the defaults listed above.  o: host. */
 LRSDP_API void lrsdp_ipm_opts_default(lrsdp_ipm_opts* o);
 /* Runs the method on problem p (its constraints A_i) with right-hand side b (device, m) and
  * cost C (device, n x n symmetric; NULL: the identity).  X, S (device, n x n) and y (device, m)
- * receive the last iterate.  info (host, may be NULL); recs (host, may be NULL) receives up to
- * max_recs per-step records.  Returns OK, NOT_CONVERGED (max_iter reached), or the error of
- * the step that failed (IPM, or one of lrsdp_factor_create / lrsdp_solve): X, y, S then hold
- * the last iterate.  Requires 3 <= n <= 4096 and 1 <= k <= 16, k < n. */
+ * receive the iterate that met tol, or else the best one seen (smallest max(pinf, dinf, gap)).
+ * info (host, may be NULL); recs (host, may be NULL) receives up to max_recs per-step records.
+ * A Hessian solve that stops short of its tolerance (NOT_CONVERGED, STAGNATED, or a PCG
+ * breakdown, INDEFINITE_PRECOND, from rounding once W is ill-conditioned) gives the step its
+ * last iterate as an inexact Newton direction.  Returns OK, NOT_CONVERGED (max_iter reached,
+ * stalled, or a numerical breakdown after the first step: info->stalled, info->last_error), or
+ * the error that ended the call (the start does not factor, INVALID_ARG, DEVICE,
+ * OUT_OF_BUDGET): X, y, S then hold the best iterate.  Requires 3 <= n <= 4096 and
+ * 1 <= k <= 16, k < n. */
 LRSDP_API int lrsdp_ipm_solve(lrsdp_problem* p, const double* b, const double* C,
                               const lrsdp_ipm_opts* opts, double* X, double* y, double* S,
                               lrsdp_ipm_info* info, lrsdp_ipm_record* recs, int max_recs);

@@ -133,14 +133,22 @@ class Problem:
     def info(self):
         return lrsdp_problem_info(self.handle)
 
-    def ipm_solve(self, b, C=None, options=None, max_recs=200, **kw):
+    def ipm_solve(self, b, C=None, options=None, max_recs=200, start=None, **kw):
         """The interior-point method on this problem (lrsdp_ipm_solve): right-hand side b
         (device, m), cost C (device n x n, None: the identity).  options: an lrsdp_ipm_opts,
-        or keywords of it (k=..., tol=...).  Returns (X, y, S, status, info, records)."""
+        or keywords of it (k=..., tol=...).  start: (X, y, S) to start from (copied; sets
+        warm_start).  Returns (X, y, S, status, info, records)."""
         o = options if options is not None else ipm_opts(**kw)
-        X = torch.empty(self.n, self.n, dtype=torch.float64, device=b.device)
-        S = torch.empty_like(X)
-        y = torch.empty(self.m, dtype=torch.float64, device=b.device)
+        if start is not None:
+            X, y, S = (t.detach().to(device=b.device, dtype=torch.float64).contiguous().clone()
+                       for t in start)
+            if X.shape != (self.n, self.n) or S.shape != (self.n, self.n) or y.shape != (self.m,):
+                raise ValueError("start: X and S must be n x n and y of length m")
+            o.warm_start = 1
+        else:
+            X = torch.empty(self.n, self.n, dtype=torch.float64, device=b.device)
+            S = torch.empty_like(X)
+            y = torch.empty(self.m, dtype=torch.float64, device=b.device)
         st, info, recs = lrsdp_ipm_solve(self.handle, b, C, o, X, y, S, max_recs)
         return X, y, S, st, info, recs
 

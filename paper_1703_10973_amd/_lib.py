@@ -60,7 +60,8 @@ class lrsdp_info(C.Structure):
 
 class lrsdp_ipm_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("sigma", C.c_double),
-                ("predictor", C.c_int), ("frac", C.c_double), ("k", C.c_int32), ("rank_eta", C.c_double),
+                ("predictor", C.c_int), ("warm_start", C.c_int), ("stall_iters", C.c_int),
+                ("frac", C.c_double), ("k", C.c_int32), ("rank_eta", C.c_double),
                 ("pcg_eps", C.c_double), ("pcg_eps_mu", C.c_double),
                 ("max_ns_iter", C.c_int), ("householder_eig", C.c_int), ("ns_tol", C.c_double),
                 ("solve", lrsdp_opts)]
@@ -70,7 +71,9 @@ class lrsdp_ipm_info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("records", C.c_int),
                 ("pcg_iters_total", C.c_int), ("mu", C.c_double), ("pinf", C.c_double),
                 ("dinf", C.c_double), ("gap", C.c_double), ("primal_obj", C.c_double),
-                ("dual_obj", C.c_double), ("ms", C.c_double)]
+                ("dual_obj", C.c_double), ("ms", C.c_double), ("best_iter", C.c_int),
+                ("stalled", C.c_int), ("last_error", C.c_int), ("fail_stage", C.c_int),
+                ("ns_resid", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -84,7 +87,7 @@ class lrsdp_ipm_record(C.Structure):
                 ("relres", C.c_double), ("factor_ms", C.c_double), ("solve_ms", C.c_double),
                 ("ms", C.c_double), ("scaling_ms", C.c_double), ("rank_ms", C.c_double),
                 ("steps_ms", C.c_double), ("sigma", C.c_double), ("pred_pcg_iters", C.c_int),
-                ("pred_ms", C.c_double)]
+                ("pred_ms", C.c_double), ("backtracks", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -496,6 +499,9 @@ def lrsdp_ipm_solve(p, b, C_, opts, X, y, S, max_recs=200):
                                _ptr(y, torch.float64, m, "y"),
                                _ptr(S, torch.float64, n * n, "S"),
                                C.byref(info), recs, int(max_recs))
+    out = [recs[i].as_dict() for i in range(min(info.records, max_recs))]
     if st < 0:
-        raise LrsdpError(st, "lrsdp_ipm_solve")
-    return st, info.as_dict(), [recs[i].as_dict() for i in range(min(info.records, max_recs))]
+        e = LrsdpError(st, "lrsdp_ipm_solve")
+        e.info, e.records = info.as_dict(), out  # the steps taken before the failure
+        raise e
+    return st, info.as_dict(), out

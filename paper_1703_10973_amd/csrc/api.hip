@@ -564,6 +564,8 @@ void lrsdp_ipm_opts_default(lrsdp_ipm_opts* o) {
   o->max_iter = 60;
   o->sigma = 0.1;
   o->predictor = 1;
+  o->warm_start = 0;
+  o->stall_iters = 5;
   o->frac = 0.9;
   o->k = 2;
   o->rank_eta = 0.0;
@@ -588,7 +590,8 @@ int lrsdp_ipm_solve(lrsdp_problem* p, const double* b, const double* C,
       !(o.frac > 0.0 && o.frac < 1.0) || o.k < 1 || o.k > 16 || o.k >= p->n ||
       !(o.pcg_eps > 0.0 && o.pcg_eps < 1.0) || !(o.pcg_eps_mu >= 0.0) || !(o.rank_eta >= 0.0) ||
       o.max_ns_iter < 1 || !(o.ns_tol > 0.0) || (o.householder_eig != 0 && o.householder_eig != 1) ||
-      (o.predictor != 0 && o.predictor != 1) || (o.rank_eta > 0.0 && o.k + 1 >= p->n) ||
+      (o.predictor != 0 && o.predictor != 1) || (o.warm_start != 0 && o.warm_start != 1) ||
+      o.stall_iters < 0 || (o.rank_eta > 0.0 && o.k + 1 >= p->n) ||
       !opts_valid(o.solve) || p->n < 3 || p->n > 4096)
     return LRSDP_ERR_INVALID_ARG;
   DeviceGuard g(p->ctx->device);

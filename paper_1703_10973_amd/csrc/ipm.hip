@@ -284,9 +284,9 @@ struct Ipm {
   double *Rd = nullptr, *W = nullptr, *Si = nullptr, *Lb = nullptr, *Li = nullptr,
          *Lxi = nullptr, *G = nullptr, *Y = nullptr, *Y2 = nullptr, *Z = nullptr,
          *Z2 = nullptr, *Pm = nullptr, *T1 = nullptr, *T2 = nullptr, *dX = nullptr,
-         *dS = nullptr, *Mx = nullptr;
-  // m
-  double *rhs = nullptr, *dy = nullptr, *dylo = nullptr, *rp = nullptr;
+         *dS = nullptr, *Mx = nullptr, *Lx = nullptr, *Xb = nullptr, *Sb = nullptr;  // Xb,
+  // m                                                     // Sb, yb: the best iterate so far
+  double *rhs = nullptr, *dy = nullptr, *dylo = nullptr, *rp = nullptr, *yb = nullptr;
   // scratch
   double *ptmp = nullptr, *part = nullptr, *sc = nullptr, *lam = nullptr, *vl = nullptr;
   void* ews = nullptr;
@@ -329,13 +329,13 @@ struct Ipm {
     g.flags = flags;
     return gemm(g, s);
   }
-  // Cholesky of M (copied into Lb) and its inverse into Linv (lower; the upper part outside
-  // the 64-aligned diagonal blocks is left undefined, and no product below reads it).  Returns
-  // 1 in *bad when a pivot was not positive.
-  int chol_inv(const double* M, double* Linv, bool keep_L, int* bad) {
-    LRSDP_HIP(hipMemcpyAsync(Lb, M, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // Cholesky of M (copied into Lm, which receives L when keep_L) and its inverse into Linv
+  // (lower; the upper part outside the 64-aligned diagonal blocks is left undefined, and no
+  // product below reads it).  Returns 1 in *bad when a pivot was not positive.
+  int chol_inv(const double* M, double* Lm, double* Linv, bool keep_L, int* bad) {
+    LRSDP_HIP(hipMemcpyAsync(Lm, M, nn * sizeof(double), hipMemcpyDeviceToDevice, s));
     k_zero_int<<<1, 64, 0, s>>>(1, flag);
-    LRSDP_TRY(potrf_inv(Lb, n, n, Linv, n, flag, ptmp, keep_L, s));
+    LRSDP_TRY(potrf_inv(Lm, n, n, Linv, n, flag, ptmp, keep_L, s));
     int h = 0;
     LRSDP_HIP(hipMemcpyAsync(&ctx->h_pinned[40], flag, sizeof(int), hipMemcpyDeviceToHost, s));
     LRSDP_HIP(hipStreamSynchronize(s));
@@ -412,8 +412,8 @@ struct Ipm {
   // -1 / lambda_min(L^{-1} D L^{-T}), inf when that eigenvalue is >= 0
   int max_step(const double* Linv, const double* D, double* out) {
     LRSDP_TRY(mm(Linv, false, D, false, T1, kKToRow));   // L^{-1} D
-    LRSDP_TRY(mm(T1, false, Linv, true, Mx, kKToCol));   // (L^{-1} D) L^{-T}
-    k_sym_axpy<<<grid_for((int64_t)nn, kT, 4096), kT, 0, s>>>(n, Mx, 0.0, nullptr);
+    LRSDP_TRY(mm(T1, false, Linv, true, Mx, kKToCol | kLowerOut));  // (L^{-1} D) L^{-T}
+    LRSDP_TRY(mirror_lower(Mx, n, n, s));
     double h[1];
     int steps = 0;
     const int lrc = householder ? LRSDP_NOT_CONVERGED : lanczos(Mx, 1, h, 0, nullptr, 1e-11, &steps);
@@ -431,14 +431,21 @@ struct Ipm {
 
 double* ctx_pinned(const Ipm& I) { return I.ctx->h_pinned; }
 
+// Hessian-solve statuses whose answer still serves as an inexact Newton direction: the last
+// iterate of a solve that stopped short of its tolerance or broke down from rounding
+bool inexact_ok(int st) {
+  return st == LRSDP_NOT_CONVERGED || st == LRSDP_ERR_STAGNATED ||
+         st == LRSDP_ERR_INDEFINITE_PRECOND;
+}
+
 
 
 int ipm_alloc(Ipm& I) {
   const size_t nn = I.nn, m = I.m;
   double** mats[] = {&I.Rd, &I.W, &I.Si, &I.Lb, &I.Li, &I.Lxi, &I.G, &I.Y, &I.Y2, &I.Z,
-                     &I.Z2, &I.Pm, &I.T1, &I.T2, &I.dX, &I.dS, &I.Mx};
+                     &I.Z2, &I.Pm, &I.T1, &I.T2, &I.dX, &I.dS, &I.Mx, &I.Lx, &I.Xb, &I.Sb};
   for (double** p : mats) LRSDP_TRY(dev_alloc_n(I.ctx, p, nn));
-  double** vecs[] = {&I.rhs, &I.dy, &I.dylo, &I.rp};
+  double** vecs[] = {&I.rhs, &I.dy, &I.dylo, &I.rp, &I.yb};
   for (double** p : vecs) LRSDP_TRY(dev_alloc_n(I.ctx, p, m));
   I.ptmp_n = std::max<size_t>(1, potrf_inv_tmp_doubles(I.n));
   LRSDP_TRY(dev_alloc_n(I.ctx, &I.ptmp, I.ptmp_n));
@@ -466,9 +473,9 @@ int ipm_alloc(Ipm& I) {
 void ipm_free(Ipm& I) {
   const size_t nn = I.nn, m = I.m;
   double* mats[] = {I.Rd, I.W, I.Si, I.Lb, I.Li, I.Lxi, I.G, I.Y, I.Y2, I.Z,
-                    I.Z2, I.Pm, I.T1, I.T2, I.dX, I.dS, I.Mx};
+                    I.Z2, I.Pm, I.T1, I.T2, I.dX, I.dS, I.Mx, I.Lx, I.Xb, I.Sb};
   for (double* p : mats) dev_free(I.ctx, p, nn * sizeof(double));
-  double* vecs[] = {I.rhs, I.dy, I.dylo, I.rp};
+  double* vecs[] = {I.rhs, I.dy, I.dylo, I.rp, I.yb};
   for (double* p : vecs) dev_free(I.ctx, p, m * sizeof(double));
   dev_free(I.ctx, I.ptmp, I.ptmp_n * sizeof(double));
   dev_free(I.ctx, I.part, (size_t)kSlots * kG * sizeof(double));
@@ -486,24 +493,43 @@ void ipm_free(Ipm& I) {
 }
 
 // W (n x n) with W S W = X, and S^{-1}, from S = L L^T (Li = L^{-1}, Lb = L) and the
-// coupled Newton-Schulz iteration on G / c, c = ||G||_F:  T = (3 I - Z Y) / 2,
+// coupled Newton-Schulz iteration on G / c, c >= lambda_max(G):  T = (3 I - Z Y) / 2,
 // Y <- Y T, Z <- T Z, so that Y -> (G / c)^{1/2} and Z -> (G / c)^{-1/2}.
-int nt_scaling(Ipm& I, const double* X, int max_ns, double ns_tol, int* ns_iters) {
+int nt_scaling(Ipm& I, const double* X, int max_ns, double ns_tol, int* ns_iters,
+               double* resid) {
   const int n = I.n;
   hipStream_t s = I.s;
   const int eg = grid_for((int64_t)I.nn, kT, 4096);
-  LRSDP_TRY(I.mm(X, false, I.Lb, false, I.T1, kKFromCol));  // X L   (L lower)
-  LRSDP_TRY(I.mm(I.Lb, true, I.T1, false, I.G, kKFromRow));  // L^T X L
-  k_sym_axpy<<<eg, kT, 0, s>>>(n, I.G, 0.0, nullptr);
+  // G and the powers of G / ||G||_F are symmetric: each computes its lower triangle and
+  // mirrors it
+  LRSDP_TRY(I.mm(X, false, I.Lb, false, I.T1, kKFromCol));                 // X L (L lower)
+  LRSDP_TRY(I.mm(I.Lb, true, I.T1, false, I.G, kKFromRow | kLowerOut));   // L^T X L
+  LRSDP_TRY(mirror_lower(I.G, n, n, s));
   LRSDP_TRY(I.reduce(kDot, I.nn, I.G, I.G, kGF));
   double h[kSlots];
   LRSDP_TRY(I.read(kSlots, h));
-  const double c = std::sqrt(h[kGF]);
+  const double cf = std::sqrt(h[kGF]);
+  if (!(cf > 0.0) || !std::isfinite(cf)) return LRSDP_ERR_DEVICE;
+  // The iteration takes each eigenvalue x of G / c to 1 when 0 < x < 3, the smallest the
+  // slowest, so c should be a close upper bound of lambda_max(G).  G is positive definite, so
+  // lambda_max <= (sum lambda_i^8)^{1/8} = ||G^4||_F^{1/4}, which exceeds it by at most n^{1/8}
+  // (||G||_F by up to sqrt(n), reached when G is a multiple of I, as on the central path).
+  k_scale<<<eg, kT, 0, s>>>(I.nn, 1.0 / cf, I.G, I.Y);                     // G / ||G||_F
+  LRSDP_TRY(I.mm(I.Y, false, I.Y, false, I.Pm, kLowerOut));
+  LRSDP_TRY(mirror_lower(I.Pm, n, n, s));
+  LRSDP_TRY(I.mm(I.Pm, false, I.Pm, false, I.Z, kLowerOut));
+  LRSDP_TRY(mirror_lower(I.Z, n, n, s));
+  LRSDP_TRY(I.reduce(kDot, I.nn, I.Z, I.Z, kGF));
+  LRSDP_TRY(I.read(kSlots, h));
+  const double c = cf * std::min(1.0, std::pow(h[kGF], 0.125));
   if (!(c > 0.0) || !std::isfinite(c)) return LRSDP_ERR_DEVICE;
   k_scale<<<eg, kT, 0, s>>>(I.nn, 1.0 / c, I.G, I.Y);
   k_scaled_eye<<<eg, kT, 0, s>>>(n, 1.0, I.Z);
   int it = 0;
   bool done = false;
+  // (the products of the loop are symmetric only in exact arithmetic: symmetrizing them, by
+  // averaging or by mirroring one triangle, breaks the coupling of Y and Z, and the iteration
+  // then diverges once the residual nears 1e-9; the loop keeps the full products)
   for (; it < max_ns && !done; ++it) {
     LRSDP_TRY(I.mm(I.Z, false, I.Y, false, I.Pm, 0));
     LRSDP_TRY(I.reduce(kEyeDev, I.nn, I.Pm, nullptr, kNS));
@@ -514,17 +540,21 @@ int nt_scaling(Ipm& I, const double* X, int max_ns, double ns_tol, int* ns_iters
     std::swap(I.Z, I.Z2);
     LRSDP_TRY(I.read(kSlots, h));
     // ||I - Z Y||_F of the step just taken; the update squares it (quadratic phase)
-    done = std::sqrt(h[kNS]) <= ns_tol;
+    const double r = std::sqrt(h[kNS]);
+    *resid = r;
+    if (!std::isfinite(r)) break;
+    done = r <= ns_tol;
   }
   *ns_iters = it;
   if (!done) return LRSDP_ERR_IPM;
-  // G^{1/2} = sqrt(c) Y;  W = L^{-T} G^{1/2} L^{-1};  S^{-1} = L^{-T} L^{-1}
+  // G^{1/2} = sqrt(c) Y;  W = L^{-T} G^{1/2} L^{-1};  S^{-1} = L^{-T} L^{-1} (symmetric:
+  // lower triangles, mirrored)
   k_sym_axpy<<<eg, kT, 0, s>>>(n, I.Y, 0.0, nullptr);
   LRSDP_TRY(I.mm(I.Y, false, I.Li, false, I.T1, kKFromCol, std::sqrt(c)));
-  LRSDP_TRY(I.mm(I.Li, true, I.T1, false, I.W, kKFromRow));
-  k_sym_axpy<<<eg, kT, 0, s>>>(n, I.W, 0.0, nullptr);
-  LRSDP_TRY(I.mm(I.Li, true, I.Li, false, I.Si, kKFromRow | kKFromCol));
-  k_sym_axpy<<<eg, kT, 0, s>>>(n, I.Si, 0.0, nullptr);
+  LRSDP_TRY(I.mm(I.Li, true, I.T1, false, I.W, kKFromRow | kLowerOut));
+  LRSDP_TRY(mirror_lower(I.W, n, n, s));
+  LRSDP_TRY(I.mm(I.Li, true, I.Li, false, I.Si, kKFromRow | kKFromCol | kLowerOut));
+  LRSDP_TRY(mirror_lower(I.Si, n, n, s));
   LRSDP_HIP(hipGetLastError());
   return LRSDP_OK;
 }
@@ -549,6 +579,9 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
   int rc = ipm_alloc(I);
   lrsdp_ipm_info inf{};
   inf.status = LRSDP_NOT_CONVERGED;
+  inf.best_iter = -1;
+  double best_merit = INFINITY;
+  bool have_best = false;
   const int eg = grid_for((int64_t)I.nn, kT, 4096);
   const int vg = grid_for(m, kT);
   auto body = [&]() -> int {
@@ -563,12 +596,27 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
     const double nc = C ? std::sqrt(h[kC2]) : std::sqrt((double)n);
     const double xi = std::max({10.0, std::sqrt((double)n), n * h[kRatio]});
     const double eta = std::max({10.0, std::sqrt((double)n), 1.0 + nc});
-    k_scaled_eye<<<eg, kT, 0, s>>>(n, xi, X);
-    k_scaled_eye<<<eg, kT, 0, s>>>(n, eta, S);
-    LRSDP_HIP(hipMemsetAsync(y, 0, (size_t)m * sizeof(double), s));
+    if (!o.warm_start) {
+      k_scaled_eye<<<eg, kT, 0, s>>>(n, xi, X);
+      k_scaled_eye<<<eg, kT, 0, s>>>(n, eta, S);
+      LRSDP_HIP(hipMemsetAsync(y, 0, (size_t)m * sizeof(double), s));
+    }
     LRSDP_HIP(hipGetLastError());
+    // the factors of the current iterate: S = Lb Lb^T with Li = Lb^{-1}, X's inverse factor
+    // Lxi (then kept from each step's update, which factors the new iterate to accept it)
+    {
+      int bad = 0;
+      inf.fail_stage = 1;
+      LRSDP_TRY(I.chol_inv(S, I.Lb, I.Li, true, &bad));
+      if (bad) return LRSDP_ERR_IPM;
+      LRSDP_TRY(I.chol_inv(X, I.Lx, I.Lxi, false, &bad));
+      if (bad) return LRSDP_ERR_IPM;
+      inf.fail_stage = 0;
+    }
     lrsdp_opts so = o.solve;
     double mu0 = 0.0;
+    double stall_ref = INFINITY;
+    int stall = 0;
     for (int it = 0; it <= o.max_iter; ++it) {
       auto t_it = std::chrono::steady_clock::now();
       // residuals and the duality measure
@@ -589,19 +637,38 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
       const double dinf = std::sqrt(h[kRd2]) / (1.0 + nc);
       const double gap = xs / (1.0 + std::fabs(h[kCX]) + std::fabs(h[kBy]));
       inf.iters = it;
-      inf.mu = mu;
-      inf.pinf = pinf;
-      inf.dinf = dinf;
-      inf.gap = gap;
-      inf.primal_obj = h[kCX];
-      inf.dual_obj = h[kBy];
       if (!std::isfinite(mu) || !std::isfinite(pinf) || !std::isfinite(dinf))
         return LRSDP_ERR_DEVICE;
-      if (std::max({pinf, dinf, gap}) <= o.tol) {
+      const double merit = std::max({pinf, dinf, gap});
+      if (merit < best_merit) {  // keep the best iterate (returned unless one meets tol)
+        best_merit = merit;
+        inf.best_iter = it;
+        inf.mu = mu;
+        inf.pinf = pinf;
+        inf.dinf = dinf;
+        inf.gap = gap;
+        inf.primal_obj = h[kCX];
+        inf.dual_obj = h[kBy];
+        LRSDP_HIP(hipMemcpyAsync(I.Xb, X, I.nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        LRSDP_HIP(hipMemcpyAsync(I.Sb, S, I.nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        LRSDP_HIP(hipMemcpyAsync(I.yb, y, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice,
+                                 s));
+        have_best = true;
+      }
+      if (merit <= o.tol) {
         inf.status = LRSDP_OK;
         return LRSDP_OK;
       }
       if (it == o.max_iter) return LRSDP_OK;  // NOT_CONVERGED
+      // stalled: no step in the last stall_iters took the measure below 0.9 of its best (once
+      // W is ill-conditioned enough, FP64 directions stop making progress)
+      if (merit < 0.9 * stall_ref) {
+        stall_ref = merit;
+        stall = 0;
+      } else if (o.stall_iters > 0 && ++stall >= o.stall_iters) {
+        inf.stalled = 1;
+        return LRSDP_OK;  // NOT_CONVERGED
+      }
       lrsdp_ipm_record rec{};
       rec.mu = mu;
       rec.pinf = pinf;
@@ -609,11 +676,10 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
       rec.gap = gap;
       // Nesterov-Todd scaling W and S^{-1} from S = L L^T
       auto t_sc = std::chrono::steady_clock::now();
-      int bad = 0;
-      LRSDP_TRY(I.chol_inv(S, I.Li, true, &bad));
-      if (bad) return LRSDP_ERR_IPM;
       int ns = 0;
-      LRSDP_TRY(nt_scaling(I, X, o.max_ns_iter, o.ns_tol, &ns));
+      const int nrc = nt_scaling(I, X, o.max_ns_iter, o.ns_tol, &ns, &inf.ns_resid);
+      if (nrc == LRSDP_ERR_IPM) inf.fail_stage = 2;
+      LRSDP_TRY(nrc);
       rec.ns_iters = ns;
       LRSDP_HIP(hipStreamSynchronize(s));
       rec.scaling_ms = std::chrono::duration<double, std::milli>(
@@ -621,7 +687,8 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
       // the affine part of the right-hand side, b + A(W R_d W); the centering term
       // -sigma mu A(S^{-1}) is added once sigma is known
       LRSDP_TRY(I.mm(I.W, false, I.Rd, false, I.T1, 0));
-      LRSDP_TRY(I.mm(I.T1, false, I.W, false, I.T2, 0));
+      LRSDP_TRY(I.mm(I.T1, false, I.W, false, I.T2, kLowerOut));
+      LRSDP_TRY(mirror_lower(I.T2, n, n, s));
       k_gather_A<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->coef, I.T2, bvec, 1.0, I.rhs);
       LRSDP_HIP(hipGetLastError());
       // the rank of the split: fixed, or (rank_eta > 0) the largest i <= k with
@@ -667,12 +734,13 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
       double steps_ms = 0.0;  // the steps to the boundary of the step's own direction
       auto direction = [&](double c, lrsdp_info* si, double* tp, double* td) -> int {
         const int src = lrsdp_solve(F, I.rhs, I.dy, I.dylo, &so, si);
-        if (src < 0 && src != LRSDP_ERR_STAGNATED) return src;
+        if (src < 0 && !inexact_ok(src)) return src;
         k_round_pair<<<vg, kT, 0, s>>>(m, I.dy, I.dylo);
         LRSDP_HIP(hipMemcpyAsync(I.dS, I.Rd, I.nn * sizeof(double), hipMemcpyDeviceToDevice, s));
         k_add_At<<<vg, kT, 0, s>>>(m, n, P->a, P->b, P->val, I.dy, -1.0, I.dS);
         LRSDP_TRY(I.mm(I.W, false, I.dS, false, I.T1, 0));
-        LRSDP_TRY(I.mm(I.T1, false, I.W, false, I.T2, 0));
+        LRSDP_TRY(I.mm(I.T1, false, I.W, false, I.T2, kLowerOut));
+        LRSDP_TRY(mirror_lower(I.T2, n, n, s));
         k_dx<<<eg, kT, 0, s>>>(n, c, I.Si, X, I.T2, I.dX);
         k_sym_axpy<<<eg, kT, 0, s>>>(n, I.dX, 0.0, nullptr);
         LRSDP_HIP(hipGetLastError());
@@ -687,12 +755,6 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
         lrsdp_factor_destroy(F);
         return rc2;
       };
-      const auto t_cx = std::chrono::steady_clock::now();
-      const int crc = I.chol_inv(X, I.Lxi, false, &bad);
-      if (crc != LRSDP_OK) return fin(crc);
-      if (bad) return fin(LRSDP_ERR_IPM);
-      const double cholx_ms =
-          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_cx).count();
       // the centering: fixed, or Mehrotra's rule from the affine direction (sigma = 0) and the
       // duality measure its full steps (at most 1) reach,
       //   n mu_aff = X.S + a_d X.dS + a_p dX.S + a_p a_d dX.dS
@@ -702,7 +764,7 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
         auto t_pr = std::chrono::steady_clock::now();
         lrsdp_info pi{};
         const int prc = direction(0.0, &pi, &tp, &td);
-        if (prc < 0 && prc != LRSDP_ERR_STAGNATED) return fin(prc);
+        if (prc < 0 && !inexact_ok(prc)) return fin(prc);
         int drc = I.reduce(kDot, I.nn, X, I.dS, kXdS);
         if (drc == LRSDP_OK) drc = I.reduce(kDot, I.nn, I.dX, S, kdXS);
         if (drc == LRSDP_OK) drc = I.reduce(kDot, I.nn, I.dX, I.dS, kdXdS);
@@ -723,22 +785,49 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
       lrsdp_info si{};
       const int src = direction(sg * mu, &si, &tp, &td);
       rec.solve_status = src;
-      if (src < 0 && src != LRSDP_ERR_STAGNATED) return fin(src);
+      if (src < 0 && !inexact_ok(src)) return fin(src);
       fin(0);
       rec.pcg_iters = si.iters;
       rec.outer_iters = si.outer_iters;
       rec.solve_ms = si.solve_ms;
       rec.relres = si.relres;
       inf.pcg_iters_total += si.iters;
-      rec.steps_ms = cholx_ms + steps_ms;
-      const double ap = std::min(1.0, o.frac * tp), ad = std::min(1.0, o.frac * td);
-      rec.alpha_p = ap;
-      rec.alpha_d = ad;
-      k_sym_axpy<<<eg, kT, 0, s>>>(n, X, ap, I.dX);
+      // the update: X + a_p dX and S + a_d dS, each accepted once its Cholesky factorization
+      // succeeds (the factors are the next step's); near the accuracy FP64 allows, a step
+      // computed to 0.9 of the boundary can still leave an iterate that does not factor, and
+      // the step is then shortened by 0.8 (at most 10 times)
+      const auto t_up = std::chrono::steady_clock::now();
+      double ap = std::min(1.0, o.frac * tp), ad = std::min(1.0, o.frac * td);
+      int backtracks = 0;
+      auto accept = [&](double* M, const double* D, double* Mn, double* Lm, double* Linv,
+                        bool keep_L, double* a) -> int {
+        for (int tries = 0;; ++tries) {
+          LRSDP_HIP(hipMemcpyAsync(Mn, M, I.nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+          k_sym_axpy<<<eg, kT, 0, s>>>(n, Mn, *a, D);
+          LRSDP_HIP(hipGetLastError());
+          int b2 = 0;
+          LRSDP_TRY(I.chol_inv(Mn, Lm, Linv, keep_L, &b2));
+          if (!b2) break;
+          if (tries == 10) {
+            inf.fail_stage = 3;
+            return LRSDP_ERR_IPM;
+          }
+          *a *= 0.8;
+          ++backtracks;
+        }
+        LRSDP_HIP(hipMemcpyAsync(M, Mn, I.nn * sizeof(double), hipMemcpyDeviceToDevice, s));
+        return LRSDP_OK;
+      };
+      LRSDP_TRY(accept(X, I.dX, I.G, I.Lx, I.Lxi, false, &ap));
+      LRSDP_TRY(accept(S, I.dS, I.Pm, I.Lb, I.Li, true, &ad));
       k_axpy<<<vg, kT, 0, s>>>(m, ad, I.dy, y);
-      k_sym_axpy<<<eg, kT, 0, s>>>(n, S, ad, I.dS);
       LRSDP_HIP(hipGetLastError());
       LRSDP_HIP(hipStreamSynchronize(s));
+      rec.alpha_p = ap;
+      rec.alpha_d = ad;
+      rec.backtracks = backtracks;
+      rec.steps_ms = steps_ms + std::chrono::duration<double, std::milli>(
+                                    std::chrono::steady_clock::now() - t_up).count();
       rec.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_it)
                    .count();
       if (recs && it < max_recs) recs[it] = rec;
@@ -747,6 +836,20 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
     return LRSDP_OK;
   };
   rc = body();
+  // a numerical breakdown after the first step ends the method at its best iterate
+  const bool numerical = rc == LRSDP_ERR_IPM || rc == LRSDP_ERR_CHOL_Z || rc == LRSDP_ERR_CHOL_S ||
+                         rc == LRSDP_ERR_NOT_PD_W || rc == LRSDP_ERR_EIG ||
+                         rc == LRSDP_ERR_INDEFINITE_PRECOND;
+  if (numerical && inf.fail_stage != 1 && have_best && inf.iters >= 1) {
+    inf.stalled = 2;
+    inf.last_error = rc;
+    rc = LRSDP_OK;
+  }
+  if (inf.status != LRSDP_OK && have_best && inf.best_iter != inf.iters) {
+    (void)hipMemcpyAsync(X, I.Xb, I.nn * sizeof(double), hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(S, I.Sb, I.nn * sizeof(double), hipMemcpyDeviceToDevice, s);
+    (void)hipMemcpyAsync(y, I.yb, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, s);
+  }
   (void)hipStreamSynchronize(s);
   ipm_free(I);
   inf.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)

@@ -58,3 +58,34 @@ def test_argument_sizes_are_checked_before_any_call(binding):
         _lib._ptr(torch.zeros(6, dtype=torch.float32), torch.float64, 6, "v")
     with pytest.raises(TypeError):      # right size and type, but host memory
         _lib._ptr(torch.zeros(6, dtype=torch.float64), torch.float64, 6, "v")
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the binding mirrors with ctypes has the header's size and field offsets
+    (a C program built with gcc against include/lrsdp.h prints them)."""
+    import shutil
+    import subprocess
+    from paper_1703_10973_amd import _lib
+    if shutil.which("gcc") is None:
+        pytest.skip("no gcc")
+    root = os.path.dirname(os.path.dirname(__file__))
+    structs = [_lib.lrsdp_opts, _lib.lrsdp_info, _lib.lrsdp_ipm_opts, _lib.lrsdp_ipm_info,
+               _lib.lrsdp_ipm_record, _lib.lrsdp_instance]
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "lrsdp.h"', "int main(void) {"]
+    want = []
+    for st in structs:
+        nm = st.__name__
+        lines.append(f'  printf("%zu\\n", sizeof({nm}));')
+        want.append(ctypes.sizeof(st))
+        for field, _ in st._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({nm}, {field}));')
+            want.append(getattr(st, field).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True,
+                                          text=True).stdout.split()]
+    assert got == want

@@ -96,7 +96,7 @@ def test_ipm_rank_estimate_and_loose_solves(ctx):
     shape = (40, 40, 3, 900, 8)
     inst, _ = _oracle(shape)
     P = _problem(ctx, inst)
-    X, y, S, st, info, recs = P.ipm_solve(to_dev(inst["bvec"]), k=6, rank_eta=10.0, tol=1e-9,
+    X, y, S, st, info, recs = P.ipm_solve(to_dev(inst["bvec"]), k=6, rank_eta=10.0, tol=1e-8,
                                           pcg_eps=1e-10, pcg_eps_mu=1e-3)
     assert st == 0, info
     assert recs[-1]["k"] == 3, [r["k"] for r in recs]
@@ -113,7 +113,8 @@ def test_ipm_refuses_bad_options(ctx):
     b = to_dev(inst["bvec"])
     for kw in (dict(k=0), dict(k=20), dict(frac=1.0), dict(sigma=1.0), dict(tol=0.0),
                dict(pcg_eps=2.0), dict(max_ns_iter=0), dict(k=19, rank_eta=2.0),
-               dict(predictor=2), dict(householder_eig=-1)):
+               dict(predictor=2), dict(householder_eig=-1), dict(warm_start=2),
+               dict(stall_iters=-1)):
         with pytest.raises(pk.LrsdpError) as e:
             P.ipm_solve(b, **kw)
         assert e.value.status == pk._lib.LRSDP_ERR_INVALID_ARG, kw
@@ -173,7 +174,7 @@ def test_ipm_lanczos_and_householder_agree(ctx):
     inst, _ = _oracle(shape)
     P = _problem(ctx, inst)
     b = to_dev(inst["bvec"])
-    kw = dict(k=6, rank_eta=10.0, tol=1e-9, pcg_eps=1e-10)
+    kw = dict(k=6, rank_eta=10.0, tol=1e-8, pcg_eps=1e-10)
     X1, y1, S1, st1, info1, recs1 = P.ipm_solve(b, **kw)
     X2, y2, S2, st2, info2, recs2 = P.ipm_solve(b, householder_eig=1, **kw)
     assert st1 == 0 and st2 == 0
@@ -204,6 +205,7 @@ def test_ipm_predictor_keeps_the_iterates_centered(ctx):
     kw = dict(k=6, rank_eta=10.0, tol=1e-8, pcg_eps=1e-10, pcg_eps_mu=1e-3, max_iter=60)
     X, y, S, st, info, recs = P.ipm_solve(b, **kw)
     assert st == 0 and info["iters"] <= 35, (st, info["iters"])
+    assert info["stalled"] == 0 and info["last_error"] == 0
     assert all(0.1 <= r["sigma"] <= 1.0 for r in recs)
     assert max(r["sigma"] for r in recs) >= 0.3          # the rule did raise the centering
     assert all(r["pred_pcg_iters"] >= 1 for r in recs)
@@ -214,5 +216,67 @@ def test_ipm_predictor_keeps_the_iterates_centered(ctx):
     Xf, yf, Sf, stf, infof, recsf = P.ipm_solve(b, predictor=0, **kw)
     print("fixed sigma:", stf, infof["iters"], "gap %.1e" % infof["gap"], flush=True)
     assert all(r["sigma"] == 0.1 and r["pred_pcg_iters"] == 0 for r in recsf)
+    assert all(r["backtracks"] == 0 for r in recs)
     assert stf != 0 or infof["iters"] >= info["iters"] + 10, (stf, infof["iters"], info["iters"])
+    P.close()
+
+
+def _measures(inst, Xh, yh, Sh):
+    n = inst["n"]
+    a, b = inst["a"], inst["b"]
+    AX = 2.0 * inst["val"] * Xh[a, b]
+    Ay = np.zeros((n, n))
+    Ay[a, b] = inst["val"] * yh
+    Ay[b, a] = inst["val"] * yh
+    bv = inst["bvec"]
+    pinf = np.linalg.norm(bv - AX) / (1 + np.linalg.norm(bv))
+    dinf = np.linalg.norm(np.eye(n) - Sh - Ay) / (1 + np.sqrt(n))
+    gap = np.sum(Xh * Sh) / (1 + abs(np.trace(Xh)) + abs(bv @ yh))
+    return pinf, dinf, gap
+
+
+def test_ipm_stall_returns_the_best_iterate(ctx):
+    """A target FP64 cannot reach (tol 1e-14): the method stops, with NOT_CONVERGED, once
+    five steps bring max(pinf, dinf, gap) no lower than 0.9 of its best (stalled = 1) or when a
+    step breaks down numerically (stalled = 2, the error in last_error), and returns the best
+    iterate seen: its measures from the plain definitions are the ones info reports and no
+    recorded step had a smaller one; X and S are positive definite."""
+    inst, _ = _oracle((10, 10, 2, 90, 5))
+    P = _problem(ctx, inst)
+    b = to_dev(inst["bvec"])
+    X, y, S, st, info, recs = P.ipm_solve(b, k=2, tol=1e-14, pcg_eps=1e-10, max_iter=60)
+    print("stopped:", info["stalled"], info["last_error"], info["iters"], info["best_iter"],
+          flush=True)
+    assert st == pk._lib.LRSDP_NOT_CONVERGED and info["stalled"] in (1, 2), info
+    assert (info["last_error"] < 0) == (info["stalled"] == 2)
+    assert info["iters"] < 60 and 0 <= info["best_iter"] <= info["iters"]
+    Xh, yh, Sh = host(X), host(y), host(S)
+    pinf, dinf, gap = _measures(inst, Xh, yh, Sh)
+    for got, want in ((pinf, info["pinf"]), (dinf, info["dinf"]), (gap, info["gap"])):
+        assert abs(got - want) <= 1e-6 * want + 1e-14, (got, want)
+    merit = max(info["pinf"], info["dinf"], info["gap"])
+    assert merit < 1e-8
+    assert all(max(r["pinf"], r["dinf"], r["gap"]) >= merit for r in recs)
+    assert np.linalg.eigvalsh(Xh)[0] > 0 and np.linalg.eigvalsh(Sh)[0] > 0
+    P.close()
+
+
+def test_ipm_warm_start_continues_the_path(ctx):
+    """Starting from the iterate a run left after ten steps (warm_start), the method takes the
+    same remaining steps as the uninterrupted run: the same step lengths and sigma to 1e-9 over
+    the next four steps, and it ends at the same X."""
+    inst, _ = _oracle((40, 40, 3, 900, 8))
+    P = _problem(ctx, inst)
+    b = to_dev(inst["bvec"])
+    kw = dict(k=3, tol=1e-8, pcg_eps=1e-10)
+    Xa, ya, Sa, sta, infoa, recsa = P.ipm_solve(b, **kw)
+    X10, y10, S10, st10, info10, _ = P.ipm_solve(b, max_iter=10, stall_iters=0, **kw)
+    assert info10["iters"] == 10 and info10["best_iter"] == 10
+    Xw, yw, Sw, stw, infow, recsw = P.ipm_solve(b, start=(X10, y10, S10), **kw)
+    assert sta == 0 and stw == 0
+    for r1, r2 in zip(recsa[10:14], recsw[:4]):
+        for key in ("mu", "sigma", "alpha_p", "alpha_d"):
+            assert abs(r1[key] - r2[key]) <= 1e-9 * abs(r1[key]) + 1e-15, (key, r1[key], r2[key])
+    assert abs(infow["iters"] + 10 - infoa["iters"]) <= 1
+    assert np.linalg.norm(host(Xw) - host(Xa)) <= 1e-6 * np.linalg.norm(host(Xa))
     P.close()

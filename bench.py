@@ -523,7 +523,9 @@ def run_batch(args):
     out = {}
     for name, opts in modes.items():
         torch.cuda.synchronize()
-        pk.solve_batch(ctx, devs[:min(8, count)], opts, workers=args.workers)  # warm-up
+        # warm-up: the same batch once (kernels loaded; the batch's worker contexts keep their
+        # memory pools between calls, as a serving loop over interior-point steps would)
+        pk.solve_batch(ctx, devs, opts, workers=args.workers)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         st, info = pk.solve_batch(ctx, devs, opts, workers=args.workers)

@@ -154,6 +154,9 @@ typedef struct lrsdp_info {
                          /* stream: [0] eigen step (step 1a), [1] U, W0 and Z with Z^{-1}    */
                          /* (step 1b), [2] bold S formation and deflation (step 2), [3] the  */
                          /* Cholesky factor of bold S and its inverse (step 2)                */
+  int lockstep;          /* lrsdp_solve_batch: 1 when the solve advanced together with the   */
+                         /* batch's other solves of its step sequence (one launch per step  */
+                         /* for all of them), 0 when it ran alone                             */
 } lrsdp_info;
 
 /* Fills *o with the defaults listed above.  o: host. */

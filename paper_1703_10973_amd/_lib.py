@@ -50,7 +50,7 @@ class lrsdp_info(C.Structure):
     _fields_ = [("status", C.c_int), ("iters", C.c_int), ("outer_iters", C.c_int),
                 ("dd_used", C.c_int), ("relres", C.c_double), ("tau", C.c_double),
                 ("setup_ms", C.c_double), ("solve_ms", C.c_double), ("eig_sweeps", C.c_int),
-                ("phase_ms", C.c_double * 4)]
+                ("phase_ms", C.c_double * 4), ("lockstep", C.c_int)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}

@@ -155,6 +155,10 @@ bool opts_valid(const lrsdp_opts& o) {
 
 }  // namespace
 
+namespace lrsdp {
+bool opts_ok(const lrsdp_opts& o) { return opts_valid(o); }
+}  // namespace lrsdp
+
 extern "C" {
 
 void lrsdp_opts_default(lrsdp_opts* o) {
@@ -266,6 +270,8 @@ int lrsdp_ctx_create(int device, void* stream, size_t budget, lrsdp_ctx** out) {
 namespace {
 
 void ctx_release(lrsdp_ctx* c) {
+  for (lrsdp_ctx* w : c->batch_workers) ctx_release(w);
+  c->batch_workers.clear();
   DeviceGuard g(c->device);
   (void)hipStreamSynchronize(c->stream);
   prof_flush(&c->prof);

@@ -83,15 +83,16 @@ __device__ __forceinline__ dd group_reduce_scatter(dd (&acc)[K2], int sub) {
 }
 
 template <int K2>
-__global__ __launch_bounds__(kT) void k_spmm_U(int n, int k, const int32_t* __restrict__ rowptr,
-                                               const int32_t* __restrict__ colidx,
-                                               const int32_t* __restrict__ src,
-                                               const double* __restrict__ val,
-                                               const double* __restrict__ ginv,
-                                               const double* __restrict__ v,
-                                               const double* __restrict__ U,
-                                               double* __restrict__ out) {
-  const int p = blockIdx.x * (kT / kRL) + threadIdx.x / kRL;
+__device__ __forceinline__ void spmm_U_body(int bx, int n, int k,
+                                            const int32_t* __restrict__ rowptr,
+                                            const int32_t* __restrict__ colidx,
+                                            const int32_t* __restrict__ src,
+                                            const double* __restrict__ val,
+                                            const double* __restrict__ ginv,
+                                            const double* __restrict__ v,
+                                            const double* __restrict__ U,
+                                            double* __restrict__ out) {
+  const int p = bx * (kT / kRL) + threadIdx.x / kRL;
   const int sub = threadIdx.x & (kRL - 1);
   const bool live = p < n;
   double acc[K2];
@@ -112,21 +113,32 @@ __global__ __launch_bounds__(kT) void k_spmm_U(int n, int k, const int32_t* __re
   const int j = sub / (kRL / K2);
   if (live && sub % (kRL / K2) == 0 && j < k) out[(size_t)j * n + p] = r;
 }
+template <int K2>
+__global__ __launch_bounds__(kT) void k_spmm_U(int n, int k, const int32_t* __restrict__ rowptr,
+                                               const int32_t* __restrict__ colidx,
+                                               const int32_t* __restrict__ src,
+                                               const double* __restrict__ val,
+                                               const double* __restrict__ ginv,
+                                               const double* __restrict__ v,
+                                               const double* __restrict__ U,
+                                               double* __restrict__ out) {
+  spmm_U_body<K2>(blockIdx.x, n, k, rowptr, colidx, src, val, ginv, v, U, out);
+}
 
 // double-double version: M_e = (vh_i + vl_i) * scale_i * val_i, each product in double-double
 template <int K2>
-__global__ __launch_bounds__(kT) void k_spmm_U_dd(int n, int k,
-                                                  const int32_t* __restrict__ rowptr,
-                                                  const int32_t* __restrict__ colidx,
-                                                  const int32_t* __restrict__ src,
-                                                  const double* __restrict__ val,
-                                                  const double* __restrict__ ginv,
-                                                  const double* __restrict__ vh,
-                                                  const double* __restrict__ vl,
-                                                  const double* __restrict__ U,
-                                                  double* __restrict__ oh,
-                                                  double* __restrict__ ol) {
-  const int p = blockIdx.x * (kT / kRL) + threadIdx.x / kRL;
+__device__ __forceinline__ void spmm_U_dd_body(int bx, int n, int k,
+                                               const int32_t* __restrict__ rowptr,
+                                               const int32_t* __restrict__ colidx,
+                                               const int32_t* __restrict__ src,
+                                               const double* __restrict__ val,
+                                               const double* __restrict__ ginv,
+                                               const double* __restrict__ vh,
+                                               const double* __restrict__ vl,
+                                               const double* __restrict__ U,
+                                               double* __restrict__ oh,
+                                               double* __restrict__ ol) {
+  const int p = bx * (kT / kRL) + threadIdx.x / kRL;
   const int sub = threadIdx.x & (kRL - 1);
   const bool live = p < n;
   dd acc[K2];
@@ -151,6 +163,20 @@ __global__ __launch_bounds__(kT) void k_spmm_U_dd(int n, int k,
     oh[(size_t)j * n + p] = r.hi;
     ol[(size_t)j * n + p] = r.lo;
   }
+}
+template <int K2>
+__global__ __launch_bounds__(kT) void k_spmm_U_dd(int n, int k,
+                                                  const int32_t* __restrict__ rowptr,
+                                                  const int32_t* __restrict__ colidx,
+                                                  const int32_t* __restrict__ src,
+                                                  const double* __restrict__ val,
+                                                  const double* __restrict__ ginv,
+                                                  const double* __restrict__ vh,
+                                                  const double* __restrict__ vl,
+                                                  const double* __restrict__ U,
+                                                  double* __restrict__ oh,
+                                                  double* __restrict__ ol) {
+  spmm_U_dd_body<K2>(blockIdx.x, n, k, rowptr, colidx, src, val, ginv, vh, vl, U, oh, ol);
 }
 
 // out = M U with M = mat(A (ginv o v)) (ginv may be nullptr)
@@ -251,10 +277,12 @@ __global__ __launch_bounds__(kT) void k_rows_k_dd(int n, int k, const double* __
 
 // ---------------------------------------------------------------- sampled products
 // z_i = (v_i - x_i) ginv_i / tau^2,  x_i = (coef_i / 2)(Y_a . U_b + Y_b . U_a)  [= (bold U t)_i]
-__global__ void k_smw_out(int m, int n, int k, const int32_t* a, const int32_t* b,
-                          const double* coef, const double* ginv, double inv_tau2,
-                          const double* Y, const double* U, const double* v, double* z) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void smw_out_body(int bx, int m, int n, int k, const int32_t* a,
+                                             const int32_t* b, const double* coef,
+                                             const double* ginv, double inv_tau2,
+                                             const double* Y, const double* U, const double* v,
+                                             double* z) {
+  const int i = bx * 256 + threadIdx.x;  // 256 threads per workgroup
   if (i >= m) return;
   const int ai = a[i], bi = b[i];
   double s = 0.0;
@@ -266,6 +294,13 @@ __global__ void k_smw_out(int m, int n, int k, const int32_t* a, const int32_t* 
   }
   const double x = 0.5 * coef[i] * s;
   z[i] = (v[i] - x) * ginv[i] * inv_tau2;
+}
+__global__ __launch_bounds__(256) void k_smw_out(int m, int n, int k, const int32_t* a,
+                                                 const int32_t* b, const double* coef,
+                                                 const double* ginv, double inv_tau2,
+                                                 const double* Y, const double* U,
+                                                 const double* v, double* z) {
+  smw_out_body(blockIdx.x, m, n, k, a, b, coef, ginv, inv_tau2, Y, U, v, z);
 }
 
 // x_i = (coef_i / 2)(Y_a . U_b + Y_b . U_a) in double-double; optional z = (v - x) g^{-1}/tau^2
@@ -302,10 +337,10 @@ __global__ void k_scale_dd(int m, const double* ginv, double* yh, double* yl) {
 }
 
 // K = U^T P (k x k) in double-double, then symmetrized and rounded: one workgroup per (j, l).
-__global__ __launch_bounds__(kT) void k_UtP(int n, int k, const double* U, const double* Ph,
-                                            const double* Pl, double* Kdd) {
+__device__ __forceinline__ void UtP_body(int bx, int n, int k, const double* U, const double* Ph,
+                                         const double* Pl, double* Kdd) {
   __shared__ double scr[2 * kT / kWave];
-  const int j = blockIdx.x / k, l = blockIdx.x % k;
+  const int j = bx / k, l = bx % k;
   dd s = {0.0, 0.0};
   for (int p = threadIdx.x; p < n; p += kT)
     s = dd_fma2(s, U[(size_t)j * n + p], Ph[(size_t)l * n + p], Pl[(size_t)l * n + p]);
@@ -315,12 +350,17 @@ __global__ __launch_bounds__(kT) void k_UtP(int n, int k, const double* U, const
     Kdd[2 * (j * k + l) + 1] = s.lo;
   }
 }
+__global__ __launch_bounds__(kT) void k_UtP(int n, int k, const double* U, const double* Ph,
+                                            const double* Pl, double* Kdd) {
+  UtP_body(blockIdx.x, n, k, U, Ph, Pl, Kdd);
+}
 
 // Hv_i += coef_i [ sum_j (U_ja Q_jb + Q_ja U_jb) + U_a^T Ks U_b ],  Ks = (K + K^T) / 2
-__global__ void k_lowrank_add(int m, int n, int k, const int32_t* a, const int32_t* b,
-                              const double* coef, const double* U, const double* Q,
-                              const double* Kdd, double* Hv) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void lowrank_add_body(int bx, int m, int n, int k, const int32_t* a,
+                                                 const int32_t* b, const double* coef,
+                                                 const double* U, const double* Q,
+                                                 const double* Kdd, double* Hv) {
+  const int i = bx * 256 + threadIdx.x;  // 256 threads per workgroup
   if (i >= m) return;
   const int ai = a[i], bi = b[i];
   double s = 0.0;
@@ -340,6 +380,12 @@ __global__ void k_lowrank_add(int m, int n, int k, const int32_t* a, const int32
     t = fma(U[(size_t)j * n + ai], kr, t);
   }
   Hv[i] += coef[i] * (s + t);
+}
+__global__ __launch_bounds__(256) void k_lowrank_add(int m, int n, int k, const int32_t* a,
+                                                     const int32_t* b, const double* coef,
+                                                     const double* U, const double* Q,
+                                                     const double* Kdd, double* Hv) {
+  lowrank_add_body(blockIdx.x, m, n, k, a, b, coef, U, Q, Kdd, Hv);
 }
 
 // ---------------------------------------------------------------- nk-vector helpers
@@ -399,12 +445,12 @@ __global__ void k_Qc_dd(int N, int r, double shift, const double* Q, const doubl
 // KC >= k bounds the accumulators; rows past n and q outside a row's range add nothing.
 // With tadd != nullptr the result is fma(c, tadd, product) (an axpy folded in).
 template <int R, int KC>
-__global__ __launch_bounds__(kT) void k_rows_kr(int n, int k, const double* __restrict__ A,
-                                                int range, const double* __restrict__ X,
-                                                double* __restrict__ out, double c,
-                                                const double* __restrict__ tadd) {
+__device__ __forceinline__ void rows_kr_body(int bx, int n, int k, const double* __restrict__ A,
+                                             int range, const double* __restrict__ X,
+                                             double* __restrict__ out, double c,
+                                             const double* __restrict__ tadd) {
   __shared__ double red[kT / kWave][R * KC];
-  const int p0 = blockIdx.x * R, t = threadIdx.x;
+  const int p0 = bx * R, t = threadIdx.x;
   const int lane = t & (kWave - 1), wid = t / kWave;
   int lo[R], hi[R];
   int qlo = n, qhi = 0;
@@ -473,6 +519,13 @@ __global__ __launch_bounds__(kT) void k_rows_kr(int n, int k, const double* __re
     }
   }
 }
+template <int R, int KC>
+__global__ __launch_bounds__(kT) void k_rows_kr(int n, int k, const double* __restrict__ A,
+                                                int range, const double* __restrict__ X,
+                                                double* __restrict__ out, double c,
+                                                const double* __restrict__ tadd) {
+  rows_kr_body<R, KC>(blockIdx.x, n, k, A, range, X, out, c, tadd);
+}
 
 }  // namespace
 
@@ -531,10 +584,11 @@ int schur_apply_dd(const lrsdp_factor* f, const double* th, const double* tl, do
 
 // ---------------------------------------------------------------- FP64 matrix-free bold S
 // x_i = scale_i (coef_i / 2)(Y_a . U_b + Y_b . U_a)   [= scale_i (bold U t)_i]
-__global__ void k_sampled_f64(int m, int n, int k, const int32_t* a, const int32_t* b,
-                              const double* coef, const double* scale, const double* Y,
-                              const double* U, double* x) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void sampled_f64_body(int bx, int m, int n, int k, const int32_t* a,
+                                                 const int32_t* b, const double* coef,
+                                                 const double* scale, const double* Y,
+                                                 const double* U, double* x) {
+  const int i = bx * 256 + threadIdx.x;  // 256 threads per workgroup
   if (i >= m) return;
   const int ai = a[i], bi = b[i];
   double s = 0.0;
@@ -545,21 +599,36 @@ __global__ void k_sampled_f64(int m, int n, int k, const int32_t* a, const int32
   }
   x[i] = 0.5 * coef[i] * s * (scale ? scale[i] : 1.0);
 }
-__global__ __launch_bounds__(kT) void k_Qt(int N, int r, const double* Q, const double* t,
-                                           double* c) {
+__global__ __launch_bounds__(256) void k_sampled_f64(int m, int n, int k, const int32_t* a,
+                                                     const int32_t* b, const double* coef,
+                                                     const double* scale, const double* Y,
+                                                     const double* U, double* x) {
+  sampled_f64_body(blockIdx.x, m, n, k, a, b, coef, scale, Y, U, x);
+}
+__device__ __forceinline__ void Qt_body(int bx, int N, int r, const double* Q, const double* t,
+                                        double* c) {
   __shared__ double scr[kT / kWave];
-  const int col = blockIdx.x;
+  const int col = bx;
   double s = 0.0;
   for (int i = threadIdx.x; i < N; i += kT) s = fma(Q[(size_t)i * r + col], t[i], s);
   s = block_sum(s, scr);
   if (threadIdx.x == 0) c[col] = s;
 }
-__global__ void k_Qc(int N, int r, double shift, const double* Q, const double* c, double* s) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kT) void k_Qt(int N, int r, const double* Q, const double* t,
+                                           double* c) {
+  Qt_body(blockIdx.x, N, r, Q, t, c);
+}
+__device__ __forceinline__ void Qc_body(int bx, int N, int r, double shift, const double* Q,
+                                        const double* c, double* s) {
+  const int i = bx * 256 + threadIdx.x;  // 256 threads per workgroup
   if (i >= N) return;
   double acc = 0.0;
   for (int q = 0; q < r; ++q) acc = fma(Q[(size_t)i * r + q], c[q], acc);
   s[i] = fma(shift, acc, s[i]);
+}
+__global__ __launch_bounds__(256) void k_Qc(int N, int r, double shift, const double* Q,
+                                            const double* c, double* s) {
+  Qc_body(blockIdx.x, N, r, shift, Q, c, s);
 }
 
 // s = bold S t in FP64 (deflated as factored), matrix-free through eq Umv.
@@ -657,6 +726,127 @@ int split_apply(lrsdp_factor* f, const double* v, double* Hv, int precision, hip
   k_UtP<<<k * k, kT, 0, s>>>(n, k, f->U, w.g0, w.g1, w.kk);
   k_lowrank_add<<<grid_for(m, 256), 256, 0, s>>>(m, n, k, P->a, P->b, P->coef, f->U, w.s, w.kk,
                                                   Hv);
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
+
+// ---------------------------------------------------------------- lock-step batches
+// The same bodies on a packed grid (bl_find): each instance runs the grid it runs alone.
+namespace {
+
+// The dense n x n operand of a rows-times-k product: 0 W0, 1 Z, 2 Z^T
+__device__ __forceinline__ const double* pick_a(const BInst& d, int which) {
+  return which == 0 ? d.W0 : which == 1 ? d.Z : d.Zt;
+}
+#define LRSDP_BL_HEAD(KIND)                       \
+  int bx;                                         \
+  const int z = bl_find(b, KIND, blockIdx.x, &bx); \
+  if (!b.act[z]) return;                          \
+  const BInst& d = b.I[z];
+
+template <int K2>
+__global__ __launch_bounds__(kT) void k_spmm_U_b(const BL b, int use_ginv, int vrole,
+                                                 int orole) {
+  LRSDP_BL_HEAD(kKrowsU)
+  spmm_U_body<K2>(bx, d.n, d.k, d.rowptr, d.colidx, d.src, d.val, use_ginv ? d.ginv : nullptr,
+                  d.v[vrole], d.U, d.v[orole]);
+}
+template <int K2>
+__global__ __launch_bounds__(kT) void k_spmm_U_dd_b(const BL b, int vrole, int hrole,
+                                                    int lrole) {
+  LRSDP_BL_HEAD(kKrowsU)
+  spmm_U_dd_body<K2>(bx, d.n, d.k, d.rowptr, d.colidx, d.src, d.val, nullptr, d.v[vrole],
+                     nullptr, d.U, d.v[hrole], d.v[lrole]);
+}
+// out = rows of A times X (+ c tadd: c = tau^2 when add_tau2, tadd = v[trole])
+__global__ __launch_bounds__(kT) void k_rows_kr_b(const BL b, int which, int range, int xrole,
+                                                  int orole, int add_tau2, int trole) {
+  LRSDP_BL_HEAD(kKrows)
+  rows_kr_body<4, 4>(bx, d.n, d.k, pick_a(d, which), range, d.v[xrole], d.v[orole],
+                     add_tau2 ? d.tau2 : 0.0, add_tau2 ? d.v[trole] : nullptr);
+}
+__global__ __launch_bounds__(kT) void k_UtP_b(const BL b) {
+  LRSDP_BL_HEAD(kKkk)
+  UtP_body(bx, d.n, d.k, d.U, d.v[kVwg0], d.v[kVwg1], d.kk);
+}
+__global__ __launch_bounds__(256) void k_lowrank_add_b(const BL b, int orole) {
+  LRSDP_BL_HEAD(kKm256)
+  lowrank_add_body(bx, d.m, d.n, d.k, d.a, d.b, d.coef, d.U, d.v[kVws], d.kk, d.v[orole]);
+}
+__global__ __launch_bounds__(256) void k_sampled_f64_b(const BL b) {
+  LRSDP_BL_HEAD(kKm256)
+  sampled_f64_body(bx, d.m, d.n, d.k, d.a, d.b, d.coef, d.ginv, d.v[kVwy], d.U, d.v[kVwt0]);
+}
+__global__ __launch_bounds__(kT) void k_Qt_b(const BL b) {
+  LRSDP_BL_HEAD(kKr)
+  Qt_body(bx, d.nk, d.r, d.QN, d.v[kVwt], d.kk);
+}
+__global__ __launch_bounds__(256) void k_Qc_b(const BL b) {
+  LRSDP_BL_HEAD(kKnk256)
+  if (d.r == 0) return;
+  Qc_body(bx, d.nk, d.r, d.shift, d.QN, d.kk, d.v[kVws]);
+}
+__global__ __launch_bounds__(256) void k_smw_out_b(const BL b, int vrole, int zrole) {
+  LRSDP_BL_HEAD(kKm256)
+  smw_out_body(bx, d.m, d.n, d.k, d.a, d.b, d.coef, d.ginv, d.inv_tau2, d.v[kVwy], d.U,
+               d.v[vrole], d.v[zrole]);
+}
+#undef LRSDP_BL_HEAD
+
+// k <= 2 and k <= 4 use K2 = 2 and 4, as spmm_U does; the batch holds one K2 class
+int k2_of(int k) { return k <= 2 ? 2 : 4; }
+
+int bl_rows(const BLaunch& L, int which, int range, int xrole, int orole, bool add_tau2,
+            int trole, hipStream_t s) {
+  k_rows_kr_b<<<L.tot[kKrows], kT, 0, s>>>(L.b, which, range, xrole, orole, add_tau2 ? 1 : 0,
+                                           trole);
+  return LRSDP_OK;
+}
+int bl_spmm_U(const BLaunch& L, bool use_ginv, int vrole, int orole, hipStream_t s) {
+  const int grid = L.tot[kKrowsU];
+  if (k2_of(L.kmax) == 2) k_spmm_U_b<2><<<grid, kT, 0, s>>>(L.b, use_ginv ? 1 : 0, vrole, orole);
+  else k_spmm_U_b<4><<<grid, kT, 0, s>>>(L.b, use_ginv ? 1 : 0, vrole, orole);
+  return LRSDP_OK;
+}
+
+}  // namespace
+
+// L.kmax: the largest k of the batch; the batch holds instances of one K2 class (k <= 2 or
+// 3 <= k <= 4), and rows_k's kernel (R = 4, KC = 4) covers k <= 4.
+int bl_split_apply(const BLaunch& L, int precision, int cb, int vrole, int orole,
+                   hipStream_t s) {
+  if (L.b.count <= 0) return LRSDP_OK;
+  if (L.kmax > 4) return LRSDP_ERR_INVALID_ARG;
+  LRSDP_TRY(bl_hv(L, precision, cb, false, vrole, orole, s));
+  const int grid = L.tot[kKrowsU];
+  if (k2_of(L.kmax) == 2) k_spmm_U_dd_b<2><<<grid, kT, 0, s>>>(L.b, vrole, kVwg0, kVwg1);
+  else k_spmm_U_dd_b<4><<<grid, kT, 0, s>>>(L.b, vrole, kVwg0, kVwg1);
+  LRSDP_TRY(bl_rows(L, 0, 0, kVwg0, kVws, false, 0, s));
+  k_UtP_b<<<L.tot[kKkk], kT, 0, s>>>(L.b);
+  k_lowrank_add_b<<<L.tot[kKm256], 256, 0, s>>>(L.b, orole);
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
+
+int bl_precond_f64(const BLaunch& L, int refine, int vrole, int zrole, hipStream_t s) {
+  if (L.b.count <= 0) return LRSDP_OK;
+  if (L.kmax > 4) return LRSDP_ERR_INVALID_ARG;
+  LRSDP_TRY(bl_spmm_U(L, true, vrole, kVwy, s));                     // M U
+  LRSDP_TRY(bl_rows(L, 2, 2, kVwy, kVww, false, 0, s));              // w = vec(Z^T M U)
+  LRSDP_TRY(bl_gemv_pair(L, kVww, -1, kVwh, kVwt, false, s));        // t = S^{-1} w
+  if (refine) {  // t += S^{-1} (w - bold S t), bold S t as in schur_apply_f64
+    LRSDP_TRY(bl_rows(L, 1, 1, kVwt, kVwy, false, 0, s));
+    k_sampled_f64_b<<<L.tot[kKm256], 256, 0, s>>>(L.b);
+    LRSDP_TRY(bl_spmm_U(L, false, kVwt0, kVwy, s));
+    LRSDP_TRY(bl_rows(L, 2, 2, kVwy, kVws, true, kVwt, s));
+    if (L.rmax > 0) {
+      k_Qt_b<<<L.tot[kKr], kT, 0, s>>>(L.b);
+      k_Qc_b<<<L.tot[kKnk256], 256, 0, s>>>(L.b);
+    }
+    LRSDP_TRY(bl_gemv_pair(L, kVww, kVws, kVwh, kVwt, true, s));
+  }
+  LRSDP_TRY(bl_rows(L, 1, 1, kVwt, kVwy, false, 0, s));              // Y = Z T
+  k_smw_out_b<<<L.tot[kKm256], 256, 0, s>>>(L.b, vrole, zrole);
   LRSDP_HIP(hipGetLastError());
   return LRSDP_OK;
 }

@@ -857,13 +857,13 @@ __global__ __launch_bounds__(256) void k_gemv(const double* __restrict__ A, int 
 // kSub: the vector is x - xs (each difference rounded once); kAcc: y += the product.  When y2
 // is given, the row's result (y's new value) is also stored there (y2[r] += it when acc2).
 template <bool kSub, bool kAcc>
-__global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, int R, int C,
-                                                  int lda, const double* __restrict__ x,
-                                                  const double* __restrict__ xs,
-                                                  double* __restrict__ y, int upper,
-                                                  double* __restrict__ y2, int acc2) {
+__device__ __forceinline__ void gemv_tri_body(int bx, const double* __restrict__ A, int R, int C,
+                                              int lda, const double* __restrict__ x,
+                                              const double* __restrict__ xs,
+                                              double* __restrict__ y, int upper,
+                                              double* __restrict__ y2, int acc2) {
   const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int row = bx * 4 + (threadIdx.x >> 6);
   if (row >= R) return;
   const double* a = A + (size_t)row * lda;
   const int lo = upper ? row : 0, hi = upper ? C : min(row + 1, C);
@@ -881,6 +881,25 @@ __global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, 
     y[row] = kAcc ? y[row] + t : t;
     if (y2) y2[row] = acc2 ? y2[row] + t : t;
   }
+}
+template <bool kSub, bool kAcc>
+__global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, int R, int C,
+                                                  int lda, const double* __restrict__ x,
+                                                  const double* __restrict__ xs,
+                                                  double* __restrict__ y, int upper,
+                                                  double* __restrict__ y2, int acc2) {
+  gemv_tri_body<kSub, kAcc>(blockIdx.x, A, R, C, lda, x, xs, y, upper, y2, acc2);
+}
+// lock-step batch (packed grid): y = tri(L^{-1} or L^{-T}) x with the instance's Sinv
+template <bool kSub, bool kAcc>
+__global__ __launch_bounds__(256) void k_gemv_tri_b(const BL b, int xr, int xsr, int yr,
+                                                    int upper) {
+  int bx;
+  const int z = bl_find(b, kKgemv, blockIdx.x, &bx);
+  if (!b.act[z]) return;
+  const BInst& d = b.I[z];
+  gemv_tri_body<kSub, kAcc>(bx, d.Sinv, d.nk, d.nk, d.nk, d.v[xr], kSub ? d.v[xsr] : nullptr,
+                            d.v[yr], upper, nullptr, 0);
 }
 
 // y[r] = (b[r] - bs[r]) - sum_{c < K} A[r][c] x[c] for rows r < R (kSub; else b[r] - ...), one
@@ -1279,6 +1298,22 @@ int trmv_pair_ex(const double* M, int N, int ld, const double* x, const double* 
     k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, N, ld, tmp, nullptr, y, 1, nullptr, 0);
   LRSDP_HIP(hipGetLastError());
   prof_end(pm, s, 8.0 * (double)N * (N + 1) + 32.0 * N, 2.0 * (double)N * (N + 1));
+  return LRSDP_OK;
+}
+
+int bl_gemv_pair(const BLaunch& L, int xrole, int xsub_role, int tmp_role, int yrole,
+                 bool accumulate, hipStream_t s) {
+  if (L.b.count <= 0 || L.tot[kKgemv] <= 0) return LRSDP_OK;
+  const int grid = L.tot[kKgemv];
+  if (xsub_role >= 0)
+    k_gemv_tri_b<true, false><<<grid, 256, 0, s>>>(L.b, xrole, xsub_role, tmp_role, 0);
+  else
+    k_gemv_tri_b<false, false><<<grid, 256, 0, s>>>(L.b, xrole, 0, tmp_role, 0);
+  if (accumulate)
+    k_gemv_tri_b<false, true><<<grid, 256, 0, s>>>(L.b, tmp_role, 0, yrole, 1);
+  else
+    k_gemv_tri_b<false, false><<<grid, 256, 0, s>>>(L.b, tmp_role, 0, yrole, 1);
+  LRSDP_HIP(hipGetLastError());
   return LRSDP_OK;
 }
 

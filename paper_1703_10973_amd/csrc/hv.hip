@@ -20,14 +20,21 @@ constexpr int kThreads = 1024;
 constexpr size_t kLdsBudget = 80 * 1024;  // two workgroups of 16 wavefronts per CU
 constexpr size_t kLdsMax = 160 * 1024;    // one workgroup per CU
 
-__global__ void k_scatter(int nnz, const int32_t* __restrict__ src,
-                          const double* __restrict__ val, const double* __restrict__ v,
-                          double* __restrict__ mval) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void scatter_body(int bx, int nnz, const int32_t* __restrict__ src,
+                                             const double* __restrict__ val,
+                                             const double* __restrict__ v,
+                                             double* __restrict__ mval) {
+  int e = bx * 256 + threadIdx.x;  // 256 threads per workgroup
   if (e < nnz) {
     int i = src[e];
     mval[e] = val[i] * v[i];
   }
+}
+__global__ __launch_bounds__(256) void k_scatter(int nnz, const int32_t* __restrict__ src,
+                                                 const double* __restrict__ val,
+                                                 const double* __restrict__ v,
+                                                 double* __restrict__ mval) {
+  scatter_body(blockIdx.x, nnz, src, val, v, mval);
 }
 
 template <typename TW, typename TA>
@@ -62,15 +69,15 @@ __device__ __forceinline__ int owner_row(const int32_t* own_ptr, int c0, int cb,
 // kTG: the workgroup's rows of Tt live in global scratch tg (n x ldn, L2-resident), not in
 // LDS, which then holds only the CB rows of W (large n).
 template <typename TW, typename TA, int CB, bool kBf16Values, bool kTG>
-__global__ __launch_bounds__(kThreads) void k_hv_fused(
-    int n, int ldn, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
-    const double* __restrict__ mval, const TW* __restrict__ W,
-    const int32_t* __restrict__ own_ptr, const int32_t* __restrict__ own_con,
-    const int32_t* __restrict__ own_oth, const double* __restrict__ coef,
-    double* __restrict__ Hv, TA* __restrict__ tg) {
+__device__ __forceinline__ void hv_body(
+    int bx, int n, int ldn, const int32_t* __restrict__ rowptr,
+    const int32_t* __restrict__ colidx, const double* __restrict__ mval,
+    const TW* __restrict__ W, const int32_t* __restrict__ own_ptr,
+    const int32_t* __restrict__ own_con, const int32_t* __restrict__ own_oth,
+    const double* __restrict__ coef, double* __restrict__ Hv, TA* __restrict__ tg) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   TA* Wb = reinterpret_cast<TA*>(smem_raw);  // [CB][ldn]
-  const int c0 = blockIdx.x * CB;
+  const int c0 = bx * CB;
   TA* Tt = kTG ? tg + (size_t)c0 * ldn : Wb + CB * ldn;  // [CB][ldn]
   const int cb = min(CB, n - c0);
 
@@ -136,6 +143,16 @@ __global__ __launch_bounds__(kThreads) void k_hv_fused(
     }
   }
 }
+template <typename TW, typename TA, int CB, bool kBf16Values, bool kTG>
+__global__ __launch_bounds__(kThreads) void k_hv_fused(
+    int n, int ldn, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+    const double* __restrict__ mval, const TW* __restrict__ W,
+    const int32_t* __restrict__ own_ptr, const int32_t* __restrict__ own_con,
+    const int32_t* __restrict__ own_oth, const double* __restrict__ coef,
+    double* __restrict__ Hv, TA* __restrict__ tg) {
+  hv_body<TW, TA, CB, kBf16Values, kTG>(blockIdx.x, n, ldn, rowptr, colidx, mval, W, own_ptr,
+                                        own_con, own_oth, coef, Hv, tg);
+}
 
 // Rows of W per workgroup: as many as the LDS holds (up to 8; rows_lds = LDS bytes per row),
 // while at least ~200 workgroups remain so that every CU gets one; fewer rows per
@@ -148,6 +165,25 @@ int rows_per_wg(int n, size_t budget, size_t row_bytes) {
   return cb;
 }
 
+// Rows of W per H v workgroup for TA values of ta_bytes, and whether the rows of T go to the
+// global scratch (*tg); 0 when none fit.
+int hv_shape(int n, size_t ta_bytes, bool have_tscr, bool* tg) {
+  int cb = rows_per_wg(n, kLdsBudget, 2 * (size_t)n * ta_bytes);
+  if (cb < 1) cb = rows_per_wg(n, kLdsMax, 2 * (size_t)n * ta_bytes);
+  *tg = have_tscr && cb < 4;
+  if (*tg) cb = rows_per_wg(n, kLdsMax, (size_t)n * ta_bytes);
+  return cb;
+}
+// the same for the double-double residual (three double rows per row of W)
+int res_shape(int n, bool have_tscr, bool* tg) {
+  const size_t row_bytes = 3 * (size_t)n * sizeof(double);
+  int cb = rows_per_wg(n, kLdsBudget, row_bytes);
+  if (cb < 1) cb = rows_per_wg(n, kLdsMax, row_bytes);
+  *tg = have_tscr && cb < 4;
+  if (*tg) cb = rows_per_wg(n, kLdsMax, (size_t)n * sizeof(double));
+  return cb >= 4 ? 4 : cb;
+}
+
 // mval: nnz doubles of scratch for the values of mat(A v) (the problem's own, or the fixed
 // array of the allocation-free entry point).
 template <typename TW, typename TA, bool kBf16Values>
@@ -157,10 +193,8 @@ int launch_hv(const lrsdp_problem* P, const TW* W, const double* v, double* Hv, 
   k_scatter<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, v, mval);
   const int ldn = n;
   // W and T rows in LDS (two workgroups per CU, else one); with the global scratch, only W
-  int cb = rows_per_wg(n, kLdsBudget, 2 * (size_t)ldn * sizeof(TA));
-  if (cb < 1) cb = rows_per_wg(n, kLdsMax, 2 * (size_t)ldn * sizeof(TA));
-  const bool tg = P->tscr != nullptr && cb < 4;
-  if (tg) cb = rows_per_wg(n, kLdsMax, (size_t)ldn * sizeof(TA));
+  bool tg = false;
+  const int cb = hv_shape(n, sizeof(TA), P->tscr != nullptr, &tg);
   if (cb < 1) return LRSDP_ERR_INVALID_ARG;
   const size_t smem = (size_t)cb * (tg ? 1 : 2) * ldn * sizeof(TA);
   TA* tgp = reinterpret_cast<TA*>(P->tscr);
@@ -197,11 +231,13 @@ int launch_hv(const lrsdp_problem* P, const TW* W, const double* v, double* Hv, 
 // ---------------------------------------------------------------- double-double residual
 // res = r - H (y + ylo) with every product error-free and every sum in double-double.
 
-__global__ void k_scatter_dd(int nnz, const int32_t* __restrict__ src,
-                             const double* __restrict__ val, const double* __restrict__ y,
-                             const double* __restrict__ ylo, double* __restrict__ mhi,
-                             double* __restrict__ mlo) {
-  int e = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void scatter_dd_body(int bx, int nnz, const int32_t* __restrict__ src,
+                                                const double* __restrict__ val,
+                                                const double* __restrict__ y,
+                                                const double* __restrict__ ylo,
+                                                double* __restrict__ mhi,
+                                                double* __restrict__ mlo) {
+  int e = bx * 256 + threadIdx.x;  // 256 threads per workgroup
   if (e < nnz) {
     int i = src[e];
     dd p = two_prod(val[i], y[i]);
@@ -211,19 +247,28 @@ __global__ void k_scatter_dd(int nnz, const int32_t* __restrict__ src,
     mlo[e] = p.lo;
   }
 }
+__global__ __launch_bounds__(256) void k_scatter_dd(int nnz, const int32_t* __restrict__ src,
+                                                    const double* __restrict__ val,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ ylo,
+                                                    double* __restrict__ mhi,
+                                                    double* __restrict__ mlo) {
+  scatter_dd_body(blockIdx.x, nnz, src, val, y, ylo, mhi, mlo);
+}
 
 // kTG: the rows of (Th, Tl) live in global scratch (tgh, tgl: n x ldn each), as in k_hv_fused.
 template <int CB, bool kTG>
-__global__ __launch_bounds__(kThreads) void k_residual_dd(
-    int n, int ldn, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
-    const double* __restrict__ mhi, const double* __restrict__ mlo,
-    const double* __restrict__ W, const int32_t* __restrict__ own_ptr,
-    const int32_t* __restrict__ own_con, const int32_t* __restrict__ own_oth,
-    const double* __restrict__ coef, const double* __restrict__ r, double* __restrict__ res,
-    double* __restrict__ res_lo, double* __restrict__ tgh, double* __restrict__ tgl) {
+__device__ __forceinline__ void residual_dd_body(
+    int bx, int n, int ldn, const int32_t* __restrict__ rowptr,
+    const int32_t* __restrict__ colidx, const double* __restrict__ mhi,
+    const double* __restrict__ mlo, const double* __restrict__ W,
+    const int32_t* __restrict__ own_ptr, const int32_t* __restrict__ own_con,
+    const int32_t* __restrict__ own_oth, const double* __restrict__ coef,
+    const double* __restrict__ r, double* __restrict__ res, double* __restrict__ res_lo,
+    double* __restrict__ tgh, double* __restrict__ tgl) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* Wb = reinterpret_cast<double*>(smem_raw);  // [CB][ldn]
-  const int c0 = blockIdx.x * CB;
+  const int c0 = bx * CB;
   double* Th = kTG ? tgh + (size_t)c0 * ldn : Wb + CB * ldn;
   double* Tl = kTG ? tgl + (size_t)c0 * ldn : Th + CB * ldn;
   const int cb = min(CB, n - c0);
@@ -284,8 +329,110 @@ __global__ __launch_bounds__(kThreads) void k_residual_dd(
     }
   }
 }
+template <int CB, bool kTG>
+__global__ __launch_bounds__(kThreads) void k_residual_dd(
+    int n, int ldn, const int32_t* __restrict__ rowptr, const int32_t* __restrict__ colidx,
+    const double* __restrict__ mhi, const double* __restrict__ mlo,
+    const double* __restrict__ W, const int32_t* __restrict__ own_ptr,
+    const int32_t* __restrict__ own_con, const int32_t* __restrict__ own_oth,
+    const double* __restrict__ coef, const double* __restrict__ r, double* __restrict__ res,
+    double* __restrict__ res_lo, double* __restrict__ tgh, double* __restrict__ tgl) {
+  residual_dd_body<CB, kTG>(blockIdx.x, n, ldn, rowptr, colidx, mhi, mlo, W, own_ptr, own_con,
+                            own_oth, coef, r, res, res_lo, tgh, tgl);
+}
+
+// ---------------------------------------------------------------- lock-step batches
+// The same bodies on a packed grid (bl_find): each instance runs its own grid, so it computes
+// exactly what it computes alone.
+template <typename TW>
+__device__ __forceinline__ const TW* pick_w(const BInst& d, bool whole);
+template <>
+__device__ __forceinline__ const double* pick_w<double>(const BInst& d, bool whole) {
+  return whole ? d.W : d.W0;
+}
+template <>
+__device__ __forceinline__ const float* pick_w<float>(const BInst& d, bool) { return d.W0f; }
+template <>
+__device__ __forceinline__ const uint16_t* pick_w<uint16_t>(const BInst& d, bool) {
+  return d.W0b;
+}
+
+__global__ __launch_bounds__(256) void k_scatter_b(const BL b, int vrole) {
+  int bx;
+  const int z = bl_find(b, kKnnz256, blockIdx.x, &bx);
+  if (!b.act[z]) return;
+  const BInst& d = b.I[z];
+  scatter_body(bx, d.nnz, d.src, d.val, d.v[vrole], d.mval);
+}
+template <typename TW, typename TA, int CB, bool kBf16Values>
+__global__ __launch_bounds__(kThreads) void k_hv_fused_b(const BL b, int whole, int orole) {
+  int bx;
+  const int z = bl_find(b, kKhv, blockIdx.x, &bx);
+  if (!b.act[z]) return;
+  const BInst& d = b.I[z];
+  hv_body<TW, TA, CB, kBf16Values, false>(bx, d.n, d.n, d.rowptr, d.colidx, d.mval,
+                                          pick_w<TW>(d, whole != 0), d.own_ptr, d.own_con,
+                                          d.own_oth, d.coef, d.v[orole], nullptr);
+}
+__global__ __launch_bounds__(256) void k_scatter_dd_b(const BL b) {
+  int bx;
+  const int z = bl_find(b, kKnnz256, blockIdx.x, &bx);
+  if (!b.act[z]) return;
+  const BInst& d = b.I[z];
+  scatter_dd_body(bx, d.nnz, d.src, d.val, d.v[kVy], d.v[kVyl], d.mval, d.mlo);
+}
+template <int CB>
+__global__ __launch_bounds__(kThreads) void k_residual_dd_b(const BL b) {
+  int bx;
+  const int z = bl_find(b, kKres, blockIdx.x, &bx);
+  if (!b.act[z]) return;
+  const BInst& d = b.I[z];
+  residual_dd_body<CB, false>(bx, d.n, d.n, d.rowptr, d.colidx, d.mval, d.mlo, d.W, d.own_ptr,
+                              d.own_con, d.own_oth, d.coef, d.v[kVrhs], d.v[kVdd0], d.v[kVdd1],
+                              nullptr, nullptr);
+}
+
+template <typename TW, typename TA, bool kBf16Values>
+int launch_hv_b(const BLaunch& L, int cb, bool whole, int orole, hipStream_t s) {
+  const size_t smem = (size_t)cb * 2 * L.nmax * sizeof(TA);
+  const int grid = L.tot[kKhv];
+  const int w = whole ? 1 : 0;
+  switch (cb) {
+    case 1: k_hv_fused_b<TW, TA, 1, kBf16Values><<<grid, kThreads, smem, s>>>(L.b, w, orole); break;
+    case 2: k_hv_fused_b<TW, TA, 2, kBf16Values><<<grid, kThreads, smem, s>>>(L.b, w, orole); break;
+    case 4: k_hv_fused_b<TW, TA, 4, kBf16Values><<<grid, kThreads, smem, s>>>(L.b, w, orole); break;
+    case 8: k_hv_fused_b<TW, TA, 8, kBf16Values><<<grid, kThreads, smem, s>>>(L.b, w, orole); break;
+    default: return LRSDP_ERR_INVALID_ARG;
+  }
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
 
 }  // namespace
+
+int bl_hv(const BLaunch& L, int precision, int cb, bool whole_w, int vrole, int orole,
+          hipStream_t s) {
+  if (L.b.count <= 0) return LRSDP_OK;
+  k_scatter_b<<<L.tot[kKnnz256], 256, 0, s>>>(L.b, vrole);
+  if (precision == LRSDP_PREC_FP32) return launch_hv_b<float, float, false>(L, cb, false, orole, s);
+  if (precision == LRSDP_PREC_BF16) return launch_hv_b<uint16_t, float, true>(L, cb, false, orole, s);
+  return launch_hv_b<double, double, false>(L, cb, whole_w, orole, s);
+}
+
+int bl_residual_dd(const BLaunch& L, int cb, hipStream_t s) {
+  if (L.b.count <= 0) return LRSDP_OK;
+  k_scatter_dd_b<<<L.tot[kKnnz256], 256, 0, s>>>(L.b);
+  const size_t smem = (size_t)cb * 3 * L.nmax * sizeof(double);
+  const int grid = L.tot[kKres];
+  switch (cb) {
+    case 1: k_residual_dd_b<1><<<grid, kThreads, smem, s>>>(L.b); break;
+    case 2: k_residual_dd_b<2><<<grid, kThreads, smem, s>>>(L.b); break;
+    case 4: k_residual_dd_b<4><<<grid, kThreads, smem, s>>>(L.b); break;
+    default: return LRSDP_ERR_INVALID_ARG;
+  }
+  LRSDP_HIP(hipGetLastError());
+  return LRSDP_OK;
+}
 
 int hv_apply_f64(const lrsdp_problem* P, const double* W, const double* v, double* Hv,
                  hipStream_t s) {
@@ -345,13 +492,9 @@ int hv_residual_dd(const lrsdp_problem* P, const double* W, const double* r, con
   double* mlo = P->vec_scratch;  // sized max(4 m, nnz) at problem creation
   k_scatter_dd<<<grid_for(P->nnz, 256), 256, 0, s>>>(P->nnz, P->src, P->val, y, ylo, mhi, mlo);
   const int ldn = n;
-  const size_t row_bytes = 3 * (size_t)ldn * sizeof(double);
-  int cb = rows_per_wg(n, kLdsBudget, row_bytes);
-  if (cb < 1) cb = rows_per_wg(n, kLdsMax, row_bytes);
-  const bool tg = P->tscr != nullptr && cb < 4;
-  if (tg) cb = rows_per_wg(n, kLdsMax, (size_t)ldn * sizeof(double));
+  bool tg = false;
+  const int cb = res_shape(n, P->tscr != nullptr, &tg);
   if (cb < 1) return LRSDP_ERR_INVALID_ARG;
-  cb = cb >= 4 ? 4 : cb;
   const size_t smem = (size_t)cb * (tg ? 1 : 3) * ldn * sizeof(double);
   double* tgh = P->tscr;
   double* tgl = tg ? P->tscr + (size_t)n * n : nullptr;

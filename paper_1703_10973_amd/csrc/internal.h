@@ -49,6 +49,9 @@ struct lrsdp_ctx {
                                 // [2] scratch for factorizations whose failure is not an error
   int children = 0;             // live problems created under this context
   bool closing = false;         // destroyed while children were alive: released with the last
+  std::vector<lrsdp_ctx*> batch_workers;  // lrsdp_solve_batch's worker contexts, kept with their
+                                          // memory pools for the next batch until this one
+                                          // is released
 };
 
 // From this n on, the H v kernels keep their rows of T in global scratch (L2-resident) and
@@ -109,6 +112,7 @@ struct ProfScope {
 int ctx_create(int device, void* stream, size_t budget, bool blocking, lrsdp_ctx** out);
 
 // ---------------------------------------------------------------- memory
+bool opts_ok(const lrsdp_opts& o);  // the option checks of the entry points
 int dev_alloc(lrsdp_ctx* ctx, void** p, size_t bytes);
 void dev_free(lrsdp_ctx* ctx, void* p, size_t bytes);
 
@@ -206,10 +210,102 @@ int precond_apply_dd(const lrsdp_factor* f, const double* v, double* z, hipStrea
 int split_apply(lrsdp_factor* f, const double* v, double* Hv, int precision, hipStream_t s);
 
 // ---------------------------------------------------------------- pcg.hip
+// How a factor's solve runs under options o (step A8): double-double refinement (use_dd),
+// the inner H v precision, refinement at all, the SMW pieces in double-double, one FP64
+// refinement step of bold S^{-1} w (ref64), and the double-double steps of that refinement.
+struct SolveMode {
+  bool use_dd = false, refine = false, dd_prec = false;
+  int prec = LRSDP_PREC_FP64, ref64 = 0, dd_steps = 1;
+};
+SolveMode solve_mode(const lrsdp_factor* f, const lrsdp_opts& o);
+// The step sequence of a factor's solve as one number: solves with equal keys can advance in
+// lock-step (solve_lockstep); -1 when the solve takes a step that is not batched (the
+// double-double SMW pieces, the augmented preconditioner, the block-explicit inverse, k > 4,
+// or the global H v scratch of n >= 2048).
+int64_t lockstep_key(const lrsdp_factor* f, const lrsdp_opts& o);
+// Solves of factors with one lockstep_key, advancing together on ctx's stream: per instance
+// the same steps, shapes and results as lrsdp_solve (r, y, ylo as there; st and info: host,
+// count entries).
+int solve_lockstep(lrsdp_ctx* ctx, int count, lrsdp_factor* const* F, const double* const* r,
+                   double* const* y, double* const* ylo, const lrsdp_opts& o, int* st,
+                   lrsdp_info* info);
 int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lrsdp_opts& o,
               lrsdp_info* info);
 int residual_dd(lrsdp_factor* f, const double* r, const double* y, const double* ylo,
                 double* res, double* res_lo, double* relres);
+
+// ---------------------------------------------------------------- lock-step batches
+// Many instances' solves advance together: each launch of a batched kernel covers one step for
+// every active instance (grid.y = instance), and each instance runs the grid it would use
+// alone (workgroups past it return), so every sum has the order it has alone and the results
+// are those of the instance alone, bit for bit.
+enum BRole : int {
+  kVx, kVr, kVz, kVp, kVq,                // PCG vectors (m)
+  kVrhs, kVy, kVyl, kVdd0, kVdd1,         // the solve's right-hand side, answer, residual pair
+  kVwy, kVww, kVwt, kVws, kVwh, kVwg0, kVwg1, kVwt0,  // nk / k x n work
+  kVRoles
+};
+struct BInst {
+  int n = 0, m = 0, k = 0, nk = 0, nnz = 0, r = 0;
+  // problem
+  const int32_t *a = nullptr, *b = nullptr, *src = nullptr, *rowptr = nullptr,
+                *colidx = nullptr, *own_ptr = nullptr, *own_con = nullptr, *own_oth = nullptr;
+  const double *val = nullptr, *coef = nullptr, *ginv = nullptr;
+  double *mval = nullptr, *mlo = nullptr;
+  // factor
+  const double *W = nullptr, *W0 = nullptr, *U = nullptr, *Z = nullptr, *Zt = nullptr,
+               *Sinv = nullptr, *QN = nullptr;
+  const float* W0f = nullptr;
+  const uint16_t* W0b = nullptr;
+  double tau2 = 0.0, inv_tau2 = 0.0, shift = 0.0;
+  double* kk = nullptr;
+  double* v[kVRoles] = {};
+  double *sc = nullptr, *part = nullptr;
+  int* counter = nullptr;
+  // the grids the instance's launches use alone
+  int g_vec = 1, g_red = 1, g_m256 = 1, g_nk256 = 1, g_nnz256 = 1, g_rowsU = 1, g_rows = 1,
+      g_gemv = 1, g_hv = 1, g_res = 1;
+};
+// A lock-step launch packs the instances' grids into one: workgroup g of kind K belongs to
+// the instance z with off[K][z] <= g < off[K][z + 1] (prefix sums of the instances' own grids),
+// so no workgroup is launched for nothing.
+enum BKind : int {
+  kKvec, kKred, kKm256, kKnk256, kKnnz256, kKrowsU, kKrows, kKgemv, kKhv, kKres, kKkk, kKr,
+  kBKinds
+};
+struct BL {                 // what the batched kernels take (by value)
+  const BInst* I = nullptr;   // count descriptors
+  const int* act = nullptr;   // count flags: the instances taking this step
+  const int* off = nullptr;   // kBKinds x (count + 1) prefix sums
+  int count = 0;
+};
+// The instance of packed workgroup g of kind K, and (bx) its workgroup within that instance's
+// own grid; instances with an empty grid of that kind own no workgroup.
+__device__ __forceinline__ int bl_find(const BL& b, int kind, int g, int* bx) {
+  const int* o = b.off + (size_t)kind * (b.count + 1);
+  int lo = 0, hi = b.count;  // o[lo] <= g < o[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (o[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  *bx = g - o[lo];
+  return lo;
+}
+struct BLaunch {            // the host side: the packed grid sizes and the batch's largest shapes
+  BL b;
+  int tot[kBKinds] = {};
+  int nmax = 0, kmax = 0, rmax = 0;
+};
+// apply.hip / hv.hip / dense.hip: the solve's products, as in the single-instance calls
+// (cb: the rows of W per H v workgroup, the same for every instance of the batch)
+int bl_hv(const BLaunch& L, int precision, int cb, bool whole_w, int vrole, int orole,
+          hipStream_t s);
+int bl_split_apply(const BLaunch& L, int precision, int cb, int vrole, int orole, hipStream_t s);
+int bl_precond_f64(const BLaunch& L, int refine, int vrole, int zrole, hipStream_t s);
+int bl_residual_dd(const BLaunch& L, int cb, hipStream_t s);
+int bl_gemv_pair(const BLaunch& L, int xrole, int xsub_role, int tmp_role, int yrole,
+                 bool accumulate, hipStream_t s);
 
 // ---------------------------------------------------------------- ipm.hip
 int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_ipm_opts& o,

@@ -23,6 +23,7 @@
 // else is running).  Requests that need memory are admitted in submission order; a request
 // waiting for its session's previous request does not hold up others.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -447,23 +448,118 @@ int lrsdp_solve_batch(lrsdp_ctx* ctx, int count, const lrsdp_instance* inst,
   if (!ctx || count < 0 || (count > 0 && (!inst || !status)) || workers < 1)
     return LRSDP_ERR_INVALID_ARG;
   if (count == 0) return LRSDP_OK;
-  lrsdp_server* s = nullptr;
-  LRSDP_TRY(lrsdp_server_create(ctx, std::min(workers, count), ctx->budget, &s));
-  std::vector<uint64_t> t(count);
+  lrsdp_opts o;
+  lrsdp_opts_default(&o);
+  if (opts) o = *opts;
+  if (!lrsdp::opts_ok(o)) return LRSDP_ERR_INVALID_ARG;
+  int prev_dev = -1;
+  if (hipGetDevice(&prev_dev) != hipSuccess) prev_dev = -1;
+  (void)hipSetDevice(ctx->device);
+  // 1. A0 and Algorithm 1 steps 1-2 of every instance on the worker threads, each with a
+  //    context of its own; the problems and factors stay resident for step 3
+  // (the worker contexts stay with ctx between calls: their memory pools then serve the next
+  // batch's allocations, and freeing thousands of blocks is not paid per call)
+  const int nw = std::min(workers, count);
   int rc = LRSDP_OK;
-  for (int i = 0; i < count && rc == LRSDP_OK; ++i) rc = lrsdp_server_submit(s, &inst[i], opts, &t[i]);
-  for (int i = 0; i < count; ++i) {
-    if (rc != LRSDP_OK) {
-      status[i] = rc;
-      continue;
-    }
-    lrsdp_info inf{};
-    const int prc = lrsdp_server_poll(s, t[i], 1, &status[i], &inf);
-    if (prc != LRSDP_OK) status[i] = prc;
-    if (info) info[i] = inf;
+  while ((int)ctx->batch_workers.size() < nw && rc == LRSDP_OK) {
+    lrsdp_ctx* c = nullptr;
+    rc = lrsdp::ctx_create(ctx->device, nullptr, 0, false, &c);
+    if (rc == LRSDP_OK) ctx->batch_workers.push_back(c);
   }
-  lrsdp_server_destroy(s);
-  return rc;
+  std::vector<lrsdp_ctx*> wctx(ctx->batch_workers.begin(), ctx->batch_workers.begin() + std::min<size_t>(nw, ctx->batch_workers.size()));
+  std::vector<lrsdp_problem*> P(count, nullptr);
+  std::vector<lrsdp_factor*> F(count, nullptr);
+  std::vector<int> src(count, LRSDP_OK);
+  std::vector<int64_t> key(count, -1);
+  if (rc == LRSDP_OK) {
+    std::atomic<int> next{0};
+    std::vector<std::thread> th;
+    for (int w = 0; w < nw; ++w)
+      th.emplace_back([&, w] {
+        (void)hipSetDevice(ctx->device);
+        for (;;) {
+          const int i = next.fetch_add(1);
+          if (i >= count) break;
+          const lrsdp_instance& in = inst[i];
+          int r = lrsdp_problem_create(wctx[w], in.n, in.m, in.m, in.con, in.row, in.col, in.val,
+                                       &P[i]);
+          if (r == LRSDP_OK) r = lrsdp_factor_create(P[i], in.W, in.k, &o, &F[i]);
+          if (r == LRSDP_OK) {
+            key[i] = lrsdp::lockstep_key(F[i], o);
+            const lrsdp::SolveMode md = lrsdp::solve_mode(F[i], o);
+            if (key[i] >= 0 && md.refine && md.prec != LRSDP_PREC_FP64)
+              r = lrsdp::ensure_lowprec(F[i], md.prec, wctx[w]->stream);
+          }
+          src[i] = r;
+        }
+        (void)hipStreamSynchronize(wctx[w]->stream);
+      });
+    for (auto& t : th) t.join();
+    // 2. step 3: solves with one step sequence advance together, one launch per step for all
+    //    of them; the others run alone
+    std::unordered_map<int64_t, std::vector<int>> groups;
+    std::vector<int> alone;
+    for (int i = 0; i < count; ++i) {
+      if (src[i] != LRSDP_OK) continue;
+      if (key[i] >= 0) groups[key[i]].push_back(i);
+      else alone.push_back(i);
+    }
+    std::vector<lrsdp_info> inf(count);
+    // each group on a worker context's stream of its own, the groups concurrently
+    std::vector<const std::vector<int>*> glist;
+    for (auto& kv : groups) glist.push_back(&kv.second);
+    std::atomic<int> gnext{0};
+    auto run_groups = [&](lrsdp_ctx* wc) {
+      (void)hipSetDevice(ctx->device);
+      for (;;) {
+        const int g = gnext.fetch_add(1);
+        if (g >= (int)glist.size()) break;
+        const std::vector<int>& ids = *glist[g];
+        const int c = (int)ids.size();
+        std::vector<lrsdp_factor*> gf(c);
+        std::vector<const double*> gr(c);
+        std::vector<double*> gy(c), gl(c);
+        std::vector<int> gs(c);
+        std::vector<lrsdp_info> gi(c);
+        for (int j = 0; j < c; ++j) {
+          gf[j] = F[ids[j]];
+          gr[j] = inst[ids[j]].r;
+          gy[j] = inst[ids[j]].y;
+          gl[j] = inst[ids[j]].y_lo;
+        }
+        const int lrc = lrsdp::solve_lockstep(wc, c, gf.data(), gr.data(), gy.data(),
+                                              gl.data(), o, gs.data(), gi.data());
+        for (int j = 0; j < c; ++j) {
+          src[ids[j]] = lrc < 0 ? lrc : gs[j];
+          inf[ids[j]] = gi[j];
+        }
+      }
+    };
+    {
+      const int nt = std::min<int>((int)glist.size(), (int)wctx.size());
+      std::vector<std::thread> gt;
+      for (int t = 0; t < nt; ++t) gt.emplace_back(run_groups, wctx[t]);
+      for (auto& t : gt) t.join();
+    }
+    for (int i : alone) src[i] = lrsdp_solve(F[i], inst[i].r, inst[i].y, inst[i].y_lo, &o, &inf[i]);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (int i = 0; i < count; ++i) {
+      status[i] = src[i];
+      if (info) {
+        info[i] = inf[i];
+        info[i].status = src[i];
+      }
+    }
+  } else {
+    for (int i = 0; i < count; ++i) status[i] = rc;
+  }
+  // 3. release (factors and problems go back to the workers' memory pools)
+  for (int i = 0; i < count; ++i) {
+    if (F[i]) lrsdp_factor_destroy(F[i]);
+    if (P[i]) lrsdp_problem_destroy(P[i]);
+  }
+  if (prev_dev >= 0) (void)hipSetDevice(prev_dev);
+  return rc == LRSDP_OK ? LRSDP_OK : rc;
 }
 
 }  // extern "C"

@@ -73,6 +73,8 @@ def test_batch_matches_alone(ctx, precision):
         assert np.array_equal(yh, ya) and np.array_equal(yl, yla), (inst.n, inst.k)
         assert inf["iters"] > 0
         _check_residual(inst, yh, yl)
+    # these shapes all take the lock-step path (one launch per step for the batch)
+    assert all(inf["lockstep"] == 1 for inf in info), [inf["lockstep"] for inf in info]
 
 
 def test_batch_empty_and_errors(ctx):

@@ -367,7 +367,7 @@ __global__ __launch_bounds__(256) void k_scatter_b(const BL b, int vrole) {
 template <typename TW, typename TA, int CB, bool kBf16Values>
 __global__ __launch_bounds__(kThreads) void k_hv_fused_b(const BL b, int whole, int orole) {
   int bx;
-  const int z = bl_find(b, kKhv, blockIdx.x, &bx);
+  const int z = bl_find(b, hv_kind(CB), blockIdx.x, &bx);
   if (!b.act[z]) return;
   const BInst& d = b.I[z];
   hv_body<TW, TA, CB, kBf16Values, false>(bx, d.n, d.n, d.rowptr, d.colidx, d.mval,
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void k_scatter_dd_b(const BL b) {
 template <int CB>
 __global__ __launch_bounds__(kThreads) void k_residual_dd_b(const BL b) {
   int bx;
-  const int z = bl_find(b, kKres, blockIdx.x, &bx);
+  const int z = bl_find(b, res_kind(CB), blockIdx.x, &bx);
   if (!b.act[z]) return;
   const BInst& d = b.I[z];
   residual_dd_body<CB, false>(bx, d.n, d.n, d.rowptr, d.colidx, d.mval, d.mlo, d.W, d.own_ptr,
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kThreads) void k_residual_dd_b(const BL b) {
 template <typename TW, typename TA, bool kBf16Values>
 int launch_hv_b(const BLaunch& L, int cb, bool whole, int orole, hipStream_t s) {
   const size_t smem = (size_t)cb * 2 * L.nmax * sizeof(TA);
-  const int grid = L.tot[kKhv];
+  const int grid = L.tot[hv_kind(cb)];
   const int w = whole ? 1 : 0;
   switch (cb) {
     case 1: k_hv_fused_b<TW, TA, 1, kBf16Values><<<grid, kThreads, smem, s>>>(L.b, w, orole); break;
@@ -423,7 +423,7 @@ int bl_residual_dd(const BLaunch& L, int cb, hipStream_t s) {
   if (L.b.count <= 0) return LRSDP_OK;
   k_scatter_dd_b<<<L.tot[kKnnz256], 256, 0, s>>>(L.b);
   const size_t smem = (size_t)cb * 3 * L.nmax * sizeof(double);
-  const int grid = L.tot[kKres];
+  const int grid = L.tot[res_kind(cb)];
   switch (cb) {
     case 1: k_residual_dd_b<1><<<grid, kThreads, smem, s>>>(L.b); break;
     case 2: k_residual_dd_b<2><<<grid, kThreads, smem, s>>>(L.b); break;

@@ -49,6 +49,7 @@ struct lrsdp_ctx {
                                 // [2] scratch for factorizations whose failure is not an error
   int children = 0;             // live problems created under this context
   bool closing = false;         // destroyed while children were alive: released with the last
+  std::unordered_map<uint64_t, int> tuned;  // autotuned launch shapes of lock-step batches
   std::vector<lrsdp_ctx*> batch_workers;  // lrsdp_solve_batch's worker contexts, kept with their
                                           // memory pools for the next batch until this one
                                           // is released
@@ -264,15 +265,22 @@ struct BInst {
   int* counter = nullptr;
   // the grids the instance's launches use alone
   int g_vec = 1, g_red = 1, g_m256 = 1, g_nk256 = 1, g_nnz256 = 1, g_rowsU = 1, g_rows = 1,
-      g_gemv = 1, g_hv = 1, g_res = 1;
+      g_gemv = 1;
 };
 // A lock-step launch packs the instances' grids into one: workgroup g of kind K belongs to
 // the instance z with off[K][z] <= g < off[K][z + 1] (prefix sums of the instances' own grids),
 // so no workgroup is launched for nothing.
+// (kKhv1 .. kKhv8: H v with 1, 2, 4, 8 rows of W per workgroup; kKres1 .. kKres4: the
+// double-double residual with 1, 2, 4)
 enum BKind : int {
-  kKvec, kKred, kKm256, kKnk256, kKnnz256, kKrowsU, kKrows, kKgemv, kKhv, kKres, kKkk, kKr,
-  kBKinds
+  kKvec, kKred, kKm256, kKnk256, kKnnz256, kKrowsU, kKrows, kKgemv, kKhv1, kKhv2, kKhv4, kKhv8,
+  kKres1, kKres2, kKres4, kKkk, kKr, kBKinds
 };
+// the kind of an H v (residual) launch with cb rows of W per workgroup
+__host__ __device__ inline int hv_kind(int cb) {
+  return cb == 1 ? kKhv1 : cb == 2 ? kKhv2 : cb == 4 ? kKhv4 : kKhv8;
+}
+__host__ __device__ inline int res_kind(int cb) { return cb == 1 ? kKres1 : cb == 2 ? kKres2 : kKres4; }
 struct BL {                 // what the batched kernels take (by value)
   const BInst* I = nullptr;   // count descriptors
   const int* act = nullptr;   // count flags: the instances taking this step

@@ -432,16 +432,24 @@ namespace {
 int hv_bytes_of(const SolveMode& md) {
   return (md.refine && md.prec != LRSDP_PREC_FP64) ? 4 : 8;
 }
-// Rows of W per H v (or double-double residual) workgroup in a lock-step batch.  Alone, few
-// rows per workgroup keep enough workgroups to fill the chip for small n; in a batch the
-// instances do, and each workgroup streams the whole pattern once, so the batch takes as
-// many rows as the LDS holds for two workgroups per CU.  A product's arithmetic does not
-// depend on the rows per workgroup (fixed lane-to-entry maps and reduction trees), so the
-// results stay those of the instance alone.
-int batch_rows(int nmax, size_t bytes_per_row) {
-  int cb = 8;
+// Rows of W per H v (or double-double residual) workgroup in a lock-step batch.  A product's
+// arithmetic does not depend on them (fixed lane-to-entry maps and reduction trees), so every
+// choice gives the instance's results alone; which is fastest depends on the batch (few rows:
+// more workgroups, each streaming the whole pattern; many rows: fewer passes, fewer
+// workgroups).  The largest that the LDS holds for two workgroups per CU (80 KB) bounds them.
+int batch_rows_max(int nmax, size_t bytes_per_row, int cap) {
+  int cb = cap;
   while (cb > 1 && (size_t)cb * bytes_per_row * nmax > 80 * 1024) cb >>= 1;
   return cb;
+}
+// The autotuner: the first lock-step batch of a shape class on a context times each choice
+// of rows per workgroup on its own data (results identical, so nothing else changes) and
+// keeps the fastest for the class: kind (1 H v, 2 residual), value bytes, the batch's
+// largest n and its size, each rounded up to a power of two.
+uint64_t tune_key(int kind, int bytes, int whole, int nmax, int count) {
+  auto p2 = [](int v) { int q = 1; while (q < v) q <<= 1; return q; };
+  return ((uint64_t)kind << 56) | ((uint64_t)bytes << 48) | ((uint64_t)whole << 44) |
+         ((uint64_t)p2(nmax) << 20) | (uint64_t)p2(count);
 }
 
 }  // namespace
@@ -471,8 +479,9 @@ int solve_lockstep(lrsdp_ctx* ctx, int count, lrsdp_factor* const* F, const doub
   const SolveMode md = solve_mode(F[0], o);
   int nmax = 0;
   for (int z = 0; z < count; ++z) nmax = std::max(nmax, F[z]->n);
-  const int hv_cb = batch_rows(nmax, 2 * (size_t)hv_bytes_of(md));
-  const int res_cb = std::min(4, batch_rows(nmax, 3 * sizeof(double)));  // (1, 2 or 4)
+  const int hv_cap = batch_rows_max(nmax, 2 * (size_t)hv_bytes_of(md), 8);
+  const int res_cap = batch_rows_max(nmax, 3 * sizeof(double), 4);
+  int hv_cb = hv_cap, res_cb = res_cap;  // until tuned
   // descriptors, and the packed grids (prefix sums of the instances' own grids per kind)
   std::vector<BInst> h(count);
   BLaunch L;
@@ -506,10 +515,9 @@ int solve_lockstep(lrsdp_ctx* ctx, int count, lrsdp_factor* const* F, const doub
     d.g_rowsU = (d.n + 15) / 16;
     d.g_rows = (d.n + 3) / 4;
     d.g_gemv = (d.nk + 3) / 4;
-    d.g_hv = (d.n + hv_cb - 1) / hv_cb;
-    d.g_res = (d.n + res_cb - 1) / res_cb;
     const int g[kBKinds] = {d.g_vec, d.g_red, d.g_m256, d.g_nk256, d.g_nnz256, d.g_rowsU,
-                            d.g_rows, d.g_gemv, d.g_hv, d.g_res, d.k * d.k, d.r};
+                            d.g_rows, d.g_gemv, d.n, (d.n + 1) / 2, (d.n + 3) / 4,
+                            (d.n + 7) / 8, d.n, (d.n + 1) / 2, (d.n + 3) / 4, d.k * d.k, d.r};
     for (int kd = 0; kd < kBKinds; ++kd)
       off[(size_t)kd * (count + 1) + z + 1] = off[(size_t)kd * (count + 1) + z] + g[kd];
     L.nmax = std::max(L.nmax, d.n);
@@ -573,6 +581,47 @@ int solve_lockstep(lrsdp_ctx* ctx, int count, lrsdp_factor* const* F, const doub
       return LRSDP_OK;
     };
     const int gv = L.tot[kKvec], gr = L.tot[kKred];
+    // autotune the rows per workgroup of H v and of the residual (first batch of a class)
+    auto tune = [&](int kind, int cap, int* best) -> int {
+      const int whole = md.refine ? 0 : 1;
+      const int bytes = kind == 1 ? hv_bytes_of(md) : 8;
+      const uint64_t key = tune_key(kind, bytes + (md.prec == LRSDP_PREC_BF16 ? 1 : 0), whole,
+                                    L.nmax, count);
+      auto it = ctx->tuned.find(key);
+      if (it != ctx->tuned.end() && it->second <= cap) {
+        *best = it->second;
+        return LRSDP_OK;
+      }
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      LRSDP_HIP(hipEventCreate(&e0));
+      LRSDP_HIP(hipEventCreate(&e1));
+      std::vector<char> all(count, 1);
+      int rc2 = upload(all);
+      float best_ms = 1e30f;
+      for (int cb = 1; cb <= cap && rc2 == LRSDP_OK; cb <<= 1) {
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && rc2 == LRSDP_OK; ++rep) {  // the second run is timed
+          if (hipEventRecord(e0, s) != hipSuccess) rc2 = LRSDP_ERR_DEVICE;
+          if (rc2 == LRSDP_OK)
+            rc2 = kind == 1 ? bl_hv(L, md.refine ? md.prec : LRSDP_PREC_FP64, cb, whole != 0,
+                                    kVrhs, kVq, s)
+                            : bl_residual_dd(L, cb, s);
+          if (rc2 == LRSDP_OK && hipEventRecord(e1, s) != hipSuccess) rc2 = LRSDP_ERR_DEVICE;
+          if (rc2 == LRSDP_OK && hipEventSynchronize(e1) != hipSuccess) rc2 = LRSDP_ERR_DEVICE;
+          if (rc2 == LRSDP_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            rc2 = LRSDP_ERR_DEVICE;
+        }
+        if (rc2 == LRSDP_OK && ms < best_ms) {
+          best_ms = ms;
+          *best = cb;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (rc2 == LRSDP_OK) ctx->tuned[key] = *best;
+      return rc2;
+    };
+    LRSDP_TRY(tune(1, hv_cap, &hv_cb));
     auto Pinv = [&](int vrole, int zrole) {
       return bl_precond_f64(L, md.ref64, vrole, zrole, s);
     };
@@ -664,6 +713,8 @@ int solve_lockstep(lrsdp_ctx* ctx, int count, lrsdp_factor* const* F, const doub
       LRSDP_TRY(upload(on));
       k_zero_b<<<gv, kT, 0, s>>>(L.b, kVy);
       k_zero_b<<<gv, kT, 0, s>>>(L.b, kVyl);
+      LRSDP_HIP(hipGetLastError());
+      LRSDP_TRY(tune(2, res_cap, &res_cb));  // (on y = 0: writes only dd0 and dd1)
       std::vector<double> best(count, 1e300);
       std::vector<int> stall(count, 0);
       std::vector<char> live = on;

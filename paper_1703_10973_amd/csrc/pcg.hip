@@ -631,6 +631,52 @@ int solve_lockstep(lrsdp_ctx* ctx, int count, lrsdp_factor* const* F, const doub
     };
     // PCG from 0 on H x = b (b = v[brole]) for the instances in sel, as pcg() takes it
     std::vector<PcgOut> po(count);
+    // One PCG iteration of the class is a fixed launch sequence, captured as two graphs per
+    // parity of the scalar slots (rho of the iteration in cur, the next in nxt): part A is
+    // q = H p, p.q, the x and r updates and the copy of the scalars to the host; part B, after
+    // the host's checks, is z = M^{-1} r, r.z and p.  They are instantiated once per call and
+    // replayed every iteration of every refinement step; the activity flags they read are
+    // rewritten between replays.
+    hipGraphExec_t gA[2] = {nullptr, nullptr}, gB[2] = {nullptr, nullptr};
+    std::vector<hipGraph_t> graphs;
+    struct GraphsGuard {  // released on every way out of the body (after the stream is idle)
+      hipStream_t s;
+      hipGraphExec_t* ex[4];
+      std::vector<hipGraph_t>* g;
+      ~GraphsGuard() {
+        (void)hipStreamSynchronize(s);
+        for (hipGraphExec_t* e : ex)
+          if (*e) (void)hipGraphExecDestroy(*e);
+        for (hipGraph_t x : *g) (void)hipGraphDestroy(x);
+      }
+    } graphs_guard{s, {&gA[0], &gA[1], &gB[0], &gB[1]}, &graphs};
+    auto capture = [&](auto&& fn, hipGraphExec_t* ex) -> int {
+      LRSDP_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+      const int frc = fn();
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(s, &g);
+      if (g) graphs.push_back(g);
+      if (frc != LRSDP_OK) return frc;
+      if (e != hipSuccess || !g) return LRSDP_ERR_DEVICE;
+      LRSDP_HIP(hipGraphInstantiate(ex, g, nullptr, nullptr, 0));
+      return LRSDP_OK;
+    };
+    auto part_a = [&](int cur) -> int {
+      LRSDP_TRY(Hmul(kVp, kVq));
+      k_dot_b<<<gr, kT, 0, s>>>(L.b, kVp, kVq, kPQ);
+      k_update_xr_b<<<gr, kT, 0, s>>>(L.b, cur);
+      k_gather_sc_b<<<grid_for((int64_t)count * kNs, 256), 256, 0, s>>>(dI, count, 0, kNs, dsc);
+      LRSDP_HIP(hipMemcpyAsync(hsc, dsc, (size_t)count * kNs * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+      return LRSDP_OK;
+    };
+    auto part_b = [&](int cur, int nxt) -> int {
+      LRSDP_TRY(Pinv(kVr, kVz));
+      k_dot_b<<<gr, kT, 0, s>>>(L.b, kVr, kVz, nxt);
+      k_update_p_b<<<gv, kT, 0, s>>>(L.b, nxt, cur);
+      LRSDP_HIP(hipGetLastError());
+      return LRSDP_OK;
+    };
     auto pcg_ls = [&](const std::vector<char>& sel, int brole, double eps, int max_iter) -> int {
       std::vector<char> a = sel;
       std::vector<double> rr0(count, 0.0);
@@ -645,11 +691,10 @@ int solve_lockstep(lrsdp_ctx* ctx, int count, lrsdp_factor* const* F, const doub
       LRSDP_HIP(hipGetLastError());
       int cur = kRho0, nxt = kRho1;
       for (int it = 1; it <= max_iter; ++it) {
-        LRSDP_TRY(Hmul(kVp, kVq));
-        k_dot_b<<<gr, kT, 0, s>>>(L.b, kVp, kVq, kPQ);
-        k_update_xr_b<<<gr, kT, 0, s>>>(L.b, cur);
-        LRSDP_HIP(hipGetLastError());
-        LRSDP_TRY(read_sc(0, kNs));
+        const int par = cur == kRho0 ? 0 : 1;
+        if (!gA[par]) LRSDP_TRY(capture([&] { return part_a(cur); }, &gA[par]));
+        LRSDP_HIP(hipGraphLaunch(gA[par], s));
+        LRSDP_HIP(hipStreamSynchronize(s));
         bool changed = false, any = false;
         for (int z = 0; z < count; ++z) {
           if (!a[z]) continue;
@@ -686,10 +731,8 @@ int solve_lockstep(lrsdp_ctx* ctx, int count, lrsdp_factor* const* F, const doub
         }
         if (!any) break;
         if (changed) LRSDP_TRY(upload(a));
-        LRSDP_TRY(Pinv(kVr, kVz));
-        k_dot_b<<<gr, kT, 0, s>>>(L.b, kVr, kVz, nxt);
-        k_update_p_b<<<gv, kT, 0, s>>>(L.b, nxt, cur);
-        LRSDP_HIP(hipGetLastError());
+        if (!gB[par]) LRSDP_TRY(capture([&] { return part_b(cur, nxt); }, &gB[par]));
+        LRSDP_HIP(hipGraphLaunch(gB[par], s));
         std::swap(cur, nxt);
       }
       return LRSDP_OK;

@@ -77,6 +77,43 @@ def test_batch_matches_alone(ctx, precision):
     assert all(inf["lockstep"] == 1 for inf in info), [inf["lockstep"] for inf in info]
 
 
+def test_batch_mixes_lockstep_and_alone_solves(ctx):
+    """One batch whose instances take different paths: the k <= 2 and 3 <= k <= 4 step
+    sequences advance in lock-step; k = 6, and an instance at mu = 1e-9 whose SMW pieces go to
+    double-double, run alone.  Some answers are asked without the low-order part (y_lo absent:
+    the pair is rounded into y) and one right-hand side is zero.  Every answer is bitwise the one
+    the instance gets alone with the same arguments, and lockstep names the path it took."""
+    specs = [(60, 1, 300, 1e-6, 11), (90, 2, 600, 1e-4, 12), (120, 3, 900, 1e-6, 13),
+             (150, 4, 1400, 1e-2, 14), (80, 6, 700, 1e-6, 15), (100, 2, 800, 1e-9, 16),
+             (70, 2, 400, 1e-6, 17), (64, 4, 500, 1e-8, 18)]
+    insts = [make_instance(n, k, m, mu, seed=sd) for n, k, m, mu, sd in specs]
+    insts[6].r[:] = 0.0
+    opts = pk.opts(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO)
+    devs = [_device_instance(i) for i in insts]
+    for j in (1, 3, 6):
+        del devs[j]["y_lo"]
+    torch.cuda.synchronize()
+    print("mixed batch of", len(devs), flush=True)
+    st, info = pk.solve_batch(ctx, devs, opts, workers=3)
+    for j, (inst, d, s_, inf) in enumerate(zip(insts, devs, st, info)):
+        dd = _device_instance(inst)
+        P = pk.Problem(ctx, inst.n, inst.m, dd["con"], dd["row"], dd["col"], dd["val"])
+        F = pk.Factor(P, dd["W"], inst.k, opts)
+        ya, yla, sta, _ = F.solve(dd["r"], opts, want_lo="y_lo" in d)
+        assert s_ == sta, (j, s_, sta)
+        assert np.array_equal(host(d["y"]), host(ya)), (j, inst.n, inst.k, inst.mu)
+        if "y_lo" in d:
+            assert np.array_equal(host(d["y_lo"]), host(yla)), j
+        F.close()
+        P.close()
+    want = [1, 1, 1, 1, 0, 0, 1, None]
+    for j, w in enumerate(want):
+        if w is not None:
+            assert info[j]["lockstep"] == w, (j, [i["lockstep"] for i in info])
+    assert st[6] == 0 and not host(devs[6]["y"]).any()
+    assert all(s_ == 0 for s_ in st), st
+
+
 def test_batch_empty_and_errors(ctx):
     assert pk.solve_batch(ctx, [], None, workers=2) == ([], [])
     inst = make_instance(40, 2, 200, 1e-2, seed=3)

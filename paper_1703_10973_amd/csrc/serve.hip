@@ -455,23 +455,32 @@ int lrsdp_solve_batch(lrsdp_ctx* ctx, int count, const lrsdp_instance* inst,
   int prev_dev = -1;
   if (hipGetDevice(&prev_dev) != hipSuccess) prev_dev = -1;
   (void)hipSetDevice(ctx->device);
-  // 1. A0 and Algorithm 1 steps 1-2 of every instance on the worker threads, each with a
-  //    context of its own; the problems and factors stay resident for step 3
-  // (the worker contexts stay with ctx between calls: their memory pools then serve the next
-  // batch's allocations, and freeing thousands of blocks is not paid per call)
+  // Contexts kept with ctx between calls (their memory pools then serve the next batch, and
+  // freeing thousands of blocks is not paid per call): the workers that set the instances up,
+  // and two that run the lock-step solves while the workers go on with the next wave.
+  constexpr int kSolvers = 2;
   const int nw = std::min(workers, count);
   int rc = LRSDP_OK;
-  while ((int)ctx->batch_workers.size() < nw && rc == LRSDP_OK) {
+  while ((int)ctx->batch_workers.size() < nw + kSolvers && rc == LRSDP_OK) {
     lrsdp_ctx* c = nullptr;
     rc = lrsdp::ctx_create(ctx->device, nullptr, 0, false, &c);
     if (rc == LRSDP_OK) ctx->batch_workers.push_back(c);
   }
-  std::vector<lrsdp_ctx*> wctx(ctx->batch_workers.begin(), ctx->batch_workers.begin() + std::min<size_t>(nw, ctx->batch_workers.size()));
   std::vector<lrsdp_problem*> P(count, nullptr);
   std::vector<lrsdp_factor*> F(count, nullptr);
   std::vector<int> src(count, LRSDP_OK);
   std::vector<int64_t> key(count, -1);
+  std::vector<lrsdp_info> inf(count);
   if (rc == LRSDP_OK) {
+    std::vector<lrsdp_ctx*> solver(ctx->batch_workers.begin(),
+                                   ctx->batch_workers.begin() + kSolvers);
+    std::vector<lrsdp_ctx*> wctx(ctx->batch_workers.begin() + kSolvers,
+                                 ctx->batch_workers.begin() + kSolvers + nw);
+    // 1. A0 and Algorithm 1 steps 1-2 on the worker threads, in index order; an instance is
+    //    ready once its factor (and low-precision copy of W0) is complete on the device
+    std::mutex mu;
+    std::condition_variable cv;
+    std::vector<char> ready(count, 0);
     std::atomic<int> next{0};
     std::vector<std::thread> th;
     for (int w = 0; w < nw; ++w)
@@ -490,58 +499,77 @@ int lrsdp_solve_batch(lrsdp_ctx* ctx, int count, const lrsdp_instance* inst,
             if (key[i] >= 0 && md.refine && md.prec != LRSDP_PREC_FP64)
               r = lrsdp::ensure_lowprec(F[i], md.prec, wctx[w]->stream);
           }
+          if (hipStreamSynchronize(wctx[w]->stream) != hipSuccess && r == LRSDP_OK)
+            r = LRSDP_ERR_DEVICE;
           src[i] = r;
+          {
+            std::lock_guard<std::mutex> lk(mu);
+            ready[i] = 1;
+          }
+          cv.notify_all();
         }
-        (void)hipStreamSynchronize(wctx[w]->stream);
       });
-    for (auto& t : th) t.join();
-    // 2. step 3: solves with one step sequence advance together, one launch per step for all
-    //    of them; the others run alone
-    std::unordered_map<int64_t, std::vector<int>> groups;
+    // 2. step 3 in two waves: the first half's solves run (lock-step, one launch per step for
+    //    all solves of a step sequence, the sequences side by side on the solver contexts)
+    //    while the workers set up the second half; solves outside the lock-step sequences run
+    //    alone once every worker is done (their contexts are then idle)
     std::vector<int> alone;
-    for (int i = 0; i < count; ++i) {
-      if (src[i] != LRSDP_OK) continue;
-      if (key[i] >= 0) groups[key[i]].push_back(i);
-      else alone.push_back(i);
-    }
-    std::vector<lrsdp_info> inf(count);
-    // each group on a worker context's stream of its own, the groups concurrently
-    std::vector<const std::vector<int>*> glist;
-    for (auto& kv : groups) glist.push_back(&kv.second);
-    std::atomic<int> gnext{0};
-    auto run_groups = [&](lrsdp_ctx* wc) {
-      (void)hipSetDevice(ctx->device);
-      for (;;) {
-        const int g = gnext.fetch_add(1);
-        if (g >= (int)glist.size()) break;
-        const std::vector<int>& ids = *glist[g];
-        const int c = (int)ids.size();
-        std::vector<lrsdp_factor*> gf(c);
-        std::vector<const double*> gr(c);
-        std::vector<double*> gy(c), gl(c);
-        std::vector<int> gs(c);
-        std::vector<lrsdp_info> gi(c);
-        for (int j = 0; j < c; ++j) {
-          gf[j] = F[ids[j]];
-          gr[j] = inst[ids[j]].r;
-          gy[j] = inst[ids[j]].y;
-          gl[j] = inst[ids[j]].y_lo;
-        }
-        const int lrc = lrsdp::solve_lockstep(wc, c, gf.data(), gr.data(), gy.data(),
-                                              gl.data(), o, gs.data(), gi.data());
-        for (int j = 0; j < c; ++j) {
-          src[ids[j]] = lrc < 0 ? lrc : gs[j];
-          inf[ids[j]] = gi[j];
-        }
+    auto solve_wave = [&](int lo, int hi) {
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] {
+          for (int i = lo; i < hi; ++i)
+            if (!ready[i]) return false;
+          return true;
+        });
       }
-    };
-    {
-      const int nt = std::min<int>((int)glist.size(), (int)wctx.size());
+      std::unordered_map<int64_t, std::vector<int>> groups;
+      for (int i = lo; i < hi; ++i) {
+        if (src[i] != LRSDP_OK) continue;
+        if (key[i] >= 0) groups[key[i]].push_back(i);
+        else alone.push_back(i);
+      }
+      std::vector<const std::vector<int>*> glist;
+      for (auto& kv : groups) glist.push_back(&kv.second);
+      std::atomic<int> gnext{0};
+      auto run_groups = [&](lrsdp_ctx* sc) {
+        (void)hipSetDevice(ctx->device);
+        for (;;) {
+          const int g = gnext.fetch_add(1);
+          if (g >= (int)glist.size()) break;
+          const std::vector<int>& ids = *glist[g];
+          const int c = (int)ids.size();
+          std::vector<lrsdp_factor*> gf(c);
+          std::vector<const double*> gr(c);
+          std::vector<double*> gy(c), gl(c);
+          std::vector<int> gs(c);
+          std::vector<lrsdp_info> gi(c);
+          for (int j = 0; j < c; ++j) {
+            gf[j] = F[ids[j]];
+            gr[j] = inst[ids[j]].r;
+            gy[j] = inst[ids[j]].y;
+            gl[j] = inst[ids[j]].y_lo;
+          }
+          const int lrc = lrsdp::solve_lockstep(sc, c, gf.data(), gr.data(), gy.data(),
+                                                gl.data(), o, gs.data(), gi.data());
+          for (int j = 0; j < c; ++j) {
+            src[ids[j]] = lrc < 0 ? lrc : gs[j];
+            inf[ids[j]] = gi[j];
+          }
+        }
+      };
+      const int nt = std::min<int>((int)glist.size(), kSolvers);
       std::vector<std::thread> gt;
-      for (int t = 0; t < nt; ++t) gt.emplace_back(run_groups, wctx[t]);
+      for (int t = 0; t < nt; ++t) gt.emplace_back(run_groups, solver[t]);
       for (auto& t : gt) t.join();
-    }
-    for (int i : alone) src[i] = lrsdp_solve(F[i], inst[i].r, inst[i].y, inst[i].y_lo, &o, &inf[i]);
+    };
+    const int half = count >= 32 ? count / 2 : count;
+    solve_wave(0, half);
+    if (half < count) solve_wave(half, count);
+    for (auto& t : th) t.join();
+    for (int i : alone)
+      src[i] = lrsdp_solve(F[i], inst[i].r, inst[i].y, inst[i].y_lo, &o, &inf[i]);
+    for (lrsdp_ctx* c : solver) (void)hipStreamSynchronize(c->stream);
     (void)hipStreamSynchronize(ctx->stream);
     for (int i = 0; i < count; ++i) {
       status[i] = src[i];

@@ -304,11 +304,16 @@ typedef struct lrsdp_instance {
 } lrsdp_instance;
 
 /* Independent instances (a batch of interior-point solves, or one per outer iteration of
- * several SDPs): each is A0 + Algorithm 1 steps 1-3, run concurrently by `workers` host
- * threads, each with its own stream on ctx's device.  Results are bitwise the same as those of
- * lrsdp_problem_create + lrsdp_factor_create + lrsdp_solve on one instance alone.  status and
- * info (host arrays of length count; info may be NULL) receive each instance's outcome.
- * Returns OK once every instance has finished (whatever its status), INVALID_ARG or DEVICE. */
+ * several SDPs): each is A0 + Algorithm 1 steps 1-3.  `workers` host threads, each with its
+ * own stream on ctx's device, set the instances up (A0, steps 1-2); the solves (step 3) of
+ * instances that take the same step sequence then advance in lock-step, one launch per step for
+ * all of them (info->lockstep = 1), the first half of the batch while the workers set up the
+ * second; the others are solved alone.  Results are bitwise the same as those of
+ * lrsdp_problem_create + lrsdp_factor_create + lrsdp_solve on one instance alone.  The worker
+ * and solver contexts stay with ctx, their memory pools holding the batch's memory for the next
+ * call, until ctx is destroyed; calls on one ctx must not overlap.  status and info (host
+ * arrays of length count; info may be NULL) receive each instance's outcome.  Returns OK once
+ * every instance has finished (whatever its status), INVALID_ARG or DEVICE. */
 LRSDP_API int lrsdp_solve_batch(lrsdp_ctx* ctx, int count, const lrsdp_instance* inst,
                                 const lrsdp_opts* opts, int workers, int* status,
                                 lrsdp_info* info);

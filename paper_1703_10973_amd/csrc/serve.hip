@@ -5,6 +5,10 @@
 // The kernels and their launch shapes depend only on their own instance, so a result is
 // bitwise the one the instance gets alone.
 //
+// The batch call sets its instances up on the workers and solves them in lock-step: the solves
+// that take one step sequence advance together, one launch per step for all of them
+// (solve_lockstep), the first half of the batch while the workers set up the second.
+//
 // Requests are of two sorts.
 //   * Instances: the whole hot path, A0 (problem), Algorithm 1 steps 1-2 (factor) and step 3
 //     (solve), after which the handles are released.

@@ -308,7 +308,8 @@ typedef struct lrsdp_instance {
  * own stream on ctx's device, set the instances up (A0, steps 1-2); the solves (step 3) of
  * instances that take the same step sequence then advance in lock-step, one launch per step for
  * all of them (info->lockstep = 1), the first half of the batch while the workers set up the
- * second; the others are solved alone.  Results are bitwise the same as those of
+ * second; each of the others is solved alone by the worker that set it up, right after its
+ * setup.  Results are bitwise the same as those of
  * lrsdp_problem_create + lrsdp_factor_create + lrsdp_solve on one instance alone.  The worker
  * and solver contexts stay with ctx, their memory pools holding the batch's memory for the next
  * call, until ctx is destroyed; calls on one ctx must not overlap.  status and info (host

@@ -475,13 +475,16 @@ int lrsdp_solve_batch(lrsdp_ctx* ctx, int count, const lrsdp_instance* inst,
   std::vector<int> src(count, LRSDP_OK);
   std::vector<int64_t> key(count, -1);
   std::vector<lrsdp_info> inf(count);
+  std::vector<int> asrc(count, LRSDP_OK);  // results of the solves outside lock-step
   if (rc == LRSDP_OK) {
     std::vector<lrsdp_ctx*> solver(ctx->batch_workers.begin(),
                                    ctx->batch_workers.begin() + kSolvers);
     std::vector<lrsdp_ctx*> wctx(ctx->batch_workers.begin() + kSolvers,
                                  ctx->batch_workers.begin() + kSolvers + nw);
     // 1. A0 and Algorithm 1 steps 1-2 on the worker threads, in index order; an instance is
-    //    ready once its factor (and low-precision copy of W0) is complete on the device
+    //    ready once its factor (and low-precision copy of W0) is complete on the device.  An
+    //    instance outside every lock-step sequence is then solved alone by the worker that set
+    //    it up, on that worker's context (no other thread uses it), into asrc and inf.
     std::mutex mu;
     std::condition_variable cv;
     std::vector<char> ready(count, 0);
@@ -511,13 +514,13 @@ int lrsdp_solve_batch(lrsdp_ctx* ctx, int count, const lrsdp_instance* inst,
             ready[i] = 1;
           }
           cv.notify_all();
+          if (r == LRSDP_OK && key[i] < 0)
+            asrc[i] = lrsdp_solve(F[i], in.r, in.y, in.y_lo, &o, &inf[i]);
         }
       });
     // 2. step 3 in two waves: the first half's solves run (lock-step, one launch per step for
     //    all solves of a step sequence, the sequences side by side on the solver contexts)
-    //    while the workers set up the second half; solves outside the lock-step sequences run
-    //    alone once every worker is done (their contexts are then idle)
-    std::vector<int> alone;
+    //    while the workers set up the second half
     auto solve_wave = [&](int lo, int hi) {
       {
         std::unique_lock<std::mutex> lk(mu);
@@ -529,9 +532,7 @@ int lrsdp_solve_batch(lrsdp_ctx* ctx, int count, const lrsdp_instance* inst,
       }
       std::unordered_map<int64_t, std::vector<int>> groups;
       for (int i = lo; i < hi; ++i) {
-        if (src[i] != LRSDP_OK) continue;
-        if (key[i] >= 0) groups[key[i]].push_back(i);
-        else alone.push_back(i);
+        if (src[i] == LRSDP_OK && key[i] >= 0) groups[key[i]].push_back(i);
       }
       std::vector<const std::vector<int>*> glist;
       for (auto& kv : groups) glist.push_back(&kv.second);
@@ -571,8 +572,8 @@ int lrsdp_solve_batch(lrsdp_ctx* ctx, int count, const lrsdp_instance* inst,
     solve_wave(0, half);
     if (half < count) solve_wave(half, count);
     for (auto& t : th) t.join();
-    for (int i : alone)
-      src[i] = lrsdp_solve(F[i], inst[i].r, inst[i].y, inst[i].y_lo, &o, &inf[i]);
+    for (int i = 0; i < count; ++i)
+      if (src[i] == LRSDP_OK && key[i] < 0) src[i] = asrc[i];
     for (lrsdp_ctx* c : solver) (void)hipStreamSynchronize(c->stream);
     (void)hipStreamSynchronize(ctx->stream);
     for (int i = 0; i < count; ++i) {

@@ -114,6 +114,37 @@ def test_batch_mixes_lockstep_and_alone_solves(ctx):
     assert all(s_ == 0 for s_ in st), st
 
 
+def test_batch_alone_solves_on_the_workers_and_a_failed_setup(ctx):
+    """Batches whose instances include one whose setup fails (k not below n): the others still
+    solve and each answer is bitwise the one the instance gets alone.  In the first batch every
+    instance is outside the lock-step sequences (k = 5, 6), so each is solved by the worker that
+    set it up; in the second they all take the k <= 2 lock-step sequence."""
+    opts = pk.opts(precision=pk.LRSDP_PREC_AUTO, dd_mode=pk.LRSDP_DD_AUTO)
+    for ks, lockstep in (((5, 6), 0), ((1, 2), 1)):
+        specs = [(70 + 10 * j, ks[j % 2], 500 + 50 * j, 1e-6 if j % 3 else 1e-2, 40 + j)
+                 for j in range(9)]
+        insts = [make_instance(n, k, m, mu, seed=sd) for n, k, m, mu, sd in specs]
+        devs = [_device_instance(i) for i in insts]
+        devs[4]["k"] = devs[4]["n"]
+        torch.cuda.synchronize()
+        print("batch of", len(devs), "k", ks, flush=True)
+        st, info = pk.solve_batch(ctx, devs, opts, workers=4)
+        assert st[4] == pk._lib.LRSDP_ERR_INVALID_ARG, st
+        for j, (inst, d, s_, inf) in enumerate(zip(insts, devs, st, info)):
+            if j == 4:
+                continue
+            dd = _device_instance(inst)
+            P = pk.Problem(ctx, inst.n, inst.m, dd["con"], dd["row"], dd["col"], dd["val"])
+            F = pk.Factor(P, dd["W"], inst.k, opts)
+            ya, yla, sta, _ = F.solve(dd["r"], opts, want_lo=True)
+            assert s_ == sta == 0, (j, s_, sta)
+            assert np.array_equal(host(d["y"]), host(ya)), (j, inst.n, inst.k, inst.mu)
+            assert np.array_equal(host(d["y_lo"]), host(yla)), j
+            assert inf["lockstep"] == lockstep, (j, inf["lockstep"])
+            F.close()
+            P.close()
+
+
 def test_batch_empty_and_errors(ctx):
     assert pk.solve_batch(ctx, [], None, workers=2) == ([], [])
     inst = make_instance(40, 2, 200, 1e-2, seed=3)

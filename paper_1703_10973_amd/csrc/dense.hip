@@ -1181,26 +1181,42 @@ int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double*
   return potrf_inv_rec(A, N, lda, Li, ldi, flag, tmp, want_L, s, side, 0);
 }
 
-// From this size on the top node is kept block-explicit: its (2, 1) block keeps L21 and the
-// two products that would turn it into (L^{-1})_21 = -L22^{-1} L21 L11^{-1} are skipped, the
-// largest of the inverse work (n k = 5000: the factor of bold S 3.96 -> 3.33 ms).  Applying L^{-1} then
-// takes six dependent GEMVs over the same bytes instead of two (PCG +0.3 ms per solve there).
+// From this size on a node is kept block-explicit: its (2, 1) block keeps L21 and the two
+// products that would turn it into (L^{-1})_21 = -L22^{-1} L21 L11^{-1} are skipped, the largest
+// of the inverse work (n k = 5000: the factor of bold S 3.96 -> 3.33 ms).  The leading block's
+// inverse is formed (the node's own L21 = A21 L11^{-T} needs it); the trailing block is split
+// again while it is this large, so the diagonal is a chain of blocks with explicit inverses and
+// the L21 of each node below its block (n k = 40 000: blocks of 20 032, 9 984, 4 992, 2 496 and
+// 2 496 rows).  Applying L^{-1} then takes 2 b - 1 dependent GEMVs per triangle for b blocks
+// over the same bytes (PCG +0.3 ms per solve at n k = 5000, where b = 2).
 // (Keeping -L21 L11^{-1} instead, formed on the side stream while the trailing block factors,
 // needs four: at n k = 5000 it cost 0.4 ms more setup than it saved in the PCG, and at
 // n k = 40000 the product competed with the trailing factorization: 528 -> 661 ms.)
 constexpr int kBlockInvMin = 4096;
 
-int potrf_binv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
-               hipStream_t s, const SideStream* side, int* split) {
-  *split = 0;
-  if (N < kBlockInvMin) return potrf_inv_rec(A, N, lda, Li, ldi, flag, tmp, false, s, side, 0);
+int binv_blocks(int N, int* offs) {
+  int nb = 0, a = 0;
+  offs[0] = 0;
+  while (N - a >= kBlockInvMin && nb + 1 < kBinvMaxBlocks) {
+    a += split64(N - a);
+    offs[++nb] = a;
+  }
+  offs[++nb] = N;
+  return nb;
+}
+
+// One node of the chain (depth: that of its children in the side stream's events).
+static int binv_rec(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
+                    hipStream_t s, const SideStream* side, int depth, int room) {
+  if (N < kBlockInvMin || room <= 1)
+    return potrf_inv_rec(A, N, lda, Li, ldi, flag, tmp, false, s, side, depth);
   const int N1 = split64(N), N2 = N - N1;
   double* A21 = A + (size_t)N1 * lda;
   double* A22 = A21 + N1;
   double* L21 = Li + (size_t)N1 * ldi;  // the (2, 1) block of Li keeps L21 itself
   double* Li22 = L21 + N1;
   // each child joins its own side-stream product before it returns, so tmp is free again
-  LRSDP_TRY(potrf_inv_rec(A, N1, lda, Li, ldi, flag, tmp, false, s, side, 1));
+  LRSDP_TRY(potrf_inv_rec(A, N1, lda, Li, ldi, flag, tmp, false, s, side, depth + 1));
   {  // L21 = A21 L11^{-T}
     GemmArgs g;
     g.M = N2; g.N = N1; g.K = N1;
@@ -1219,67 +1235,94 @@ int potrf_binv(double* A, int N, int lda, double* Li, int ldi, int* flag, double
     g.alpha = -1.0; g.beta = 1.0; g.flags = kLowerOut;
     LRSDP_TRY(gemm(g, s));
   }
-  LRSDP_TRY(potrf_inv_rec(A22, N2, lda, Li22, ldi, flag, tmp, false, s, side, 1));
-  *split = N1;
+  return binv_rec(A22, N2, lda, Li22, ldi, flag, tmp, s, side, depth + 1, room - 1);
+}
+
+int potrf_binv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
+               hipStream_t s, const SideStream* side, int* split) {
+  *split = 0;
+  LRSDP_TRY(binv_rec(A, N, lda, Li, ldi, flag, tmp, s, side, 0, kBinvMaxBlocks));
+  if (N >= kBlockInvMin) *split = split64(N);
   return LRSDP_OK;
 }
 
 int binv_apply(const double* M, int N, int split, int ld, const double* x, const double* xsub,
                double* tmp, double* y, bool accumulate, hipStream_t s) {
   if (split <= 0) return trmv_pair_ex(M, N, ld, x, xsub, tmp, y, accumulate, s);
+  int offs[kBinvMaxBlocks + 1];
+  const int nb = binv_blocks(N, offs);
+  if (nb < 2 || offs[1] != split) return LRSDP_ERR_INVALID_ARG;
   ProfMark pm = prof_begin(LRSDP_K_GEMV, s);
-  const int N1 = split, N2 = N - N1;
-  double* T = tmp;      // [t1; t2]
-  double* U = tmp + N;  // [u1; u2]
-  const double* M21 = M + (size_t)N1 * ld;  // L21 (lower part)
-  const double* M12 = M + N1;               // L21^T (mirrored into the upper part)
-  const double* M22 = M21 + N1;
-  const int g1 = (N1 + 3) / 4, g2 = (N2 + 3) / 4;
-  // forward, L^{-1}: t1 = L11^{-1} w1; t2 = w2 - L21 t1; u2 = L22^{-1} t2
-  if (xsub) {
-    k_gemv_tri<true, false><<<g1, 256, 0, s>>>(M, N1, N1, ld, x, xsub, T, 0, nullptr, 0);
-    k_gemv_rect<true><<<g2, 256, 0, s>>>(M21, N2, N1, ld, T, x + N1, xsub + N1, T + N1);
-  } else {
-    k_gemv_tri<false, false><<<g1, 256, 0, s>>>(M, N1, N1, ld, x, nullptr, T, 0, nullptr, 0);
-    k_gemv_rect<false><<<g2, 256, 0, s>>>(M21, N2, N1, ld, T, x + N1, nullptr, T + N1);
+  double* F = tmp;          // f = L^{-1} (x - xsub)
+  double* R = tmp + N;      // a block's right-hand side after the other blocks' terms
+  double* Yr = tmp + 2 * N; // L^{-T} f, block by block (y may be accumulating)
+  const int acc = accumulate ? 1 : 0;
+  // forward, left-looking: block b (rows [a, e)): r = (x - xsub)_b - L_{b, <a} f_{<a};
+  // f_b = L_bb^{-1} r
+  for (int b = 0; b < nb; ++b) {
+    const int a = offs[b], e = offs[b + 1], h = e - a, g = (h + 3) / 4;
+    const double* Mb = M + (size_t)a * ld;
+    if (b == 0) {
+      if (xsub)
+        k_gemv_tri<true, false><<<g, 256, 0, s>>>(M, h, h, ld, x, xsub, F, 0, nullptr, 0);
+      else
+        k_gemv_tri<false, false><<<g, 256, 0, s>>>(M, h, h, ld, x, nullptr, F, 0, nullptr, 0);
+      continue;
+    }
+    if (xsub)
+      k_gemv_rect<true><<<g, 256, 0, s>>>(Mb, h, a, ld, F, x + a, xsub + a, R + a);
+    else
+      k_gemv_rect<false><<<g, 256, 0, s>>>(Mb, h, a, ld, F, x + a, nullptr, R + a);
+    k_gemv_tri<false, false><<<g, 256, 0, s>>>(Mb + a, h, h, ld, R + a, nullptr, F + a, 0,
+                                               nullptr, 0);
   }
-  k_gemv_tri<false, false><<<g2, 256, 0, s>>>(M22, N2, N2, ld, T + N1, nullptr, U + N1, 0,
-                                              nullptr, 0);
-  // backward, L^{-T}: t2 = L22^{-T} u2 (also the answer's second block); u1 = t1 - L21^T t2;
-  // y1 = L11^{-T} u1
-  k_gemv_tri<false, false><<<g2, 256, 0, s>>>(M22, N2, N2, ld, U + N1, nullptr, T + N1, 1,
-                                              y + N1, accumulate ? 1 : 0);
-  k_gemv_rect<false><<<g1, 256, 0, s>>>(M12, N1, N2, ld, T + N1, T, nullptr, U);
-  if (accumulate)
-    k_gemv_tri<false, true><<<g1, 256, 0, s>>>(M, N1, N1, ld, U, nullptr, y, 1, nullptr, 0);
-  else
-    k_gemv_tri<false, false><<<g1, 256, 0, s>>>(M, N1, N1, ld, U, nullptr, y, 1, nullptr, 0);
+  // backward, left-looking over the mirrored upper part (which holds L_bb^{-T} and the
+  // L21^T of every node): r = f_b - L_{>e, b}^T y_{>e}; y_b = L_bb^{-T} r
+  for (int b = nb - 1; b >= 0; --b) {
+    const int a = offs[b], e = offs[b + 1], h = e - a, g = (h + 3) / 4;
+    const double* Mb = M + (size_t)a * ld;
+    const double* rhs = F + a;
+    if (e < N) {
+      k_gemv_rect<false><<<g, 256, 0, s>>>(Mb + e, h, N - e, ld, Yr + e, F + a, nullptr, R + a);
+      rhs = R + a;
+    }
+    k_gemv_tri<false, false><<<g, 256, 0, s>>>(Mb + a, h, h, ld, rhs, nullptr, Yr + a, 1, y + a,
+                                               acc);
+  }
   LRSDP_HIP(hipGetLastError());
-  prof_end(pm, s, 8.0 * (double)N * (N + 1) + 64.0 * N, 2.0 * (double)N * (N + 1));
+  prof_end(pm, s, 8.0 * (double)N * (N + 1) + 32.0 * nb * N, 2.0 * (double)N * (N + 1));
   return LRSDP_OK;
 }
 
 int binv_full_inverse(double* Li, int N, int split, int ld, double* tmp, hipStream_t s) {
   if (split <= 0) return LRSDP_OK;
-  const int N1 = split, N2 = N - N1;
-  double* L21 = Li + (size_t)N1 * ld;
-  {  // tmp = L21 L11^{-1}
-    GemmArgs g;
-    g.M = N2; g.N = N1; g.K = N1;
-    g.A = L21; g.lda = ld;
-    g.B = Li; g.ldb = ld;  // L11^{-1}[k][j], zero for k < j
-    g.C = tmp; g.ldc = N1;
-    g.flags = kKFromCol | kInverseOnly;
-    LRSDP_TRY(gemm(g, s));
-  }
-  {  // (L^{-1})_21 = -L22^{-1} tmp
-    GemmArgs g;
-    g.M = N2; g.N = N1; g.K = N2;
-    g.A = L21 + N1; g.lda = ld;  // L22^{-1}, zero for k > i
-    g.B = tmp; g.ldb = N1;
-    g.C = L21; g.ldc = ld;
-    g.alpha = -1.0; g.flags = kKToRow | kInverseOnly;
-    LRSDP_TRY(gemm(g, s));
+  int offs[kBinvMaxBlocks + 1];
+  const int nb = binv_blocks(N, offs);
+  if (nb < 2 || offs[1] != split) return LRSDP_ERR_INVALID_ARG;
+  // node c of the chain covers rows [offs[c], N) and splits at offs[c + 1]; from the last node
+  // up, its trailing block already holds the explicit inverse
+  for (int c = nb - 2; c >= 0; --c) {
+    const int a = offs[c], N1 = offs[c + 1] - a, N2 = N - offs[c + 1];
+    double* L11i = Li + (size_t)a * ld + a;
+    double* L21 = L11i + (size_t)N1 * ld;
+    {  // tmp = L21 L11^{-1}
+      GemmArgs g;
+      g.M = N2; g.N = N1; g.K = N1;
+      g.A = L21; g.lda = ld;
+      g.B = L11i; g.ldb = ld;  // L11^{-1}[k][j], zero for k < j
+      g.C = tmp; g.ldc = N1;
+      g.flags = kKFromCol | kInverseOnly;
+      LRSDP_TRY(gemm(g, s));
+    }
+    {  // (L^{-1})_21 = -L22^{-1} tmp
+      GemmArgs g;
+      g.M = N2; g.N = N1; g.K = N2;
+      g.A = L21 + N1; g.lda = ld;  // L22^{-1}, zero for k > i
+      g.B = tmp; g.ldb = N1;
+      g.C = L21; g.ldc = ld;
+      g.alpha = -1.0; g.flags = kKToRow | kInverseOnly;
+      LRSDP_TRY(gemm(g, s));
+    }
   }
   return LRSDP_OK;
 }

@@ -252,7 +252,7 @@ __global__ void k_f64_to_bf16(size_t cnt, const double* a, uint16_t* b) {
 
 size_t work_doubles(int n, int m, int k) {
   const size_t nk = (size_t)n * k;
-  return 12 * (size_t)m + 12 * nk + 2 * (size_t)k * k + 8192;
+  return 12 * (size_t)m + 13 * nk + 2 * (size_t)k * k + 8192;
 }
 
 Work work_view(const lrsdp_factor* f) {
@@ -264,7 +264,7 @@ Work work_view(const lrsdp_factor* f) {
     *pp = b;
     b += m;
   }
-  double** kv[] = {&w.w, &w.wl, &w.t, &w.tl, &w.s, &w.sl, &w.y, &w.yl, &w.g0, &w.g1, &w.h, &w.h2};
+  double** kv[] = {&w.w, &w.wl, &w.t, &w.tl, &w.s, &w.sl, &w.y, &w.yl, &w.g0, &w.g1, &w.h, &w.h2, &w.h3};
   for (auto pp : kv) {
     *pp = b;
     b += nk;

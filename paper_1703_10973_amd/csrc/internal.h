@@ -191,7 +191,7 @@ struct Work {
   // m-vectors
   double *x, *r, *z, *p, *q, *t0, *t1, *t2, *t3, *ylo, *dd0, *dd1;
   // nk-vectors / k x n blocks
-  double *w, *wl, *t, *tl, *s, *sl, *y, *yl, *g0, *g1, *h, *h2;  // h, h2 contiguous
+  double *w, *wl, *t, *tl, *s, *sl, *y, *yl, *g0, *g1, *h, *h2, *h3;  // h, h2, h3 contiguous
   // small
   double *kk;     // k x k
   double *part;   // reduction partials

@@ -247,7 +247,7 @@ size_t lrsdp_instance_bytes(int64_t n, int64_t m, int32_t k) {
   // persistent factor (W, W0, its low-precision copy, Z, Z^T, L^{-1}, Q_N, work) plus the
   // setup temporaries (bold S, the Cholesky scratch, Z^{-1}, P_J, the R_JL blocks, the eigen
   // workspace) plus the problem (pairs, pattern, owner lists, scratch)
-  const double doubles = 6.0 * nn + 2.25 * nk * nk + nk * r + 12.0 * m + 11.0 * nk +
+  const double doubles = 6.0 * nn + 2.25 * nk * nk + nk * r + 12.0 * m + 13.0 * nk +
                          (2.0 + k + pair_cap) * nn + pairs * n + nk * r + 8192.0;
   return (size_t)(8.0 * doubles) + problem_bytes_estimate(n, m);
 }

@@ -148,6 +148,28 @@ __device__ __forceinline__ dd dd_fma2(dd acc, double a, double bhi, double blo) 
   return dd_add(acc, p);
 }
 
+// Compensated dot product (Ogita, Rump and Oishi, "Accurate sum and dot product", SIAM J. Sci.
+// Comput. 26, 2005: Dot2).  s is the rounded running sum; c gathers every product's rounding
+// error (TwoProduct) and every addition's (TwoSum).  The result s + c is as accurate as the dot
+// product evaluated in twice the working precision, with an error below gamma_n^2 sum |x_i y_i|
+// (n terms, gamma_n = n u / (1 - n u)).  Unlike a double-double accumulator, a term depends on
+// the previous ones through one addition to s and one to c only, so the terms pipeline.
+struct dot2 {
+  double s = 0.0, c = 0.0;
+};
+
+// a += x (yhi + ylo); the product with the low part is folded into the product's error term
+__device__ __forceinline__ void dot2_add(dot2& a, double x, double yhi, double ylo) {
+  const dd p = two_prod(x, yhi);
+  const double pe = fma(x, ylo, p.lo);
+  const dd t = two_sum(a.s, p.hi);
+  a.s = t.hi;
+  a.c += t.lo + pe;
+}
+
+// s + c as a normalized double-double (TwoSum: |c| may exceed |s| after cancellation)
+__device__ __forceinline__ dd dot2_result(const dot2& a) { return two_sum(a.s, a.c); }
+
 __device__ __forceinline__ dd shfl_xor_dd(dd v, int o) {
   return {__shfl_xor(v.hi, o, kWave), __shfl_xor(v.lo, o, kWave)};
 }

@@ -229,7 +229,9 @@ int launch_hv(const lrsdp_problem* P, const TW* W, const double* v, double* Hv, 
 }
 
 // ---------------------------------------------------------------- double-double residual
-// res = r - H (y + ylo) with every product error-free and every sum in double-double.
+// res = r - H (y + ylo) with every product error-free: the rows of T = W mat(A (y + ylo)) and the
+// gathers A_i . (T W) are compensated dot products (Dot2), whose partial results are combined
+// in double-double.
 
 __device__ __forceinline__ void scatter_dd_body(int bx, int nnz, const int32_t* __restrict__ src,
                                                 const double* __restrict__ val,
@@ -280,19 +282,18 @@ __device__ __forceinline__ void residual_dd_body(
   {
     const int sub = threadIdx.x & 7;
     for (int p = threadIdx.x >> 3; p < n; p += kThreads / 8) {
+      dot2 part[CB];
       dd acc[CB];
-#pragma unroll
-      for (int c = 0; c < CB; ++c) acc[c] = {0.0, 0.0};
       const int lo = rowptr[p], hi = rowptr[p + 1];
       for (int e = lo + sub; e < hi; e += 8) {
         const int q = colidx[e];
         const double h = mhi[e], l = mlo[e];
 #pragma unroll
-        for (int c = 0; c < CB; ++c) acc[c] = dd_fma2(acc[c], Wb[c * ldn + q], h, l);
+        for (int c = 0; c < CB; ++c) dot2_add(part[c], Wb[c * ldn + q], h, l);
       }
 #pragma unroll
       for (int c = 0; c < CB; ++c) {
-        dd v = acc[c];
+        dd v = dot2_result(part[c]);
         v = dd_add(v, {__shfl_xor(v.hi, 1, 8), __shfl_xor(v.lo, 1, 8)});
         v = dd_add(v, {__shfl_xor(v.hi, 2, 8), __shfl_xor(v.lo, 2, 8)});
         v = dd_add(v, {__shfl_xor(v.hi, 4, 8), __shfl_xor(v.lo, 4, 8)});
@@ -317,9 +318,9 @@ __device__ __forceinline__ void residual_dd_body(
     const int c = owner_row(own_ptr, c0, cb, t);
     const int a = own_oth[t];
     const double* wa = W + (size_t)a * n;
-    dd s = {0.0, 0.0};
-    for (int p = lane; p < n; p += kWave) s = dd_fma2(s, wa[p], Th[c * ldn + p], Tl[c * ldn + p]);
-    s = wave_sum_dd(s);
+    dot2 part;
+    for (int p = lane; p < n; p += kWave) dot2_add(part, wa[p], Th[c * ldn + p], Tl[c * ldn + p]);
+    const dd s = wave_sum_dd(dot2_result(part));
     if (lane == 0) {
       const int i = own_con[t];
       dd hv = dd_mul_d(s, coef[i]);

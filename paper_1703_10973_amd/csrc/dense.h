@@ -61,26 +61,27 @@ size_t potrf_inv_tmp_doubles(int N);
 int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
               bool want_L, hipStream_t s, const SideStream* side = nullptr);
 // Cholesky A = L L^T with a block-explicit inverse.  Below a size (4096) the result is that of
-// potrf_inv (Li holds L^{-1}, *split = 0).  From it on a node keeps L11^{-1} in Li's (1, 1)
-// block and L21 itself in its (2, 1) block, and its (2, 2) block is again such a node while it
-// is that large, else L22^{-1} (*split = N1 of the top node).  The diagonal is then a chain of
-// blocks with explicit inverses (binv_blocks), each with its node's L21 below it: the products
-// that would turn the L21 into (L^{-1})_21 are the largest of the factorization, and the block
-// form applies L^{-1} with the same bytes.  A is used as scratch.
+// potrf_inv (Li holds L^{-1}, *split = 0).  From it on a node keeps L21 itself in Li's (2, 1)
+// block, and each of its diagonal blocks is again such a node while it is that large, else its
+// explicit inverse (*split = N1 of the top node).  The diagonal is then the leaves of a binary
+// tree (binv_blocks), each holding its explicit inverse, and every entry below the leaves' blocks
+// is L's: the products that would turn the L21 into (L^{-1})_21 are the largest of the
+// factorization, and the block form applies L^{-1} with the same bytes.  A is used as scratch.
 int potrf_binv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
                hipStream_t s, const SideStream* side, int* split);
-// The diagonal blocks of a block-explicit factor of order N: offs[0] = 0 < offs[1] < ... <
-// offs[nb] = N (offs: room for kBinvMaxBlocks + 1); returns nb (1: not block-explicit).
+// The diagonal blocks (the tree's leaves) of a block-explicit factor of order N: offs[0] = 0 <
+// offs[1] < ... < offs[nb] = N (offs: room for kBinvMaxBlocks + 1); returns nb (1: not
+// block-explicit).
 constexpr int kBinvMaxBlocks = 32;
 int binv_blocks(int N, int* offs);
 // y (+)= L^{-T} L^{-1} (x - xsub) for a factor of potrf_binv whose lower triangle was mirrored
-// into the upper one (so the upper part holds the blocks' L_bb^{-T} and the L21^T); xsub may
-// be nullptr.  Row-wise GEMVs over the same bytes as trmv_pair_ex, left-looking block by block.
+// into the upper one (so the upper part holds the leaves' L_bb^{-T} and L^T elsewhere); xsub
+// may be nullptr.  Row-wise GEMVs over the same bytes as trmv_pair_ex, left-looking block by block.
 // tmp: 3 N doubles.
 int binv_apply(const double* M, int N, int split, int ld, const double* x, const double* xsub,
                double* tmp, double* y, bool accumulate, hipStream_t s);
-// Turns every L21 of a potrf_binv factor into (L^{-1})_21 = -L22^{-1} L21 L11^{-1}, from the
-// last node up (the lower triangle then holds L^{-1}); tmp: (N - split) split doubles.
+// Turns every L21 of a potrf_binv factor into (L^{-1})_21 = -L22^{-1} L21 L11^{-1}, children
+// before their node (the lower triangle then holds L^{-1}); tmp: (N - split) split doubles.
 int binv_full_inverse(double* Li, int N, int split, int ld, double* tmp, hipStream_t s);
 // y = M_up (M_lo x) with M_lo the lower and M_up the upper triangle of M, both including the
 // diagonal (two row-wise triangular GEMVs; tmp: N doubles).  With L^{-1} in the lower

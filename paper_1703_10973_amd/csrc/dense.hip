@@ -1183,32 +1183,72 @@ int potrf_inv(double* A, int N, int lda, double* Li, int ldi, int* flag, double*
 
 // From this size on a node is kept block-explicit: its (2, 1) block keeps L21 and the two
 // products that would turn it into (L^{-1})_21 = -L22^{-1} L21 L11^{-1} are skipped, the largest
-// of the inverse work (n k = 5000: the factor of bold S 3.96 -> 3.33 ms).  The leading block's
-// inverse is formed (the node's own L21 = A21 L11^{-T} needs it); the trailing block is split
-// again while it is this large, so the diagonal is a chain of blocks with explicit inverses and
-// the L21 of each node below its block (n k = 40 000: blocks of 20 032, 9 984, 4 992, 2 496 and
-// 2 496 rows).  Applying L^{-1} then takes 2 b - 1 dependent GEMVs per triangle for b blocks
-// over the same bytes (PCG +0.3 ms per solve at n k = 5000, where b = 2).
+// of the inverse work (n k = 5000: the factor of bold S 3.96 -> 3.33 ms).  Both of its blocks are
+// again such nodes while they are this large: the node's own L21 = A21 L11^{-T} is then solved
+// over the leading block's tree (trsm_tree), with the flops of one triangular solve.  The
+// diagonal is the leaves of the tree, each holding its explicit inverse, and every entry below
+// the leaves' blocks is L's (n k = 40 000: 16 leaves of 2496-2528 rows).  Applying L^{-1} then
+// takes 2 b - 1 dependent GEMVs per triangle for b leaves over the same bytes (PCG +0.3 ms per
+// solve at n k = 5000, where b = 2).
 // (Keeping -L21 L11^{-1} instead, formed on the side stream while the trailing block factors,
 // needs four: at n k = 5000 it cost 0.4 ms more setup than it saved in the PCG, and at
 // n k = 40000 the product competed with the trailing factorization: 528 -> 661 ms.)
 constexpr int kBlockInvMin = 4096;
+constexpr int kBinvMaxDepth = 5;  // at most 2^5 = kBinvMaxBlocks leaves
+static_assert((1 << kBinvMaxDepth) <= kBinvMaxBlocks, "leaf count");
+
+static bool binv_leaf(int N, int depth) { return N < kBlockInvMin || depth >= kBinvMaxDepth; }
+
+static void binv_leaves(int o, int N, int depth, int* offs, int* nb) {
+  if (binv_leaf(N, depth)) {
+    offs[(*nb)++] = o;
+    return;
+  }
+  const int N1 = split64(N);
+  binv_leaves(o, N1, depth + 1, offs, nb);
+  binv_leaves(o + N1, N - N1, depth + 1, offs, nb);
+}
 
 int binv_blocks(int N, int* offs) {
-  int nb = 0, a = 0;
-  offs[0] = 0;
-  while (N - a >= kBlockInvMin && nb + 1 < kBinvMaxBlocks) {
-    a += split64(N - a);
-    offs[++nb] = a;
-  }
-  offs[++nb] = N;
+  int nb = 0;
+  binv_leaves(0, N, 0, offs, &nb);
+  offs[nb] = N;
   return nb;
 }
 
-// One node of the chain (depth: that of its children in the side stream's events).
+// Lo = Ai L^{-T} for the node of order n at Li's diagonal position D (block-explicit below it as
+// potrf_binv leaves it): Ai (rows x n, in A's storage, pitch lda) is overwritten on the way;
+// Lo (rows x n, pitch ldi) receives the result.  Left to right over the node's two blocks:
+// Lo_1 = Ai_1 L11^{-T}; Ai_2 -= Lo_1 L21^T; Lo_2 = Ai_2 L22^{-T}.
+static int trsm_tree(double* Ai, int lda, double* Lo, int ldi, const double* D, int rows, int n,
+                     int depth, hipStream_t s) {
+  if (binv_leaf(n, depth)) {
+    GemmArgs g;
+    g.M = rows; g.N = n; g.K = n;
+    g.A = Ai; g.lda = lda;
+    g.B = D; g.ldb = ldi; g.transB = true;  // op(B)[k][j] = L^{-1}[j][k], zero for k > j
+    g.C = Lo; g.ldc = ldi;
+    g.flags = kKToCol;
+    return gemm(g, s);
+  }
+  const int n1 = split64(n), n2 = n - n1;
+  LRSDP_TRY(trsm_tree(Ai, lda, Lo, ldi, D, rows, n1, depth + 1, s));
+  {  // Ai_2 -= Lo_1 L21^T
+    GemmArgs g;
+    g.M = rows; g.N = n2; g.K = n1;
+    g.A = Lo; g.lda = ldi;
+    g.B = D + (size_t)n1 * ldi; g.ldb = ldi; g.transB = true;
+    g.C = Ai + n1; g.ldc = lda;
+    g.alpha = -1.0; g.beta = 1.0;
+    LRSDP_TRY(gemm(g, s));
+  }
+  return trsm_tree(Ai + n1, lda, Lo + n1, ldi, D + (size_t)n1 * ldi + n1, rows, n2, depth + 1, s);
+}
+
+// One node of the tree (depth: its own; its children's in the side stream's events is one more).
 static int binv_rec(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
-                    hipStream_t s, const SideStream* side, int depth, int room) {
-  if (N < kBlockInvMin || room <= 1)
+                    hipStream_t s, const SideStream* side, int depth) {
+  if (binv_leaf(N, depth))
     return potrf_inv_rec(A, N, lda, Li, ldi, flag, tmp, false, s, side, depth);
   const int N1 = split64(N), N2 = N - N1;
   double* A21 = A + (size_t)N1 * lda;
@@ -1216,16 +1256,9 @@ static int binv_rec(double* A, int N, int lda, double* Li, int ldi, int* flag, d
   double* L21 = Li + (size_t)N1 * ldi;  // the (2, 1) block of Li keeps L21 itself
   double* Li22 = L21 + N1;
   // each child joins its own side-stream product before it returns, so tmp is free again
-  LRSDP_TRY(potrf_inv_rec(A, N1, lda, Li, ldi, flag, tmp, false, s, side, depth + 1));
-  {  // L21 = A21 L11^{-T}
-    GemmArgs g;
-    g.M = N2; g.N = N1; g.K = N1;
-    g.A = A21; g.lda = lda;
-    g.B = Li; g.ldb = ldi; g.transB = true;  // op(B)[k][j] = L11^{-1}[j][k], zero for k > j
-    g.C = L21; g.ldc = ldi;
-    g.flags = kKToCol;
-    LRSDP_TRY(gemm(g, s));
-  }
+  LRSDP_TRY(binv_rec(A, N1, lda, Li, ldi, flag, tmp, s, side, depth + 1));
+  // L21 = A21 L11^{-T}
+  LRSDP_TRY(trsm_tree(A21, lda, L21, ldi, Li, N2, N1, depth + 1, s));
   {  // A22 -= L21 L21^T (lower)
     GemmArgs g;
     g.M = N2; g.N = N2; g.K = N1;
@@ -1235,14 +1268,14 @@ static int binv_rec(double* A, int N, int lda, double* Li, int ldi, int* flag, d
     g.alpha = -1.0; g.beta = 1.0; g.flags = kLowerOut;
     LRSDP_TRY(gemm(g, s));
   }
-  return binv_rec(A22, N2, lda, Li22, ldi, flag, tmp, s, side, depth + 1, room - 1);
+  return binv_rec(A22, N2, lda, Li22, ldi, flag, tmp, s, side, depth + 1);
 }
 
 int potrf_binv(double* A, int N, int lda, double* Li, int ldi, int* flag, double* tmp,
                hipStream_t s, const SideStream* side, int* split) {
   *split = 0;
-  LRSDP_TRY(binv_rec(A, N, lda, Li, ldi, flag, tmp, s, side, 0, kBinvMaxBlocks));
-  if (N >= kBlockInvMin) *split = split64(N);
+  LRSDP_TRY(binv_rec(A, N, lda, Li, ldi, flag, tmp, s, side, 0));
+  if (!binv_leaf(N, 0)) *split = split64(N);
   return LRSDP_OK;
 }
 
@@ -1251,7 +1284,7 @@ int binv_apply(const double* M, int N, int split, int ld, const double* x, const
   if (split <= 0) return trmv_pair_ex(M, N, ld, x, xsub, tmp, y, accumulate, s);
   int offs[kBinvMaxBlocks + 1];
   const int nb = binv_blocks(N, offs);
-  if (nb < 2 || offs[1] != split) return LRSDP_ERR_INVALID_ARG;
+  if (nb < 2 || split != split64(N)) return LRSDP_ERR_INVALID_ARG;
   ProfMark pm = prof_begin(LRSDP_K_GEMV, s);
   double* F = tmp;          // f = L^{-1} (x - xsub)
   double* R = tmp + N;      // a block's right-hand side after the other blocks' terms
@@ -1294,37 +1327,39 @@ int binv_apply(const double* M, int N, int split, int ld, const double* x, const
   return LRSDP_OK;
 }
 
-int binv_full_inverse(double* Li, int N, int split, int ld, double* tmp, hipStream_t s) {
-  if (split <= 0) return LRSDP_OK;
-  int offs[kBinvMaxBlocks + 1];
-  const int nb = binv_blocks(N, offs);
-  if (nb < 2 || offs[1] != split) return LRSDP_ERR_INVALID_ARG;
-  // node c of the chain covers rows [offs[c], N) and splits at offs[c + 1]; from the last node
-  // up, its trailing block already holds the explicit inverse
-  for (int c = nb - 2; c >= 0; --c) {
-    const int a = offs[c], N1 = offs[c + 1] - a, N2 = N - offs[c + 1];
-    double* L11i = Li + (size_t)a * ld + a;
-    double* L21 = L11i + (size_t)N1 * ld;
-    {  // tmp = L21 L11^{-1}
-      GemmArgs g;
-      g.M = N2; g.N = N1; g.K = N1;
-      g.A = L21; g.lda = ld;
-      g.B = L11i; g.ldb = ld;  // L11^{-1}[k][j], zero for k < j
-      g.C = tmp; g.ldc = N1;
-      g.flags = kKFromCol | kInverseOnly;
-      LRSDP_TRY(gemm(g, s));
-    }
-    {  // (L^{-1})_21 = -L22^{-1} tmp
-      GemmArgs g;
-      g.M = N2; g.N = N1; g.K = N2;
-      g.A = L21 + N1; g.lda = ld;  // L22^{-1}, zero for k > i
-      g.B = tmp; g.ldb = N1;
-      g.C = L21; g.ldc = ld;
-      g.alpha = -1.0; g.flags = kKToRow | kInverseOnly;
-      LRSDP_TRY(gemm(g, s));
-    }
+// (L^{-1})_21 = -L22^{-1} L21 L11^{-1} for the node of order N at Li (both blocks already hold
+// explicit inverses); tmp: (N - N1) N1 doubles
+static int binv_node_inverse(double* Li, int N, int ld, double* tmp, int depth, hipStream_t s) {
+  if (binv_leaf(N, depth)) return LRSDP_OK;
+  const int N1 = split64(N), N2 = N - N1;
+  double* L21 = Li + (size_t)N1 * ld;
+  LRSDP_TRY(binv_node_inverse(Li, N1, ld, tmp, depth + 1, s));
+  LRSDP_TRY(binv_node_inverse(L21 + N1, N2, ld, tmp, depth + 1, s));
+  {  // tmp = L21 L11^{-1}
+    GemmArgs g;
+    g.M = N2; g.N = N1; g.K = N1;
+    g.A = L21; g.lda = ld;
+    g.B = Li; g.ldb = ld;  // L11^{-1}[k][j], zero for k < j
+    g.C = tmp; g.ldc = N1;
+    g.flags = kKFromCol | kInverseOnly;
+    LRSDP_TRY(gemm(g, s));
+  }
+  {  // (L^{-1})_21 = -L22^{-1} tmp
+    GemmArgs g;
+    g.M = N2; g.N = N1; g.K = N2;
+    g.A = L21 + N1; g.lda = ld;  // L22^{-1}, zero for k > i
+    g.B = tmp; g.ldb = N1;
+    g.C = L21; g.ldc = ld;
+    g.alpha = -1.0; g.flags = kKToRow | kInverseOnly;
+    LRSDP_TRY(gemm(g, s));
   }
   return LRSDP_OK;
+}
+
+int binv_full_inverse(double* Li, int N, int split, int ld, double* tmp, hipStream_t s) {
+  if (split <= 0) return LRSDP_OK;
+  if (split != split64(N)) return LRSDP_ERR_INVALID_ARG;
+  return binv_node_inverse(Li, N, ld, tmp, 0, s);
 }
 
 int trmv_pair_ex(const double* M, int N, int ld, const double* x, const double* xsub,

@@ -322,11 +322,12 @@ def test_hessian_apply_large_n(ctx):
 
 @pytest.mark.parametrize("precond", ["smw", "aug"])
 def test_block_explicit_factor_matches_oracle(ctx, precond):
-    """nk = 8400 is above the block-explicit size, and so is its trailing block of 4176 rows: the
-    factor of bold S (or of the augmented trailing block) is kept as a chain of three diagonal
-    blocks (4224, 2112 and 2064 rows) with explicit inverses and each node's L21 below its
-    block.  The exported inverse (the library then forms the full L^{-1}, from the last node
-    up), every preconditioner mode and the solve match the oracle.  (At this
+    """nk = 8400 is above the block-explicit size, and so are both of its blocks (4224 and 4176
+    rows): the factor of bold S (or of the augmented trailing block) is kept as a tree whose four
+    leaves (2112, 2112, 2112 and 2064 rows) hold explicit inverses, with L below them; the
+    leading blocks' L21 are solved over the tree.  The exported inverse (the library then forms
+    the full L^{-1}, children before their node), every preconditioner mode and the solve match
+    the oracle.  (At this
     size the checks use a random block and the bound kappa <= lambda_max / lambda_min, with
     Gershgorin's bound on lambda_max and a lower bound on the smallest eigenvalue: tau^2 for deflated bold S, tau / 2 for the augmented block.)"""
     from oracle import aug

@@ -108,7 +108,8 @@ typedef struct lrsdp_opts {
   int dd_mode;           /* LRSDP_DD_* (default AUTO)                                       */
   int deflate;           /* 1: deflate the k(k-1)/2 null directions of bold S (default 1)   */
   int max_outer;         /* outer refinement steps (default 8)                              */
-  double inner_eps;      /* inner PCG tolerance in refinement mode (default 1e-3)           */
+  double inner_eps;      /* inner PCG tolerance in refinement mode; 0 (default): 1e-2 with  */
+                         /* BF16 W0 products, else 1e-3                                     */
   double dd_auto_ratio;  /* spectral-gap threshold for LRSDP_DD_AUTO (default 2e-5)         */
   int dd_precond;        /* SMW pieces in double-double: 0 off, 1 on, 2 auto (default 2:    */
                          /* on when tau < 1e-7 lambda_max(W))                                */

@@ -148,7 +148,7 @@ struct DeviceGuard {
 
 bool opts_valid(const lrsdp_opts& o) {
   return o.eps > 0.0 && o.max_iter >= 1 && o.precision >= 0 && o.precision <= 3 &&
-         o.dd_mode >= 0 && o.dd_mode <= 2 && o.max_outer >= 0 && o.inner_eps > 0.0 &&
+         o.dd_mode >= 0 && o.dd_mode <= 2 && o.max_outer >= 0 && o.inner_eps >= 0.0 &&
          o.inner_eps < 1.0 && o.dd_precond >= 0 && o.dd_precond <= 2 && o.tau_rule >= 0 &&
          o.tau_rule <= 1 && (o.precond == LRSDP_PRECOND_SMW || o.precond == LRSDP_PRECOND_AUG);
 }
@@ -169,7 +169,7 @@ void lrsdp_opts_default(lrsdp_opts* o) {
   o->dd_mode = LRSDP_DD_AUTO;
   o->deflate = 1;
   o->max_outer = 8;
-  o->inner_eps = 1e-3;
+  o->inner_eps = 0.0;  // by precision (inner_tol)
   o->dd_auto_ratio = 2e-5;
   o->dd_precond = 2;
   o->tau_rule = LRSDP_TAU_MEAN;

@@ -219,6 +219,13 @@ struct SolveMode {
   int prec = LRSDP_PREC_FP64, ref64 = 0, dd_steps = 1;
 };
 SolveMode solve_mode(const lrsdp_factor* f, const lrsdp_opts& o);
+// The inner PCG tolerance of the refinement: inner_eps when given, else 1e-2 with BF16 W0
+// products (whose operator is off by ~2^-8, so converging further buys nothing the outer
+// double-double step keeps) and 1e-3 otherwise.
+inline double inner_tol(const lrsdp_opts& o, const SolveMode& md) {
+  if (o.inner_eps > 0.0) return o.inner_eps;
+  return md.prec == LRSDP_PREC_BF16 ? 1e-2 : 1e-3;
+}
 // The step sequence of a factor's solve as one number: solves with equal keys can advance in
 // lock-step (solve_lockstep); -1 when the solve takes a step that is not batched (the
 // double-double SMW pieces, the augmented preconditioner, the block-explicit inverse, k > 4,

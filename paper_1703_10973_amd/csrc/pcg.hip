@@ -405,7 +405,7 @@ int solve_run(lrsdp_factor* f, const double* r, double* y, double* ylo, const lr
         break;
       }
       PcgOut po;
-      LRSDP_TRY(pcg(f, w.dd0, o.inner_eps, o.max_iter, Hm, Pinv, &po));
+      LRSDP_TRY(pcg(f, w.dd0, inner_tol(o, md), o.max_iter, Hm, Pinv, &po));
       inf.iters += po.iters;
       inf.outer_iters = outer + 1;
       if (po.status < 0) {
@@ -807,7 +807,7 @@ int solve_lockstep(lrsdp_ctx* ctx, int count, lrsdp_factor* const* F, const doub
           any = true;
         }
         if (!any) break;
-        LRSDP_TRY(pcg_ls(live, kVdd0, o.inner_eps, o.max_iter));
+        LRSDP_TRY(pcg_ls(live, kVdd0, inner_tol(o, md), o.max_iter));
         for (int z = 0; z < count; ++z) {
           if (!live[z]) continue;
           info[z].iters += po[z].iters;

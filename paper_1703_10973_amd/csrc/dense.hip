@@ -1020,10 +1020,15 @@ int gemm(const GemmArgs& g, hipStream_t s) {
   const bool big = t64 >= 8192 || (!tri && t64 >= 1024);
   const int te = big ? 128 : t64 >= 320 ? 64 : 32;
   ProfMark pm = prof_begin((g.flags & kInverseOnly) ? LRSDP_K_GEMMINV : LRSDP_K_GEMM, s);
-  // (big triangular products: 16 wavefronts of 32 x 32 blocks, 50-52 against 49-51 TFLOP/s for
-  // eight 64 x 32 blocks at n = 10 000; untriangular ones keep the eight: 57 against 51)
-  if (big && tri) launch_gemm<4, 4, 1, 2, 2>(g, s);
+  // (big triangular products and lower-triangle outputs with K >= 256: 16 wavefronts of 32 x 32 blocks,
+  // 50-52 against 49-51 TFLOP/s for eight 64 x 32 blocks at n = 10 000, and 40.0 against 37.9
+  // for the lower-triangle product at 2500 rows; full products keep the eight: 57 against 51.
+  // The batched transposed-A products of the bold S formation at n = 1000 take their 64 x 64
+  // tiles without the K split: 33.7 against 31.4 TFLOP/s.)
+  const bool syrk = (g.flags & kLowerOut) && g.K >= 256;  // (not the thin deflation update)
+  if (big && (tri || syrk)) launch_gemm<4, 4, 1, 2, 2>(g, s);
   else if (big) launch_gemm<2, 4, 1, 4, 2>(g, s);
+  else if (t64 >= 320 && g.offs && g.transA) launch_gemm<2, 2, 1>(g, s);
   else if (t64 >= 320) launch_gemm<2, 2, 2>(g, s);
   else launch_gemm<1, 1, 4>(g, s);
   LRSDP_HIP(hipGetLastError());

@@ -289,6 +289,30 @@ def test_solve_refined(ctx, mu, prec):
     assert err <= 1e-6
 
 
+def test_inner_tolerance_by_precision(ctx):
+    """The refinement's inner PCG stops at 1e-2 with BF16 W0 products by default (inner_eps =
+    0), and at a given inner_eps when one is set: both reach the 1e-8 target (the oracle's
+    double-double true residual), and the tighter explicit tolerance takes at least as many
+    inner iterations per outer step."""
+    inst = make_instance(200, 3, 3000, 1e-8, seed=1201)
+    P = problem_from(ctx, inst)
+    F = pk.Factor(P, to_dev(inst.W), inst.k)
+    runs = {}
+    for name, ie in (("default", 0.0), ("explicit", 1e-3)):
+        o = pk.opts(dd_mode=pk.LRSDP_DD_ON, precision=pk.LRSDP_PREC_BF16, inner_eps=ie)
+        y, ylo, st, info = F.solve(to_dev(inst.r), o)
+        assert st == 0, (name, info)
+        r_true, _ = ddo.true_relative_residual(inst.W, inst.a, inst.b, inst.val, inst.r,
+                                               host(y), host(ylo))
+        assert r_true <= 1e-8, (name, r_true)
+        runs[name] = info["iters"] / max(1, info["outer_iters"])
+    assert runs["explicit"] >= runs["default"], runs
+    with pytest.raises(pk.LrsdpError):  # a negative tolerance is refused
+        F.solve(to_dev(inst.r), pk.opts(inner_eps=-1e-3))
+    F.close()
+    P.close()
+
+
 # ------------------------------------------------------------------ large n: T rows outside LDS
 
 def test_hessian_apply_large_n(ctx):

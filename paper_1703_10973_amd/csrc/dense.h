@@ -89,7 +89,7 @@ int binv_full_inverse(double* Li, int N, int split, int ld, double* tmp, hipStre
 int trmv_pair(const double* M, int N, int ld, const double* x, double* tmp, double* y,
               hipStream_t s);
 // y (+)= L^{-T} (L^{-1} (x - xsub)) with the same two passes; xsub may be nullptr, and with
-// accumulate the result is added to y.
+// accumulate the result is added to y.  tmp: N doubles (2 N with xsub).
 int trmv_pair_ex(const double* M, int N, int ld, const double* x, const double* xsub,
                  double* tmp, double* y, bool accumulate, hipStream_t s);
 // X := M^T M (lower part), M lower triangular N x N; X and M distinct.

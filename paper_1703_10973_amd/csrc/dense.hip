@@ -902,6 +902,16 @@ __global__ __launch_bounds__(256) void k_gemv_tri_b(const BL b, int xr, int xsr,
                             d.v[yr], upper, nullptr, 0);
 }
 
+// d = x - xs, each difference rounded once.  (The triangular GEMVs then read one vector: with
+// x - xs formed inside them the compiler keeps fewer loads in flight, 40 VGPRs against 64, and
+// the product took 18 us against 9 at 2528 rows.)
+__global__ __launch_bounds__(256) void k_sub_vec(int N, const double* __restrict__ x,
+                                                 const double* __restrict__ xs,
+                                                 double* __restrict__ d) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < N) d[i] = x[i] - xs[i];
+}
+
 // y[r] = (b[r] - bs[r]) - sum_{c < K} A[r][c] x[c] for rows r < R (kSub; else b[r] - ...), one
 // wavefront per row with eight loads in flight per lane, like k_gemv_tri.
 template <bool kSub>
@@ -1301,10 +1311,12 @@ int binv_apply(const double* M, int N, int split, int ld, const double* x, const
     const int a = offs[b], e = offs[b + 1], h = e - a, g = (h + 3) / 4;
     const double* Mb = M + (size_t)a * ld;
     if (b == 0) {
-      if (xsub)
-        k_gemv_tri<true, false><<<g, 256, 0, s>>>(M, h, h, ld, x, xsub, F, 0, nullptr, 0);
-      else
-        k_gemv_tri<false, false><<<g, 256, 0, s>>>(M, h, h, ld, x, nullptr, F, 0, nullptr, 0);
+      const double* xb = x;
+      if (xsub) {  // x - xsub into R's first block (not used otherwise)
+        k_sub_vec<<<(h + 255) / 256, 256, 0, s>>>(h, x, xsub, R);
+        xb = R;
+      }
+      k_gemv_tri<false, false><<<g, 256, 0, s>>>(M, h, h, ld, xb, nullptr, F, 0, nullptr, 0);
       continue;
     }
     if (xsub)
@@ -1371,10 +1383,12 @@ int trmv_pair_ex(const double* M, int N, int ld, const double* x, const double* 
                  double* tmp, double* y, bool accumulate, hipStream_t s) {
   ProfMark pm = prof_begin(LRSDP_K_GEMV, s);
   const int grid = (N + 3) / 4;
-  if (xsub)
-    k_gemv_tri<true, false><<<grid, 256, 0, s>>>(M, N, N, ld, x, xsub, tmp, 0, nullptr, 0);
-  else
-    k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, N, ld, x, nullptr, tmp, 0, nullptr, 0);
+  const double* xv = x;
+  if (xsub) {  // x - xsub into tmp's second half
+    k_sub_vec<<<(N + 255) / 256, 256, 0, s>>>(N, x, xsub, tmp + N);
+    xv = tmp + N;
+  }
+  k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, N, ld, xv, nullptr, tmp, 0, nullptr, 0);
   if (accumulate)
     k_gemv_tri<false, true><<<grid, 256, 0, s>>>(M, N, N, ld, tmp, nullptr, y, 1, nullptr, 0);
   else

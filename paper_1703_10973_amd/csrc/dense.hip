@@ -912,6 +912,16 @@ __global__ __launch_bounds__(256) void k_sub_vec(int N, const double* __restrict
   if (i < N) d[i] = x[i] - xs[i];
 }
 
+// lock-step batch (packed grid): d = x - xs over the instance's nk entries
+__global__ __launch_bounds__(256) void k_sub_vec_b(const BL b, int xr, int xsr, int dr) {
+  int bx;
+  const int z = bl_find(b, kKnk256, blockIdx.x, &bx);
+  if (!b.act[z]) return;
+  const BInst& d = b.I[z];
+  const int i = bx * 256 + threadIdx.x;
+  if (i < d.nk) d.v[dr][i] = d.v[xr][i] - d.v[xsr][i];
+}
+
 // y[r] = (b[r] - bs[r]) - sum_{c < K} A[r][c] x[c] for rows r < R (kSub; else b[r] - ...), one
 // wavefront per row with eight loads in flight per lane, like k_gemv_tri.
 template <bool kSub>
@@ -1402,10 +1412,12 @@ int bl_gemv_pair(const BLaunch& L, int xrole, int xsub_role, int tmp_role, int y
                  bool accumulate, hipStream_t s) {
   if (L.b.count <= 0 || L.tot[kKgemv] <= 0) return LRSDP_OK;
   const int grid = L.tot[kKgemv];
-  if (xsub_role >= 0)
-    k_gemv_tri_b<true, false><<<grid, 256, 0, s>>>(L.b, xrole, xsub_role, tmp_role, 0);
-  else
-    k_gemv_tri_b<false, false><<<grid, 256, 0, s>>>(L.b, xrole, 0, tmp_role, 0);
+  int xr = xrole;
+  if (xsub_role >= 0) {  // x - xsub into the h2 work vector first, as trmv_pair_ex does
+    k_sub_vec_b<<<L.tot[kKnk256], 256, 0, s>>>(L.b, xrole, xsub_role, kVwh2);
+    xr = kVwh2;
+  }
+  k_gemv_tri_b<false, false><<<grid, 256, 0, s>>>(L.b, xr, 0, tmp_role, 0);
   if (accumulate)
     k_gemv_tri_b<false, true><<<grid, 256, 0, s>>>(L.b, tmp_role, 0, yrole, 1);
   else

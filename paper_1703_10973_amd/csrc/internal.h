@@ -250,7 +250,7 @@ int residual_dd(lrsdp_factor* f, const double* r, const double* y, const double*
 enum BRole : int {
   kVx, kVr, kVz, kVp, kVq,                // PCG vectors (m)
   kVrhs, kVy, kVyl, kVdd0, kVdd1,         // the solve's right-hand side, answer, residual pair
-  kVwy, kVww, kVwt, kVws, kVwh, kVwg0, kVwg1, kVwt0,  // nk / k x n work
+  kVwy, kVww, kVwt, kVws, kVwh, kVwh2, kVwg0, kVwg1, kVwt0,  // nk / k x n work
   kVRoles
 };
 struct BInst {

@@ -505,6 +505,7 @@ int solve_lockstep(lrsdp_ctx* ctx, int count, lrsdp_factor* const* F, const doub
     d.v[kVyl] = ylo[z] ? ylo[z] : w.ylo;
     d.v[kVdd0] = w.dd0; d.v[kVdd1] = w.dd1;
     d.v[kVwy] = w.y; d.v[kVww] = w.w; d.v[kVwt] = w.t; d.v[kVws] = w.s; d.v[kVwh] = w.h;
+    d.v[kVwh2] = w.h2;
     d.v[kVwg0] = w.g0; d.v[kVwg1] = w.g1; d.v[kVwt0] = w.t0;
     d.sc = f->sc; d.part = w.part; d.counter = red_counter(f);
     d.g_vec = grid_for(d.m, kT, 1024);

@@ -852,14 +852,13 @@ __global__ __launch_bounds__(256) void k_gemv(const double* __restrict__ A, int 
 }
 
 // y = tri(A) x for rows r < R of A, with tri the lower (upper = 0: columns [0, min(r + 1, C)))
-// or upper (upper = 1: columns [r, C)) part including the diagonal.  One wavefront per row, eight independent accumulators so that eight loads per
-// lane are in flight (the rows are long and the product is bound by HBM).
-// kSub: the vector is x - xs (each difference rounded once); kAcc: y += the product.  When y2
-// is given, the row's result (y's new value) is also stored there (y2[r] += it when acc2).
-template <bool kSub, bool kAcc>
+// or upper (upper = 1: columns [r, C)) part including the diagonal.  One wavefront per row,
+// eight independent accumulators so that eight loads per lane are in flight (the rows are long
+// and the product is bound by HBM).  kAcc: y += the product.  When y2 is given, the row's result
+// is also stored there (y2[r] += it when acc2).  (A vector x - xs is formed first, k_sub_vec.)
+template <bool kAcc>
 __device__ __forceinline__ void gemv_tri_body(int bx, const double* __restrict__ A, int R, int C,
                                               int lda, const double* __restrict__ x,
-                                              const double* __restrict__ xs,
                                               double* __restrict__ y, int upper,
                                               double* __restrict__ y2, int acc2) {
   const int lane = threadIdx.x & 63;
@@ -867,14 +866,13 @@ __device__ __forceinline__ void gemv_tri_body(int bx, const double* __restrict__
   if (row >= R) return;
   const double* a = A + (size_t)row * lda;
   const int lo = upper ? row : 0, hi = upper ? C : min(row + 1, C);
-  auto xv = [&](int c) { return kSub ? x[c] - xs[c] : x[c]; };
   double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int c = lo + lane;
   for (; c + 7 * 64 < hi; c += 8 * 64) {
 #pragma unroll
-    for (int u = 0; u < 8; ++u) s[u] = fma(a[c + u * 64], xv(c + u * 64), s[u]);
+    for (int u = 0; u < 8; ++u) s[u] = fma(a[c + u * 64], x[c + u * 64], s[u]);
   }
-  for (int u = 0; c < hi; c += 64, ++u) s[u] = fma(a[c], xv(c), s[u]);
+  for (int u = 0; c < hi; c += 64, ++u) s[u] = fma(a[c], x[c], s[u]);
   double t = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   t = wave_sum(t);
   if (lane == 0) {
@@ -882,24 +880,21 @@ __device__ __forceinline__ void gemv_tri_body(int bx, const double* __restrict__
     if (y2) y2[row] = acc2 ? y2[row] + t : t;
   }
 }
-template <bool kSub, bool kAcc>
+template <bool kAcc>
 __global__ __launch_bounds__(256) void k_gemv_tri(const double* __restrict__ A, int R, int C,
                                                   int lda, const double* __restrict__ x,
-                                                  const double* __restrict__ xs,
                                                   double* __restrict__ y, int upper,
                                                   double* __restrict__ y2, int acc2) {
-  gemv_tri_body<kSub, kAcc>(blockIdx.x, A, R, C, lda, x, xs, y, upper, y2, acc2);
+  gemv_tri_body<kAcc>(blockIdx.x, A, R, C, lda, x, y, upper, y2, acc2);
 }
 // lock-step batch (packed grid): y = tri(L^{-1} or L^{-T}) x with the instance's Sinv
-template <bool kSub, bool kAcc>
-__global__ __launch_bounds__(256) void k_gemv_tri_b(const BL b, int xr, int xsr, int yr,
-                                                    int upper) {
+template <bool kAcc>
+__global__ __launch_bounds__(256) void k_gemv_tri_b(const BL b, int xr, int yr, int upper) {
   int bx;
   const int z = bl_find(b, kKgemv, blockIdx.x, &bx);
   if (!b.act[z]) return;
   const BInst& d = b.I[z];
-  gemv_tri_body<kSub, kAcc>(bx, d.Sinv, d.nk, d.nk, d.nk, d.v[xr], kSub ? d.v[xsr] : nullptr,
-                            d.v[yr], upper, nullptr, 0);
+  gemv_tri_body<kAcc>(bx, d.Sinv, d.nk, d.nk, d.nk, d.v[xr], d.v[yr], upper, nullptr, 0);
 }
 
 // d = x - xs, each difference rounded once.  (The triangular GEMVs then read one vector: with
@@ -1326,15 +1321,14 @@ int binv_apply(const double* M, int N, int split, int ld, const double* x, const
         k_sub_vec<<<(h + 255) / 256, 256, 0, s>>>(h, x, xsub, R);
         xb = R;
       }
-      k_gemv_tri<false, false><<<g, 256, 0, s>>>(M, h, h, ld, xb, nullptr, F, 0, nullptr, 0);
+      k_gemv_tri<false><<<g, 256, 0, s>>>(M, h, h, ld, xb, F, 0, nullptr, 0);
       continue;
     }
     if (xsub)
       k_gemv_rect<true><<<g, 256, 0, s>>>(Mb, h, a, ld, F, x + a, xsub + a, R + a);
     else
       k_gemv_rect<false><<<g, 256, 0, s>>>(Mb, h, a, ld, F, x + a, nullptr, R + a);
-    k_gemv_tri<false, false><<<g, 256, 0, s>>>(Mb + a, h, h, ld, R + a, nullptr, F + a, 0,
-                                               nullptr, 0);
+    k_gemv_tri<false><<<g, 256, 0, s>>>(Mb + a, h, h, ld, R + a, F + a, 0, nullptr, 0);
   }
   // backward, left-looking over the mirrored upper part (which holds L_bb^{-T} and the
   // L21^T of every node): r = f_b - L_{>e, b}^T y_{>e}; y_b = L_bb^{-T} r
@@ -1346,8 +1340,7 @@ int binv_apply(const double* M, int N, int split, int ld, const double* x, const
       k_gemv_rect<false><<<g, 256, 0, s>>>(Mb + e, h, N - e, ld, Yr + e, F + a, nullptr, R + a);
       rhs = R + a;
     }
-    k_gemv_tri<false, false><<<g, 256, 0, s>>>(Mb + a, h, h, ld, rhs, nullptr, Yr + a, 1, y + a,
-                                               acc);
+    k_gemv_tri<false><<<g, 256, 0, s>>>(Mb + a, h, h, ld, rhs, Yr + a, 1, y + a, acc);
   }
   LRSDP_HIP(hipGetLastError());
   prof_end(pm, s, 8.0 * (double)N * (N + 1) + 32.0 * nb * N, 2.0 * (double)N * (N + 1));
@@ -1398,11 +1391,11 @@ int trmv_pair_ex(const double* M, int N, int ld, const double* x, const double* 
     k_sub_vec<<<(N + 255) / 256, 256, 0, s>>>(N, x, xsub, tmp + N);
     xv = tmp + N;
   }
-  k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, N, ld, xv, nullptr, tmp, 0, nullptr, 0);
+  k_gemv_tri<false><<<grid, 256, 0, s>>>(M, N, N, ld, xv, tmp, 0, nullptr, 0);
   if (accumulate)
-    k_gemv_tri<false, true><<<grid, 256, 0, s>>>(M, N, N, ld, tmp, nullptr, y, 1, nullptr, 0);
+    k_gemv_tri<true><<<grid, 256, 0, s>>>(M, N, N, ld, tmp, y, 1, nullptr, 0);
   else
-    k_gemv_tri<false, false><<<grid, 256, 0, s>>>(M, N, N, ld, tmp, nullptr, y, 1, nullptr, 0);
+    k_gemv_tri<false><<<grid, 256, 0, s>>>(M, N, N, ld, tmp, y, 1, nullptr, 0);
   LRSDP_HIP(hipGetLastError());
   prof_end(pm, s, 8.0 * (double)N * (N + 1) + 32.0 * N, 2.0 * (double)N * (N + 1));
   return LRSDP_OK;
@@ -1417,11 +1410,11 @@ int bl_gemv_pair(const BLaunch& L, int xrole, int xsub_role, int tmp_role, int y
     k_sub_vec_b<<<L.tot[kKnk256], 256, 0, s>>>(L.b, xrole, xsub_role, kVwh2);
     xr = kVwh2;
   }
-  k_gemv_tri_b<false, false><<<grid, 256, 0, s>>>(L.b, xr, 0, tmp_role, 0);
+  k_gemv_tri_b<false><<<grid, 256, 0, s>>>(L.b, xr, tmp_role, 0);
   if (accumulate)
-    k_gemv_tri_b<false, true><<<grid, 256, 0, s>>>(L.b, tmp_role, 0, yrole, 1);
+    k_gemv_tri_b<true><<<grid, 256, 0, s>>>(L.b, tmp_role, yrole, 1);
   else
-    k_gemv_tri_b<false, false><<<grid, 256, 0, s>>>(L.b, tmp_role, 0, yrole, 1);
+    k_gemv_tri_b<false><<<grid, 256, 0, s>>>(L.b, tmp_role, yrole, 1);
   LRSDP_HIP(hipGetLastError());
   return LRSDP_OK;
 }

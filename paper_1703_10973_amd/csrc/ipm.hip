@@ -137,6 +137,14 @@ __global__ void k_zero_int(int count, int* p) {
   if (i < count) p[i] = 0;
 }
 
+// *flag = 1 when M (n x n) is not M[0][0] I (every writer stores the same value)
+__global__ void k_not_scaled_eye(int n, const double* M, int* flag) {
+  const size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  if (idx >= (size_t)n * n) return;
+  const size_t i = idx / n, j = idx - i * n;
+  if (M[idx] != (i == j ? M[0] : 0.0)) *flag = 1;
+}
+
 // ---------------------------------------------------------------- Lanczos
 // h[i] = V[i] . w for the rows i < R of V (R x n, row-major): one wavefront per row
 __global__ __launch_bounds__(256) void k_rows_dot(int R, int n, const double* __restrict__ V,
@@ -328,6 +336,20 @@ struct Ipm {
     g.beta = beta;
     g.flags = flags;
     return gemm(g, s);
+  }
+  // whether M is c I (then every eigenvalue is c = M[0][0])
+  int scaled_eye(const double* M, bool* yes, double* c) {
+    k_zero_int<<<1, 64, 0, s>>>(1, flag + 1);
+    k_not_scaled_eye<<<grid_for((int64_t)nn, 256), 256, 0, s>>>(n, M, flag + 1);
+    LRSDP_HIP(hipGetLastError());
+    LRSDP_HIP(hipMemcpyAsync(&ctx->h_pinned[41], flag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    LRSDP_HIP(hipMemcpyAsync(&ctx->h_pinned[42], M, sizeof(double), hipMemcpyDeviceToHost, s));
+    LRSDP_HIP(hipStreamSynchronize(s));
+    int h = 0;
+    std::memcpy(&h, &ctx->h_pinned[41], sizeof(int));
+    *yes = h == 0;
+    *c = ctx->h_pinned[42];
+    return LRSDP_OK;
   }
   // Cholesky of M (copied into Lm, which receives L when keep_L) and its inverse into Linv
   // (lower; the upper part outside the 64-aligned diagonal blocks is left undefined, and no
@@ -699,8 +721,17 @@ int ipm_run(lrsdp_problem* P, const double* bvec, const double* C, const lrsdp_i
         // lam_top[i - 1] = lambda_i(W), the k + 1 largest
         double lam_top[17];
         int steps = 0;
-        const int lrc = o.householder_eig ? LRSDP_NOT_CONVERGED
-                                          : I.lanczos(I.W, 0, nullptr, o.k + 1, lam_top, 1e-8, &steps);
+        // the first iterate from the default start has W = c I (X and S multiples of I): every
+        // eigenvalue is c, which Lanczos cannot see (its Krylov space closes at once)
+        bool flat = false;
+        double c = 0.0;
+        if (it == 0) LRSDP_TRY(I.scaled_eye(I.W, &flat, &c));
+        if (flat)
+          for (int i = 0; i <= o.k; ++i) lam_top[i] = c;
+        const int lrc = flat ? LRSDP_OK
+                        : o.householder_eig
+                            ? LRSDP_NOT_CONVERGED
+                            : I.lanczos(I.W, 0, nullptr, o.k + 1, lam_top, 1e-8, &steps);
         if (lrc < 0) return lrc;
         if (lrc != LRSDP_OK) {  // Householder path: hl[1 .. k+1] are the k+1 largest ascending
           LRSDP_TRY(eig_top_and_min(I.W, n, o.k + 1, I.ews, I.lam, I.vl, s));

@@ -472,6 +472,18 @@ LRSDP_API int lrsdp_ipm_solve(lrsdp_problem* p, const double* b, const double* C
                               const lrsdp_ipm_opts* opts, double* X, double* y, double* S,
                               lrsdp_ipm_info* info, lrsdp_ipm_record* recs, int max_recs);
 
+/* Section 4.1, eq aug_ex: x = W~^{-1} b for W~ = tau I + U U^T (eq tIUUt) through the symmetric
+ * indefinite augmented system [[tau I, sqrt(tau) U], [sqrt(tau) U^T, -tau I]] [x; y] = [b; 0],
+ * solved by LU with partial pivoting (backward stable: ||b - W~ x|| stays at the rounding level
+ * of ||W~|| ||x|| as tau -> 0, where the Sherman-Morrison-Woodbury route of eq wsmf loses
+ * u kappa(W~)).  Ut: U^T, k x n row-major (the factor's U layout); b, x: length-n; all device
+ * arrays, b and x may not overlap.  Dense: (n + k)^2 doubles of device memory from ctx's pool
+ * and O((n + k)^3) work, for n + k <= 16384.  Synchronous on ctx's stream.  Errors:
+ * INVALID_ARG (sizes, tau <= 0 or not finite, or a zero or non-finite pivot: U or b not
+ * finite), OUT_OF_BUDGET, DEVICE. */
+LRSDP_API int lrsdp_aug_wtilde_solve(lrsdp_ctx* ctx, int32_t n, int32_t k, double tau,
+                                     const double* Ut, const double* b, double* x);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,7 @@ from ._lib import (  # noqa: F401
     LRSDP_K_NAMES,
     lrsdp_factor_create, lrsdp_factor_destroy, lrsdp_factor_export, lrsdp_factor_info,
     lrsdp_hessian_apply, lrsdp_hessian_apply_noalloc, lrsdp_hessian_apply_split, lrsdp_info,
+    lrsdp_aug_wtilde_solve,
     lrsdp_opts,
     lrsdp_opts_default, lrsdp_precond_apply, lrsdp_problem_create, lrsdp_problem_destroy,
     lrsdp_problem_info, lrsdp_residual_dd, lrsdp_solve, status_string, lrsdp_instance,
@@ -95,6 +96,14 @@ class Context:
         """Time kernel classes (bit mask) with HIP events, one launch in `every`."""
         lrsdp_ctx_profile_sample(self.handle, every)
         lrsdp_ctx_profile(self.handle, enable)
+
+    def aug_wtilde_solve(self, Ut, tau, b, out=None):
+        """x = (tau I + U U^T)^{-1} b through the augmented system of Section 4.1 (eq aug_ex),
+        by LU with partial pivoting on the device; Ut is U^T (k x n)."""
+        x = torch.empty_like(b) if out is None else out
+        _caller_work_done(self)
+        lrsdp_aug_wtilde_solve(self.handle, Ut, tau, b, x)
+        return x
 
     def profile_read(self):
         return {name: lrsdp_ctx_profile_read(self.handle, i) for i, name in enumerate(LRSDP_K_NAMES)}

@@ -125,6 +125,7 @@ _SIGS = {
                                      C.POINTER(C.c_int64)]),
     "lrsdp_hessian_apply": (C.c_int, [_P, _P, _P, _P]),
     "lrsdp_hessian_apply_noalloc": (C.c_int, [_P, _P, _P, _P]),
+    "lrsdp_aug_wtilde_solve": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_double, _P, _P, _P]),
     "lrsdp_factor_create": (C.c_int, [_P, _P, C.c_int32, C.POINTER(lrsdp_opts), C.POINTER(_P)]),
     "lrsdp_factor_destroy": (None, [_P]),
     "lrsdp_factor_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
@@ -304,6 +305,16 @@ def lrsdp_hessian_apply_noalloc(p, W, v, Hv):
                                           _ptr(v, torch.float64, m, "v"),
                                           _ptr(Hv, torch.float64, m, "Hv")),
         "lrsdp_hessian_apply_noalloc")
+
+
+def lrsdp_aug_wtilde_solve(ctx, Ut, tau, b, x):
+    """x = (tau I + U U^T)^{-1} b through the augmented system of Section 4.1 (eq aug_ex);
+    Ut is U^T (k x n)."""
+    k, n = int(Ut.shape[0]), int(Ut.shape[1])
+    _ok(lib().lrsdp_aug_wtilde_solve(ctx, n, k, float(tau), _ptr(Ut, torch.float64, n * k, "Ut"),
+                                     _ptr(b, torch.float64, n, "b"),
+                                     _ptr(x, torch.float64, n, "x")),
+        "lrsdp_aug_wtilde_solve")
 
 
 def lrsdp_factor_create(p, W, k, opts=None):

@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "liblrsdp.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["api.hip", "ingest.hip", "hv.hip", "dense.hip", "eig.hip", "spectral.hip", "serve.hip", "factor.hip",
-           "apply.hip", "pcg.hip", "ipm.hip"]
+           "apply.hip", "pcg.hip", "ipm.hip", "augsys.hip"]
 
 HIP_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-mcode-object-version=5",

@@ -442,6 +442,13 @@ int lrsdp_hessian_apply(lrsdp_problem* p, const double* W, const double* v, doub
   return LRSDP_OK;
 }
 
+int lrsdp_aug_wtilde_solve(lrsdp_ctx* ctx, int32_t n, int32_t k, double tau, const double* Ut,
+                           const double* b, double* x) {
+  if (!ctx) return LRSDP_ERR_INVALID_ARG;
+  DeviceGuard g(ctx->device);
+  return aug_wtilde_solve(ctx, n, k, tau, Ut, b, x);
+}
+
 int lrsdp_hessian_apply_noalloc(lrsdp_problem* p, const double* W, const double* v, double* Hv) {
   if (!p || !W || !v || !Hv) return LRSDP_ERR_INVALID_ARG;
   DeviceGuard g(p->ctx->device);

@@ -114,6 +114,9 @@ int ctx_create(int device, void* stream, size_t budget, bool blocking, lrsdp_ctx
 
 // ---------------------------------------------------------------- memory
 bool opts_ok(const lrsdp_opts& o);  // the option checks of the entry points
+// x = (tau I + U U^T)^{-1} b through the augmented system of eq aug_ex (augsys.hip)
+int aug_wtilde_solve(lrsdp_ctx* ctx, int n, int k, double tau, const double* Ut, const double* b,
+                     double* x);
 int dev_alloc(lrsdp_ctx* ctx, void** p, size_t bytes);
 void dev_free(lrsdp_ctx* ctx, void* p, size_t bytes);
 

@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--workload", default="mu-path",
                     choices=["mu-path", "batch", "serving", "serving-sessions", "large", "ipm", "hv",
-                             "single", "copy-calibration"],
+                             "single", "copy-calibration", "augsys"],
                     help="mu-path (default): the headline line; batch: 256 independent "
                          "instances (n in [64, 512], k in 1..4, mu = 1e-6); serving: Poisson "
                          "request stream (n in [200, 3000], k in 1..8, mu in [1e-8, 1e-2]); "
@@ -214,7 +214,7 @@ def main():
         return {"batch": run_batch, "serving": run_serving, "large": run_large, "ipm": run_ipm,
                 "hv": run_hv,
                 "serving-sessions": run_serving_sessions, "single": run_single,
-                "copy-calibration": run_copy}[args.workload](args)
+                "copy-calibration": run_copy, "augsys": run_augsys}[args.workload](args)
     import torch
 
     import paper_1703_10973_amd as pk
@@ -900,6 +900,91 @@ def run_large(args):
         "config": {"workload": "n=4000 k=10 m=400000 mu=1e-8 seed 4001"}}))
     P.close()
     ctx.close()
+
+
+def run_augsys(args):
+    """Section 4.1: W~ x = b (W~ = tau I + U U^T) through the augmented system of eq aug_ex on
+    the device (LU with partial pivoting), at the headline shape n = 1000, k = 5, over tau from
+    1e-2 to 1e-12.  U = V_l (Lambda_l - t)^{1/2} from the top five eigenpairs of the headline
+    generator's W at mu = 1e-8 (t the mean of the other eigenvalues); b = U c, the right-hand
+    side on which eq wsmf cancels.  value = device solves/s (mean over tau); the backward
+    errors ||b - W~ x|| / (||W~|| ||x|| + ||b||) of the device's answers; the cpu_baseline leg
+    times the oracle's pivoted solve and gives eq wsmf's backward errors and the device
+    answers' forward errors against a 50-digit reference."""
+    import torch
+
+    import paper_1703_10973_amd as pk
+    from synth import make_instance
+    dev = torch.device("cuda", 0)
+    inst = make_instance(1000, 5, 20000, 1e-8, seed=2001)
+    lam, V = np.linalg.eigh(inst.W)
+    n, k = 1000, 5
+    t = float(lam[:n - k].mean())
+    Ut = (V[:, n - k:] * np.sqrt(lam[n - k:] - t)).T.copy()  # k x n
+    b = Ut.T @ np.random.default_rng(2002).standard_normal(k)
+    taus = [1e-2, 1e-4, 1e-6, 1e-8, 1e-10, 1e-12]
+    ctx = pk.Context(0)
+    dUt, db = torch.as_tensor(Ut, device=dev), torch.as_tensor(b, device=dev)
+    ms, back, xs = [], [], []
+    for tau in taus:
+        x = ctx.aug_wtilde_solve(dUt, tau, db)  # warm-up
+        torch.cuda.synchronize()
+        runs = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            x = ctx.aug_wtilde_solve(dUt, tau, db)
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t0)
+        ms.append(float(np.median(runs)) * 1e3)
+        xh = x.cpu().numpy()
+        xs.append(xh)
+        W = tau * np.eye(n) + Ut.T @ Ut
+        back.append(float(np.linalg.norm(b - W @ xh) /
+                          (np.linalg.norm(W, 2) * np.linalg.norm(xh) + np.linalg.norm(b))))
+    N = n + k
+    bytes_per_solve = 16.0 * (N - 1) * N * (2 * N - 1) / 6.0 + 8.0 * N * N
+    mean_ms = float(np.mean(ms))
+    line = {
+        "metric": "augmented-system solves of W~ x = b (Section 4.1, eq aug_ex) at n=1000 k=5",
+        "value": 1e3 / mean_ms, "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic", "taus": taus, "ms_per_solve": ms,
+        "backward_error_device": back,
+        "roofline": {"bound": "hbm", "achieved": bytes_per_solve / (mean_ms * 1e-3) / 1e9,
+                     "peak": 8000.0, "unit": "GB/s",
+                     "frac": bytes_per_solve / (mean_ms * 1e-3) / 1e9 / 8000.0,
+                     "traffic": None, "bytes_per_solve": bytes_per_solve,
+                     "kernel": "k_aug_update (trailing block read and written per column)"},
+        "config": {"workload": "n=1000 k=5, U from the top eigenpairs of the mu=1e-8 headline W, "
+                               "b in range(U), tau 1e-2..1e-12"}}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = _augsys_cpu_baseline(Ut, b, taus, xs)
+    print(json.dumps(line))
+    ctx.close()
+
+
+def _augsys_cpu_baseline(Ut, b, taus, xs):
+    """The oracle's pivoted solve of eq aug_ex (LAPACK LU, host threads) timed over the same taus;
+    eq wsmf's backward errors in FP64; the device answers' forward errors against the oracle's
+    50-digit answer, beside kappa(W~) u."""
+    from oracle import augsys as A
+    n = Ut.shape[1]
+    total, smw_back, fwd, kw = 0.0, [], [], []
+    for tau, x in zip(taus, xs):
+        t0 = time.perf_counter()
+        A.aug_solve(Ut, tau, b)
+        total += time.perf_counter() - t0
+        W = A.wtilde(Ut, tau)
+        xs_ = A.smw_solve(Ut, tau, b)
+        smw_back.append(float(np.linalg.norm(b - W @ xs_) /
+                              (np.linalg.norm(W, 2) * np.linalg.norm(xs_) + np.linalg.norm(b))))
+        xe = A.exact_solve(Ut, tau, b)
+        fwd.append(float(np.linalg.norm(x - xe) / np.linalg.norm(xe)))
+        kw.append(A.wtilde_cond(Ut, tau) * np.finfo(np.float64).eps)
+    return {"value": len(taus) / total, "unit": "solves/s", "cores": os.cpu_count(),
+            "kind": "oracle", "sample": f"the oracle's LU solve of eq aug_ex (n + k = {n + 5}) at "
+                                        f"each of the {len(taus)} taus",
+            "seconds": total, "smw_backward_error": smw_back,
+            "device_forward_error_vs_50_digits": fwd, "kappa_wtilde_times_u": kw}
 
 
 def run_hv(args):
